@@ -1,0 +1,713 @@
+/*
+ * Plain FP64 CPU oracle of one coupled time step of the conservative
+ * Allen-Cahn phase-field lattice Boltzmann method (D3Q15, SRT) and the
+ * velocity-based hydrodynamic lattice Boltzmann method (D3Q27, weighted
+ * orthogonal MRT) of Holzer, Bauer, Koestler and Ruede (IJHPCA 2020,
+ * arXiv 2012.06144), Sections 3.1 and 3.2.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the slow, literal checker the
+ * GPU library is compared against.  Only the tests, the smoke check and
+ * the CPU-baseline leg of the benchmark may load it.  It shares no code,
+ * header, table or helper with the GPU library.
+ *
+ * What follows each formula of the paper in its own words and order:
+ *   - lattice weights: the standard D3Q15 / D3Q27 sets (not printed in the
+ *     paper; pinned by the isotropy conditions in the tests);
+ *   - phase-field step: pull streaming, phi = sum of the pulled PDFs
+ *     (eq. updatePhaseField), isotropic gradient (eq. grad), normal and
+ *     theta (eq. allen_cahn), forcing F^phi (eq. interfaceTracking),
+ *     equilibrium phi*Gamma, single-relaxation collision (eq. lb_interface
+ *     with a scalar relaxation rate, as used in Section 5);
+ *   - hydrodynamic step: moments, rho and tau interpolation (eq. density
+ *     and the tau interpolation of Section 3.2), isotropic gradient and
+ *     Laplacian (eqs. grad, lap), chemical potential (eq. chemPot),
+ *     pressure, surface tension, viscous and body forces (eqs.
+ *     forceHydro, pressure_force, surfaceTension, viscousForce, and the
+ *     buoyancy of Section 6.1), velocity update (eq. updateVelocityField),
+ *     and the moment-space collision m* = m - S(m - m_eq + F_m/2) + F_m,
+ *     g* = M^-1 m* (eq. improved_collision and the listing beside it),
+ *     with a literal 27x27 moment matrix; push streaming.
+ *
+ * Readings where the paper is silent or ambiguous (each also listed in
+ * the design notes of the repository):
+ *   - the phase relaxation rate is 1/(tau_phi + 1/2) with tau_phi = M/cs^2
+ *     (the literal 1/tau_phi is outside the stable range);
+ *   - the hydrodynamic tau is the model tau of nu = tau*cs^2, rate
+ *     s_nu = 1/(tau + 1/2) on all six second-order moments, 1 elsewhere;
+ *   - the moment basis is Gram-Schmidt of the 27 monomials x^a y^b z^c
+ *     (a,b,c <= 2) in total-degree order under sum_i w_i f_i g_i, rows not
+ *     normalised (rows 1..3 stay e_x, e_y, e_z, so F_m = (0, F/rho, 0..));
+ *   - fused time levels: the phase step takes grad(phi) and theta from the
+ *     previous phi field (phi_A) and u from the previous hydrodynamic step;
+ *     the hydrodynamic step takes the new phi (phi_B) and uses the stored
+ *     (old) u only inside the viscous force;
+ *   - the normal is grad/(|grad| + eps); gradients are summed as
+ *     antisymmetric pair differences so an exactly symmetric field gives an
+ *     exactly zero gradient;
+ *   - rho and tau interpolations divide by (phi_H - phi_L);
+ *   - y walls: rows 0 and ny-1 are solid, halfway bounce-back for h and g,
+ *     phi stencils mirror the wall row onto the first fluid row.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define Q15 15
+#define Q27 27
+
+typedef struct {
+    int32_t nx, ny, nz;
+    int32_t walls_y;
+    double phi_L, phi_H, xi, mobility, sigma;
+    double rho_L, rho_H, tau_L, tau_H;
+    double accel[3];
+    double normal_eps;
+} orc_params;
+
+typedef struct {
+    double mass;
+    double momentum[3];
+    double gas_volume;
+    double centroid[3];
+    double rise_velocity;
+    double interface_sum;   /* sum 4 chi (1 - chi) */
+    double grad_sum;        /* sum |grad phi| / (phi_H - phi_L) */
+    double xi_eff;
+    double max_speed;
+} orc_stats;
+
+/* ---- velocity sets ------------------------------------------------------
+ * Canonical order: rest, then axis pairs, then (D3Q27) edge pairs, then
+ * corner pairs; every odd index i has its opposite at i+1.               */
+static const int E15[Q15][3] = {
+    {0, 0, 0},
+    {1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0}, {0, 0, 1}, {0, 0, -1},
+    {1, 1, 1}, {-1, -1, -1}, {1, 1, -1}, {-1, -1, 1},
+    {1, -1, 1}, {-1, 1, -1}, {-1, 1, 1}, {1, -1, -1}};
+
+static const int E27[Q27][3] = {
+    {0, 0, 0},
+    {1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0}, {0, 0, 1}, {0, 0, -1},
+    {1, 1, 0}, {-1, -1, 0}, {1, -1, 0}, {-1, 1, 0},
+    {1, 0, 1}, {-1, 0, -1}, {1, 0, -1}, {-1, 0, 1},
+    {0, 1, 1}, {0, -1, -1}, {0, 1, -1}, {0, -1, 1},
+    {1, 1, 1}, {-1, -1, -1}, {1, 1, -1}, {-1, -1, 1},
+    {1, -1, 1}, {-1, 1, -1}, {-1, 1, 1}, {1, -1, -1}};
+
+static double W15[Q15];
+static double W27[Q27];
+
+static void init_weights(void)
+{
+    for (int i = 0; i < Q15; ++i) {
+        int n = abs(E15[i][0]) + abs(E15[i][1]) + abs(E15[i][2]);
+        W15[i] = (n == 0) ? 2.0 / 9.0 : (n == 1) ? 1.0 / 9.0 : 1.0 / 72.0;
+    }
+    for (int i = 0; i < Q27; ++i) {
+        int n = abs(E27[i][0]) + abs(E27[i][1]) + abs(E27[i][2]);
+        W27[i] = (n == 0) ? 8.0 / 27.0 : (n == 1) ? 2.0 / 27.0
+               : (n == 2) ? 1.0 / 54.0 : 1.0 / 216.0;
+    }
+}
+
+static int opposite(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1); }
+
+static const double CS2 = 1.0 / 3.0; /* c_s^2 with dx = dt = 1 */
+
+/* ---- lattice queries used by the pins ---------------------------------- */
+int orc_velocity_set(int32_t q, int32_t *e, double *w)
+{
+    init_weights();
+    if (q == Q15) {
+        for (int i = 0; i < Q15; ++i) {
+            for (int a = 0; a < 3; ++a) e[3 * i + a] = E15[i][a];
+            w[i] = W15[i];
+        }
+        return 0;
+    }
+    if (q == Q27) {
+        for (int i = 0; i < Q27; ++i) {
+            for (int a = 0; a < 3; ++a) e[3 * i + a] = E27[i][a];
+            w[i] = W27[i];
+        }
+        return 0;
+    }
+    return -1;
+}
+
+/* Gamma_i(u) = w_i [1 + e.u/cs^2 + (e.u)^2/(2 cs^4) - u.u/(2 cs^2)]
+ * (dimensionless distribution of Section 3.1).                          */
+static double gamma_i(const int e[3], double w, const double u[3])
+{
+    double eu = e[0] * u[0] + e[1] * u[1] + e[2] * u[2];
+    double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    return w * (1.0 + eu / CS2 + (eu * eu) / (2.0 * CS2 * CS2) - uu / (2.0 * CS2));
+}
+
+void orc_gamma(int32_t q, const double *u, double *out)
+{
+    init_weights();
+    for (int i = 0; i < q; ++i)
+        out[i] = (q == Q15) ? gamma_i(E15[i], W15[i], u) : gamma_i(E27[i], W27[i], u);
+}
+
+/* g_eq_i = p* w_i + (Gamma_i - w_i)  (Section 3.2) */
+static void hydro_equilibrium(double pstar, const double u[3], double out[Q27])
+{
+    for (int i = 0; i < Q27; ++i)
+        out[i] = pstar * W27[i] + (gamma_i(E27[i], W27[i], u) - W27[i]);
+}
+
+void orc_hydro_equilibrium(double pstar, const double *u, double *out)
+{
+    init_weights();
+    hydro_equilibrium(pstar, u, out);
+}
+
+/* F^phi_i = theta w_i e_i . n  (eq. interfaceTracking, dt = 1) */
+static void phase_forcing(double theta, const double n[3], double out[Q15])
+{
+    for (int i = 0; i < Q15; ++i)
+        out[i] = theta * W15[i] * (E15[i][0] * n[0] + E15[i][1] * n[1] + E15[i][2] * n[2]);
+}
+
+void orc_phase_forcing(double theta, const double *n, double *out)
+{
+    init_weights();
+    phase_forcing(theta, n, out);
+}
+
+/* ---- D3Q27 weighted-orthogonal moment matrix ---------------------------- */
+static double MM[Q27][Q27];   /* row k: orthogonalised monomial k at e_i */
+static double MINV[Q27][Q27];
+static int DEG[Q27];          /* total degree of the monomial of row k */
+static int EXPO[Q27][3];      /* exponents (a, b, c) of the monomial of row k */
+static int mrt_ready = 0;
+
+static double monomial(const int e[3], int a, int b, int c)
+{
+    double v = 1.0;
+    for (int k = 0; k < a; ++k) v *= e[0];
+    for (int k = 0; k < b; ++k) v *= e[1];
+    for (int k = 0; k < c; ++k) v *= e[2];
+    return v;
+}
+
+static double winner(const double *f, const double *g)
+{
+    double s = 0.0;
+    for (int i = 0; i < Q27; ++i) s += W27[i] * f[i] * g[i];
+    return s;
+}
+
+/* Gauss-Jordan inverse with partial pivoting. */
+static int invert27(double A[Q27][Q27], double R[Q27][Q27])
+{
+    double T[Q27][2 * Q27];
+    for (int r = 0; r < Q27; ++r)
+        for (int c = 0; c < 2 * Q27; ++c)
+            T[r][c] = (c < Q27) ? A[r][c] : (c - Q27 == r ? 1.0 : 0.0);
+    for (int col = 0; col < Q27; ++col) {
+        int piv = col;
+        for (int r = col + 1; r < Q27; ++r)
+            if (fabs(T[r][col]) > fabs(T[piv][col])) piv = r;
+        if (fabs(T[piv][col]) < 1e-14) return -1;
+        if (piv != col)
+            for (int c = 0; c < 2 * Q27; ++c) {
+                double t = T[col][c]; T[col][c] = T[piv][c]; T[piv][c] = t;
+            }
+        double d = T[col][col];
+        for (int c = 0; c < 2 * Q27; ++c) T[col][c] /= d;
+        for (int r = 0; r < Q27; ++r) {
+            if (r == col) continue;
+            double f = T[r][col];
+            if (f != 0.0)
+                for (int c = 0; c < 2 * Q27; ++c) T[r][c] -= f * T[col][c];
+        }
+    }
+    for (int r = 0; r < Q27; ++r)
+        for (int c = 0; c < Q27; ++c) R[r][c] = T[r][Q27 + c];
+    return 0;
+}
+
+static int build_mrt(void)
+{
+    if (mrt_ready) return 0;
+    init_weights();
+    /* monomials x^a y^b z^c, a,b,c in {0,1,2}, sorted by total degree;
+     * within a degree the order is fixed but irrelevant (equal rates). */
+    int k = 0;
+    for (int deg = 0; deg <= 6; ++deg)
+        for (int a = 2; a >= 0; --a)
+            for (int b = 2; b >= 0; --b)
+                for (int c = 2; c >= 0; --c) {
+                    if (a + b + c != deg) continue;
+                    for (int i = 0; i < Q27; ++i) MM[k][i] = monomial(E27[i], a, b, c);
+                    DEG[k] = deg;
+                    EXPO[k][0] = a;
+                    EXPO[k][1] = b;
+                    EXPO[k][2] = c;
+                    ++k;
+                }
+    /* modified Gram-Schmidt, weighted inner product, no normalisation */
+    for (int r = 0; r < Q27; ++r)
+        for (int s = 0; s < r; ++s) {
+            double proj = winner(MM[r], MM[s]) / winner(MM[s], MM[s]);
+            for (int i = 0; i < Q27; ++i) MM[r][i] -= proj * MM[s][i];
+        }
+    if (invert27(MM, MINV) != 0) return -1;
+    mrt_ready = 1;
+    return 0;
+}
+
+/* Export M, M^-1 and the degree of each row for the pins. */
+int orc_moment_matrix(double *M, double *Minv, int32_t *deg)
+{
+    if (build_mrt() != 0) return -1;
+    for (int r = 0; r < Q27; ++r) {
+        deg[r] = DEG[r];
+        for (int c = 0; c < Q27; ++c) {
+            M[r * Q27 + c] = MM[r][c];
+            Minv[r * Q27 + c] = MINV[r][c];
+        }
+    }
+    return 0;
+}
+
+static void relaxation_rates(double s_nu, double S[Q27])
+{
+    for (int k = 0; k < Q27; ++k) S[k] = (DEG[k] == 2) ? s_nu : 1.0;
+}
+
+static void matvec(double A[Q27][Q27], const double *x, double *y)
+{
+    for (int r = 0; r < Q27; ++r) {
+        double s = 0.0;
+        for (int c = 0; c < Q27; ++c) s += A[r][c] * x[c];
+        y[r] = s;
+    }
+}
+
+/* Sum_k e_k e_k^T (Omega (g - g_eq(p*, u)))_k with Omega = M^-1 S M:
+ * the bracket of eq. viscousForce, before the factor -nu/cs^2 and the
+ * contraction with grad(rho).                                          */
+static void viscous_bracket(const double g[Q27], double s_nu, const double u[3],
+                            double V[3][3])
+{
+    double pstar = 0.0;
+    for (int i = 0; i < Q27; ++i) pstar += g[i];
+    double geq[Q27], d[Q27], m[Q27], Sd[Q27], om[Q27], S[Q27];
+    hydro_equilibrium(pstar, u, geq);
+    for (int i = 0; i < Q27; ++i) d[i] = g[i] - geq[i];
+    relaxation_rates(s_nu, S);
+    matvec(MM, d, m);
+    for (int k = 0; k < Q27; ++k) Sd[k] = S[k] * m[k];
+    matvec(MINV, Sd, om);
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            double s = 0.0;
+            for (int i = 0; i < Q27; ++i) s += E27[i][a] * E27[i][b] * om[i];
+            V[a][b] = s;
+        }
+}
+
+int orc_viscous_bracket(const double *g, double s_nu, const double *u, double *V)
+{
+    if (build_mrt() != 0) return -1;
+    double v[3][3];
+    viscous_bracket(g, s_nu, u, v);
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) V[3 * a + b] = v[a][b];
+    return 0;
+}
+
+/* Moment-space collision (eq. improved_collision, with the "m -" of the
+ * listing): m = M g, m_eq = M g_eq(p*, u), F_m = (0, F/rho, 0, ...),
+ * m* = m - S (m - m_eq + F_m/2) + F_m, g* = M^-1 m*.                  */
+static void mrt_collide(const double g[Q27], double pstar, const double u[3],
+                        const double F[3], double rho, double s_nu, double out[Q27])
+{
+    double geq[Q27], m[Q27], meq[Q27], Fm[Q27], ms[Q27], S[Q27];
+    hydro_equilibrium(pstar, u, geq);
+    matvec(MM, g, m);
+    matvec(MM, geq, meq);
+    relaxation_rates(s_nu, S);
+    /* F_m is F/rho on the three first-order rows (the monomials x, y, z,
+     * already orthogonal to row 0) and zero on every other row.        */
+    for (int k = 0; k < Q27; ++k) {
+        Fm[k] = 0.0;
+        if (DEG[k] == 1)
+            for (int a = 0; a < 3; ++a)
+                if (EXPO[k][a] == 1) Fm[k] = F[a] / rho;
+    }
+    for (int k = 0; k < Q27; ++k) ms[k] = m[k] - S[k] * (m[k] - meq[k] + 0.5 * Fm[k]) + Fm[k];
+    matvec(MINV, ms, out);
+}
+
+int orc_mrt_collide(const double *g, double pstar, const double *u, const double *F,
+                    double rho, double s_nu, double *out)
+{
+    if (build_mrt() != 0) return -1;
+    mrt_collide(g, pstar, u, F, rho, s_nu, out);
+    return 0;
+}
+
+/* ---- grid --------------------------------------------------------------- */
+typedef struct {
+    orc_params p;
+    int64_t n;
+    double *H, *Hn;      /* 15 planes: post-collision phase PDFs at x */
+    double *G, *Gn;      /* 27 planes: pre-collision hydro PDFs at x */
+    double *phiA, *phiB; /* phase field, previous / new               */
+    double *u;           /* 3 planes                                   */
+} orc_state;
+
+static inline int64_t cidx(const orc_params *p, int x, int y, int z)
+{
+    return (int64_t)x + (int64_t)p->nx * ((int64_t)y + (int64_t)p->ny * z);
+}
+
+static inline int wrap(int v, int n) { return ((v % n) + n) % n; }
+
+static inline int is_wall_row(const orc_params *p, int y)
+{
+    return p->walls_y && (y == 0 || y == p->ny - 1);
+}
+
+/* Neighbour y coordinate: periodic without walls; with walls rows 0 and
+ * ny-1 exist as solid rows and fluid rows never step past them.        */
+static inline int ny_nb(const orc_params *p, int y, int dy)
+{
+    return p->walls_y ? y + dy : wrap(y + dy, p->ny);
+}
+
+/* phi at x + d for the finite-difference stencils; a wall row is replaced
+ * by its mirror image about the wall, which is the current fluid row.  */
+static inline double phi_at(const orc_params *p, const double *phi, int x, int y, int z,
+                            int dx, int dy, int dz)
+{
+    int yy = ny_nb(p, y, dy);
+    if (is_wall_row(p, yy)) yy = y;
+    return phi[cidx(p, wrap(x + dx, p->nx), yy, wrap(z + dz, p->nz))];
+}
+
+/* Isotropic gradient (eq. grad): (1/cs^2) sum_i w_i e_i phi(x + e_i),
+ * evaluated as sum over the half set of w_i e_i (phi(x+e_i) - phi(x-e_i)). */
+static void iso_gradient(const orc_params *p, const double *phi, int q, int x, int y, int z,
+                         double grad[3])
+{
+    const int (*E)[3] = (q == Q15) ? E15 : E27;
+    const double *W = (q == Q15) ? W15 : W27;
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (int i = 1; i < q; i += 2) {
+        double d = phi_at(p, phi, x, y, z, E[i][0], E[i][1], E[i][2]) -
+                   phi_at(p, phi, x, y, z, -E[i][0], -E[i][1], -E[i][2]);
+        for (int a = 0; a < 3; ++a) acc[a] += W[i] * E[i][a] * d;
+    }
+    for (int a = 0; a < 3; ++a) grad[a] = acc[a] / CS2;
+}
+
+/* Isotropic Laplacian (eq. lap): (2/cs^2) sum_i w_i [phi(x+e_i) - phi(x)]. */
+static double iso_laplacian(const orc_params *p, const double *phi, int q, int x, int y, int z)
+{
+    const int (*E)[3] = (q == Q15) ? E15 : E27;
+    const double *W = (q == Q15) ? W15 : W27;
+    double c = phi[cidx(p, x, y, z)];
+    double acc = 0.0;
+    for (int i = 0; i < q; ++i)
+        acc += W[i] * (phi_at(p, phi, x, y, z, E[i][0], E[i][1], E[i][2]) - c);
+    return 2.0 * acc / CS2;
+}
+
+/* Stencil queries on a caller field, for the finite-difference pins. */
+void orc_stencil(const orc_params *p, const double *phi, int32_t q, int32_t x, int32_t y,
+                 int32_t z, double *grad, double *lap)
+{
+    init_weights();
+    iso_gradient(p, phi, q, x, y, z, grad);
+    *lap = iso_laplacian(p, phi, q, x, y, z);
+}
+
+/* ---- state lifecycle ------------------------------------------------------ */
+orc_state *orc_create(const orc_params *p)
+{
+    if (!p || p->nx <= 0 || p->ny <= 0 || p->nz <= 0) return NULL;
+    if (p->walls_y && p->ny < 3) return NULL;
+    if (build_mrt() != 0) return NULL;
+    orc_state *s = (orc_state *)calloc(1, sizeof(orc_state));
+    if (!s) return NULL;
+    s->p = *p;
+    s->n = (int64_t)p->nx * p->ny * p->nz;
+    size_t n = (size_t)s->n;
+    s->H = calloc(Q15 * n, sizeof(double));
+    s->Hn = calloc(Q15 * n, sizeof(double));
+    s->G = calloc(Q27 * n, sizeof(double));
+    s->Gn = calloc(Q27 * n, sizeof(double));
+    s->phiA = calloc(n, sizeof(double));
+    s->phiB = calloc(n, sizeof(double));
+    s->u = calloc(3 * n, sizeof(double));
+    if (!s->H || !s->Hn || !s->G || !s->Gn || !s->phiA || !s->phiB || !s->u) {
+        free(s->H); free(s->Hn); free(s->G); free(s->Gn);
+        free(s->phiA); free(s->phiB); free(s->u); free(s);
+        return NULL;
+    }
+    return s;
+}
+
+void orc_destroy(orc_state *s)
+{
+    if (!s) return;
+    free(s->H); free(s->Hn); free(s->G); free(s->Gn);
+    free(s->phiA); free(s->phiB); free(s->u); free(s);
+}
+
+/* Initial state: h = phi Gamma(u) taken as post-collision, g = g_eq(p*, u)
+ * taken as pre-collision, phi_A = phi, u = u.  Wall cells hold zeros.   */
+void orc_init(orc_state *s, const double *phi, const double *u, const double *pstar)
+{
+    const orc_params *p = &s->p;
+    int64_t n = s->n;
+    memset(s->H, 0, sizeof(double) * Q15 * n);
+    memset(s->G, 0, sizeof(double) * Q27 * n);
+    memset(s->Hn, 0, sizeof(double) * Q15 * n);
+    memset(s->Gn, 0, sizeof(double) * Q27 * n);
+    memset(s->phiA, 0, sizeof(double) * n);
+    memset(s->phiB, 0, sizeof(double) * n);
+    memset(s->u, 0, sizeof(double) * 3 * n);
+    for (int z = 0; z < p->nz; ++z)
+        for (int y = 0; y < p->ny; ++y)
+            for (int x = 0; x < p->nx; ++x) {
+                if (is_wall_row(p, y)) continue;
+                int64_t c = cidx(p, x, y, z);
+                double uc[3] = {u[c], u[n + c], u[2 * n + c]};
+                double geq[Q27];
+                for (int i = 0; i < Q15; ++i) s->H[i * n + c] = phi[c] * gamma_i(E15[i], W15[i], uc);
+                hydro_equilibrium(pstar[c], uc, geq);
+                for (int i = 0; i < Q27; ++i) s->G[i * n + c] = geq[i];
+                s->phiA[c] = phi[c];
+                for (int a = 0; a < 3; ++a) s->u[a * n + c] = uc[a];
+            }
+}
+
+/* ---- phase-field step (pull, sum, collide) ------------------------------ */
+static void phase_cell(orc_state *s, int x, int y, int z)
+{
+    const orc_params *p = &s->p;
+    const int64_t n = s->n;
+    const int64_t c = cidx(p, x, y, z);
+    double P[Q15];
+    for (int i = 0; i < Q15; ++i) {
+        int sy = ny_nb(p, y, -E15[i][1]);
+        if (is_wall_row(p, sy)) {
+            P[i] = s->H[opposite(i) * n + c]; /* halfway bounce-back */
+        } else {
+            int64_t src = cidx(p, wrap(x - E15[i][0], p->nx), sy, wrap(z - E15[i][2], p->nz));
+            P[i] = s->H[i * n + src];
+        }
+    }
+    double phi = 0.0;
+    for (int i = 0; i < Q15; ++i) phi += P[i];
+    s->phiB[c] = phi;
+
+    double grad[3];
+    iso_gradient(p, s->phiA, Q15, x, y, z, grad);
+    double gnorm = sqrt(grad[0] * grad[0] + grad[1] * grad[1] + grad[2] * grad[2]);
+    double nrm[3];
+    for (int a = 0; a < 3; ++a) nrm[a] = grad[a] / (gnorm + p->normal_eps);
+    double phi0 = 0.5 * (p->phi_L + p->phi_H);
+    double dphi = s->phiA[c] - phi0;
+    double theta = (1.0 - 4.0 * dphi * dphi) / p->xi;
+
+    double uc[3] = {s->u[c], s->u[n + c], s->u[2 * n + c]};
+    double tau_phi = p->mobility / CS2;            /* eq. mobility, dt = 1 */
+    double omega = 1.0 / (tau_phi + 0.5);
+    double Fphi[Q15];
+    phase_forcing(theta, nrm, Fphi);
+    for (int i = 0; i < Q15; ++i) {
+        double heq = phi * gamma_i(E15[i], W15[i], uc);
+        s->Hn[i * n + c] = P[i] + omega * (heq - P[i] - 0.5 * Fphi[i]) + Fphi[i];
+    }
+}
+
+/* ---- hydrodynamic step (collide, push, velocity update) ----------------- */
+static void hydro_cell(orc_state *s, int x, int y, int z)
+{
+    const orc_params *p = &s->p;
+    const int64_t n = s->n;
+    const int64_t c = cidx(p, x, y, z);
+    double g[Q27];
+    for (int i = 0; i < Q27; ++i) g[i] = s->G[i * n + c];
+
+    const double dphi = p->phi_H - p->phi_L;
+    double phi = s->phiB[c];
+    double rho = p->rho_L + (phi - p->phi_L) * (p->rho_H - p->rho_L) / dphi;
+    double tau = p->tau_L + (phi - p->phi_L) * (p->tau_H - p->tau_L) / dphi;
+    double s_nu = 1.0 / (tau + 0.5);
+    double nu = tau * CS2;
+
+    double grad[3];
+    iso_gradient(p, s->phiB, Q27, x, y, z, grad);
+    double lap = iso_laplacian(p, s->phiB, Q27, x, y, z);
+    double grad_rho[3];
+    for (int a = 0; a < 3; ++a) grad_rho[a] = (p->rho_H - p->rho_L) / dphi * grad[a];
+
+    double beta = 12.0 * p->sigma / p->xi;
+    double kappa = 1.5 * p->sigma * p->xi;
+    double phi0 = 0.5 * (p->phi_L + p->phi_H);
+    double mu_phi = 4.0 * beta * (phi - p->phi_L) * (phi - p->phi_H) * (phi - phi0) - kappa * lap;
+
+    double pstar = 0.0, j[3] = {0.0, 0.0, 0.0};
+    for (int i = 0; i < Q27; ++i) {
+        pstar += g[i];
+        for (int a = 0; a < 3; ++a) j[a] += g[i] * E27[i][a];
+    }
+
+    double u_old[3] = {s->u[c], s->u[n + c], s->u[2 * n + c]};
+    double V[3][3];
+    viscous_bracket(g, s_nu, u_old, V);
+
+    double F[3];
+    for (int a = 0; a < 3; ++a) {
+        double Fp = -pstar * CS2 * grad_rho[a];
+        double Fs = mu_phi * grad[a];
+        double Fmu = 0.0;
+        for (int b = 0; b < 3; ++b) Fmu += V[a][b] * grad_rho[b];
+        Fmu *= -nu / CS2;
+        double Fb = rho * p->accel[a];
+        F[a] = Fp + Fs + Fmu + Fb;
+    }
+
+    double u_new[3];
+    for (int a = 0; a < 3; ++a) u_new[a] = j[a] + F[a] / (2.0 * rho);
+    for (int a = 0; a < 3; ++a) s->u[a * n + c] = u_new[a];
+
+    double gs[Q27];
+    mrt_collide(g, pstar, u_new, F, rho, s_nu, gs);
+
+    for (int i = 0; i < Q27; ++i) {
+        int dy = ny_nb(p, y, E27[i][1]);
+        if (is_wall_row(p, dy)) {
+            s->Gn[opposite(i) * n + c] = gs[i]; /* halfway bounce-back */
+        } else {
+            int64_t dst = cidx(p, wrap(x + E27[i][0], p->nx), dy, wrap(z + E27[i][2], p->nz));
+            s->Gn[i * n + dst] = gs[i];
+        }
+    }
+}
+
+static void swap_ptr(double **a, double **b) { double *t = *a; *a = *b; *b = t; }
+
+/* One coupled time step: phase pass over all fluid cells, then hydro pass,
+ * then the buffer swap.  Cells are independent within a pass, so the
+ * result does not depend on the number of threads.                     */
+void orc_step(orc_state *s, int32_t nsteps)
+{
+    const orc_params *p = &s->p;
+    const int nyz = p->ny * p->nz;
+    for (int t = 0; t < nsteps; ++t) {
+#pragma omp parallel for schedule(static)
+        for (int yz = 0; yz < nyz; ++yz) {
+            int y = yz % p->ny, z = yz / p->ny;
+            if (is_wall_row(p, y)) continue;
+            for (int x = 0; x < p->nx; ++x) phase_cell(s, x, y, z);
+        }
+#pragma omp parallel for schedule(static)
+        for (int yz = 0; yz < nyz; ++yz) {
+            int y = yz % p->ny, z = yz / p->ny;
+            if (is_wall_row(p, y)) continue;
+            for (int x = 0; x < p->nx; ++x) hydro_cell(s, x, y, z);
+        }
+        swap_ptr(&s->H, &s->Hn);
+        swap_ptr(&s->G, &s->Gn);
+        swap_ptr(&s->phiA, &s->phiB);
+    }
+}
+
+/* Canonical state: H (post-collision phase PDFs), G (pre-collision hydro
+ * PDFs), phi_A (latest phase field), u (latest velocity). Any pointer may
+ * be NULL.                                                             */
+void orc_get_state(const orc_state *s, double *H, double *G, double *phi, double *u)
+{
+    size_t n = (size_t)s->n;
+    if (H) memcpy(H, s->H, sizeof(double) * Q15 * n);
+    if (G) memcpy(G, s->G, sizeof(double) * Q27 * n);
+    if (phi) memcpy(phi, s->phiA, sizeof(double) * n);
+    if (u) memcpy(u, s->u, sizeof(double) * 3 * n);
+}
+
+void orc_set_state(orc_state *s, const double *H, const double *G, const double *phi,
+                   const double *u)
+{
+    size_t n = (size_t)s->n;
+    if (H) memcpy(s->H, H, sizeof(double) * Q15 * n);
+    if (G) memcpy(s->G, G, sizeof(double) * Q27 * n);
+    if (phi) memcpy(s->phiA, phi, sizeof(double) * n);
+    if (u) memcpy(s->u, u, sizeof(double) * 3 * n);
+}
+
+/* Pressure p = p* rho cs^2 with p* = sum_i g_i (Section 3.2). */
+void orc_pressure(const orc_state *s, double *pout)
+{
+    const orc_params *p = &s->p;
+    const int64_t n = s->n;
+    const double dphi = p->phi_H - p->phi_L;
+    for (int64_t c = 0; c < n; ++c) {
+        int y = (int)((c / p->nx) % p->ny);
+        if (is_wall_row(p, y)) { pout[c] = 0.0; continue; }
+        double ps = 0.0;
+        for (int i = 0; i < Q27; ++i) ps += s->G[i * n + c];
+        double rho = p->rho_L + (s->phiA[c] - p->phi_L) * (p->rho_H - p->rho_L) / dphi;
+        pout[c] = ps * rho * CS2;
+    }
+}
+
+/* Diagnostics over fluid cells, FP64, serial in z, y, x order.
+ * chi = (phi_H - phi)/(phi_H - phi_L) marks the light phase; the centroid
+ * and rise velocity are chi-weighted means; xi_eff = sum 4chi(1-chi) /
+ * sum |grad phi|/(phi_H - phi_L), which equals xi for the planar
+ * equilibrium profile; the gradient is the D3Q27 isotropic one.       */
+void orc_stats_compute(const orc_state *s, orc_stats *out)
+{
+    const orc_params *p = &s->p;
+    const int64_t n = s->n;
+    const double dphi = p->phi_H - p->phi_L;
+    memset(out, 0, sizeof(*out));
+    double cx = 0.0, cy = 0.0, cz = 0.0, ury = 0.0;
+    for (int z = 0; z < p->nz; ++z)
+        for (int y = 0; y < p->ny; ++y) {
+            if (is_wall_row(p, y)) continue;
+            for (int x = 0; x < p->nx; ++x) {
+                int64_t c = cidx(p, x, y, z);
+                double phi = s->phiA[c];
+                double rho = p->rho_L + (phi - p->phi_L) * (p->rho_H - p->rho_L) / dphi;
+                double ux = s->u[c], uy = s->u[n + c], uz = s->u[2 * n + c];
+                double chi = (p->phi_H - phi) / dphi;
+                double grad[3];
+                iso_gradient(p, s->phiA, Q27, x, y, z, grad);
+                double gn = sqrt(grad[0] * grad[0] + grad[1] * grad[1] + grad[2] * grad[2]);
+                double sp = sqrt(ux * ux + uy * uy + uz * uz);
+                out->mass += phi;
+                out->momentum[0] += rho * ux;
+                out->momentum[1] += rho * uy;
+                out->momentum[2] += rho * uz;
+                out->gas_volume += chi;
+                cx += chi * x;
+                cy += chi * y;
+                cz += chi * z;
+                ury += chi * uy;
+                out->interface_sum += 4.0 * chi * (1.0 - chi);
+                out->grad_sum += gn / dphi;
+                if (sp > out->max_speed) out->max_speed = sp;
+            }
+        }
+    if (out->gas_volume != 0.0) {
+        out->centroid[0] = cx / out->gas_volume;
+        out->centroid[1] = cy / out->gas_volume;
+        out->centroid[2] = cz / out->gas_volume;
+        out->rise_velocity = ury / out->gas_volume;
+    }
+    out->xi_eff = (out->grad_sum != 0.0) ? out->interface_sum / out->grad_sum : 0.0;
+}
+
+int64_t orc_num_cells(const orc_state *s) { return s->n; }
