@@ -1,0 +1,231 @@
+#!/usr/bin/env python3
+"""Benchmark of the coupled phase-field / hydrodynamic LBM step on one GPU.
+
+One step = the phase-field sweep plus the hydrodynamic sweep over the whole
+grid (walls, forces and the storage codec included).  Default workload: the
+512^3 bubble swarm (200 bubbles, D ~ U[16, 32], rising-bubble physics, walls
+at y = 0 and 511) with FP32 PDF storage and FP32 collision arithmetic.
+Inputs are resident in HBM before the timed region starts.
+
+Prints ONE JSON line: coupled MLUPS (fluid cells x steps / s / 1e6), the
+roofline of the dominant kernel (the hydrodynamic sweep) from HIP-event
+timings on the solver stream, and the FP64 CPU oracle timed on the host on a
+bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+WORKLOAD_KEYS = {
+    "bubble_swarm_512": "bubble_swarm_512",
+    "rising_bubble_128x512x128": "rising_bubble_128x512x128",
+    "static_droplet_32": "static_droplet_32",
+    "paper_bubble_260": "paper_bubble_260",
+    "rising_bubble_256x1024x256": "rising_bubble_256x1024x256",
+}
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("lbm_kernels.hpp", "lbm_lattice.hpp", "lbm_api.hip"):
+        with open(os.path.join(ROOT, "paper_2012_06144_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kernel: str, workload: str, storage: str, src_hash: str):
+    """HBM bytes per launch from a committed rocprofv3 counter summary, if it
+    was taken on the current kernel source (else None)."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_{storage}_counters.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m = re.search(r"^traffic_json:\s*(\{.*\})\s*$", text, flags=re.M)
+    if not m:
+        return None
+    d = json.loads(m.group(1))
+    if d.get("source_hash") != src_hash:
+        return None
+    return d
+
+
+def cpu_baseline(setup, phi, u, ps, target_s: float = 15.0):
+    """Time the FP64 oracle on a 128 x ny x 128 slab of the same workload."""
+    import numpy as np
+
+    from oracle import oracle as orc
+    nx = min(128, setup.nx)
+    nz = min(128, setup.nz)
+    phys = setup.physics()
+    phys.update(nx=nx, nz=nz)
+    o = orc.Oracle(orc.Params(**phys))
+    o.init(np.ascontiguousarray(phi[:nz, :, :nx]), np.ascontiguousarray(u[:, :nz, :, :nx]),
+           np.ascontiguousarray(ps[:nz, :, :nx]))
+    fluid = nx * nz * (setup.ny - 2 if setup.walls_y else setup.ny)
+    t0 = time.perf_counter()
+    o.step(1)
+    t1 = time.perf_counter()
+    per = t1 - t0
+    extra = max(0, min(9, int(target_s / max(per, 1e-3)) - 1))
+    if extra:
+        o.step(extra)
+    t2 = time.perf_counter()
+    steps = 1 + extra
+    mlups = fluid * steps / (t2 - t0) / 1e6
+    o.close()
+    return {"value": mlups, "unit": "MLUPS", "cores": orc.num_threads(), "kind": "oracle",
+            "sample": f"{steps} coupled steps of the FP64 oracle on a {nx}x{setup.ny}x{nz} slab of "
+                      f"the {setup.name} fields ({fluid} fluid cells), {t2 - t0:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="bubble_swarm_512", choices=sorted(WORKLOAD_KEYS))
+    ap.add_argument("--storage", default="f32", choices=["f64", "f32", "f16s", "bf16s"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--timed-steps", type=int, default=50,
+                    help="steps of the per-kernel event timing (roofline)")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py measures one GPU: the coupled step is built and measured on a single "
+              f"MI355X (requested --gpus {args.gpus}, WORLD_SIZE {world}); multi-GPU domain "
+              f"decomposition is not part of this build.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2012_06144_amd import inputs, lbm, perf
+
+    setup = inputs.WORKLOADS[WORKLOAD_KEYS[args.workload]]()
+    log(f"[bench] workload {setup.name} {setup.nx}x{setup.ny}x{setup.nz} storage {args.storage}")
+    t = time.perf_counter()
+    phi, u, ps = inputs.build_fields(setup)
+    log(f"[bench] inputs built in {time.perf_counter() - t:.1f}s")
+
+    dev = torch.device("cuda:0")
+    solver = lbm.Solver(setup.physics(), storage=args.storage, device="cuda:0")
+    solver.init_fields(phi, u, ps)
+    fluid = setup.nx * setup.nz * (setup.ny - 2 if setup.walls_y else setup.ny)
+    stream = torch.cuda.current_stream(dev)
+
+    mass0 = solver.reduce_mass()
+    log(f"[bench] warmup {args.warmup} steps")
+    if args.warmup > 0:
+        solver.step(args.warmup)
+    torch.cuda.synchronize()
+
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    log(f"[bench] timed {args.steps} steps")
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    e0.record(stream)
+    solver.step(args.steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    ms = e0.elapsed_time(e1) / args.steps
+    mass1 = solver.reduce_mass()
+    mlups = fluid / (ms * 1e-3) / 1e6
+    log(f"[bench] {ms:.3f} ms/step, {mlups:.0f} MLUPS (wall {wall:.2f}s)")
+
+    # per-kernel durations (HIP events around each sweep on the solver stream)
+    nt = max(1, min(args.timed_steps, 4096))
+    phase_ms, hydro_ms = solver.step_timed(nt)
+    bpc = perf.bytes_per_cell(args.storage)
+    hydro_gbs = bpc["hydro"] * fluid / (hydro_ms * 1e-3) / 1e9
+    phase_gbs = bpc["phase"] * fluid / (phase_ms * 1e-3) / 1e9
+    coupled_gbs = bpc["total"] * fluid / (ms * 1e-3) / 1e9
+    log(f"[bench] phase {phase_ms:.3f} ms ({phase_gbs:.0f} GB/s), hydro {hydro_ms:.3f} ms "
+        f"({hydro_gbs:.0f} GB/s)")
+
+    # STREAM copy bandwidth b_s (the paper's roofline denominator)
+    nbytes = 4 << 30
+    a = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    b = torch.empty_like(a)
+    lbm.lbm_stream_copy(a, b, nbytes, stream.cuda_stream)
+    c0 = torch.cuda.Event(enable_timing=True)
+    c1 = torch.cuda.Event(enable_timing=True)
+    c0.record(stream)
+    reps = 10
+    for _ in range(reps):
+        lbm.lbm_stream_copy(a, b, nbytes, stream.cuda_stream)
+    c1.record(stream)
+    torch.cuda.synchronize()
+    b_s = 2 * nbytes * reps / (c0.elapsed_time(c1) * 1e-3) / 1e9
+    del a, b
+    log(f"[bench] STREAM copy b_s = {b_s:.0f} GB/s")
+
+    src_hash = kernel_source_hash()
+    traffic = load_traffic("hydro_sweep", setup.name, args.storage, src_hash)
+    traffic_val = None
+    if traffic is not None:
+        traffic_val = traffic["bytes_per_launch"]
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("[bench] CPU oracle baseline")
+        cpu = cpu_baseline(setup, phi, u, ps)
+        log(f"[bench] oracle {cpu['value']:.2f} MLUPS on {cpu['cores']} threads")
+
+    line = {
+        "metric": "coupled MLUPS + %HBM roofline",
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"f64": "f64", "f32": "f32", "f16s": "f32 (f16 storage)",
+                  "bf16s": "f32 (bf16 storage)"}[args.storage],
+        "data": "synthetic",
+        "config": {"workload": setup.name, "grid": [setup.nx, setup.ny, setup.nz],
+                   "fluid_cells": fluid, "storage": args.storage,
+                   "walls_y": bool(setup.walls_y), "bubbles": setup.n_bubbles or 1},
+        "roofline": {"bound": "hbm", "kernel": "hydro_sweep",
+                     "achieved": round(hydro_gbs, 1), "peak": perf.HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(hydro_gbs / perf.HBM_PEAK_GBS, 4), "traffic": traffic_val,
+                     "bytes_per_cell": bpc["hydro"], "units_per_launch": fluid,
+                     "launch_ms": round(hydro_ms, 4)},
+        "kernels": {"phase_ms": round(phase_ms, 4), "phase_gbs": round(phase_gbs, 1),
+                    "hydro_ms": round(hydro_ms, 4), "hydro_gbs": round(hydro_gbs, 1)},
+        "coupled_gbs": round(coupled_gbs, 1),
+        "coupled_frac_hbm": round(coupled_gbs / perf.HBM_PEAK_GBS, 4),
+        "stream_copy_gbs": round(b_s, 1),
+        "coupled_frac_stream": round(coupled_gbs / b_s, 4),
+        "bytes_per_cell": bpc["total"],
+        "mlups_all_cells": round(setup.cells / (ms * 1e-3) / 1e6, 1),
+        "mass_drift_rel": (mass1 - mass0) / mass0,
+        "paper_context": {"mlups": 550, "hardware": "Tesla P100", "precision": "f64",
+                          "roofline_frac_of_stream": 0.78},
+        "cpu_baseline": cpu,
+        "kernel_source_hash": src_hash,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

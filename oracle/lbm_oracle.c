@@ -711,3 +711,16 @@ void orc_stats_compute(const orc_state *s, orc_stats *out)
 }
 
 int64_t orc_num_cells(const orc_state *s) { return s->n; }
+
+/* Threads the OpenMP cell loops use (1 without OpenMP). */
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+int orc_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

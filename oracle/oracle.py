@@ -78,6 +78,8 @@ def lib():
     L.orc_set_state.argtypes = [C.c_void_p] + [C.c_void_p] * 4
     L.orc_pressure.argtypes = [C.c_void_p, _D]
     L.orc_stats_compute.argtypes = [C.c_void_p, C.POINTER(OrcStats)]
+    L.orc_num_threads.argtypes = []
+    L.orc_num_threads.restype = C.c_int
     L.orc_num_cells.argtypes = [C.c_void_p]
     L.orc_num_cells.restype = C.c_int64
     _lib = L
@@ -121,6 +123,11 @@ def velocity_set(q: int):
     if lib().orc_velocity_set(q, e, w) != 0:
         raise ValueError(f"no velocity set with q={q}")
     return e.reshape(q, 3), w
+
+
+def num_threads() -> int:
+    """OpenMP threads the oracle's cell loops use."""
+    return int(lib().orc_num_threads())
 
 
 def gamma(q: int, u) -> np.ndarray:

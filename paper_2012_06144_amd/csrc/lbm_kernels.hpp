@@ -1,0 +1,522 @@
+// Fused stream-collide sweeps of the coupled phase-field / hydrodynamic
+// lattice Boltzmann step (Holzer et al., IJHPCA 2020) for gfx950.
+//
+// Memory layout (all in the caller-provided workspace):
+//   PDF sets: q planes of `plane` elements each, x fastest inside a plane
+//   (structure of arrays, so every direction is a unit-stride stream);
+//   two copies per set (source / destination, swapped every step).
+//   phi: two planes (previous / new); u: three planes.
+// One thread updates one cell; blocks of 256 threads cover consecutive
+// cells.  Block indices are remapped so that each of the 8 XCDs of the
+// MI355X works on one contiguous slab of the grid, which keeps the phase
+// field rows a cell's stencil re-reads inside that XCD's L2.
+#pragma once
+
+#include "lbm_lattice.hpp"
+
+namespace lbm {
+
+constexpr int kBlock = 256;
+constexpr int kXcds = 8;
+constexpr int kRedBlocks = 1024;  // fixed grid of the deterministic reductions
+constexpr int kRedVals = 12;      // 11 sums + 1 max
+
+// Physical constants of one launch, in the sweep's arithmetic type.
+template <class R>
+struct Phys {
+    R phi_L, phi_H, phi_0, inv_dphi;     // inv_dphi = 1/(phi_H - phi_L)
+    R xi, omega_phi;                     // phase-field relaxation rate
+    R rho_L, drho;                       // drho = rho_H - rho_L
+    R tau_L, dtau;                       // dtau = tau_H - tau_L
+    R beta, kappa;                       // 12 sigma/xi, 3 sigma xi/2
+    R accel[3];
+    R normal_eps;
+    R shift_h;                           // stored h_i = h_i - shift_h * w_i (low precision)
+};
+
+struct Grid {
+    int nx, ny, nz;
+    int walls;
+    int ncells;
+    int64_t plane;   // PDF plane stride (elements)
+    int64_t fplane;  // field plane stride (elements)
+};
+
+// Logical block index: block b runs on XCD b % 8 (round-robin dispatch);
+// give XCD k the k-th contiguous share of the logical blocks.
+__device__ inline int xcd_block()
+{
+    const int b = blockIdx.x, G = gridDim.x;
+    const int xcd = b % kXcds, idx = b / kXcds;
+    const int q = G / kXcds, r = G % kXcds;
+    return xcd < r ? xcd * (q + 1) + idx : r * (q + 1) + (xcd - r) * q + idx;
+}
+
+// Neighbour offsets of one cell (relative element offsets inside a plane).
+struct Nbr {
+    int xm, xp, ym, yp, zm, zp;
+    bool wm, wp;  // y-1 / y+1 is a wall row
+    __device__ int off(int dx, int dy, int dz) const
+    {
+        return (dx < 0 ? xm : dx > 0 ? xp : 0) + (dy < 0 ? ym : dy > 0 ? yp : 0) +
+               (dz < 0 ? zm : dz > 0 ? zp : 0);
+    }
+    // Phase-field stencil offset: a wall row is read at its mirror image,
+    // which is the current row.
+    __device__ int offm(int dx, int dy, int dz) const
+    {
+        return (dx < 0 ? xm : dx > 0 ? xp : 0) + (dy < 0 ? (wm ? 0 : ym) : dy > 0 ? (wp ? 0 : yp) : 0) +
+               (dz < 0 ? zm : dz > 0 ? zp : 0);
+    }
+};
+
+__device__ inline bool decode(const Grid &g, int c, int &x, int &y, int &z, Nbr &n)
+{
+    x = c % g.nx;
+    const int t = c / g.nx;
+    y = t % g.ny;
+    z = t / g.ny;
+    if (g.walls && (y == 0 || y == g.ny - 1)) return false;
+    const int nxy = g.nx * g.ny;
+    n.xm = (x == 0) ? g.nx - 1 : -1;
+    n.xp = (x == g.nx - 1) ? -(g.nx - 1) : 1;
+    if (g.walls) {
+        n.ym = -g.nx;
+        n.yp = g.nx;
+        n.wm = (y == 1);
+        n.wp = (y == g.ny - 2);
+    } else {
+        n.ym = (y == 0) ? (g.ny - 1) * g.nx : -g.nx;
+        n.yp = (y == g.ny - 1) ? -(g.ny - 1) * g.nx : g.nx;
+        n.wm = n.wp = false;
+    }
+    n.zm = (z == 0) ? (g.nz - 1) * nxy : -nxy;
+    n.zp = (z == g.nz - 1) ? -(g.nz - 1) * nxy : nxy;
+    return true;
+}
+
+// x / c_s^2.  FP64 divides by the rounded 1/3 exactly as a literal reading of
+// the formulas does; FP32 multiplies by 3.
+__device__ inline double by_cs2(double v) { return v / (1.0 / 3.0); }
+__device__ inline float by_cs2(float v) { return v * 3.0f; }
+template <class R>
+__device__ inline R cs2() { return R(1) / R(3); }
+
+// Gamma_i(u) = w_i [1 + e.u/cs^2 + (e.u)^2/(2 cs^4) - u.u/(2 cs^2)] (Sec. 3.1)
+template <int Q, class R>
+__device__ inline R gamma_i(int i, R ux, R uy, R uz, R uu)
+{
+    const R eu = R(ev<Q>(i, 0)) * ux + R(ev<Q>(i, 1)) * uy + R(ev<Q>(i, 2)) * uz;
+    const R c2 = cs2<R>();
+    return wgt<Q, R>(i) * (R(1) + by_cs2(eu) + (eu * eu) / (R(2) * c2 * c2) - uu / (R(2) * c2));
+}
+
+// Hydrodynamic equilibrium g_eq_i = p* w_i + (Gamma_i - w_i) (Sec. 3.2), with
+// the w_i of Gamma cancelled algebraically so small g are not formed as a
+// difference of O(w) numbers.
+template <class R>
+__device__ inline R geq_i(int i, R ps, R ux, R uy, R uz, R uu)
+{
+    const R eu = R(e27(i, 0)) * ux + R(e27(i, 1)) * uy + R(e27(i, 2)) * uz;
+    const R c2 = cs2<R>();
+    return wgt<27, R>(i) * (ps + by_cs2(eu) + (eu * eu) / (R(2) * c2 * c2) - uu / (R(2) * c2));
+}
+
+// Isotropic gradient (eq. grad) as antisymmetric pair differences over the
+// half set, and (optionally) Laplacian (eq. lap), on phi with the wall mirror.
+template <int Q, class R, bool LAP>
+__device__ inline void stencil(const R *__restrict__ phi, int c, const Nbr &n, R grad[3], R &lap)
+{
+    R acc[3] = {R(0), R(0), R(0)};
+#pragma unroll
+    for (int i = 1; i < Q; i += 2) {
+        const int dx = ev<Q>(i, 0), dy = ev<Q>(i, 1), dz = ev<Q>(i, 2);
+        const R d = phi[c + n.offm(dx, dy, dz)] - phi[c + n.offm(-dx, -dy, -dz)];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const int ea = ev<Q>(i, a);
+            if (ea > 0) acc[a] += wgt<Q, R>(i) * d;
+            if (ea < 0) acc[a] -= wgt<Q, R>(i) * d;
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) grad[a] = by_cs2(acc[a]);
+    if (LAP) {
+        const R pc = phi[c];
+        R s = R(0);
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const int dx = ev<Q>(i, 0), dy = ev<Q>(i, 1), dz = ev<Q>(i, 2);
+            s += wgt<Q, R>(i) * (phi[c + n.offm(dx, dy, dz)] - pc);
+        }
+        lap = R(2) * by_cs2(s);
+    }
+}
+
+template <class S>
+struct SweepArgs {
+    const typename S::pdf_t *__restrict__ src;
+    typename S::pdf_t *__restrict__ dst;
+    const typename S::real *__restrict__ phi_in;
+    typename S::real *__restrict__ phi_out;
+    typename S::real *__restrict__ u;
+    Grid g;
+    Phys<typename S::real> ph;
+};
+
+// ---- phase-field sweep: pull-stream h, phi = sum h (eq. updatePhaseField),
+// normal and theta from the previous phi (eqs. allen_cahn, grad), forcing
+// (eq. interfaceTracking), equilibrium phi Gamma(u), single-rate collision
+// (eq. lb_interface); store post-collision h at the cell ----------------------
+template <class S>
+__global__ __launch_bounds__(kBlock) void k_phase(const SweepArgs<S> a)
+{
+    using R = typename S::real;
+    const int c = xcd_block() * kBlock + threadIdx.x;
+    if (c >= a.g.ncells) return;
+    int x, y, z;
+    Nbr n;
+    if (!decode(a.g, c, x, y, z, n)) return;
+    const int64_t P = a.g.plane;
+
+    R Pi[15];
+#pragma unroll
+    for (int i = 0; i < 15; ++i) {
+        const int dx = e15(i, 0), dy = e15(i, 1), dz = e15(i, 2);
+        const bool bb = (dy > 0 && n.wm) || (dy < 0 && n.wp);  // source is a wall cell
+        const int64_t idx = bb ? (int64_t)opp(i) * P + c : (int64_t)i * P + c + n.off(-dx, -dy, -dz);
+        const R sh = a.ph.shift_h * wgt<15, R>(i);  // w_opp(i) == w_i
+        Pi[i] = S::ld(a.src[idx], sh);
+    }
+    R phi = R(0);
+#pragma unroll
+    for (int i = 0; i < 15; ++i) phi += Pi[i];
+    a.phi_out[c] = phi;
+
+    R grad[3], lap_unused;
+    stencil<15, R, false>(a.phi_in, c, n, grad, lap_unused);
+    const R gn = sqrt(grad[0] * grad[0] + grad[1] * grad[1] + grad[2] * grad[2]);
+    R nrm[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) nrm[k] = grad[k] / (gn + a.ph.normal_eps);
+    const R dp = a.phi_in[c] - a.ph.phi_0;
+    const R theta = (R(1) - R(4) * dp * dp) / a.ph.xi;
+
+    const R ux = a.u[c], uy = a.u[a.g.fplane + c], uz = a.u[2 * a.g.fplane + c];
+    const R uu = ux * ux + uy * uy + uz * uz;
+    const R om = a.ph.omega_phi;
+#pragma unroll
+    for (int i = 0; i < 15; ++i) {
+        const R en = R(e15(i, 0)) * nrm[0] + R(e15(i, 1)) * nrm[1] + R(e15(i, 2)) * nrm[2];
+        const R F = theta * wgt<15, R>(i) * en;
+        const R heq = phi * gamma_i<15, R>(i, ux, uy, uz, uu);
+        const R h = Pi[i] + om * (heq - Pi[i] - R(0.5) * F) + F;
+        a.dst[(int64_t)i * P + c] = S::st(h, a.ph.shift_h * wgt<15, R>(i));
+    }
+}
+
+// ---- hydrodynamic sweep: moments of the local g, forces from the new phi
+// (eqs. forceHydro, pressure_force, surfaceTension, chemPot, viscousForce and
+// buoyancy), velocity update (eq. updateVelocityField), moment-space
+// collision (eq. improved_collision) in closed form, push-stream g ----------
+//
+// Closed form of the collision: with a weighted-orthogonal moment basis, the
+// six second-order moments relaxed with s and all others with 1, and the
+// force on the first-order moments only,
+//   g*_i = g_eq_i(p*, u) + F_i/2 + (1 - s) w_i/(2 cs^4) (e_i e_i - cs^2 I) : A,
+//   A = Pi - p* cs^2 I - u u^T,  F_i = w_i e_i.F/(rho cs^2),
+// and the bracket of the viscous force is s A(u_old).
+template <class S>
+__global__ __launch_bounds__(kBlock) void k_hydro(const SweepArgs<S> a)
+{
+    using R = typename S::real;
+    const int c = xcd_block() * kBlock + threadIdx.x;
+    if (c >= a.g.ncells) return;
+    int x, y, z;
+    Nbr n;
+    if (!decode(a.g, c, x, y, z, n)) return;
+    const int64_t P = a.g.plane;
+
+    R ps = R(0), j[3] = {R(0), R(0), R(0)};
+    R Pxx = R(0), Pyy = R(0), Pzz = R(0), Pxy = R(0), Pxz = R(0), Pyz = R(0);
+#pragma unroll
+    for (int i = 0; i < 27; ++i) {
+        const R gi = S::ld(a.src[(int64_t)i * P + c], R(0));
+        const int ex = e27(i, 0), ey = e27(i, 1), ez = e27(i, 2);
+        ps += gi;
+        if (ex) j[0] += ex > 0 ? gi : -gi;
+        if (ey) j[1] += ey > 0 ? gi : -gi;
+        if (ez) j[2] += ez > 0 ? gi : -gi;
+        if (ex) Pxx += gi;
+        if (ey) Pyy += gi;
+        if (ez) Pzz += gi;
+        if (ex && ey) Pxy += (ex * ey > 0) ? gi : -gi;
+        if (ex && ez) Pxz += (ex * ez > 0) ? gi : -gi;
+        if (ey && ez) Pyz += (ey * ez > 0) ? gi : -gi;
+    }
+
+    const R phi = a.phi_in[c];
+    R grad[3], lap;
+    stencil<27, R, true>(a.phi_in, c, n, grad, lap);
+
+    const Phys<R> &ph = a.ph;
+    const R rho = ph.rho_L + (phi - ph.phi_L) * ph.drho * ph.inv_dphi;
+    const R tau = ph.tau_L + (phi - ph.phi_L) * ph.dtau * ph.inv_dphi;
+    const R s = R(1) / (tau + R(0.5));
+    const R nu = tau * cs2<R>();
+    R grho[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) grho[k] = ph.drho * ph.inv_dphi * grad[k];
+    const R mu = R(4) * ph.beta * (phi - ph.phi_L) * (phi - ph.phi_H) * (phi - ph.phi_0) - ph.kappa * lap;
+
+    const R c2 = cs2<R>();
+    const R uox = a.u[c], uoy = a.u[a.g.fplane + c], uoz = a.u[2 * a.g.fplane + c];
+    // A(u_old) = Pi - p* cs^2 I - u_old u_old^T; viscous bracket = s A
+    const R Axx = Pxx - ps * c2 - uox * uox, Ayy = Pyy - ps * c2 - uoy * uoy, Azz = Pzz - ps * c2 - uoz * uoz;
+    const R Axy = Pxy - uox * uoy, Axz = Pxz - uox * uoz, Ayz = Pyz - uoy * uoz;
+    const R vf = -nu / c2 * s;
+    R F[3];
+    F[0] = -ps * c2 * grho[0] + mu * grad[0] + vf * (Axx * grho[0] + Axy * grho[1] + Axz * grho[2]) +
+           rho * ph.accel[0];
+    F[1] = -ps * c2 * grho[1] + mu * grad[1] + vf * (Axy * grho[0] + Ayy * grho[1] + Ayz * grho[2]) +
+           rho * ph.accel[1];
+    F[2] = -ps * c2 * grho[2] + mu * grad[2] + vf * (Axz * grho[0] + Ayz * grho[1] + Azz * grho[2]) +
+           rho * ph.accel[2];
+
+    const R ux = j[0] + F[0] / (R(2) * rho), uy = j[1] + F[1] / (R(2) * rho), uz = j[2] + F[2] / (R(2) * rho);
+    a.u[c] = ux;
+    a.u[a.g.fplane + c] = uy;
+    a.u[2 * a.g.fplane + c] = uz;
+
+    const R uu = ux * ux + uy * uy + uz * uz;
+    const R Bxx = Pxx - ps * c2 - ux * ux, Byy = Pyy - ps * c2 - uy * uy, Bzz = Pzz - ps * c2 - uz * uz;
+    const R Bxy = Pxy - ux * uy, Bxz = Pxz - ux * uz, Byz = Pyz - uy * uz;
+    const R trB = Bxx + Byy + Bzz;
+    const R neq = (R(1) - s) / (R(2) * c2 * c2);
+    const R finv = R(1) / (rho * c2);
+#pragma unroll
+    for (int i = 0; i < 27; ++i) {
+        const int ex = e27(i, 0), ey = e27(i, 1), ez = e27(i, 2);
+        const R w = wgt<27, R>(i);
+        const R geq = geq_i<R>(i, ps, ux, uy, uz, uu);
+        const R eF = R(ex) * F[0] + R(ey) * F[1] + R(ez) * F[2];
+        // (e e - cs^2 I) : B
+        const R eBe = R(ex * ex) * Bxx + R(ey * ey) * Byy + R(ez * ez) * Bzz +
+                      R(2 * ex * ey) * Bxy + R(2 * ex * ez) * Bxz + R(2 * ey * ez) * Byz - c2 * trB;
+        const R gs = geq + R(0.5) * w * eF * finv + neq * w * eBe;
+        const bool bb = (ey > 0 && n.wp) || (ey < 0 && n.wm);  // destination is a wall cell
+        const int64_t idx = bb ? (int64_t)opp(i) * P + c : (int64_t)i * P + c + n.off(ex, ey, ez);
+        a.dst[idx] = S::st(gs, R(0));
+    }
+}
+
+// ---- initial / equilibrium state from (phi, u, p*) ---------------------------
+template <class S, class In>
+__global__ __launch_bounds__(kBlock) void k_equilibrium(typename S::pdf_t *__restrict__ H,
+                                                        typename S::pdf_t *__restrict__ G,
+                                                        typename S::real *__restrict__ phiA,
+                                                        typename S::real *__restrict__ u,
+                                                        const In *__restrict__ phi_in,
+                                                        const In *__restrict__ u_in,
+                                                        const In *__restrict__ p_in, int p_is_pressure,
+                                                        Grid g, Phys<typename S::real> ph)
+{
+    using R = typename S::real;
+    const int c = blockIdx.x * kBlock + threadIdx.x;
+    if (c >= g.ncells) return;
+    const int y = (c / g.nx) % g.ny;
+    const int64_t N = g.ncells;
+    const bool wall = g.walls && (y == 0 || y == g.ny - 1);
+    R phi = wall ? R(0) : R(phi_in[c]);
+    R ux = wall ? R(0) : R(u_in[c]), uy = wall ? R(0) : R(u_in[N + c]), uz = wall ? R(0) : R(u_in[2 * N + c]);
+    R ps = wall ? R(0) : R(p_in[c]);
+    if (p_is_pressure && !wall) {
+        const R rho = ph.rho_L + (phi - ph.phi_L) * ph.drho * ph.inv_dphi;
+        ps = ps / (rho * cs2<R>());
+    }
+    const R uu = ux * ux + uy * uy + uz * uz;
+#pragma unroll
+    for (int i = 0; i < 15; ++i) {
+        const R h = wall ? R(0) : phi * gamma_i<15, R>(i, ux, uy, uz, uu);
+        H[(int64_t)i * g.plane + c] = S::st(h, wall ? R(0) : ph.shift_h * wgt<15, R>(i));
+    }
+#pragma unroll
+    for (int i = 0; i < 27; ++i) {
+        const R ge = wall ? R(0) : geq_i<R>(i, ps, ux, uy, uz, uu);
+        G[(int64_t)i * g.plane + c] = S::st(ge, R(0));
+    }
+    phiA[c] = phi;
+    u[c] = ux;
+    u[g.fplane + c] = uy;
+    u[2 * g.fplane + c] = uz;
+}
+
+// Canonical FP64 planes <-> storage.
+template <class S>
+__global__ __launch_bounds__(kBlock) void k_get_pdfs(const typename S::pdf_t *__restrict__ H,
+                                                     const typename S::pdf_t *__restrict__ G,
+                                                     double *__restrict__ Ho, double *__restrict__ Go,
+                                                     Grid g, Phys<typename S::real> ph)
+{
+    using R = typename S::real;
+    const int c = blockIdx.x * kBlock + threadIdx.x;
+    if (c >= g.ncells) return;
+    const int y = (c / g.nx) % g.ny;
+    const bool wall = g.walls && (y == 0 || y == g.ny - 1);
+    const int64_t N = g.ncells;
+    if (Ho)
+#pragma unroll
+        for (int i = 0; i < 15; ++i)
+            Ho[i * N + c] = wall ? 0.0 : (double)S::ld(H[(int64_t)i * g.plane + c], ph.shift_h * wgt<15, R>(i));
+    if (Go)
+#pragma unroll
+        for (int i = 0; i < 27; ++i)
+            Go[i * N + c] = wall ? 0.0 : (double)S::ld(G[(int64_t)i * g.plane + c], R(0));
+}
+
+template <class S>
+__global__ __launch_bounds__(kBlock) void k_set_pdfs(typename S::pdf_t *__restrict__ H,
+                                                     typename S::pdf_t *__restrict__ G,
+                                                     typename S::real *__restrict__ phiA,
+                                                     typename S::real *__restrict__ u,
+                                                     const double *__restrict__ Hi, const double *__restrict__ Gi,
+                                                     const double *__restrict__ phi_i,
+                                                     const double *__restrict__ u_i, Grid g,
+                                                     Phys<typename S::real> ph)
+{
+    using R = typename S::real;
+    const int c = blockIdx.x * kBlock + threadIdx.x;
+    if (c >= g.ncells) return;
+    const int y = (c / g.nx) % g.ny;
+    const bool wall = g.walls && (y == 0 || y == g.ny - 1);
+    const int64_t N = g.ncells;
+#pragma unroll
+    for (int i = 0; i < 15; ++i) {
+        const R sh = wall ? R(0) : ph.shift_h * wgt<15, R>(i);
+        H[(int64_t)i * g.plane + c] = S::st(wall ? R(0) : R(Hi[i * N + c]), sh);
+    }
+#pragma unroll
+    for (int i = 0; i < 27; ++i) G[(int64_t)i * g.plane + c] = S::st(wall ? R(0) : R(Gi[i * N + c]), R(0));
+    phiA[c] = wall ? R(0) : R(phi_i[c]);
+    for (int k = 0; k < 3; ++k) u[k * g.fplane + c] = wall ? R(0) : R(u_i[k * N + c]);
+}
+
+template <class S, class Out>
+__global__ __launch_bounds__(kBlock) void k_get_macro(const typename S::pdf_t *__restrict__ G,
+                                                      const typename S::real *__restrict__ phiA,
+                                                      const typename S::real *__restrict__ u,
+                                                      Out *__restrict__ phi_o, Out *__restrict__ u_o,
+                                                      Out *__restrict__ p_o, Grid g,
+                                                      Phys<typename S::real> ph)
+{
+    using R = typename S::real;
+    const int c = blockIdx.x * kBlock + threadIdx.x;
+    if (c >= g.ncells) return;
+    const int y = (c / g.nx) % g.ny;
+    const bool wall = g.walls && (y == 0 || y == g.ny - 1);
+    const int64_t N = g.ncells;
+    if (phi_o) phi_o[c] = wall ? Out(0) : Out(phiA[c]);
+    if (u_o)
+        for (int k = 0; k < 3; ++k) u_o[k * N + c] = wall ? Out(0) : Out(u[k * g.fplane + c]);
+    if (p_o) {
+        R ps = R(0);
+#pragma unroll
+        for (int i = 0; i < 27; ++i) ps += S::ld(G[(int64_t)i * g.plane + c], R(0));
+        const R rho = ph.rho_L + (phiA[c] - ph.phi_L) * ph.drho * ph.inv_dphi;
+        p_o[c] = wall ? Out(0) : Out(ps * rho * cs2<R>());
+    }
+}
+
+// ---- deterministic FP64 reductions --------------------------------------------
+// Pass 1: a fixed grid of kRedBlocks blocks; thread t of block b visits
+// cells b*kBlock + t + k*kRedBlocks*kBlock in order; the block combines its
+// threads with a fixed tree.  Pass 2: one block combines the block partials
+// with a fixed tree.  Same result for every run on any device.
+__device__ inline void block_reduce(double v[kRedVals], double *sh /* kRedVals*kBlock */)
+{
+    const int t = threadIdx.x;
+    for (int k = 0; k < kRedVals; ++k) sh[k * kBlock + t] = v[k];
+    __syncthreads();
+    for (int s = kBlock / 2; s > 0; s >>= 1) {
+        if (t < s)
+            for (int k = 0; k < kRedVals; ++k) {
+                const double o = sh[k * kBlock + t + s];
+                double &m = sh[k * kBlock + t];
+                m = (k == kRedVals - 1) ? fmax(m, o) : m + o;
+            }
+        __syncthreads();
+    }
+}
+
+template <class S>
+__global__ __launch_bounds__(kBlock) void k_reduce1(const typename S::real *__restrict__ phiA,
+                                                    const typename S::real *__restrict__ u, Grid g,
+                                                    Phys<typename S::real> ph, int mass_only,
+                                                    double *__restrict__ partial)
+{
+    using R = typename S::real;
+    __shared__ double sh[kRedVals * kBlock];
+    double v[kRedVals];
+    for (int k = 0; k < kRedVals; ++k) v[k] = 0.0;
+    const double phiH = (double)ph.phi_H, phiL = (double)ph.phi_L, idp = (double)ph.inv_dphi;
+    for (int c = blockIdx.x * kBlock + threadIdx.x; c < g.ncells; c += kRedBlocks * kBlock) {
+        int x, y, z;
+        Nbr n;
+        if (!decode(g, c, x, y, z, n)) continue;
+        const double phi = (double)phiA[c];
+        v[0] += phi;
+        if (mass_only) continue;
+        const double rho = (double)ph.rho_L + (phi - phiL) * (double)ph.drho * idp;
+        const double ux = u[c], uy = u[g.fplane + c], uz = u[2 * g.fplane + c];
+        const double chi = (phiH - phi) * idp;
+        R grad[3], lapu;
+        stencil<27, R, false>(phiA, c, n, grad, lapu);
+        const double gn = sqrt((double)grad[0] * grad[0] + (double)grad[1] * grad[1] + (double)grad[2] * grad[2]);
+        v[1] += rho * ux;
+        v[2] += rho * uy;
+        v[3] += rho * uz;
+        v[4] += chi;
+        v[5] += chi * x;
+        v[6] += chi * y;
+        v[7] += chi * z;
+        v[8] += chi * uy;
+        v[9] += 4.0 * chi * (1.0 - chi);
+        v[10] += gn * idp;
+        v[11] = fmax(v[11], sqrt(ux * ux + uy * uy + uz * uz));
+    }
+    block_reduce(v, sh);
+    if (threadIdx.x < kRedVals) partial[blockIdx.x * kRedVals + threadIdx.x] = sh[threadIdx.x * kBlock];
+}
+
+__global__ __launch_bounds__(kBlock) void k_reduce2(const double *__restrict__ partial,
+                                                    double *__restrict__ out)
+{
+    __shared__ double sh[kRedVals * kBlock];
+    double v[kRedVals];
+    for (int k = 0; k < kRedVals; ++k) v[k] = 0.0;
+    for (int b = threadIdx.x; b < kRedBlocks; b += kBlock)
+        for (int k = 0; k < kRedVals; ++k) {
+            const double o = partial[b * kRedVals + k];
+            v[k] = (k == kRedVals - 1) ? fmax(v[k], o) : v[k] + o;
+        }
+    block_reduce(v, sh);
+    if (threadIdx.x < kRedVals) out[threadIdx.x] = sh[threadIdx.x * kBlock];
+}
+
+// ---- fill with zeros (16-byte vectors); used instead of a runtime memset so
+// the calls stay plain kernels --------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_zero(uint4 *__restrict__ dst, int64_t n)
+{
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) dst[i] = make_uint4(0, 0, 0, 0);
+}
+
+// ---- STREAM copy a_i = b_i (16-byte vectors) ---------------------------------
+__global__ __launch_bounds__(kBlock) void k_copy(const uint4 *__restrict__ src, uint4 *__restrict__ dst,
+                                                 int64_t n)
+{
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) dst[i] = src[i];
+}
+
+}  // namespace lbm

@@ -1,0 +1,101 @@
+// Velocity sets, weights and storage codecs for the gfx950 sweeps.
+//
+// D3Q15 (phase field) and D3Q27 (hydrodynamics), Section 3 of Holzer et
+// al. (IJHPCA 2020).  The weights are not printed in the paper; they are
+// the standard isotropic sets (sum w = 1, sum w e e = I/3, fourth-order
+// isotropy), spelled out here.  Canonical order: rest, axis pairs, edge
+// pairs (D3Q27 only), corner pairs; the opposite of odd i is i+1.
+#pragma once
+
+#include <hip/hip_bf16.h>
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbm {
+
+__host__ __device__ constexpr int e15(int i, int a)
+{
+    constexpr int T[15][3] = {
+        {0, 0, 0},
+        {1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0}, {0, 0, 1}, {0, 0, -1},
+        {1, 1, 1}, {-1, -1, -1}, {1, 1, -1}, {-1, -1, 1},
+        {1, -1, 1}, {-1, 1, -1}, {-1, 1, 1}, {1, -1, -1}};
+    return T[i][a];
+}
+
+__host__ __device__ constexpr int e27(int i, int a)
+{
+    constexpr int T[27][3] = {
+        {0, 0, 0},
+        {1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0}, {0, 0, 1}, {0, 0, -1},
+        {1, 1, 0}, {-1, -1, 0}, {1, -1, 0}, {-1, 1, 0},
+        {1, 0, 1}, {-1, 0, -1}, {1, 0, -1}, {-1, 0, 1},
+        {0, 1, 1}, {0, -1, -1}, {0, 1, -1}, {0, -1, 1},
+        {1, 1, 1}, {-1, -1, -1}, {1, 1, -1}, {-1, -1, 1},
+        {1, -1, 1}, {-1, 1, -1}, {-1, 1, 1}, {1, -1, -1}};
+    return T[i][a];
+}
+
+template <int Q>
+__host__ __device__ constexpr int ev(int i, int a)
+{
+    return Q == 15 ? e15(i, a) : e27(i, a);
+}
+
+__host__ __device__ constexpr int opp(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1); }
+
+template <int Q>
+__host__ __device__ constexpr int l1(int i)
+{
+    return (ev<Q>(i, 0) != 0) + (ev<Q>(i, 1) != 0) + (ev<Q>(i, 2) != 0);
+}
+
+// Weight of direction i as a value of type R (divisions done in R).
+template <int Q, class R>
+__host__ __device__ constexpr R wgt(int i)
+{
+    return Q == 15 ? (l1<15>(i) == 0 ? R(2) / R(9) : l1<15>(i) == 1 ? R(1) / R(9) : R(1) / R(72))
+                   : (l1<27>(i) == 0 ? R(8) / R(27)
+                      : l1<27>(i) == 1 ? R(2) / R(27)
+                      : l1<27>(i) == 2 ? R(1) / R(54)
+                                       : R(1) / R(216));
+}
+
+// ---- storage codecs ---------------------------------------------------------
+// pdf_t: element type of the PDF planes; real: arithmetic type of the sweeps
+// (also the type of the phi and u fields).  Low-precision codecs hold a
+// shifted population s = f - shift, rounded to nearest even on store.
+struct StoreF64 {
+    using pdf_t = double;
+    using real = double;
+    static constexpr int id = 0;
+    __device__ static real ld(pdf_t v, real shift) { return v; }
+    __device__ static pdf_t st(real v, real shift) { return v; }
+};
+
+struct StoreF32 {
+    using pdf_t = float;
+    using real = float;
+    static constexpr int id = 1;
+    __device__ static real ld(pdf_t v, real shift) { return v; }
+    __device__ static pdf_t st(real v, real shift) { return v; }
+};
+
+struct StoreF16S {
+    using pdf_t = __half;
+    using real = float;
+    static constexpr int id = 2;
+    __device__ static real ld(pdf_t v, real shift) { return __half2float(v) + shift; }
+    __device__ static pdf_t st(real v, real shift) { return __float2half_rn(v - shift); }
+};
+
+struct StoreBF16S {
+    using pdf_t = __hip_bfloat16;
+    using real = float;
+    static constexpr int id = 3;
+    __device__ static real ld(pdf_t v, real shift) { return __bfloat162float(v) + shift; }
+    __device__ static pdf_t st(real v, real shift) { return __float2bfloat16(v - shift); }
+};
+
+}  // namespace lbm

@@ -1,0 +1,47 @@
+"""Performance model of the coupled step (host arithmetic only).
+
+Algorithmic bytes per cell update follow the paper's count (Section 5.1):
+every PDF of a sweep is read and written once, the velocity is read by both
+sweeps and written by the hydrodynamic one, and the phase field is read once
+per sweep (the ideal case where the stencil neighbours come from cache) and
+written by the phase-field sweep.  The paper's P_max = b_s / n_b turns bytes
+into a lattice-update ceiling.
+"""
+from __future__ import annotations
+
+PDF_BYTES = {"f64": 8, "f32": 4, "f16s": 2, "bf16s": 2}
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
+FP64_VECTOR_TFLOPS = 78.6
+FP32_VECTOR_TFLOPS = 157.3
+
+
+def field_bytes(storage: str) -> int:
+    return 8 if storage == "f64" else 4
+
+
+def bytes_per_cell(storage: str) -> dict:
+    """Algorithmic HBM bytes per cell update of each sweep."""
+    p = PDF_BYTES[storage]
+    r = field_bytes(storage)
+    phase_r = 15 * p + 3 * r + 1 * r      # h, u, phi (previous)
+    phase_w = 15 * p + 1 * r              # h, phi (new)
+    hydro_r = 27 * p + 3 * r + 1 * r      # g, u, phi (new)
+    hydro_w = 27 * p + 3 * r              # g, u
+    return {
+        "phase_read": phase_r, "phase_write": phase_w, "phase": phase_r + phase_w,
+        "hydro_read": hydro_r, "hydro_write": hydro_w, "hydro": hydro_r + hydro_w,
+        "total": phase_r + phase_w + hydro_r + hydro_w,
+    }
+
+
+def p_max_glups(b_s_gbs: float, n_b: float) -> float:
+    """The paper's roofline P_max = b_s / n_b, in giga lattice updates/s."""
+    return b_s_gbs / n_b
+
+
+def balance(n_b: float, n_f: float, b_s_gbs: float, p_peak_tflops: float) -> dict:
+    """Code balance B_c = n_b / n_f, machine balance B_m = b_s / p_peak and the
+    light-speed factor l = min(1, B_m / B_c) (Section 5.1)."""
+    B_c = n_b / n_f
+    B_m = b_s_gbs / (p_peak_tflops * 1e3)
+    return {"B_c": B_c, "B_m": B_m, "l": min(1.0, B_m / B_c)}
