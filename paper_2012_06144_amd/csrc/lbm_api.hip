@@ -43,8 +43,9 @@ lbm_status fail(lbm_status s, const char *fmt, ...)
     } while (0)
 
 constexpr size_t kAlign = 256;
-// Extra elements between PDF planes so that the q streams of one cell do not
-// start on the same HBM channel when nx*ny*nz is a large power of two.
+// Extra elements between the three velocity planes so that the streams of
+// one cell do not start on the same HBM channel when nx*ny*nz is a large
+// power of two.
 constexpr int64_t kPlanePadElems = 512;
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
@@ -53,7 +54,7 @@ size_t pdf_bytes(int storage) { return storage == LBM_F64 ? 8 : storage == LBM_F
 size_t real_bytes(int storage) { return storage == LBM_F64 ? 8 : 4; }
 
 struct Layout {
-    int64_t ncells, plane, fplane;
+    int64_t ncells, nblk, fplane;
     size_t off_H[2], off_G[2], off_phi[2], off_u, off_red, off_out, total;
 };
 
@@ -80,17 +81,17 @@ Layout layout(const lbm_params *p)
 {
     Layout L{};
     L.ncells = (int64_t)p->nx * p->ny * p->nz;
-    L.plane = (int64_t)align_up((size_t)L.ncells, 512) + kPlanePadElems;
+    L.nblk = (L.ncells + kB - 1) / kB;  // blocked PDF layout, kB cells per block
     L.fplane = (int64_t)align_up((size_t)L.ncells, 512) + kPlanePadElems;
     const size_t pb = pdf_bytes(p->storage), rb = real_bytes(p->storage);
     size_t off = 0;
     for (int k = 0; k < 2; ++k) {
         L.off_H[k] = off;
-        off = align_up(off + 15 * (size_t)L.plane * pb, kAlign);
+        off = align_up(off + 15 * (size_t)L.nblk * kB * pb, kAlign);
     }
     for (int k = 0; k < 2; ++k) {
         L.off_G[k] = off;
-        off = align_up(off + 27 * (size_t)L.plane * pb, kAlign);
+        off = align_up(off + 27 * (size_t)L.nblk * kB * pb, kAlign);
     }
     for (int k = 0; k < 2; ++k) {
         L.off_phi[k] = off;
@@ -172,7 +173,9 @@ struct Ops {
         if (s != LBM_OK) return s;
         c->cur = 0;
         hipLaunchKernelGGL((k_equilibrium<S, In>), dim3(blocks(c)), dim3(kBlock), 0, c->stream, H(c, 0),
-                           G(c, 0), phi(c, 0), u(c), phi_in, u_in, p_in, is_p, c->g, make_phys<R>(&c->p));
+                           G(c, 1), phi(c, 0), u(c), phi_in, u_in, p_in, is_p, c->g, make_phys<R>(&c->p));
+        LAUNCH_CHECK();
+        hipLaunchKernelGGL((k_unpull27<S>), dim3(blocks(c)), dim3(kBlock), 0, c->stream, G(c, 1), G(c, 0), c->g);
         LAUNCH_CHECK();
         c->initialized = true;
         c->steps = 0;
@@ -266,8 +269,10 @@ struct Ops {
         lbm_status s = zero_all(c);
         if (s != LBM_OK) return s;
         c->cur = 0;
-        hipLaunchKernelGGL((k_set_pdfs<S>), dim3(blocks(c)), dim3(kBlock), 0, c->stream, H(c, 0), G(c, 0),
+        hipLaunchKernelGGL((k_set_pdfs<S>), dim3(blocks(c)), dim3(kBlock), 0, c->stream, H(c, 0), G(c, 1),
                            phi(c, 0), u(c), Hi, Gi, phi_i, u_i, c->g, make_phys<R>(&c->p));
+        LAUNCH_CHECK();
+        hipLaunchKernelGGL((k_unpull27<S>), dim3(blocks(c)), dim3(kBlock), 0, c->stream, G(c, 1), G(c, 0), c->g);
         LAUNCH_CHECK();
         c->initialized = true;
         c->steps = 0;
@@ -396,8 +401,9 @@ lbm_status lbm_create(const lbm_params *p, void *ws, size_t bytes, void *stream,
     c->g.nz = p->nz;
     c->g.walls = p->walls_y ? 1 : 0;
     c->g.ncells = (int)L.ncells;
-    c->g.plane = L.plane;
     c->g.fplane = L.fplane;
+    c->g.dnx = make_fastdiv((uint32_t)p->nx);
+    c->g.dny = make_fastdiv((uint32_t)p->ny);
     c->cur = 0;
     c->initialized = false;
     c->steps = 0;
@@ -520,9 +526,9 @@ lbm_status lbm_stream_copy(const void *src, void *dst, size_t bytes, void *strea
     if (((uintptr_t)src) % 16 || ((uintptr_t)dst) % 16) return fail(LBM_EARG, "buffers must be 16-byte aligned");
     const int64_t n = (int64_t)(bytes / 16);
     if (n == 0) return LBM_OK;
-    int64_t nb = (n + kBlock - 1) / kBlock;
-    const int blocks = (int)(nb < 8192 ? nb : 8192);
-    hipLaunchKernelGGL(k_copy, dim3(blocks), dim3(kBlock), 0, (hipStream_t)stream, (const uint4 *)src,
+    const int64_t nb = (n + kBlock - 1) / kBlock;
+    if (nb > 0x7fffffff) return fail(LBM_EARG, "copy of %zu bytes is too large", bytes);
+    hipLaunchKernelGGL(k_copy, dim3((unsigned)nb), dim3(kBlock), 0, (hipStream_t)stream, (const uint4 *)src,
                        (uint4 *)dst, n);
     LAUNCH_CHECK();
     return LBM_OK;

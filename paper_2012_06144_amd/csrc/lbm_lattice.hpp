@@ -98,4 +98,53 @@ struct StoreBF16S {
     __device__ static pdf_t st(real v, real shift) { return __float2bfloat16(v - shift); }
 };
 
+// ---- streaming memory access ---------------------------------------------------
+// PDFs are touched once per sweep; LBM_NT_LOAD / LBM_NT_STORE mark those
+// accesses non-temporal so they do not displace the phase-field rows the
+// stencils re-read from L2.
+#ifndef LBM_NT_LOAD
+#define LBM_NT_LOAD 0
+#endif
+#ifndef LBM_NT_STORE
+#define LBM_NT_STORE 1
+#endif
+#ifndef LBM_NT_FIELD
+#define LBM_NT_FIELD 1
+#endif
+
+template <class T>
+__device__ inline T ld_stream(const T *p)
+{
+    if constexpr (LBM_NT_LOAD && (sizeof(T) == 4 || sizeof(T) == 8) && !__is_class(T)) {
+        return __builtin_nontemporal_load(p);
+    } else if constexpr (LBM_NT_LOAD && sizeof(T) == 2) {
+        const unsigned short v = __builtin_nontemporal_load(reinterpret_cast<const unsigned short *>(p));
+        return __builtin_bit_cast(T, v);
+    } else {
+        return *p;
+    }
+}
+
+template <class T>
+__device__ inline void st_stream(T *p, T v)
+{
+    if constexpr (LBM_NT_STORE && (sizeof(T) == 4 || sizeof(T) == 8) && !__is_class(T)) {
+        __builtin_nontemporal_store(v, p);
+    } else if constexpr (LBM_NT_STORE && sizeof(T) == 2) {
+        __builtin_nontemporal_store(__builtin_bit_cast(unsigned short, v), reinterpret_cast<unsigned short *>(p));
+    } else {
+        *p = v;
+    }
+}
+
+template <class T>
+__device__ inline void st_field(T *p, T v)
+{
+    if constexpr (LBM_NT_FIELD) {
+        __builtin_nontemporal_store(v, p);
+    } else {
+        *p = v;
+    }
+}
+
 }  // namespace lbm
