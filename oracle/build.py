@@ -4,13 +4,13 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRC = os.path.join(HERE, "lbm_oracle.c")
+SRCS = [os.path.join(HERE, "lbm_oracle.c"), os.path.join(HERE, "conv_oracle.c")]
 LIB = os.path.join(HERE, "liblbm_oracle.so")
 
 
 def build(verbose: bool = False) -> str:
     cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp",
-           "-ffp-contract=off", "-Wall", "-Wextra", "-o", LIB, SRC, "-lm"]
+           "-ffp-contract=off", "-Wall", "-Wextra", "-o", LIB] + SRCS + ["-lm"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

@@ -1,0 +1,162 @@
+/*
+ * Plain FP64 CPU oracle of the surrogate network's operations: 3x3x3
+ * convolution (forward, gradient with respect to the input, gradient with
+ * respect to the weights and bias), 2x average pooling, 2x nearest
+ * upsampling, leaky ReLU, mean-squared error and the Adam update.
+ *
+ * TEST INFRASTRUCTURE ONLY: for the tests and the smoke check; shares no code
+ * with the GPU library.
+ *
+ * Tensors are channels-last: x[((n*D + d)*H + h)*W + w][c].  Convolution
+ * weights are w[t][co][ci] with tap t = (a+1)*9 + (b+1)*3 + (c+1) for the
+ * offset (a, b, c) in (d, h, w); zero padding of one cell, stride one:
+ *   y[v][co] = bias[co] + sum_t sum_ci x[v + offset(t)][ci] w[t][co][ci].
+ */
+#include <math.h>
+#include <stddef.h>
+#include <stdint.h>
+#include <string.h>
+
+static inline int64_t vox(int n, int d, int h, int w, int D, int H, int W)
+{
+    return (((int64_t)n * D + d) * H + h) * W + w;
+}
+
+void orc_conv3d_fwd(const double *x, int N, int D, int H, int W, int Ci, const double *wt,
+                    const double *bias, int Co, double *y)
+{
+    for (int n = 0; n < N; ++n)
+        for (int d = 0; d < D; ++d)
+            for (int h = 0; h < H; ++h)
+                for (int w = 0; w < W; ++w) {
+                    double *yo = y + vox(n, d, h, w, D, H, W) * Co;
+                    for (int co = 0; co < Co; ++co) yo[co] = bias ? bias[co] : 0.0;
+                    for (int a = -1; a <= 1; ++a)
+                        for (int b = -1; b <= 1; ++b)
+                            for (int c = -1; c <= 1; ++c) {
+                                const int dd = d + a, hh = h + b, ww = w + c;
+                                if (dd < 0 || dd >= D || hh < 0 || hh >= H || ww < 0 || ww >= W) continue;
+                                const int t = (a + 1) * 9 + (b + 1) * 3 + (c + 1);
+                                const double *xi = x + vox(n, dd, hh, ww, D, H, W) * Ci;
+                                for (int co = 0; co < Co; ++co) {
+                                    const double *wr = wt + ((int64_t)t * Co + co) * Ci;
+                                    double s = 0.0;
+                                    for (int ci = 0; ci < Ci; ++ci) s += xi[ci] * wr[ci];
+                                    yo[co] += s;
+                                }
+                            }
+                }
+}
+
+/* dx[v][ci] = sum_t sum_co dy[v - offset(t)][co] w[t][co][ci] */
+void orc_conv3d_bwd_data(const double *dy, int N, int D, int H, int W, int Co, const double *wt, int Ci,
+                         double *dx)
+{
+    memset(dx, 0, sizeof(double) * (size_t)N * D * H * W * Ci);
+    for (int n = 0; n < N; ++n)
+        for (int d = 0; d < D; ++d)
+            for (int h = 0; h < H; ++h)
+                for (int w = 0; w < W; ++w) {
+                    const double *g = dy + vox(n, d, h, w, D, H, W) * Co;
+                    for (int a = -1; a <= 1; ++a)
+                        for (int b = -1; b <= 1; ++b)
+                            for (int c = -1; c <= 1; ++c) {
+                                const int dd = d + a, hh = h + b, ww = w + c;
+                                if (dd < 0 || dd >= D || hh < 0 || hh >= H || ww < 0 || ww >= W) continue;
+                                const int t = (a + 1) * 9 + (b + 1) * 3 + (c + 1);
+                                double *xo = dx + vox(n, dd, hh, ww, D, H, W) * Ci;
+                                for (int co = 0; co < Co; ++co) {
+                                    const double *wr = wt + ((int64_t)t * Co + co) * Ci;
+                                    for (int ci = 0; ci < Ci; ++ci) xo[ci] += g[co] * wr[ci];
+                                }
+                            }
+                }
+}
+
+/* dw[t][co][ci] = sum_v dy[v][co] x[v + offset(t)][ci];  db[co] = sum_v dy[v][co] */
+void orc_conv3d_bwd_weight(const double *x, const double *dy, int N, int D, int H, int W, int Ci, int Co,
+                           double *dw, double *db)
+{
+    memset(dw, 0, sizeof(double) * 27 * (size_t)Co * Ci);
+    if (db) memset(db, 0, sizeof(double) * Co);
+    for (int n = 0; n < N; ++n)
+        for (int d = 0; d < D; ++d)
+            for (int h = 0; h < H; ++h)
+                for (int w = 0; w < W; ++w) {
+                    const double *g = dy + vox(n, d, h, w, D, H, W) * Co;
+                    if (db)
+                        for (int co = 0; co < Co; ++co) db[co] += g[co];
+                    for (int a = -1; a <= 1; ++a)
+                        for (int b = -1; b <= 1; ++b)
+                            for (int c = -1; c <= 1; ++c) {
+                                const int dd = d + a, hh = h + b, ww = w + c;
+                                if (dd < 0 || dd >= D || hh < 0 || hh >= H || ww < 0 || ww >= W) continue;
+                                const int t = (a + 1) * 9 + (b + 1) * 3 + (c + 1);
+                                const double *xi = x + vox(n, dd, hh, ww, D, H, W) * Ci;
+                                for (int co = 0; co < Co; ++co) {
+                                    double *wr = dw + ((int64_t)t * Co + co) * Ci;
+                                    for (int ci = 0; ci < Ci; ++ci) wr[ci] += g[co] * xi[ci];
+                                }
+                            }
+                }
+}
+
+/* y = mean of each 2x2x2 block (D, H, W even) */
+void orc_pool2(const double *x, int N, int D, int H, int W, int C, double *y)
+{
+    const int d2 = D / 2, h2 = H / 2, w2 = W / 2;
+    for (int n = 0; n < N; ++n)
+        for (int d = 0; d < d2; ++d)
+            for (int h = 0; h < h2; ++h)
+                for (int w = 0; w < w2; ++w)
+                    for (int c = 0; c < C; ++c) {
+                        double s = 0.0;
+                        for (int a = 0; a < 2; ++a)
+                            for (int b = 0; b < 2; ++b)
+                                for (int e = 0; e < 2; ++e)
+                                    s += x[vox(n, 2 * d + a, 2 * h + b, 2 * w + e, D, H, W) * C + c];
+                        y[vox(n, d, h, w, d2, h2, w2) * C + c] = s / 8.0;
+                    }
+}
+
+/* y[2d+a][2h+b][2w+e] = x[d][h][w]  (D, H, W of the coarse input) */
+void orc_up2(const double *x, int N, int D, int H, int W, int C, double *y)
+{
+    for (int n = 0; n < N; ++n)
+        for (int d = 0; d < 2 * D; ++d)
+            for (int h = 0; h < 2 * H; ++h)
+                for (int w = 0; w < 2 * W; ++w)
+                    for (int c = 0; c < C; ++c)
+                        y[vox(n, d, h, w, 2 * D, 2 * H, 2 * W) * C + c] = x[vox(n, d / 2, h / 2, w / 2, D, H, W) * C + c];
+}
+
+/* leaky ReLU: y = x (x > 0), slope * x otherwise */
+void orc_leaky(const double *x, size_t n, double slope, double *y)
+{
+    for (size_t i = 0; i < n; ++i) y[i] = x[i] > 0.0 ? x[i] : slope * x[i];
+}
+
+/* mean squared error and its gradient with respect to pred */
+double orc_mse(const double *pred, const double *target, size_t n, double *grad)
+{
+    double s = 0.0;
+    for (size_t i = 0; i < n; ++i) {
+        const double d = pred[i] - target[i];
+        s += d * d;
+        if (grad) grad[i] = 2.0 * d / (double)n;
+    }
+    return s / (double)n;
+}
+
+/* Adam (Kingma and Ba, 2015): m = b1 m + (1-b1) g; v = b2 v + (1-b2) g^2;
+ * p -= lr * (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps), t >= 1. */
+void orc_adam(double *p, const double *g, double *m, double *v, size_t n, double lr, double b1, double b2,
+              double eps, int t)
+{
+    const double c1 = 1.0 - pow(b1, t), c2 = 1.0 - pow(b2, t);
+    for (size_t i = 0; i < n; ++i) {
+        m[i] = b1 * m[i] + (1.0 - b1) * g[i];
+        v[i] = b2 * v[i] + (1.0 - b2) * g[i] * g[i];
+        p[i] -= lr * (m[i] / c1) / (sqrt(v[i] / c2) + eps);
+    }
+}

@@ -46,7 +46,10 @@
  *     exactly zero gradient;
  *   - rho and tau interpolations divide by (phi_H - phi_L);
  *   - y walls: rows 0 and ny-1 are solid, halfway bounce-back for h and g,
- *     phi stencils mirror the wall row onto the first fluid row.
+ *     phi stencils mirror the wall row onto the first fluid row;
+ *   - buoyancy F_b = (rho - rho_ref) a: rho_ref = 0 is the printed rho g;
+ *     rho_ref = rho_H leaves out the hydrostatic pressure of the heavy fluid
+ *     (a uniform force the walls balance).
  */
 #include <math.h>
 #include <stdint.h>
@@ -62,6 +65,7 @@ typedef struct {
     double phi_L, phi_H, xi, mobility, sigma;
     double rho_L, rho_H, tau_L, tau_H;
     double accel[3];
+    double rho_ref;      /* buoyancy reference density: F_b = (rho - rho_ref) a */
     double normal_eps;
 } orc_params;
 
@@ -574,7 +578,7 @@ static void hydro_cell(orc_state *s, int x, int y, int z)
         double Fmu = 0.0;
         for (int b = 0; b < 3; ++b) Fmu += V[a][b] * grad_rho[b];
         Fmu *= -nu / CS2;
-        double Fb = rho * p->accel[a];
+        double Fb = (rho - p->rho_ref) * p->accel[a];
         F[a] = Fp + Fs + Fmu + Fb;
     }
 

@@ -30,7 +30,7 @@ class OrcParams(C.Structure):
         ("mobility", C.c_double), ("sigma", C.c_double),
         ("rho_L", C.c_double), ("rho_H", C.c_double),
         ("tau_L", C.c_double), ("tau_H", C.c_double),
-        ("accel", C.c_double * 3), ("normal_eps", C.c_double),
+        ("accel", C.c_double * 3), ("rho_ref", C.c_double), ("normal_eps", C.c_double),
     ]
 
 
@@ -103,6 +103,7 @@ class Params:
     tau_L: float = 1.0
     tau_H: float = 1.0
     accel: tuple = (0.0, 0.0, 0.0)
+    buoyancy_rho_ref: float = 0.0
     normal_eps: float = 1e-12
 
     def to_c(self) -> OrcParams:
@@ -113,6 +114,7 @@ class Params:
         p.rho_L, p.rho_H, p.tau_L, p.tau_H = self.rho_L, self.rho_H, self.tau_L, self.tau_H
         for a in range(3):
             p.accel[a] = self.accel[a]
+        p.rho_ref = self.buoyancy_rho_ref
         p.normal_eps = self.normal_eps
         return p
 

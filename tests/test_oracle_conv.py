@@ -1,0 +1,139 @@
+"""Pins of the surrogate-network oracle (FP64 CPU): each operation against a
+library routine or a property that does not come from the oracle itself.
+
+* 3x3x3 convolution = scipy.ndimage.correlate per (C_out, C_in) pair, zero
+  padding, plus bias.
+* Gradient with respect to the input: the adjoint identity
+  <conv(x, w), y> = <x, bwd_data(y, w)>.
+* Gradient with respect to the weights: <conv(x, dw), y> = <dw, bwd_weight(x, y)>
+  (the convolution is linear in w), db = sum of y; and central finite
+  differences of an MSE loss.
+* Pooling = numpy block mean; upsampling = numpy repeat; pooling is the
+  adjoint of upsampling divided by 8.
+* Adam with a constant gradient moves every parameter by exactly
+  lr * g / (|g| + eps) per step (bias correction makes m_hat = g, v_hat = g^2).
+"""
+import numpy as np
+import pytest
+from scipy import ndimage
+
+from oracle import conv
+
+
+def _rand(*shape, seed=0):
+    return np.random.default_rng(seed).standard_normal(shape)
+
+
+@pytest.mark.parametrize("shape,ci,co", [((1, 4, 5, 6), 3, 2), ((2, 3, 3, 3), 5, 4), ((1, 1, 2, 7), 2, 3)])
+def test_conv3d_matches_scipy_correlate(shape, ci, co):
+    x = _rand(*shape, ci, seed=1)
+    w = _rand(27, co, ci, seed=2)
+    b = _rand(co, seed=3)
+    y = conv.conv3d(x, w, b)
+    ref = np.zeros(shape + (co,))
+    for n in range(shape[0]):
+        for o in range(co):
+            acc = np.full(shape[1:], b[o])
+            for i in range(ci):
+                k = w[:, o, i].reshape(3, 3, 3)   # k[a+1, b+1, c+1] = w[t]
+                acc += ndimage.correlate(x[n, ..., i], k, mode="constant", cval=0.0)
+            ref[n, ..., o] = acc
+    assert np.abs(y - ref).max() < 1e-12
+
+
+def test_bwd_data_is_adjoint_of_conv():
+    x = _rand(2, 4, 5, 3, 6, seed=4)
+    w = _rand(27, 7, 6, seed=5)
+    y = _rand(2, 4, 5, 3, 7, seed=6)
+    lhs = np.sum(conv.conv3d(x, w) * y)
+    rhs = np.sum(x * conv.conv3d_bwd_data(y, w))
+    assert abs(lhs - rhs) < 1e-12 * (abs(lhs) + 1)
+
+
+def test_bwd_weight_is_gradient_of_bilinear_form():
+    x = _rand(1, 5, 4, 6, 3, seed=7)
+    y = _rand(1, 5, 4, 6, 4, seed=8)
+    dw = _rand(27, 4, 3, seed=9)
+    gw, gb = conv.conv3d_bwd_weight(x, y)
+    lhs = np.sum(conv.conv3d(x, dw) * y)
+    assert abs(lhs - np.sum(dw * gw)) < 1e-12 * (abs(lhs) + 1)
+    assert np.abs(gb - y.sum(axis=(0, 1, 2, 3))).max() < 1e-12
+
+
+def test_conv_gradients_by_finite_differences():
+    """L = mse(leaky(conv(x, w, b)), t): central differences (h = 1e-6) of a
+    few weights, biases and inputs against the chain rule built from the
+    oracle's backward operations."""
+    slope = 0.1
+    x = _rand(1, 3, 4, 3, 2, seed=10)
+    w = 0.5 * _rand(27, 3, 2, seed=11)
+    b = 0.1 * _rand(3, seed=12)
+    t = _rand(1, 3, 4, 3, 3, seed=13)
+
+    def loss(x, w, b):
+        return conv.mse(conv.leaky(conv.conv3d(x, w, b), slope), t, want_grad=False)[0]
+
+    pre = conv.conv3d(x, w, b)
+    y = conv.leaky(pre, slope)
+    _, gy = conv.mse(y, t)
+    gpre = gy * np.where(pre > 0, 1.0, slope)
+    gw, gb = conv.conv3d_bwd_weight(x, gpre)
+    gx = conv.conv3d_bwd_data(gpre, w)
+    h = 1e-6
+    rng = np.random.default_rng(14)
+    for _ in range(6):
+        idx = tuple(rng.integers(0, s) for s in w.shape)
+        wp, wm = w.copy(), w.copy()
+        wp[idx] += h
+        wm[idx] -= h
+        fd = (loss(x, wp, b) - loss(x, wm, b)) / (2 * h)
+        assert abs(fd - gw[idx]) < 1e-6 * max(1.0, abs(fd))
+    for k in range(3):
+        bp, bm = b.copy(), b.copy()
+        bp[k] += h
+        bm[k] -= h
+        fd = (loss(x, w, bp) - loss(x, w, bm)) / (2 * h)
+        assert abs(fd - gb[k]) < 1e-6 * max(1.0, abs(fd))
+    for _ in range(6):
+        idx = tuple(rng.integers(0, s) for s in x.shape)
+        xp, xm = x.copy(), x.copy()
+        xp[idx] += h
+        xm[idx] -= h
+        fd = (loss(xp, w, b) - loss(xm, w, b)) / (2 * h)
+        assert abs(fd - gx[idx]) < 1e-6 * max(1.0, abs(fd))
+
+
+def test_pool_and_upsample():
+    x = _rand(2, 4, 6, 2, 3, seed=15)
+    p = conv.pool2(x)
+    ref = x.reshape(2, 2, 2, 3, 2, 1, 2, 3).mean(axis=(2, 4, 6))
+    assert np.abs(p - ref).max() < 1e-15
+    c = _rand(2, 2, 3, 1, 3, seed=16)
+    u = conv.up2(c)
+    ref_u = np.repeat(np.repeat(np.repeat(c, 2, axis=1), 2, axis=2), 2, axis=3)
+    assert np.array_equal(u, ref_u)
+    # <pool(x), c> = <x, up(c)> / 8
+    assert abs(np.sum(p * c) - np.sum(x * u) / 8.0) < 1e-12
+
+
+def test_leaky_and_mse():
+    x = _rand(5, 7, seed=17)
+    assert np.array_equal(conv.leaky(x, 0.1), np.where(x > 0, x, 0.1 * x))
+    t = _rand(5, 7, seed=18)
+    v, g = conv.mse(x, t)
+    assert abs(v - np.mean((x - t) ** 2)) < 1e-15
+    assert np.abs(g - 2 * (x - t) / x.size).max() < 1e-15
+
+
+def test_adam_constant_gradient():
+    rng = np.random.default_rng(19)
+    p0 = rng.standard_normal(50)
+    g = rng.standard_normal(50)
+    p = p0.copy()
+    m = np.zeros(50)
+    v = np.zeros(50)
+    lr, eps = 1e-3, 1e-8
+    for t in range(1, 11):
+        conv.adam(p, g, m, v, lr, 0.9, 0.999, eps, t)
+        expect = p0 - t * lr * g / (np.abs(g) + eps)
+        assert np.abs(p - expect).max() < 1e-12
