@@ -50,10 +50,11 @@ typedef enum {
 } lbm_status;
 
 /* PDF storage formats.  Collision arithmetic is FP64 for LBM_F64 and FP32
- * for the others; phi and u are stored in the arithmetic type.  The
- * low-precision formats store shifted populations: h_i - phi_shift * w_i
- * for the phase-field PDFs, g_i unshifted (the velocity-based g is already
- * a deviation, g_i ~ p* w_i + O(u)). */
+ * for the others; phi and u are stored in the arithmetic type.  The 16-bit
+ * formats store shifted / scaled populations of order u instead of the
+ * populations: h_i - phi w_i with phi of the cell the value is stored at, and
+ * g_i / w_i (the velocity-based g_i ~ w_i (p* + 3 e_i.u + ...) is already a
+ * deviation). */
 typedef enum { LBM_F64 = 0, LBM_F32 = 1, LBM_F16S = 2, LBM_BF16S = 3 } lbm_storage;
 
 /* Element types of the field arrays exchanged by the get/set calls. */
@@ -69,22 +70,25 @@ typedef enum { LBM_DTYPE_F64 = 0, LBM_DTYPE_F32 = 1 } lbm_dtype;
  *   tau_L, tau_H   hydrodynamic relaxation times with nu = tau c_s^2,
  *                  interpolated linearly in phi; the second-order moments
  *                  relax with 1/(tau + 1/2), all others with 1 (Sec. 3.2)
- *   body_accel     body force F_b = rho * body_accel (buoyancy of Sec. 6.1 is
- *                  body_accel = (0, -g, 0))
+ *   body_accel     body acceleration a; the body force is
+ *   buoyancy_rho_ref   F_b = (rho - buoyancy_rho_ref) a.  0 gives the buoyancy
+ *                  rho g of Sec. 6.1 literally; rho_H removes the hydrostatic
+ *                  part of the pressure (same flow between the y walls, the
+ *                  pressure differs by a linear field), which keeps p* small
+ *                  in tall domains
  *   normal_eps     interface normal n = grad phi / (|grad phi| + normal_eps)
  *   storage        an lbm_storage value
- *   phi_shift      reference phase for the shifted low-precision h storage
- *                  (usually the majority phase); ignored for F64 / F32 */
+ *   reserved0      must be 0 */
 typedef struct {
     int32_t nx, ny, nz;
     int32_t walls_y;
     double phi_L, phi_H, xi, mobility, sigma;
     double rho_L, rho_H, tau_L, tau_H;
     double body_accel[3];
+    double buoyancy_rho_ref;
     double normal_eps;
     int32_t storage;
     int32_t reserved0;
-    double phi_shift;
 } lbm_params;
 
 /* FP64 diagnostics over fluid cells (one deterministic two-pass reduction).
@@ -179,6 +183,18 @@ lbm_status lbm_get_pdfs(lbm_ctx *ctx, double *H, double *G);
  * phase field and velocity); rounds to the storage format. */
 lbm_status lbm_set_pdfs(lbm_ctx *ctx, const double *H, const double *G, const double *phi,
                         const double *u);
+
+/* Bytes of one saved state: the current PDFs in storage format, the phase
+ * field and the velocity. */
+size_t lbm_state_bytes(const lbm_ctx *ctx);
+
+/* Copies the current state into `dst` (device, lbm_state_bytes(ctx) bytes,
+ * 256-byte aligned); asynchronous. */
+lbm_status lbm_save_state(lbm_ctx *ctx, void *dst);
+
+/* Makes a state saved by lbm_save_state from a context with the same
+ * parameters the current state; asynchronous. */
+lbm_status lbm_restore_state(lbm_ctx *ctx, const void *src);
 
 /* STREAM-copy probe a_i = b_i over `bytes` bytes (multiple of 16) between
  * two device buffers on `hip_stream`; measures the copy bandwidth b_s used

@@ -1,0 +1,139 @@
+/*
+ * sg.h -- C ABI of the surrogate-network kernels for gfx950: a 3D
+ * convolutional encoder-decoder that predicts the macroscopic state (phi, u,
+ * p) of the coupled phase-field / hydrodynamic LBM K steps ahead, trained on
+ * snapshots the solver itself produces.  The network is an addition to the
+ * method of Holzer et al. (IJHPCA 2020); the LBM re-relaxes after every
+ * jump and remains the reference (lbm.h).
+ *
+ * Conventions:
+ *   - Activations are BF16, channels last: x[((n*D + d)*H + h)*W + w][c].
+ *   - Convolutions are 3x3x3, stride 1, zero padding 1.  Weights are BF16
+ *     w[t][c_out][c_in], tap t = (a+1)*9 + (b+1)*3 + (c+1) for the offset
+ *     (a, b, c) along (d, h, w); bias is FP32.  Products are accumulated in
+ *     FP32 on the matrix cores (v_mfma_f32_32x32x16_bf16).
+ *   - Shape rules: c_in % 16 == 0, c_out % 32 == 0 (the output may keep only
+ *     the first n_store channels), activation and weight pointers 16-byte
+ *     aligned.
+ *   - Pointers are device pointers owned by the caller; every call enqueues
+ *     on hip_stream and returns sg_status; sg_last_error() has the text.
+ */
+#ifndef SG_H
+#define SG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum { SG_OK = 0, SG_EARG = -1, SG_EHIP = -2, SG_ESIZE = -3 } sg_status;
+
+/* y = act(conv(x, w) + bias), act = leaky ReLU with `slope` if act != 0.
+ * y is BF16 with n_store channels per voxel if y_f32 == 0, else FP32. */
+sg_status sg_conv3d_fwd(const void *x, int32_t n, int32_t d, int32_t h, int32_t w, int32_t c_in,
+                        const void *wt, const float *bias, int32_t c_out, int32_t n_store, int32_t act,
+                        float slope, void *y, int32_t y_f32, void *hip_stream);
+
+/* Weights of the input gradient: wm[26 - t][ci][co] = wt[t][co][ci] (BF16).
+ * sg_conv3d_fwd(dy, wm, bias = NULL) then gives dx[v][ci] =
+ * sum_t sum_co dy[v - offset(t)][co] wt[t][co][ci]. */
+sg_status sg_weight_mirror(const void *wt, int32_t c_out, int32_t c_in, void *wm, void *hip_stream);
+
+/* Bytes of FP32 scratch sg_conv3d_bwd_weight needs for this shape. */
+size_t sg_bwd_weight_workspace(int32_t n, int32_t d, int32_t h, int32_t w, int32_t c_in, int32_t c_out);
+
+/* dw[t][co][ci] = sum_v dy[v][co] x[v + offset(t)][ci] and db[co] = sum_v dy[v][co]
+ * (FP32 outputs, overwritten), deterministic two-pass reduction through
+ * `workspace` (sg_bwd_weight_workspace bytes).  db may be NULL. */
+sg_status sg_conv3d_bwd_weight(const void *x, const void *dy, int32_t n, int32_t d, int32_t h, int32_t w,
+                               int32_t c_in, int32_t c_out, float *dw, float *db, void *workspace,
+                               size_t workspace_bytes, void *hip_stream);
+
+/* Elementwise leaky-ReLU backward from the layer output: dpre = dy * (y > 0 ? 1 : slope). */
+sg_status sg_leaky_bwd(const void *y, const void *dy, void *dpre, size_t count, float slope, void *hip_stream);
+
+/* 2x average pooling (d, h, w even) and its backward (dx = dy / 8 spread). */
+sg_status sg_pool2_fwd(const void *x, int32_t n, int32_t d, int32_t h, int32_t w, int32_t c, void *y,
+                       void *hip_stream);
+sg_status sg_pool2_bwd(const void *dy, int32_t n, int32_t d, int32_t h, int32_t w, int32_t c, void *dx,
+                       void *hip_stream);
+
+/* 2x nearest upsampling of a (n, d, h, w, c) tensor and its backward (sum of
+ * the 8 children). */
+sg_status sg_up2_fwd(const void *x, int32_t n, int32_t d, int32_t h, int32_t w, int32_t c, void *y,
+                     void *hip_stream);
+sg_status sg_up2_bwd(const void *dy, int32_t n, int32_t d, int32_t h, int32_t w, int32_t c, void *dx,
+                     void *hip_stream);
+
+/* Channel concatenation y = [a | b] (ca + cb channels) and its split. */
+sg_status sg_concat(const void *a, int32_t ca, const void *b, int32_t cb, int64_t voxels, void *y,
+                    void *hip_stream);
+sg_status sg_split(const void *y, int32_t ca, int32_t cb, int64_t voxels, void *a, void *b, void *hip_stream);
+
+/* Mean squared error over `count` FP32 values: loss (device FP32 scalar,
+ * deterministic fixed-order reduction through `scratch`, 1024 floats) and
+ * the BF16 gradient 2 (pred - target) / count. */
+sg_status sg_mse(const float *pred, const float *target, int64_t count, float *loss, void *grad_bf16,
+                 float *scratch, void *hip_stream);
+
+/* One Adam step (Kingma and Ba) on FP32 master weights p with FP32 moments m, v
+ * and gradient g; also writes the BF16 copy wt of p.  step >= 1. */
+sg_status sg_adam(float *p, const float *g, float *m, float *v, void *wt_bf16, int64_t count, float lr,
+                  float beta1, float beta2, float eps, int32_t step, void *hip_stream);
+
+/* FP32 -> BF16 and BF16 -> FP32 conversions (round to nearest even). */
+sg_status sg_to_bf16(const float *x, void *y, int64_t count, void *hip_stream);
+sg_status sg_to_f32(const void *x, float *y, int64_t count, void *hip_stream);
+
+/* y = a + b elementwise (BF16), used to join gradients of a skip connection. */
+sg_status sg_add(const void *a, const void *b, void *y, int64_t count, void *hip_stream);
+
+/* ---- between the LBM fields and the network ------------------------------------
+ * Fields are FP32 planes of an nx * ny * nz grid, x fastest (phi, u as 3
+ * planes, p); a box is (x0, y0, z0, bx, by, bz), wrapped periodically in x
+ * and z; y must lie inside [0, ny).  A box becomes one network sample with
+ * D = bz, H = by, W = bx.  `box` (6 int32) and the per-channel scales (5
+ * floats) are HOST arrays read during the call. */
+
+/* Network input of a box: channels (phi, u_x, u_y, u_z, p) / scale_in, then
+ * zeros up to c_in (>= 5) channels, BF16; optionally the raw FP32 state
+ * (5 channels per voxel) into `state` (may be NULL). */
+sg_status sg_fields_to_input(const float *phi, const float *u, const float *p, int32_t nx, int32_t ny,
+                             int32_t nz, const int32_t *box, const float *scale_in, int32_t c_in, void *x_bf16,
+                             float *state, void *hip_stream);
+
+/* Network input of raw states stored channels last (5 FP32 channels per
+ * voxel, as written by sg_fields_to_input): state / scale_in, zero-padded to
+ * c_in channels, BF16. */
+sg_status sg_state_to_input(const float *state, int64_t voxels, const float *scale_in, int32_t c_in, void *x_bf16,
+                            void *hip_stream);
+
+/* Training target of a pair of raw states: (s1 - s0) / scale_out in the first
+ * 5 of c_out channels, zeros in the rest (FP32). */
+sg_status sg_make_target(const float *s0, const float *s1, int64_t voxels, const float *scale_out,
+                         int32_t c_out, float *target, void *hip_stream);
+
+/* Applies a predicted increment to the fields of a box: field += out * scale_out
+ * (out has c_out FP32 channels, the first 5 used); phi is clipped to
+ * [phi_min, phi_max] afterwards; cells of the rows y = 0 and ny-1 are left
+ * unchanged if walls_y. */
+sg_status sg_apply_prediction(const float *out, int32_t c_out, const float *scale_out, float *phi, float *u,
+                              float *p, int32_t nx, int32_t ny, int32_t nz, const int32_t *box, int32_t walls_y,
+                              float phi_min, float phi_max, void *hip_stream);
+
+/* Mass projection of a phase field over ncells cells: phi += c * 4 phi' (1 - phi')
+ * with phi' = (phi - phi_min)/(phi_max - phi_min), c chosen (FP64, fixed-order
+ * reduction through `scratch`, 2048 doubles) so that sum(phi) equals
+ * target_mass; the correction stays in the interface. */
+sg_status sg_mass_project(float *phi, int64_t ncells, double target_mass, float phi_min, float phi_max,
+                          double *scratch, void *hip_stream);
+
+const char *sg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SG_H */

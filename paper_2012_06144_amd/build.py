@@ -10,7 +10,7 @@ LIBDIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(LIBDIR, "liblbm.so")
 ARCH = "gfx950"
 
-SOURCES = [os.path.join(CSRC, "lbm_api.hip")]
+SOURCES = [os.path.join(CSRC, "lbm_api.hip"), os.path.join(CSRC, "sg_api.hip")]
 HEADERS = [os.path.join(CSRC, f) for f in ("lbm_kernels.hpp", "lbm_lattice.hpp")] + [
     os.path.join(ROOT, "include", "lbm.h")]
 

@@ -74,6 +74,7 @@ lbm_status validate(const lbm_params *p)
     if (!(p->rho_L > 0) || !(p->rho_H > 0)) return fail(LBM_EARG, "densities must be > 0");
     if (!(p->sigma >= 0)) return fail(LBM_EARG, "sigma must be >= 0");
     if (!(p->normal_eps >= 0)) return fail(LBM_EARG, "normal_eps must be >= 0");
+    if (p->reserved0 != 0) return fail(LBM_EARG, "reserved0 must be 0");
     return LBM_OK;
 }
 
@@ -126,8 +127,8 @@ Phys<R> make_phys(const lbm_params *p)
     ph.beta = (R)(12.0 * p->sigma / p->xi);
     ph.kappa = (R)(1.5 * p->sigma * p->xi);
     for (int k = 0; k < 3; ++k) ph.accel[k] = (R)p->body_accel[k];
+    ph.rho_ref = (R)p->buoyancy_rho_ref;
     ph.normal_eps = (R)p->normal_eps;
-    ph.shift_h = (p->storage == LBM_F16S || p->storage == LBM_BF16S) ? (R)p->phi_shift : (R)0;
     return ph;
 }
 
@@ -258,7 +259,7 @@ struct Ops {
     static lbm_status get_pdfs(lbm_ctx *c, double *Ho, double *Go)
     {
         hipLaunchKernelGGL((k_get_pdfs<S>), dim3(blocks(c)), dim3(kBlock), 0, c->stream, H(c, c->cur),
-                           G(c, c->cur), Ho, Go, c->g, make_phys<R>(&c->p));
+                           G(c, c->cur), phi(c, c->cur), Ho, Go, c->g, make_phys<R>(&c->p));
         LAUNCH_CHECK();
         return LBM_OK;
     }
@@ -531,6 +532,54 @@ lbm_status lbm_stream_copy(const void *src, void *dst, size_t bytes, void *strea
     hipLaunchKernelGGL(k_copy, dim3((unsigned)nb), dim3(kBlock), 0, (hipStream_t)stream, (const uint4 *)src,
                        (uint4 *)dst, n);
     LAUNCH_CHECK();
+    return LBM_OK;
+}
+
+static void state_parts(const lbm_ctx *c, size_t sz[4], size_t off_dst[5])
+{
+    const size_t pb = pdf_bytes(c->p.storage), rb = real_bytes(c->p.storage);
+    sz[0] = 15 * (size_t)c->L.nblk * kB * pb;
+    sz[1] = 27 * (size_t)c->L.nblk * kB * pb;
+    sz[2] = (size_t)c->L.fplane * rb;
+    sz[3] = 3 * (size_t)c->L.fplane * rb;
+    off_dst[0] = 0;
+    for (int k = 0; k < 4; ++k) off_dst[k + 1] = align_up(off_dst[k] + sz[k], kAlign);
+}
+
+size_t lbm_state_bytes(const lbm_ctx *c)
+{
+    if (!c) return 0;
+    size_t sz[4], off[5];
+    state_parts(c, sz, off);
+    return off[4];
+}
+
+lbm_status lbm_save_state(lbm_ctx *c, void *dst)
+{
+    lbm_status s = check_ctx(c, true);
+    if (s != LBM_OK) return s;
+    if (!dst || ((uintptr_t)dst) % kAlign) return fail(LBM_EARG, "dst must be a 256-byte aligned device pointer");
+    size_t sz[4], off[5];
+    state_parts(c, sz, off);
+    const int k = c->cur;
+    const char *src[4] = {c->ws + c->L.off_H[k], c->ws + c->L.off_G[k], c->ws + c->L.off_phi[k], c->ws + c->L.off_u};
+    for (int i = 0; i < 4; ++i)
+        HIP_TRY(hipMemcpyAsync((char *)dst + off[i], src[i], sz[i], hipMemcpyDeviceToDevice, c->stream));
+    return LBM_OK;
+}
+
+lbm_status lbm_restore_state(lbm_ctx *c, const void *src)
+{
+    lbm_status s = check_ctx(c, false);
+    if (s != LBM_OK) return s;
+    if (!src || ((uintptr_t)src) % kAlign) return fail(LBM_EARG, "src must be a 256-byte aligned device pointer");
+    size_t sz[4], off[5];
+    state_parts(c, sz, off);
+    char *dst[4] = {c->ws + c->L.off_H[0], c->ws + c->L.off_G[0], c->ws + c->L.off_phi[0], c->ws + c->L.off_u};
+    for (int i = 0; i < 4; ++i)
+        HIP_TRY(hipMemcpyAsync(dst[i], (const char *)src + off[i], sz[i], hipMemcpyDeviceToDevice, c->stream));
+    c->cur = 0;
+    c->initialized = true;
     return LBM_OK;
 }
 

@@ -54,8 +54,8 @@ struct Phys {
     R tau_L, dtau;                       // dtau = tau_H - tau_L
     R beta, kappa;                       // 12 sigma/xi, 3 sigma xi/2
     R accel[3];
+    R rho_ref;                           // F_b = (rho - rho_ref) accel
     R normal_eps;
-    R shift_h;                           // stored h_i = h_i - shift_h * w_i (low precision)
 };
 
 // Division by a run-time invariant d >= 1 with a multiply-high and shifts
@@ -245,36 +245,82 @@ __global__ __launch_bounds__(kBlock) void k_phase(const SweepArgs<S> a)
     Nbr n;
     if (!decode(a.g, c, x, y, z, n)) return;
 
+    // previous phase field at x + e_i (D3Q15 stencil points; wall rows mirrored)
+    R phs[15];
+#pragma unroll
+    for (int i = 0; i < 15; ++i) phs[i] = a.phi_in[c + n.offm(e15(i, 0), e15(i, 1), e15(i, 2))];
+
+    // The population arrives from x - e_i (phs[opp(i)]) or bounces back at x.
+    // The FP32 and 16-bit paths keep the phi budget of the cell in FP64: the
+    // decoded populations are summed exactly, so sum(phi) moves only by the
+    // single rounding of the rest population below.
     R Pi[15];
+    double phi_acc = 0.0;
 #pragma unroll
     for (int i = 0; i < 15; ++i) {
-        const R sh = a.ph.shift_h * wgt<15, R>(i);  // w_opp(i) == w_i
-        Pi[i] = S::ld(ld_stream(a.src + pull_idx<15>(i, c, n)), sh);
+        const bool bb = (e15(i, 1) > 0 && n.wm) || (e15(i, 1) < 0 && n.wp);
+        const typename S::pdf_t v = ld_stream(a.src + pull_idx<15>(i, c, n));
+        const R up = bb ? phs[0] : phs[opp(i)];
+        if constexpr (std::is_same<R, double>::value) {
+            Pi[i] = dec_h<S>(v, up, i);
+            phi_acc += Pi[i];
+        } else {
+            const double p64 = dec_h64<S>(v, up, i);
+            Pi[i] = R(p64);
+            phi_acc += p64;
+        }
     }
-    R phi = R(0);
-#pragma unroll
-    for (int i = 0; i < 15; ++i) phi += Pi[i];
+    const R phi = R(phi_acc);
     st_field(a.phi_out + c, phi);
 
-    R grad[3], lap_unused;
-    stencil<15, R, false>(a.phi_in, c, n, grad, lap_unused);
+    // isotropic gradient (eq. grad) from antisymmetric pairs of the half set
+    R acc[3] = {R(0), R(0), R(0)};
+#pragma unroll
+    for (int i = 1; i < 15; i += 2) {
+        const R d = phs[i] - phs[i + 1];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            if (e15(i, k) > 0) acc[k] += wgt<15, R>(i) * d;
+            if (e15(i, k) < 0) acc[k] -= wgt<15, R>(i) * d;
+        }
+    }
+    R grad[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) grad[k] = by_cs2(acc[k]);
     const R gn = sqrt(grad[0] * grad[0] + grad[1] * grad[1] + grad[2] * grad[2]);
     R nrm[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) nrm[k] = grad[k] / (gn + a.ph.normal_eps);
-    const R dp = a.phi_in[c] - a.ph.phi_0;
+    const R dp = phs[0] - a.ph.phi_0;
     const R theta = (R(1) - R(4) * dp * dp) / a.ph.xi;
 
     const R ux = a.u[c], uy = a.u[a.g.fplane + c], uz = a.u[2 * a.g.fplane + c];
     const R uu = ux * ux + uy * uy + uz * uz;
     const R om = a.ph.omega_phi;
+    R hs[15];
 #pragma unroll
     for (int i = 0; i < 15; ++i) {
         const R en = R(e15(i, 0)) * nrm[0] + R(e15(i, 1)) * nrm[1] + R(e15(i, 2)) * nrm[2];
         const R F = theta * wgt<15, R>(i) * en;
         const R heq = phi * gamma_i<15, R>(i, ux, uy, uz, uu);
-        const R h = Pi[i] + om * (heq - Pi[i] - R(0.5) * F) + F;
-        st_stream(a.dst + pidx<15>(i, c), S::st(h, a.ph.shift_h * wgt<15, R>(i)));
+        hs[i] = Pi[i] + om * (heq - Pi[i] - R(0.5) * F) + F;
+    }
+    if constexpr (std::is_same<R, double>::value) {
+#pragma unroll
+        for (int i = 0; i < 15; ++i) st_stream(a.dst + pidx<15>(i, c), enc_h<S>(hs[i], phi, i));
+    } else {
+        // The collision conserves phi exactly; in FP32 the rounded weights do
+        // not sum to one and 16-bit storage rounds every population, which
+        // would bias sum(phi) every step.  Close the budget on the rest
+        // population, using the values the next sweep will decode.
+        double rest = phi_acc;
+#pragma unroll
+        for (int i = 1; i < 15; ++i) {
+            const typename S::pdf_t v = enc_h<S>(hs[i], phi, i);
+            rest -= dec_h64<S>(v, phi, i);
+            st_stream(a.dst + pidx<15>(i, c), v);
+        }
+        st_stream(a.dst + pidx<15>(0, c), enc_h64<S>(rest, phi, 0));
     }
 }
 
@@ -304,7 +350,7 @@ __global__ __launch_bounds__(kBlock) void k_hydro(const SweepArgs<S> a)
     R Pxx = R(0), Pyy = R(0), Pzz = R(0), Pxy = R(0), Pxz = R(0), Pyz = R(0);
 #pragma unroll
     for (int i = 0; i < 27; ++i) {
-        const R gi = S::ld(ld_stream(a.src + pull_idx<27>(i, c, n)), R(0));
+        const R gi = dec_g<S>(ld_stream(a.src + pull_idx<27>(i, c, n)), i);
         const int ex = e27(i, 0), ey = e27(i, 1), ez = e27(i, 2);
         ps += gi;
         if (ex) j[0] += ex > 0 ? gi : -gi;
@@ -338,13 +384,14 @@ __global__ __launch_bounds__(kBlock) void k_hydro(const SweepArgs<S> a)
     const R Axx = Pxx - ps * c2 - uox * uox, Ayy = Pyy - ps * c2 - uoy * uoy, Azz = Pzz - ps * c2 - uoz * uoz;
     const R Axy = Pxy - uox * uoy, Axz = Pxz - uox * uoz, Ayz = Pyz - uoy * uoz;
     const R vf = -nu / c2 * s;
+    const R rb = rho - ph.rho_ref;
     R F[3];
     F[0] = -ps * c2 * grho[0] + mu * grad[0] + vf * (Axx * grho[0] + Axy * grho[1] + Axz * grho[2]) +
-           rho * ph.accel[0];
+           rb * ph.accel[0];
     F[1] = -ps * c2 * grho[1] + mu * grad[1] + vf * (Axy * grho[0] + Ayy * grho[1] + Ayz * grho[2]) +
-           rho * ph.accel[1];
+           rb * ph.accel[1];
     F[2] = -ps * c2 * grho[2] + mu * grad[2] + vf * (Axz * grho[0] + Ayz * grho[1] + Azz * grho[2]) +
-           rho * ph.accel[2];
+           rb * ph.accel[2];
 
     const R ux = j[0] + F[0] / (R(2) * rho), uy = j[1] + F[1] / (R(2) * rho), uz = j[2] + F[2] / (R(2) * rho);
     st_field(a.u + c, ux);
@@ -367,7 +414,7 @@ __global__ __launch_bounds__(kBlock) void k_hydro(const SweepArgs<S> a)
         const R eBe = R(ex * ex) * Bxx + R(ey * ey) * Byy + R(ez * ez) * Bzz +
                       R(2 * ex * ey) * Bxy + R(2 * ex * ez) * Bxz + R(2 * ey * ez) * Byz - c2 * trB;
         const R gs = geq + R(0.5) * w * eF * finv + neq * w * eBe;
-        st_stream(a.dst + pidx<27>(i, c), S::st(gs, R(0)));
+        st_stream(a.dst + pidx<27>(i, c), enc_g<S>(gs, i));
     }
 }
 
@@ -402,12 +449,12 @@ __global__ __launch_bounds__(kBlock) void k_equilibrium(typename S::pdf_t *__res
 #pragma unroll
     for (int i = 0; i < 15; ++i) {
         const R h = wall ? R(0) : phi * gamma_i<15, R>(i, ux, uy, uz, uu);
-        H[pidx<15>(i, c)] = S::st(h, wall ? R(0) : ph.shift_h * wgt<15, R>(i));
+        H[pidx<15>(i, c)] = enc_h<S>(h, phi, i);
     }
 #pragma unroll
     for (int i = 0; i < 27; ++i) {
         const R ge = wall ? R(0) : geq_i<R>(i, ps, ux, uy, uz, uu);
-        Gc[pidx<27>(i, c)] = S::st(ge, R(0));
+        Gc[pidx<27>(i, c)] = enc_g<S>(ge, i);
     }
     phiA[c] = phi;
     u[c] = ux;
@@ -441,6 +488,7 @@ __global__ __launch_bounds__(kBlock) void k_unpull27(const typename S::pdf_t *__
 template <class S>
 __global__ __launch_bounds__(kBlock) void k_get_pdfs(const typename S::pdf_t *__restrict__ H,
                                                      const typename S::pdf_t *__restrict__ G,
+                                                     const typename S::real *__restrict__ phiA,
                                                      double *__restrict__ Ho, double *__restrict__ Go,
                                                      Grid g, Phys<typename S::real> ph)
 {
@@ -454,11 +502,11 @@ __global__ __launch_bounds__(kBlock) void k_get_pdfs(const typename S::pdf_t *__
     if (Ho)
 #pragma unroll
         for (int i = 0; i < 15; ++i)
-            Ho[i * N + c] = fluid ? (double)S::ld(H[pidx<15>(i, c)], ph.shift_h * wgt<15, R>(i)) : 0.0;
+            Ho[i * N + c] = fluid ? (double)dec_h<S>(H[pidx<15>(i, c)], phiA[c], i) : 0.0;
     if (Go)
 #pragma unroll
         for (int i = 0; i < 27; ++i)
-            Go[i * N + c] = fluid ? (double)S::ld(G[pull_idx<27>(i, c, n)], R(0)) : 0.0;
+            Go[i * N + c] = fluid ? (double)dec_g<S>(G[pull_idx<27>(i, c, n)], i) : 0.0;
 }
 
 // Storage from canonical FP64 planes: H stored directly, G (pre-collision)
@@ -482,11 +530,10 @@ __global__ __launch_bounds__(kBlock) void k_set_pdfs(typename S::pdf_t *__restri
     const int64_t N = g.ncells;
 #pragma unroll
     for (int i = 0; i < 15; ++i) {
-        const R sh = wall ? R(0) : ph.shift_h * wgt<15, R>(i);
-        H[pidx<15>(i, c)] = S::st(wall ? R(0) : R(Hi[i * N + c]), sh);
+        H[pidx<15>(i, c)] = enc_h<S>(wall ? R(0) : R(Hi[i * N + c]), wall ? R(0) : R(phi_i[c]), i);
     }
 #pragma unroll
-    for (int i = 0; i < 27; ++i) Gc[pidx<27>(i, c)] = S::st(wall ? R(0) : R(Gi[i * N + c]), R(0));
+    for (int i = 0; i < 27; ++i) Gc[pidx<27>(i, c)] = enc_g<S>(wall ? R(0) : R(Gi[i * N + c]), i);
     phiA[c] = wall ? R(0) : R(phi_i[c]);
     for (int k = 0; k < 3; ++k) u[k * g.fplane + c] = wall ? R(0) : R(u_i[k * N + c]);
 }
@@ -513,7 +560,7 @@ __global__ __launch_bounds__(kBlock) void k_get_macro(const typename S::pdf_t *_
         R ps = R(0);
         if (fluid)
 #pragma unroll
-            for (int i = 0; i < 27; ++i) ps += S::ld(G[pull_idx<27>(i, c, n)], R(0));
+            for (int i = 0; i < 27; ++i) ps += dec_g<S>(G[pull_idx<27>(i, c, n)], i);
         const R rho = ph.rho_L + (phiA[c] - ph.phi_L) * ph.drho * ph.inv_dphi;
         p_o[c] = fluid ? Out(ps * rho * cs2<R>()) : Out(0);
     }

@@ -12,6 +12,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace lbm {
 
 __host__ __device__ constexpr int e15(int i, int a)
@@ -64,39 +66,101 @@ __host__ __device__ constexpr R wgt(int i)
 
 // ---- storage codecs ---------------------------------------------------------
 // pdf_t: element type of the PDF planes; real: arithmetic type of the sweeps
-// (also the type of the phi and u fields).  Low-precision codecs hold a
-// shifted population s = f - shift, rounded to nearest even on store.
+// (also the type of the phi and u fields).  The 16-bit codecs (lowp) do not
+// store the populations themselves but small numbers of order u:
+//   phase field:  h_i - phi(cell) w_i   (decoded with the phi of the cell the
+//                 population was stored at, which the stencil loads anyway)
+//   hydrodynamic: g_i / w_i            (1/w_i is exact in binary)
+// FP16 values are further scaled by 2^10 (exact) so that deviations down to
+// ~1e-8 stay in the normal range of the format instead of its subnormals,
+// whose coarse spacing would round the small same-signed bulk deviations
+// with a bias.  BF16 has the exponent range of FP32 and needs no scaling.
+// Rounding is to nearest even.
 struct StoreF64 {
     using pdf_t = double;
     using real = double;
-    static constexpr int id = 0;
-    __device__ static real ld(pdf_t v, real shift) { return v; }
-    __device__ static pdf_t st(real v, real shift) { return v; }
+    static constexpr bool lowp = false;
+    __device__ static real ld(pdf_t v) { return v; }
+    __device__ static pdf_t st(real v) { return v; }
 };
 
 struct StoreF32 {
     using pdf_t = float;
     using real = float;
-    static constexpr int id = 1;
-    __device__ static real ld(pdf_t v, real shift) { return v; }
-    __device__ static pdf_t st(real v, real shift) { return v; }
+    static constexpr bool lowp = false;
+    __device__ static real ld(pdf_t v) { return v; }
+    __device__ static pdf_t st(real v) { return v; }
 };
 
 struct StoreF16S {
     using pdf_t = __half;
     using real = float;
-    static constexpr int id = 2;
-    __device__ static real ld(pdf_t v, real shift) { return __half2float(v) + shift; }
-    __device__ static pdf_t st(real v, real shift) { return __float2half_rn(v - shift); }
+    static constexpr bool lowp = true;
+    __device__ static real ld(pdf_t v) { return __half2float(v) * 0x1p-10f; }
+    __device__ static pdf_t st(real v) { return __float2half_rn(v * 0x1p10f); }
 };
 
 struct StoreBF16S {
     using pdf_t = __hip_bfloat16;
     using real = float;
-    static constexpr int id = 3;
-    __device__ static real ld(pdf_t v, real shift) { return __bfloat162float(v) + shift; }
-    __device__ static pdf_t st(real v, real shift) { return __float2bfloat16(v - shift); }
+    static constexpr bool lowp = true;
+    __device__ static real ld(pdf_t v) { return __bfloat162float(v); }
+    __device__ static pdf_t st(real v) { return __float2bfloat16(v); }
 };
+
+// 1/w_i of D3Q27 (all exact in binary): 27/8, 27/2, 54, 216.
+template <class R>
+__host__ __device__ constexpr R inv_w27(int i)
+{
+    return l1<27>(i) == 0 ? R(3.375) : l1<27>(i) == 1 ? R(13.5) : l1<27>(i) == 2 ? R(54) : R(216);
+}
+
+// Phase-field population i stored at a cell whose phase field is phi_cell.
+template <class S>
+__device__ inline typename S::pdf_t enc_h(typename S::real h, typename S::real phi_cell, int i)
+{
+    using R = typename S::real;
+    if constexpr (S::lowp) return S::st(h - phi_cell * wgt<15, R>(i));
+    else return S::st(h);
+}
+template <class S>
+__device__ inline typename S::real dec_h(typename S::pdf_t v, typename S::real phi_cell, int i)
+{
+    using R = typename S::real;
+    if constexpr (S::lowp) return S::ld(v) + phi_cell * wgt<15, R>(i);
+    else return S::ld(v);
+}
+// Mass-budget forms of the phase-field codec for the FP32 and 16-bit paths:
+// the decoded value in FP64 (the same operations wherever a population is
+// decoded, so both sides of a sweep see identical numbers) and the encoding
+// of an FP64 value with a single rounding to the storage type.
+template <class S>
+__device__ inline double dec_h64(typename S::pdf_t v, typename S::real phi_cell, int i)
+{
+    if constexpr (S::lowp) return double(S::ld(v)) + double(phi_cell) * wgt<15, double>(i);
+    else return double(S::ld(v));
+}
+template <class S>
+__device__ inline typename S::pdf_t enc_h64(double h, typename S::real phi_cell, int i)
+{
+    using R = typename S::real;
+    if constexpr (S::lowp) return S::st(R(h - double(phi_cell) * wgt<15, double>(i)));
+    else return S::st(R(h));
+}
+template <class S>
+__device__ inline typename S::pdf_t enc_g(typename S::real g, int i)
+{
+    using R = typename S::real;
+    if constexpr (S::lowp) return S::st(g * inv_w27<R>(i));
+    else return S::st(g);
+}
+template <class S>
+__device__ inline typename S::real dec_g(typename S::pdf_t v, int i)
+{
+    using R = typename S::real;
+    if constexpr (S::lowp) return S::ld(v) / inv_w27<R>(i);
+    else return S::ld(v);
+}
 
 // ---- streaming memory access ---------------------------------------------------
 // PDFs are touched once per sweep; LBM_NT_LOAD / LBM_NT_STORE mark those

@@ -1,0 +1,804 @@
+// Surrogate-network kernels for gfx950 (C ABI in include/sg.h).
+//
+// The 3x3x3 convolution is an implicit GEMM: rows are output voxels, columns
+// output channels, the reduction runs over the 27 taps times the input
+// channels.  Each wavefront owns 32 consecutive voxels and NT x 32 output
+// channels and issues v_mfma_f32_32x32x16_bf16: lane l supplies 8 BF16
+// values of row l % 32 (the voxel, shifted by the tap) at channels
+// 8 * (l / 32) .. +7 of a 16-channel slice, and 8 BF16 weights of column
+// l % 32 at the same channels.  Channels-last activations and weights stored
+// as [tap][c_out][c_in] make both operands single 16-byte loads; zero
+// padding is a predicated load.  Accumulation is FP32; the epilogue adds the
+// bias, applies the activation and rounds to BF16 (or stores FP32).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+
+#include "sg.h"
+
+namespace {
+
+typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
+typedef __attribute__((ext_vector_type(16))) float f32x16;
+typedef __bf16 bf16;
+
+thread_local char g_err[512] = "";
+
+sg_status fail(sg_status s, const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return s;
+}
+
+#define SG_LAUNCH_CHECK()                                                                            \
+    do {                                                                                             \
+        hipError_t e_ = hipGetLastError();                                                           \
+        if (e_ != hipSuccess) return fail(SG_EHIP, "kernel launch failed: %s", hipGetErrorString(e_)); \
+    } while (0)
+
+constexpr int kThreads = 256;
+constexpr int kRowsPerBlock = 128;  // 4 waves x 32 voxels
+
+__device__ inline float leaky(float v, float slope) { return v > 0.f ? v : slope * v; }
+
+// ---- convolution forward -------------------------------------------------------
+template <int NT>
+__global__ __launch_bounds__(kThreads) void k_conv3d(const bf16 *__restrict__ x, const bf16 *__restrict__ wt,
+                                                     const float *__restrict__ bias, void *__restrict__ y,
+                                                     int N, int D, int H, int W, int Ci, int Co, int n_store,
+                                                     int act, float slope, int y_f32)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t V = (int64_t)N * D * H * W;
+    const int64_t m0 = (int64_t)blockIdx.x * kRowsPerBlock + wave * 32;
+    const int col0 = blockIdx.y * NT * 32;  // first output channel of this block
+    const int64_t mv = m0 + (lane & 31);
+    const bool valid = mv < V;
+    int w = 0, h = 0, d = 0, n = 0;
+    if (valid) {
+        int64_t t = mv;
+        w = (int)(t % W);
+        t /= W;
+        h = (int)(t % H);
+        t /= H;
+        d = (int)(t % D);
+        n = (int)(t / D);
+    }
+    const int kh = (lane >> 5) * 8;
+    f32x16 acc[NT];
+#pragma unroll
+    for (int j = 0; j < NT; ++j)
+        for (int r = 0; r < 16; ++r) acc[j][r] = 0.f;
+    const bf16x8 zero = {};
+
+    for (int t = 0; t < 27; ++t) {
+        const int a = t / 9 - 1, b = (t / 3) % 3 - 1, c = t % 3 - 1;
+        const int dd = d + a, hh = h + b, ww = w + c;
+        const bool in = valid && dd >= 0 && dd < D && hh >= 0 && hh < H && ww >= 0 && ww < W;
+        const int64_t src = in ? ((((int64_t)n * D + dd) * H + hh) * W + ww) : 0;
+        const bf16 *xp = x + src * Ci + kh;
+        const bf16 *wp = wt + ((int64_t)t * Co + col0 + (lane & 31)) * Ci + kh;
+        for (int c0 = 0; c0 < Ci; c0 += 16) {
+            const bf16x8 av = in ? *reinterpret_cast<const bf16x8 *>(xp + c0) : zero;
+#pragma unroll
+            for (int j = 0; j < NT; ++j) {
+                const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(wp + (int64_t)j * 32 * Ci + c0);
+                acc[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc[j], 0, 0, 0);
+            }
+        }
+    }
+    // D layout of the 32x32 tile: column l % 32, row 8 (r/4) + 4 (l/32) + r % 4
+#pragma unroll
+    for (int j = 0; j < NT; ++j) {
+        const int col = col0 + j * 32 + (lane & 31);
+        if (col >= n_store) continue;
+        const float bc = bias ? bias[col] : 0.f;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int row = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+            const int64_t m = m0 + row;
+            if (m >= V) continue;
+            float v = acc[j][r] + bc;
+            if (act) v = leaky(v, slope);
+            if (y_f32)
+                reinterpret_cast<float *>(y)[m * n_store + col] = v;
+            else
+                reinterpret_cast<bf16 *>(y)[m * n_store + col] = (bf16)v;
+        }
+    }
+}
+
+__global__ void k_weight_mirror(const bf16 *__restrict__ wt, int Co, int Ci, bf16 *__restrict__ wm)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t total = (int64_t)27 * Co * Ci;
+    if (i >= total) return;
+    const int ci = (int)(i % Ci);
+    const int co = (int)((i / Ci) % Co);
+    const int t = (int)(i / ((int64_t)Ci * Co));
+    wm[((int64_t)(26 - t) * Ci + ci) * Co + co] = wt[i];
+}
+
+// ---- convolution weight gradient ------------------------------------------------
+// dw[t][co][ci] = sum_v dy[v][co] x[v + off(t)][ci].  A GEMM per tap with the
+// voxels as the reduction: rows co, columns ci.  Grid (chunk, tap, tile):
+// each block computes one 32x32 (co, ci) tile of one tap over one chunk of
+// voxels, its 4 waves splitting the chunk; the waves' sums are combined in
+// LDS and the block partial goes to partial[chunk][t][co][ci], summed over
+// chunks in a fixed order by k_reduce_partials.
+constexpr int kBwChunk = 16384;  // voxels per block
+
+__global__ __launch_bounds__(kThreads) void k_conv3d_bwd_weight(const bf16 *__restrict__ x,
+                                                                const bf16 *__restrict__ dy, int N, int D,
+                                                                int H, int W, int Ci, int Co,
+                                                                float *__restrict__ partial)
+{
+    __shared__ float red[4][32][33];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t V = (int64_t)N * D * H * W;
+    const int chunk = blockIdx.x, t = blockIdx.y;
+    const int ntc = (Ci + 31) / 32;
+    const int co0 = (blockIdx.z / ntc) * 32, ci0 = (blockIdx.z % ntc) * 32;
+    const bool ci_ok = ci0 + (lane & 31) < Ci;  // a 16-channel input fills half a tile
+    const int a = t / 9 - 1, b = (t / 3) % 3 - 1, c = t % 3 - 1;
+    f32x16 acc;
+    for (int r = 0; r < 16; ++r) acc[r] = 0.f;
+    const int64_t vbeg = (int64_t)chunk * kBwChunk;
+    const int64_t vend = vbeg + kBwChunk < V ? vbeg + kBwChunk : V;
+    const int kh = (lane >> 5) * 8;
+    // each wave walks 16-voxel K slices: wave w takes slices w, w+4, ...
+    for (int64_t k0 = vbeg + wave * 16; k0 < vend; k0 += 64) {
+        bf16x8 av, bv;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int64_t v = k0 + kh + e;
+            bf16 dval = (bf16)0.f, xval = (bf16)0.f;
+            if (v < vend) {
+                dval = dy[v * Co + co0 + (lane & 31)];
+                int64_t q = v;
+                const int ww = (int)(q % W);
+                q /= W;
+                const int hh = (int)(q % H);
+                q /= H;
+                const int dd = (int)(q % D);
+                const int nn = (int)(q / D);
+                const int d2 = dd + a, h2 = hh + b, w2 = ww + c;
+                if (ci_ok && d2 >= 0 && d2 < D && h2 >= 0 && h2 < H && w2 >= 0 && w2 < W)
+                    xval = x[((((int64_t)nn * D + d2) * H + h2) * W + w2) * Ci + ci0 + (lane & 31)];
+            }
+            av[e] = dval;
+            bv[e] = xval;
+        }
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int row = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        red[wave][row][lane & 31] = acc[r];
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < 32 * 32; i += kThreads) {
+        const int row = i / 32, col = i % 32;
+        if (ci0 + col >= Ci) continue;
+        const float s = (red[0][row][col] + red[1][row][col]) + (red[2][row][col] + red[3][row][col]);
+        partial[(((int64_t)chunk * 27 + t) * Co + co0 + row) * Ci + ci0 + col] = s;
+    }
+}
+
+__global__ void k_reduce_partials(const float *__restrict__ partial, int nchunk, int64_t stride,
+                                  float *__restrict__ out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= stride) return;
+    float s = 0.f;
+    for (int k = 0; k < nchunk; ++k) s += partial[(int64_t)k * stride + i];
+    out[i] = s;
+}
+
+// db[co] = sum_v dy[v][co]: one block per 32 channels x chunk, fixed order
+__global__ __launch_bounds__(kThreads) void k_bias_grad_partial(const bf16 *__restrict__ dy, int64_t V, int Co,
+                                                                float *__restrict__ partial)
+{
+    __shared__ float s[kThreads];
+    const int chunk = blockIdx.x;
+    const int co = blockIdx.y;
+    const int64_t vbeg = (int64_t)chunk * kBwChunk;
+    const int64_t vend = vbeg + kBwChunk < V ? vbeg + kBwChunk : V;
+    float acc = 0.f;
+    for (int64_t v = vbeg + threadIdx.x; v < vend; v += kThreads) acc += (float)dy[v * Co + co];
+    s[threadIdx.x] = acc;
+    __syncthreads();
+    for (int k = kThreads / 2; k > 0; k >>= 1) {
+        if (threadIdx.x < k) s[threadIdx.x] += s[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[(int64_t)chunk * Co + co] = s[0];
+}
+
+// ---- elementwise and resampling ----------------------------------------------------
+__global__ void k_leaky_bwd(const bf16 *__restrict__ y, const bf16 *__restrict__ dy, bf16 *__restrict__ dp,
+                            int64_t count, float slope)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    const float g = (float)dy[i];
+    dp[i] = (bf16)((float)y[i] > 0.f ? g : slope * g);
+}
+
+__global__ void k_pool2_fwd(const bf16 *__restrict__ x, int N, int D, int H, int W, int C, bf16 *__restrict__ y)
+{
+    const int D2 = D / 2, H2 = H / 2, W2 = W / 2;
+    const int64_t total = (int64_t)N * D2 * H2 * W2 * C;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= total) return;
+    const int c = (int)(i % C);
+    int64_t v = i / C;
+    const int w = (int)(v % W2);
+    v /= W2;
+    const int h = (int)(v % H2);
+    v /= H2;
+    const int d = (int)(v % D2);
+    const int n = (int)(v / D2);
+    float s = 0.f;
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b)
+            for (int e = 0; e < 2; ++e)
+                s += (float)x[((((int64_t)n * D + 2 * d + a) * H + 2 * h + b) * W + 2 * w + e) * C + c];
+    y[i] = (bf16)(s * 0.125f);
+}
+
+// dx[fine] = dy[coarse] / 8 (D, H, W of the fine tensor)
+__global__ void k_pool2_bwd(const bf16 *__restrict__ dy, int N, int D, int H, int W, int C, bf16 *__restrict__ dx)
+{
+    const int64_t total = (int64_t)N * D * H * W * C;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= total) return;
+    const int c = (int)(i % C);
+    int64_t v = i / C;
+    const int w = (int)(v % W);
+    v /= W;
+    const int h = (int)(v % H);
+    v /= H;
+    const int d = (int)(v % D);
+    const int n = (int)(v / D);
+    const int D2 = D / 2, H2 = H / 2, W2 = W / 2;
+    dx[i] = (bf16)((float)dy[((((int64_t)n * D2 + d / 2) * H2 + h / 2) * W2 + w / 2) * C + c] * 0.125f);
+}
+
+// y[fine] = x[coarse] (D, H, W of the coarse tensor)
+__global__ void k_up2_fwd(const bf16 *__restrict__ x, int N, int D, int H, int W, int C, bf16 *__restrict__ y)
+{
+    const int D2 = 2 * D, H2 = 2 * H, W2 = 2 * W;
+    const int64_t total = (int64_t)N * D2 * H2 * W2 * C;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= total) return;
+    const int c = (int)(i % C);
+    int64_t v = i / C;
+    const int w = (int)(v % W2);
+    v /= W2;
+    const int h = (int)(v % H2);
+    v /= H2;
+    const int d = (int)(v % D2);
+    const int n = (int)(v / D2);
+    y[i] = x[((((int64_t)n * D + d / 2) * H + h / 2) * W + w / 2) * C + c];
+}
+
+// dx[coarse] = sum of the 8 fine dy (D, H, W of the coarse tensor)
+__global__ void k_up2_bwd(const bf16 *__restrict__ dy, int N, int D, int H, int W, int C, bf16 *__restrict__ dx)
+{
+    const int64_t total = (int64_t)N * D * H * W * C;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= total) return;
+    const int c = (int)(i % C);
+    int64_t v = i / C;
+    const int w = (int)(v % W);
+    v /= W;
+    const int h = (int)(v % H);
+    v /= H;
+    const int d = (int)(v % D);
+    const int n = (int)(v / D);
+    const int D2 = 2 * D, H2 = 2 * H, W2 = 2 * W;
+    float s = 0.f;
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b)
+            for (int e = 0; e < 2; ++e)
+                s += (float)dy[((((int64_t)n * D2 + 2 * d + a) * H2 + 2 * h + b) * W2 + 2 * w + e) * C + c];
+    dx[i] = (bf16)s;
+}
+
+__global__ void k_concat(const bf16 *__restrict__ a, int ca, const bf16 *__restrict__ b, int cb, int64_t V,
+                         bf16 *__restrict__ y)
+{
+    const int cc = ca + cb;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= V * cc) return;
+    const int64_t v = i / cc;
+    const int c = (int)(i % cc);
+    y[i] = c < ca ? a[v * ca + c] : b[v * cb + (c - ca)];
+}
+
+__global__ void k_split(const bf16 *__restrict__ y, int ca, int cb, int64_t V, bf16 *__restrict__ a,
+                        bf16 *__restrict__ b)
+{
+    const int cc = ca + cb;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= V * cc) return;
+    const int64_t v = i / cc;
+    const int c = (int)(i % cc);
+    if (c < ca) {
+        if (a) a[v * ca + c] = y[i];
+    } else {
+        if (b) b[v * cb + (c - ca)] = y[i];
+    }
+}
+
+// MSE: per-block partial sums (fixed order), second pass sums them
+constexpr int kMseBlocks = 1024;
+__global__ __launch_bounds__(kThreads) void k_mse1(const float *__restrict__ p, const float *__restrict__ t,
+                                                   int64_t count, bf16 *__restrict__ g, float *__restrict__ part)
+{
+    __shared__ float s[kThreads];
+    float acc = 0.f;
+    const float scale = 2.0f / (float)count;
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < count; i += (int64_t)kMseBlocks * kThreads) {
+        const float d = p[i] - t[i];
+        acc += d * d;
+        g[i] = (bf16)(scale * d);
+    }
+    s[threadIdx.x] = acc;
+    __syncthreads();
+    for (int k = kThreads / 2; k > 0; k >>= 1) {
+        if (threadIdx.x < k) s[threadIdx.x] += s[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = s[0];
+}
+
+__global__ __launch_bounds__(kThreads) void k_mse2(const float *__restrict__ part, int64_t count,
+                                                   float *__restrict__ loss)
+{
+    __shared__ float s[kThreads];
+    float acc = 0.f;
+    for (int i = threadIdx.x; i < kMseBlocks; i += kThreads) acc += part[i];
+    s[threadIdx.x] = acc;
+    __syncthreads();
+    for (int k = kThreads / 2; k > 0; k >>= 1) {
+        if (threadIdx.x < k) s[threadIdx.x] += s[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) loss[0] = s[0] / (float)count;
+}
+
+__global__ void k_adam(float *__restrict__ p, const float *__restrict__ g, float *__restrict__ m,
+                       float *__restrict__ v, bf16 *__restrict__ wt, int64_t count, float lr, float b1, float b2,
+                       float eps, float c1, float c2)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    const float pi = p[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    p[i] = pi;
+    if (wt) wt[i] = (bf16)pi;
+}
+
+__global__ void k_to_bf16(const float *__restrict__ x, bf16 *__restrict__ y, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = (bf16)x[i];
+}
+
+__global__ void k_to_f32(const bf16 *__restrict__ x, float *__restrict__ y, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = (float)x[i];
+}
+
+__global__ void k_add(const bf16 *__restrict__ a, const bf16 *__restrict__ b, bf16 *__restrict__ y, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = (bf16)((float)a[i] + (float)b[i]);
+}
+
+struct Box {
+    int x0, y0, z0, bx, by, bz;
+};
+
+__device__ inline int64_t box_cell(const Box &b, int64_t v, int nx, int ny, int nz, int &yy)
+{
+    const int x = (int)(v % b.bx);
+    const int64_t t = v / b.bx;
+    const int y = (int)(t % b.by);
+    const int z = (int)(t / b.by);
+    const int gx = ((b.x0 + x) % nx + nx) % nx;
+    const int gz = ((b.z0 + z) % nz + nz) % nz;
+    yy = b.y0 + y;
+    return (int64_t)gx + (int64_t)nx * ((int64_t)yy + (int64_t)ny * gz);
+}
+
+__global__ void k_fields_to_input(const float *__restrict__ phi, const float *__restrict__ u,
+                                  const float *__restrict__ p, int nx, int ny, int nz, Box b, float s0, float s1,
+                                  float s2, float s3, float s4, int c_in, bf16 *__restrict__ x,
+                                  float *__restrict__ state)
+{
+    const int64_t V = (int64_t)b.bx * b.by * b.bz;
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= V) return;
+    int yy;
+    const int64_t c = box_cell(b, v, nx, ny, nz, yy);
+    const int64_t N = (int64_t)nx * ny * nz;
+    const float f[5] = {phi[c], u[c], u[N + c], u[2 * N + c], p[c]};
+    const float sc[5] = {s0, s1, s2, s3, s4};
+    for (int k = 0; k < c_in; ++k) x[v * c_in + k] = (bf16)(k < 5 ? f[k] / sc[k] : 0.f);
+    if (state)
+        for (int k = 0; k < 5; ++k) state[v * 5 + k] = f[k];
+}
+
+__global__ void k_state_to_input(const float *__restrict__ s, int64_t V, float q0, float q1, float q2, float q3,
+                                 float q4, int c_in, bf16 *__restrict__ x)
+{
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= V) return;
+    const float sc[5] = {q0, q1, q2, q3, q4};
+    for (int k = 0; k < c_in; ++k) x[v * c_in + k] = (bf16)(k < 5 ? s[v * 5 + k] / sc[k] : 0.f);
+}
+
+__global__ void k_make_target(const float *__restrict__ s0, const float *__restrict__ s1, int64_t V, float q0,
+                              float q1, float q2, float q3, float q4, int c_out, float *__restrict__ t)
+{
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= V) return;
+    const float sc[5] = {q0, q1, q2, q3, q4};
+    for (int k = 0; k < c_out; ++k) t[v * c_out + k] = k < 5 ? (s1[v * 5 + k] - s0[v * 5 + k]) / sc[k] : 0.f;
+}
+
+__global__ void k_apply_prediction(const float *__restrict__ out, int c_out, float q0, float q1, float q2,
+                                   float q3, float q4, float *__restrict__ phi, float *__restrict__ u,
+                                   float *__restrict__ p, int nx, int ny, int nz, Box b, int walls, float pmin,
+                                   float pmax)
+{
+    const int64_t V = (int64_t)b.bx * b.by * b.bz;
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= V) return;
+    int yy;
+    const int64_t c = box_cell(b, v, nx, ny, nz, yy);
+    if (walls && (yy == 0 || yy == ny - 1)) return;
+    const int64_t N = (int64_t)nx * ny * nz;
+    const float *o = out + v * c_out;
+    const float f = phi[c] + o[0] * q0;
+    phi[c] = fminf(fmaxf(f, pmin), pmax);
+    u[c] += o[1] * q1;
+    u[N + c] += o[2] * q2;
+    u[2 * N + c] += o[3] * q3;
+    p[c] += o[4] * q4;
+}
+
+constexpr int kProjBlocks = 1024;
+__global__ __launch_bounds__(kThreads) void k_mass_sums(const float *__restrict__ phi, int64_t n, float pmin,
+                                                        float pmax, double *__restrict__ part)
+{
+    __shared__ double s0[kThreads], s1[kThreads];
+    double a = 0.0, w = 0.0;
+    const double inv = 1.0 / ((double)pmax - (double)pmin);
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)kProjBlocks * kThreads) {
+        const double f = phi[i];
+        const double q = (f - pmin) * inv;
+        a += f;
+        w += 4.0 * q * (1.0 - q);
+    }
+    s0[threadIdx.x] = a;
+    s1[threadIdx.x] = w;
+    __syncthreads();
+    for (int k = kThreads / 2; k > 0; k >>= 1) {
+        if (threadIdx.x < k) {
+            s0[threadIdx.x] += s0[threadIdx.x + k];
+            s1[threadIdx.x] += s1[threadIdx.x + k];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = s0[0];
+        part[2 * blockIdx.x + 1] = s1[0];
+    }
+}
+
+// sums the block partials in a fixed order (one thread), then corrects phi
+__global__ void k_mass_correct(float *__restrict__ phi, int64_t n, const double *__restrict__ part,
+                               double target, float pmin, float pmax)
+{
+    __shared__ double coef;
+    if (threadIdx.x == 0) {
+        double a = 0.0, w = 0.0;
+        for (int k = 0; k < kProjBlocks; ++k) {
+            a += part[2 * k];
+            w += part[2 * k + 1];
+        }
+        coef = w > 0.0 ? (target - a) / w : 0.0;
+    }
+    __syncthreads();
+    const double inv = 1.0 / ((double)pmax - (double)pmin);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const double f = phi[i];
+        const double q = (f - pmin) * inv;
+        phi[i] = (float)(f + coef * 4.0 * q * (1.0 - q));
+    }
+}
+
+unsigned blocks_for(int64_t n) { return (unsigned)((n + kThreads - 1) / kThreads); }
+
+bool aligned16(const void *p) { return ((uintptr_t)p & 15) == 0; }
+
+}  // namespace
+
+extern "C" {
+
+sg_status sg_conv3d_fwd(const void *x, int32_t n, int32_t d, int32_t h, int32_t w, int32_t c_in,
+                        const void *wt, const float *bias, int32_t c_out, int32_t n_store, int32_t act,
+                        float slope, void *y, int32_t y_f32, void *stream)
+{
+    if (!x || !wt || !y) return fail(SG_EARG, "NULL tensor");
+    if (n < 1 || d < 1 || h < 1 || w < 1) return fail(SG_EARG, "bad shape");
+    if (c_in < 16 || c_in % 16) return fail(SG_EARG, "c_in must be a positive multiple of 16 (got %d)", c_in);
+    if (c_out < 32 || c_out % 32) return fail(SG_EARG, "c_out must be a positive multiple of 32 (got %d)", c_out);
+    if (n_store < 1 || n_store > c_out) return fail(SG_EARG, "n_store must be in [1, c_out]");
+    if (!aligned16(x) || !aligned16(wt)) return fail(SG_EARG, "x and wt must be 16-byte aligned");
+    const int64_t V = (int64_t)n * d * h * w;
+    const int tiles = c_out / 32;
+    const int nt = tiles % 4 == 0 ? 4 : tiles % 3 == 0 ? 3 : tiles % 2 == 0 ? 2 : 1;
+    const dim3 grid((unsigned)((V + kRowsPerBlock - 1) / kRowsPerBlock), (unsigned)(tiles / nt));
+    hipStream_t s = (hipStream_t)stream;
+    const bf16 *X = (const bf16 *)x, *Wt = (const bf16 *)wt;
+    switch (nt) {
+    case 4: hipLaunchKernelGGL(k_conv3d<4>, grid, dim3(kThreads), 0, s, X, Wt, bias, y, n, d, h, w, c_in, c_out, n_store, act, slope, y_f32); break;
+    case 3: hipLaunchKernelGGL(k_conv3d<3>, grid, dim3(kThreads), 0, s, X, Wt, bias, y, n, d, h, w, c_in, c_out, n_store, act, slope, y_f32); break;
+    case 2: hipLaunchKernelGGL(k_conv3d<2>, grid, dim3(kThreads), 0, s, X, Wt, bias, y, n, d, h, w, c_in, c_out, n_store, act, slope, y_f32); break;
+    default: hipLaunchKernelGGL(k_conv3d<1>, grid, dim3(kThreads), 0, s, X, Wt, bias, y, n, d, h, w, c_in, c_out, n_store, act, slope, y_f32); break;
+    }
+    SG_LAUNCH_CHECK();
+    return SG_OK;
+}
+
+sg_status sg_weight_mirror(const void *wt, int32_t c_out, int32_t c_in, void *wm, void *stream)
+{
+    if (!wt || !wm || c_out < 1 || c_in < 1) return fail(SG_EARG, "bad arguments");
+    const int64_t total = (int64_t)27 * c_out * c_in;
+    hipLaunchKernelGGL(k_weight_mirror, dim3(blocks_for(total)), dim3(kThreads), 0, (hipStream_t)stream,
+                       (const bf16 *)wt, c_out, c_in, (bf16 *)wm);
+    SG_LAUNCH_CHECK();
+    return SG_OK;
+}
+
+size_t sg_bwd_weight_workspace(int32_t n, int32_t d, int32_t h, int32_t w, int32_t c_in, int32_t c_out)
+{
+    const int64_t V = (int64_t)n * d * h * w;
+    const int64_t nchunk = (V + kBwChunk - 1) / kBwChunk;
+    return (size_t)nchunk * (27 * (size_t)c_in * c_out + (size_t)c_out) * sizeof(float);
+}
+
+sg_status sg_conv3d_bwd_weight(const void *x, const void *dy, int32_t n, int32_t d, int32_t h, int32_t w,
+                               int32_t c_in, int32_t c_out, float *dw, float *db, void *ws, size_t ws_bytes,
+                               void *stream)
+{
+    if (!x || !dy || !dw || !ws) return fail(SG_EARG, "NULL tensor");
+    if (c_in < 16 || c_in % 16) return fail(SG_EARG, "c_in must be a positive multiple of 16 (got %d)", c_in);
+    if (c_out < 32 || c_out % 32) return fail(SG_EARG, "c_out must be a multiple of 32 (got %d)", c_out);
+    const size_t need = sg_bwd_weight_workspace(n, d, h, w, c_in, c_out);
+    if (ws_bytes < need) return fail(SG_ESIZE, "workspace has %zu bytes, needs %zu", ws_bytes, need);
+    const int64_t V = (int64_t)n * d * h * w;
+    const int nchunk = (int)((V + kBwChunk - 1) / kBwChunk);
+    float *part = (float *)ws;
+    float *bpart = part + (int64_t)nchunk * 27 * c_in * c_out;
+    hipStream_t s = (hipStream_t)stream;
+    const dim3 grid((unsigned)nchunk, 27, (unsigned)((c_out / 32) * ((c_in + 31) / 32)));
+    hipLaunchKernelGGL(k_conv3d_bwd_weight, grid, dim3(kThreads), 0, s, (const bf16 *)x, (const bf16 *)dy, n, d,
+                       h, w, c_in, c_out, part);
+    SG_LAUNCH_CHECK();
+    const int64_t stride = (int64_t)27 * c_in * c_out;
+    hipLaunchKernelGGL(k_reduce_partials, dim3(blocks_for(stride)), dim3(kThreads), 0, s, part, nchunk, stride, dw);
+    SG_LAUNCH_CHECK();
+    if (db) {
+        hipLaunchKernelGGL(k_bias_grad_partial, dim3((unsigned)nchunk, (unsigned)c_out), dim3(kThreads), 0, s,
+                           (const bf16 *)dy, V, c_out, bpart);
+        SG_LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_reduce_partials, dim3(blocks_for(c_out)), dim3(kThreads), 0, s, bpart, nchunk,
+                           (int64_t)c_out, db);
+        SG_LAUNCH_CHECK();
+    }
+    return SG_OK;
+}
+
+sg_status sg_leaky_bwd(const void *y, const void *dy, void *dp, size_t count, float slope, void *stream)
+{
+    if (!y || !dy || !dp) return fail(SG_EARG, "NULL tensor");
+    hipLaunchKernelGGL(k_leaky_bwd, dim3(blocks_for((int64_t)count)), dim3(kThreads), 0, (hipStream_t)stream,
+                       (const bf16 *)y, (const bf16 *)dy, (bf16 *)dp, (int64_t)count, slope);
+    SG_LAUNCH_CHECK();
+    return SG_OK;
+}
+
+sg_status sg_pool2_fwd(const void *x, int32_t n, int32_t d, int32_t h, int32_t w, int32_t c, void *y, void *stream)
+{
+    if (!x || !y || d % 2 || h % 2 || w % 2) return fail(SG_EARG, "pool2 needs even d, h, w");
+    const int64_t total = (int64_t)n * (d / 2) * (h / 2) * (w / 2) * c;
+    hipLaunchKernelGGL(k_pool2_fwd, dim3(blocks_for(total)), dim3(kThreads), 0, (hipStream_t)stream,
+                       (const bf16 *)x, n, d, h, w, c, (bf16 *)y);
+    SG_LAUNCH_CHECK();
+    return SG_OK;
+}
+
+sg_status sg_pool2_bwd(const void *dy, int32_t n, int32_t d, int32_t h, int32_t w, int32_t c, void *dx, void *stream)
+{
+    if (!dy || !dx || d % 2 || h % 2 || w % 2) return fail(SG_EARG, "pool2 needs even d, h, w");
+    const int64_t total = (int64_t)n * d * h * w * c;
+    hipLaunchKernelGGL(k_pool2_bwd, dim3(blocks_for(total)), dim3(kThreads), 0, (hipStream_t)stream,
+                       (const bf16 *)dy, n, d, h, w, c, (bf16 *)dx);
+    SG_LAUNCH_CHECK();
+    return SG_OK;
+}
+
+sg_status sg_up2_fwd(const void *x, int32_t n, int32_t d, int32_t h, int32_t w, int32_t c, void *y, void *stream)
+{
+    if (!x || !y) return fail(SG_EARG, "NULL tensor");
+    const int64_t total = (int64_t)n * 8 * d * h * w * c;
+    hipLaunchKernelGGL(k_up2_fwd, dim3(blocks_for(total)), dim3(kThreads), 0, (hipStream_t)stream,
+                       (const bf16 *)x, n, d, h, w, c, (bf16 *)y);
+    SG_LAUNCH_CHECK();
+    return SG_OK;
+}
+
+sg_status sg_up2_bwd(const void *dy, int32_t n, int32_t d, int32_t h, int32_t w, int32_t c, void *dx, void *stream)
+{
+    if (!dy || !dx) return fail(SG_EARG, "NULL tensor");
+    const int64_t total = (int64_t)n * d * h * w * c;
+    hipLaunchKernelGGL(k_up2_bwd, dim3(blocks_for(total)), dim3(kThreads), 0, (hipStream_t)stream,
+                       (const bf16 *)dy, n, d, h, w, c, (bf16 *)dx);
+    SG_LAUNCH_CHECK();
+    return SG_OK;
+}
+
+sg_status sg_concat(const void *a, int32_t ca, const void *b, int32_t cb, int64_t V, void *y, void *stream)
+{
+    if (!a || !b || !y) return fail(SG_EARG, "NULL tensor");
+    hipLaunchKernelGGL(k_concat, dim3(blocks_for(V * (ca + cb))), dim3(kThreads), 0, (hipStream_t)stream,
+                       (const bf16 *)a, ca, (const bf16 *)b, cb, V, (bf16 *)y);
+    SG_LAUNCH_CHECK();
+    return SG_OK;
+}
+
+sg_status sg_split(const void *y, int32_t ca, int32_t cb, int64_t V, void *a, void *b, void *stream)
+{
+    if (!y) return fail(SG_EARG, "NULL tensor");
+    hipLaunchKernelGGL(k_split, dim3(blocks_for(V * (ca + cb))), dim3(kThreads), 0, (hipStream_t)stream,
+                       (const bf16 *)y, ca, cb, V, (bf16 *)a, (bf16 *)b);
+    SG_LAUNCH_CHECK();
+    return SG_OK;
+}
+
+sg_status sg_mse(const float *pred, const float *target, int64_t count, float *loss, void *grad, float *scratch,
+                 void *stream)
+{
+    if (!pred || !target || !loss || !grad || !scratch || count < 1) return fail(SG_EARG, "bad arguments");
+    hipStream_t s = (hipStream_t)stream;
+    hipLaunchKernelGGL(k_mse1, dim3(kMseBlocks), dim3(kThreads), 0, s, pred, target, count, (bf16 *)grad, scratch);
+    SG_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_mse2, dim3(1), dim3(kThreads), 0, s, scratch, count, loss);
+    SG_LAUNCH_CHECK();
+    return SG_OK;
+}
+
+sg_status sg_adam(float *p, const float *g, float *m, float *v, void *wt, int64_t count, float lr, float b1,
+                  float b2, float eps, int32_t step, void *stream)
+{
+    if (!p || !g || !m || !v || count < 1 || step < 1) return fail(SG_EARG, "bad arguments");
+    const float c1 = (float)(1.0 - std::pow((double)b1, step)), c2 = (float)(1.0 - std::pow((double)b2, step));
+    hipLaunchKernelGGL(k_adam, dim3(blocks_for(count)), dim3(kThreads), 0, (hipStream_t)stream, p, g, m, v,
+                       (bf16 *)wt, count, lr, b1, b2, eps, c1, c2);
+    SG_LAUNCH_CHECK();
+    return SG_OK;
+}
+
+sg_status sg_to_bf16(const float *x, void *y, int64_t count, void *stream)
+{
+    if (!x || !y) return fail(SG_EARG, "NULL tensor");
+    hipLaunchKernelGGL(k_to_bf16, dim3(blocks_for(count)), dim3(kThreads), 0, (hipStream_t)stream, x, (bf16 *)y, count);
+    SG_LAUNCH_CHECK();
+    return SG_OK;
+}
+
+sg_status sg_to_f32(const void *x, float *y, int64_t count, void *stream)
+{
+    if (!x || !y) return fail(SG_EARG, "NULL tensor");
+    hipLaunchKernelGGL(k_to_f32, dim3(blocks_for(count)), dim3(kThreads), 0, (hipStream_t)stream, (const bf16 *)x, y, count);
+    SG_LAUNCH_CHECK();
+    return SG_OK;
+}
+
+sg_status sg_add(const void *a, const void *b, void *y, int64_t count, void *stream)
+{
+    if (!a || !b || !y) return fail(SG_EARG, "NULL tensor");
+    hipLaunchKernelGGL(k_add, dim3(blocks_for(count)), dim3(kThreads), 0, (hipStream_t)stream, (const bf16 *)a,
+                       (const bf16 *)b, (bf16 *)y, count);
+    SG_LAUNCH_CHECK();
+    return SG_OK;
+}
+
+static sg_status read_box(const int32_t *box, int nx, int ny, int nz, Box &b)
+{
+    if (!box) return fail(SG_EARG, "NULL box");
+    b = Box{box[0], box[1], box[2], box[3], box[4], box[5]};
+    if (b.bx < 1 || b.by < 1 || b.bz < 1 || b.bx > nx || b.bz > nz) return fail(SG_EARG, "bad box size");
+    if (b.y0 < 0 || b.y0 + b.by > ny) return fail(SG_EARG, "box leaves [0, ny) in y");
+    return SG_OK;
+}
+
+sg_status sg_fields_to_input(const float *phi, const float *u, const float *p, int32_t nx, int32_t ny, int32_t nz,
+                             const int32_t *box, const float *si, int32_t c_in, void *x, float *state, void *stream)
+{
+    if (!phi || !u || !p || !si || !x || c_in < 5) return fail(SG_EARG, "bad arguments");
+    Box b;
+    sg_status st = read_box(box, nx, ny, nz, b);
+    if (st != SG_OK) return st;
+    const int64_t V = (int64_t)b.bx * b.by * b.bz;
+    hipLaunchKernelGGL(k_fields_to_input, dim3(blocks_for(V)), dim3(kThreads), 0, (hipStream_t)stream, phi, u, p, nx,
+                       ny, nz, b, si[0], si[1], si[2], si[3], si[4], c_in, (bf16 *)x, state);
+    SG_LAUNCH_CHECK();
+    return SG_OK;
+}
+
+sg_status sg_state_to_input(const float *s, int64_t V, const float *si, int32_t c_in, void *x, void *stream)
+{
+    if (!s || !si || !x || c_in < 5) return fail(SG_EARG, "bad arguments");
+    hipLaunchKernelGGL(k_state_to_input, dim3(blocks_for(V)), dim3(kThreads), 0, (hipStream_t)stream, s, V, si[0],
+                       si[1], si[2], si[3], si[4], c_in, (bf16 *)x);
+    SG_LAUNCH_CHECK();
+    return SG_OK;
+}
+
+sg_status sg_make_target(const float *s0, const float *s1, int64_t V, const float *so, int32_t c_out, float *t,
+                         void *stream)
+{
+    if (!s0 || !s1 || !so || !t || c_out < 5) return fail(SG_EARG, "bad arguments");
+    hipLaunchKernelGGL(k_make_target, dim3(blocks_for(V)), dim3(kThreads), 0, (hipStream_t)stream, s0, s1, V, so[0],
+                       so[1], so[2], so[3], so[4], c_out, t);
+    SG_LAUNCH_CHECK();
+    return SG_OK;
+}
+
+sg_status sg_apply_prediction(const float *out, int32_t c_out, const float *so, float *phi, float *u, float *p,
+                              int32_t nx, int32_t ny, int32_t nz, const int32_t *box, int32_t walls_y,
+                              float pmin, float pmax, void *stream)
+{
+    if (!out || !so || !phi || !u || !p || c_out < 5) return fail(SG_EARG, "bad arguments");
+    Box b;
+    sg_status st = read_box(box, nx, ny, nz, b);
+    if (st != SG_OK) return st;
+    const int64_t V = (int64_t)b.bx * b.by * b.bz;
+    hipLaunchKernelGGL(k_apply_prediction, dim3(blocks_for(V)), dim3(kThreads), 0, (hipStream_t)stream, out, c_out,
+                       so[0], so[1], so[2], so[3], so[4], phi, u, p, nx, ny, nz, b, walls_y, pmin, pmax);
+    SG_LAUNCH_CHECK();
+    return SG_OK;
+}
+
+sg_status sg_mass_project(float *phi, int64_t n, double target, float pmin, float pmax, double *scratch,
+                          void *stream)
+{
+    if (!phi || !scratch || n < 1 || !(pmax > pmin)) return fail(SG_EARG, "bad arguments");
+    hipStream_t s = (hipStream_t)stream;
+    hipLaunchKernelGGL(k_mass_sums, dim3(kProjBlocks), dim3(kThreads), 0, s, phi, n, pmin, pmax, scratch);
+    SG_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_mass_correct, dim3(4096), dim3(kThreads), 0, s, phi, n, scratch, target, pmin, pmax);
+    SG_LAUNCH_CHECK();
+    return SG_OK;
+}
+
+const char *sg_last_error(void) { return g_err; }
+
+}  // extern "C"

@@ -39,6 +39,7 @@ class Setup:
     tau_L: float = 0.3
     tau_H: float = 0.03
     accel: tuple = (0.0, 0.0, 0.0)
+    buoyancy_rho_ref: float = 0.0
     normal_eps: float = 1e-12
     steps: int = 1000
     # field recipe
@@ -65,7 +66,7 @@ class Setup:
                     phi_L=self.phi_L, phi_H=self.phi_H, xi=self.xi, mobility=self.mobility,
                     sigma=self.sigma, rho_L=self.rho_L, rho_H=self.rho_H,
                     tau_L=self.tau_L, tau_H=self.tau_H, accel=tuple(self.accel),
-                    normal_eps=self.normal_eps)
+                    buoyancy_rho_ref=self.buoyancy_rho_ref, normal_eps=self.normal_eps)
 
     def with_grid(self, nx, ny, nz, **kw):
         d = asdict(self)
@@ -99,13 +100,16 @@ def rising_bubble(nx: int = 128, ny: int = 512, nz: int = 128, D: float = 32.0,
                   center=(64.0, 64.0, 64.0), g: float = 9.78e-7, steps: int = 20000) -> Setup:
     """Single rising bubble: y up, periodic x/z, walls at y = 0 and ny-1,
     rho_H = 1, rho_L = 0.001, mu_H = 0.01, mu_L = 1e-4, xi = 5, M = 0.02,
-    sigma = 1e-4, gravity g along -y, u = 0, p* = 0."""
+    sigma = 1e-4, gravity g along -y, u = 0, p* = 0.  Buoyancy is taken
+    relative to the heavy fluid, F_b = (rho - rho_H) g (buoyancy_rho_ref =
+    rho_H): between the walls this is the printed rho g less the heavy fluid's
+    hydrostatic pressure."""
     return Setup(name=f"rising_bubble_{nx}x{ny}x{nz}", nx=nx, ny=ny, nz=nz, walls_y=True,
                  xi=5.0, mobility=0.02, sigma=1e-4, rho_L=0.001, rho_H=1.0,
                  tau_L=tau_from_dynamic_viscosity(1e-4, 0.001),
                  tau_H=tau_from_dynamic_viscosity(0.01, 1.0),
-                 accel=(0.0, -g, 0.0), steps=steps, kind="bubble", radius=D / 2.0,
-                 center=tuple(center))
+                 accel=(0.0, -g, 0.0), buoyancy_rho_ref=1.0, steps=steps, kind="bubble",
+                 radius=D / 2.0, center=tuple(center))
 
 
 def bubble_swarm(n: int = 512, n_bubbles: int = 200, d_range=(16.0, 32.0),

@@ -27,7 +27,7 @@ EXPORTS = [
     "lbm_velocity_set", "lbm_workspace_bytes", "lbm_create", "lbm_set_stream", "lbm_init_fields",
     "lbm_step", "lbm_step_timed", "lbm_reduce_mass", "lbm_reduce_stats", "lbm_get_macroscopic",
     "lbm_set_macroscopic", "lbm_get_pdfs", "lbm_set_pdfs", "lbm_stream_copy", "lbm_steps_done",
-    "lbm_destroy", "lbm_last_error",
+    "lbm_state_bytes", "lbm_save_state", "lbm_restore_state", "lbm_destroy", "lbm_last_error",
 ]
 
 
@@ -37,8 +37,8 @@ class LbmParams(C.Structure):
         ("phi_L", C.c_double), ("phi_H", C.c_double), ("xi", C.c_double),
         ("mobility", C.c_double), ("sigma", C.c_double),
         ("rho_L", C.c_double), ("rho_H", C.c_double), ("tau_L", C.c_double), ("tau_H", C.c_double),
-        ("body_accel", C.c_double * 3), ("normal_eps", C.c_double),
-        ("storage", C.c_int32), ("reserved0", C.c_int32), ("phi_shift", C.c_double),
+        ("body_accel", C.c_double * 3), ("buoyancy_rho_ref", C.c_double), ("normal_eps", C.c_double),
+        ("storage", C.c_int32), ("reserved0", C.c_int32),
     ]
 
 
@@ -77,6 +77,9 @@ def _load():
         "lbm_set_pdfs": ([vp, vp, vp, vp, vp], C.c_int),
         "lbm_stream_copy": ([vp, vp, C.c_size_t, vp], C.c_int),
         "lbm_steps_done": ([vp], C.c_int64),
+        "lbm_state_bytes": ([vp], C.c_size_t),
+        "lbm_save_state": ([vp, vp], C.c_int),
+        "lbm_restore_state": ([vp, vp], C.c_int),
         "lbm_destroy": ([vp], None),
         "lbm_last_error": ([], C.c_char_p),
     }
@@ -184,6 +187,18 @@ def lbm_steps_done(ctx) -> int:
     return int(_lib.lbm_steps_done(ctx))
 
 
+def lbm_state_bytes(ctx) -> int:
+    return int(_lib.lbm_state_bytes(ctx))
+
+
+def lbm_save_state(ctx, dst):
+    _check(_lib.lbm_save_state(ctx, _ptr(dst)), "lbm_save_state")
+
+
+def lbm_restore_state(ctx, src):
+    _check(_lib.lbm_restore_state(ctx, _ptr(src)), "lbm_restore_state")
+
+
 def lbm_destroy(ctx):
     _lib.lbm_destroy(ctx)
 
@@ -196,30 +211,29 @@ def lbm_last_error() -> str:
 
 def make_params(nx, ny, nz, walls_y=False, phi_L=0.0, phi_H=1.0, xi=4.0, mobility=0.02,
                 sigma=1e-3, rho_L=1.0, rho_H=10.0, tau_L=1.0, tau_H=1.0, accel=(0.0, 0.0, 0.0),
-                normal_eps=1e-12, storage="f64", phi_shift=1.0) -> LbmParams:
+                buoyancy_rho_ref=0.0, normal_eps=1e-12, storage="f64") -> LbmParams:
     p = LbmParams()
     p.nx, p.ny, p.nz, p.walls_y = int(nx), int(ny), int(nz), int(bool(walls_y))
     p.phi_L, p.phi_H, p.xi, p.mobility, p.sigma = phi_L, phi_H, xi, mobility, sigma
     p.rho_L, p.rho_H, p.tau_L, p.tau_H = rho_L, rho_H, tau_L, tau_H
     for a in range(3):
         p.body_accel[a] = float(accel[a])
+    p.buoyancy_rho_ref = float(buoyancy_rho_ref)
     p.normal_eps = normal_eps
     p.storage = STORAGE[storage] if isinstance(storage, str) else int(storage)
-    p.phi_shift = phi_shift
     return p
 
 
 class Solver:
     """One solver context on one device, with a torch-allocated workspace."""
 
-    def __init__(self, physics: dict, storage: str = "f64", phi_shift: float = 1.0,
-                 device: str = "cuda:0", stream=None):
+    def __init__(self, physics: dict, storage: str = "f64", device: str = "cuda:0", stream=None):
         import torch
         self.torch = torch
         self.device = torch.device(device)
         self.physics = dict(physics)
         self.storage = storage
-        self.params = make_params(storage=storage, phi_shift=phi_shift, **physics)
+        self.params = make_params(storage=storage, **physics)
         self.shape = (self.params.nz, self.params.ny, self.params.nx)
         self.n = self.params.nx * self.params.ny * self.params.nz
         self.nbytes = lbm_workspace_bytes(self.params)
@@ -298,6 +312,16 @@ class Solver:
         lbm_set_pdfs(self.ctx, self._dev64(H, (15,) + self.shape), self._dev64(G, (27,) + self.shape),
                      self._dev64(phi, self.shape), self._dev64(u, (3,) + self.shape))
         self.stream.synchronize()
+
+    def new_state_buffer(self):
+        """A device buffer for save_state / restore_state."""
+        return self.torch.empty(lbm_state_bytes(self.ctx), dtype=self.torch.uint8, device=self.device)
+
+    def save_state(self, buf):
+        lbm_save_state(self.ctx, buf)
+
+    def restore_state(self, buf):
+        lbm_restore_state(self.ctx, buf)
 
     def pressure(self):
         _, _, p = self.macroscopic(self.torch.float64)

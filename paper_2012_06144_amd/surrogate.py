@@ -1,0 +1,475 @@
+"""Learned fast-forward for the coupled LBM: a 3D convolutional encoder-decoder
+that predicts the macroscopic state (phi, u, p) K steps ahead, trained on
+snapshots the solver itself produces, and a jump driver that alternates one
+prediction with plain LBM relaxation steps and falls back to the plain solver
+when its indicators trip.
+
+Every tensor operation runs in the gfx950 kernels of ``sg.h`` (BF16
+activations and weights, FP32 accumulation on the matrix cores, FP32 master
+weights and Adam state); torch only allocates device memory.
+
+Network (4 levels, 32-128 channels, 3x3x3 convolutions, leaky ReLU):
+    enc0 16->32->32 | pool | enc1 32->64->64 | pool | enc2 64->128->128 | pool
+    bottom 128->128->128 | up, concat enc2 | dec2 256->128->128 | up, concat enc1
+    | dec1 192->64->64 | up, concat enc0 | dec0 96->32->32 | out 32->32 (FP32)
+The output's first 5 channels are the increment (state(t+K) - state(t)) /
+scale_out; the input's first 5 channels are state(t) / scale_in.
+"""
+from __future__ import annotations
+
+import json
+import math
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import sg
+
+SLOPE = 0.1
+C_IN = 16
+C_OUT = 32
+NCH = 5
+
+# (name, c_in, c_out, activation)
+LAYERS = [
+    ("enc0a", 16, 32, 1), ("enc0b", 32, 32, 1),
+    ("enc1a", 32, 64, 1), ("enc1b", 64, 64, 1),
+    ("enc2a", 64, 128, 1), ("enc2b", 128, 128, 1),
+    ("bot_a", 128, 128, 1), ("bot_b", 128, 128, 1),
+    ("dec2a", 256, 128, 1), ("dec2b", 128, 128, 1),
+    ("dec1a", 192, 64, 1), ("dec1b", 64, 64, 1),
+    ("dec0a", 96, 32, 1), ("dec0b", 32, 32, 1),
+    ("out", 32, 32, 0),
+]
+
+
+def flops_per_voxel() -> float:
+    """Multiply-adds x 2 per full-resolution voxel of one forward pass."""
+    lvl = {"enc0": 1, "enc1": 8, "enc2": 64, "bot_": 512, "dec2": 64, "dec1": 8, "dec0": 1, "out": 1}
+    total = 0.0
+    for name, ci, co, _ in LAYERS:
+        total += 2.0 * 27 * ci * co / lvl[name[:4] if name != "out" else "out"]
+    return total
+
+
+class Net:
+    """Parameters, activations and gradients of the encoder-decoder on one device."""
+
+    def __init__(self, device="cuda:0", seed: int = 0):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        g = torch.Generator(device="cpu").manual_seed(seed)
+        self.p = {}
+        for name, ci, co, act in LAYERS:
+            fan_in = 27 * ci
+            std = math.sqrt(2.0 / ((1 + SLOPE ** 2) * fan_in)) if act else 1e-3 / math.sqrt(fan_in)
+            w = torch.randn((27, co, ci), generator=g) * std
+            if name == "out":
+                w[:, NCH:, :] = 0.0            # unused output channels stay zero
+            d = {"w": w.to(self.device, torch.float32).contiguous(),
+                 "b": torch.zeros(co, device=self.device, dtype=torch.float32)}
+            d["wt"] = torch.empty((27, co, ci), device=self.device, dtype=torch.bfloat16)
+            d["wm"] = torch.empty((27, ci, co), device=self.device, dtype=torch.bfloat16)
+            for k in ("w", "b"):
+                d["g" + k] = torch.zeros_like(d[k])
+                d["m" + k] = torch.zeros_like(d[k])
+                d["v" + k] = torch.zeros_like(d[k])
+            sg.sg_to_bf16(d["w"], d["wt"])
+            self.p[name] = d
+        self.scale_in = [1.0, 1e-2, 1e-2, 1e-2, 1e-4]
+        self.scale_out = [1e-2, 1e-3, 1e-3, 1e-3, 1e-5]
+        self.step_count = 0
+        self._ws = None
+
+    # ---- helpers -----------------------------------------------------------------
+    def _empty(self, shape, dtype=None):
+        t = self.torch
+        return t.empty(shape, device=self.device, dtype=dtype or t.bfloat16)
+
+    def _conv(self, name, x, f32_out=False):
+        d = self.p[name]
+        _, ci, co, act = next(l for l in LAYERS if l[0] == name)
+        assert x.shape[-1] == ci, (name, x.shape, ci)
+        y = self._empty(x.shape[:-1] + (co,), self.torch.float32 if f32_out else None)
+        sg.sg_conv3d_fwd(x, d["wt"], d["b"], co, co, act, SLOPE, y, int(f32_out))
+        return y
+
+    def _pool(self, x):
+        n, dd, h, w, c = x.shape
+        y = self._empty((n, dd // 2, h // 2, w // 2, c))
+        sg.sg_pool2_fwd(x, y)
+        return y
+
+    def _up(self, x):
+        n, dd, h, w, c = x.shape
+        y = self._empty((n, 2 * dd, 2 * h, 2 * w, c))
+        sg.sg_up2_fwd(x, y)
+        return y
+
+    def _cat(self, a, b):
+        y = self._empty(a.shape[:-1] + (a.shape[-1] + b.shape[-1],))
+        sg.sg_concat(a, b, y)
+        return y
+
+    # ---- forward -------------------------------------------------------------------
+    def forward(self, x, keep=True):
+        """x: (N, D, H, W, 16) BF16 with D, H, W divisible by 8 -> (N, D, H, W, 32) FP32."""
+        a = {}
+        a["x"] = x
+        a["e0a"] = self._conv("enc0a", x)
+        a["s0"] = self._conv("enc0b", a["e0a"])
+        a["p1"] = self._pool(a["s0"])
+        a["e1a"] = self._conv("enc1a", a["p1"])
+        a["s1"] = self._conv("enc1b", a["e1a"])
+        a["p2"] = self._pool(a["s1"])
+        a["e2a"] = self._conv("enc2a", a["p2"])
+        a["s2"] = self._conv("enc2b", a["e2a"])
+        a["p3"] = self._pool(a["s2"])
+        a["ba"] = self._conv("bot_a", a["p3"])
+        a["bb"] = self._conv("bot_b", a["ba"])
+        a["c2"] = self._cat(self._up(a["bb"]), a["s2"])
+        a["d2a"] = self._conv("dec2a", a["c2"])
+        a["t2"] = self._conv("dec2b", a["d2a"])
+        a["c1"] = self._cat(self._up(a["t2"]), a["s1"])
+        a["d1a"] = self._conv("dec1a", a["c1"])
+        a["t1"] = self._conv("dec1b", a["d1a"])
+        a["c0"] = self._cat(self._up(a["t1"]), a["s0"])
+        a["d0a"] = self._conv("dec0a", a["c0"])
+        a["t0"] = self._conv("dec0b", a["d0a"])
+        out = self._conv("out", a["t0"], f32_out=True)
+        if keep:
+            self.acts = a
+        else:
+            self.acts = None
+        return out
+
+    # ---- backward ------------------------------------------------------------------
+    def _ws_for(self, x, co):
+        n, d, h, w, ci = x.shape
+        need = sg.sg_bwd_weight_workspace(n, d, h, w, ci, co)
+        if self._ws is None or self._ws.numel() * 4 < need:
+            self._ws = self._empty((need // 4 + 1,), self.torch.float32)
+        return self._ws
+
+    def _conv_bwd(self, name, x, y, dy, need_dx=True):
+        """dy: gradient w.r.t. the layer output y; returns the gradient w.r.t. x."""
+        d = self.p[name]
+        _, ci, co, act = next(l for l in LAYERS if l[0] == name)
+        if act:
+            dp = self._empty(dy.shape)
+            sg.sg_leaky_bwd(y, dy, dp, SLOPE)
+        else:
+            dp = dy
+        sg.sg_conv3d_bwd_weight(x, dp, d["gw"], d["gb"], self._ws_for(x, co))
+        if not need_dx:
+            return None
+        sg.sg_weight_mirror(d["wt"], d["wm"])
+        dx = self._empty(x.shape)
+        sg.sg_conv3d_fwd(dp, d["wm"], None, ci, ci, 0, 0.0, dx, 0)
+        return dx
+
+    def _split(self, g, ca, cb):
+        a = self._empty(g.shape[:-1] + (ca,))
+        b = self._empty(g.shape[:-1] + (cb,))
+        sg.sg_split(g, ca, cb, a, b)
+        return a, b
+
+    def _up_bwd(self, g):
+        n, dd, h, w, c = g.shape
+        dx = self._empty((n, dd // 2, h // 2, w // 2, c))
+        sg.sg_up2_bwd(g, dx)
+        return dx
+
+    def _pool_bwd(self, g, like):
+        dx = self._empty(like.shape)
+        sg.sg_pool2_bwd(g, dx)
+        return dx
+
+    def _add(self, a, b):
+        y = self._empty(a.shape)
+        sg.sg_add(a, b, y)
+        return y
+
+    def backward(self, dout):
+        """dout: BF16 gradient of the loss w.r.t. the FP32 output (32 channels)."""
+        a = self.acts
+        g_t0 = self._conv_bwd("out", a["t0"], None, dout)
+        g_d0a = self._conv_bwd("dec0b", a["d0a"], a["t0"], g_t0)
+        g_c0 = self._conv_bwd("dec0a", a["c0"], a["d0a"], g_d0a)
+        g_u0, g_s0 = self._split(g_c0, 64, 32)
+        g_t1 = self._up_bwd(g_u0)
+        g_d1a = self._conv_bwd("dec1b", a["d1a"], a["t1"], g_t1)
+        g_c1 = self._conv_bwd("dec1a", a["c1"], a["d1a"], g_d1a)
+        g_u1, g_s1 = self._split(g_c1, 128, 64)
+        g_t2 = self._up_bwd(g_u1)
+        g_d2a = self._conv_bwd("dec2b", a["d2a"], a["t2"], g_t2)
+        g_c2 = self._conv_bwd("dec2a", a["c2"], a["d2a"], g_d2a)
+        g_u2, g_s2 = self._split(g_c2, 128, 128)
+        g_bb = self._up_bwd(g_u2)
+        g_ba = self._conv_bwd("bot_b", a["ba"], a["bb"], g_bb)
+        g_p3 = self._conv_bwd("bot_a", a["p3"], a["ba"], g_ba)
+        g_s2 = self._add(g_s2, self._pool_bwd(g_p3, a["s2"]))
+        g_e2a = self._conv_bwd("enc2b", a["e2a"], a["s2"], g_s2)
+        g_p2 = self._conv_bwd("enc2a", a["p2"], a["e2a"], g_e2a)
+        g_s1 = self._add(g_s1, self._pool_bwd(g_p2, a["s1"]))
+        g_e1a = self._conv_bwd("enc1b", a["e1a"], a["s1"], g_s1)
+        g_p1 = self._conv_bwd("enc1a", a["p1"], a["e1a"], g_e1a)
+        g_s0 = self._add(g_s0, self._pool_bwd(g_p1, a["s0"]))
+        g_e0a = self._conv_bwd("enc0b", a["e0a"], a["s0"], g_s0)
+        self._conv_bwd("enc0a", a["x"], a["e0a"], g_e0a, need_dx=False)
+
+    def adam(self, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+        self.step_count += 1
+        for name, d in self.p.items():
+            sg.sg_adam(d["w"], d["gw"], d["mw"], d["vw"], d["wt"], lr, beta1, beta2, eps, self.step_count)
+            sg.sg_adam(d["b"], d["gb"], d["mb"], d["vb"], None, lr, beta1, beta2, eps, self.step_count)
+
+    def n_params(self) -> int:
+        return sum(d["w"].numel() + d["b"].numel() for d in self.p.values())
+
+    # ---- persistence -----------------------------------------------------------------
+    def state_dict(self) -> dict:
+        return {"w": {k: d["w"].cpu() for k, d in self.p.items()},
+                "b": {k: d["b"].cpu() for k, d in self.p.items()},
+                "scale_in": self.scale_in, "scale_out": self.scale_out, "steps": self.step_count}
+
+    def load_state_dict(self, st):
+        for k, d in self.p.items():
+            d["w"].copy_(st["w"][k].to(self.device))
+            d["b"].copy_(st["b"][k].to(self.device))
+            sg.sg_to_bf16(d["w"], d["wt"])
+        self.scale_in = list(st["scale_in"])
+        self.scale_out = list(st["scale_out"])
+        self.step_count = int(st["steps"])
+
+
+# ---------------------------------------------------------------------------------------
+# training data from the solver
+# ---------------------------------------------------------------------------------------
+
+@dataclass
+class DataConfig:
+    """Rising-bubble runs on an nx x ny x nz grid with seeded diameter, Eotvos
+    number and centre offset; a crop of `box` cells around the bubble every
+    `every` steps from step `start`."""
+    n_runs: int = 32
+    grid: tuple = (128, 256, 128)
+    d_range: tuple = (16.0, 40.0)
+    eo_range: tuple = (2.0, 20.0)
+    offset: float = 8.0
+    steps: int = 3000
+    every: int = 50
+    start: int = 200
+    K: int = 200
+    box: tuple = (64, 96, 64)      # (bx, by, bz)
+    seed: int = 7
+    storage: str = "f32"
+
+
+def generate_snapshots(cfg: DataConfig, device="cuda:0", log=print):
+    """Runs the solver and returns FP32 crops (runs, snapshots, bz*by*bx*5) on
+    the device, with the crop box of each snapshot kept fixed per pair so the
+    target is the change inside one window."""
+    import torch
+
+    from . import inputs, lbm
+    rng = np.random.default_rng(cfg.seed)
+    nx, ny, nz = cfg.grid
+    bx, by, bz = cfg.box
+    nsnap = (cfg.steps - cfg.start) // cfg.every + 1
+    lag = cfg.K // cfg.every
+    V = bx * by * bz
+    pairs_s0, pairs_s1 = [], []
+    meta = []
+    for r in range(cfg.n_runs):
+        D = rng.uniform(*cfg.d_range)
+        eo = rng.uniform(*cfg.eo_range)
+        off = rng.uniform(-cfg.offset, cfg.offset, 3)
+        g = eo * 1e-4 / (1.0 * D * D)
+        c = (nx / 2 + off[0], 72.0 + off[1], nz / 2 + off[2])
+        s = inputs.rising_bubble(nx, ny, nz, D=D, center=c, g=g)
+        phi, u, ps = inputs.build_fields(s)
+        sv = lbm.Solver(s.physics(), storage=cfg.storage, device=device)
+        sv.init_fields(phi, u, ps)
+        sv.step(cfg.start)
+        snaps = []
+        cents = []
+        for k in range(nsnap):
+            if k:
+                sv.step(cfg.every)
+            ph, uu, pp = sv.macroscopic(torch.float32)
+            cents.append(sv.stats()["centroid"])
+            snaps.append((ph, uu, pp))
+        # pair (k, k + lag) cropped with the window centred on the bubble at k
+        for k in range(nsnap - lag):
+            cx, cy, cz = cents[k]
+            y0 = int(min(max(round(cy) - by // 2, 1), ny - 1 - by))
+            box = (int(round(cx)) - bx // 2, y0, int(round(cz)) - bz // 2, bx, by, bz)
+            s0 = torch.empty(V * NCH, device=device, dtype=torch.float32)
+            s1 = torch.empty_like(s0)
+            xb = torch.empty(V * C_IN, device=device, dtype=torch.bfloat16)
+            sg.sg_fields_to_input(*snaps[k], nx, ny, nz, box, [1] * 5, C_IN, xb, s0)
+            sg.sg_fields_to_input(*snaps[k + lag], nx, ny, nz, box, [1] * 5, C_IN, xb, s1)
+            pairs_s0.append(s0)
+            pairs_s1.append(s1)
+        meta.append({"D": D, "Eo": eo, "g": g, "centre": list(c)})
+        log(f"[data] run {r}: D={D:.1f} Eo={eo:.1f} -> {nsnap - lag} pairs, "
+            f"rise {cents[-1][1] - cents[0][1]:.2f} cells")
+        del sv, snaps
+        torch.cuda.empty_cache()
+    S0 = torch.stack(pairs_s0)
+    S1 = torch.stack(pairs_s1)
+    return S0, S1, meta
+
+
+def channel_scales(S0, S1):
+    """Per-channel input scale (max |value|) and output scale (std of the
+    increment) of the (phi, u_x, u_y, u_z, p) crops, used to normalise."""
+    a = S0.view(-1, NCH)
+    d = (S1 - S0).view(-1, NCH)
+    sin = a.abs().amax(0).clamp_min(1e-12).tolist()
+    sout = d.std(0).clamp_min(1e-12).tolist()
+    sin[0] = 1.0
+    return [float(v) for v in sin], [float(v) for v in sout]
+
+
+def make_batch(net, S0, S1, idx, box):
+    """Network input (BF16) and target (FP32) of the pairs `idx`."""
+    import torch
+    bx, by, bz = box
+    V = bx * by * bz
+    n = len(idx)
+    x = torch.empty((n, bz, by, bx, C_IN), device=S0.device, dtype=torch.bfloat16)
+    t = torch.empty((n, bz, by, bx, C_OUT), device=S0.device, dtype=torch.float32)
+    for j, i in enumerate(idx):
+        sg.sg_state_to_input(S0[i], net.scale_in, C_IN, x[j])
+        sg.sg_make_target(S0[i], S1[i], net.scale_out, C_OUT, t[j])
+    return x, t
+
+
+def train(net, S0, S1, box, steps=500, batch=8, lr=1e-3, val_frac=0.1, seed=0, log=print):
+    """Adam on the MSE of the normalised increment; returns the loss history
+    and the validation losses of the network and of persistence (increment 0)."""
+    import torch
+    n = S0.shape[0]
+    rng = np.random.default_rng(seed)
+    perm = rng.permutation(n)
+    nval = max(1, int(val_frac * n))
+    val, tr = perm[:nval], perm[nval:]
+    loss = torch.zeros(1, device=S0.device, dtype=torch.float32)
+    scratch = torch.zeros(1024, device=S0.device, dtype=torch.float32)
+    hist = []
+    t0 = time.perf_counter()
+    for it in range(steps):
+        idx = rng.choice(tr, size=min(batch, len(tr)), replace=False)
+        x, t = make_batch(net, S0, S1, idx, box)
+        out = net.forward(x)
+        g = torch.empty(out.shape, device=out.device, dtype=torch.bfloat16)
+        sg.sg_mse(out, t, loss, g, scratch)
+        net.backward(g)
+        cur_lr = lr * 0.5 * (1 + math.cos(math.pi * it / steps))
+        net.adam(cur_lr)
+        if it % 25 == 0 or it == steps - 1:
+            lv = float(loss.item())
+            hist.append((it, lv))
+            log(f"[train] step {it} loss {lv:.4e} ({time.perf_counter() - t0:.1f}s)")
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    v_net, v_zero = evaluate(net, S0, S1, val, box)
+    return {"history": hist, "val_loss": v_net, "val_loss_persistence": v_zero, "seconds": wall,
+            "n_train": int(len(tr)), "n_val": int(nval)}
+
+
+def evaluate(net, S0, S1, idx, box, batch=8):
+    """Mean validation MSE of the network and of the zero increment."""
+    import torch
+    loss = torch.zeros(1, device=S0.device, dtype=torch.float32)
+    scratch = torch.zeros(1024, device=S0.device, dtype=torch.float32)
+    tot_n, tot_z, cnt = 0.0, 0.0, 0
+    for k in range(0, len(idx), batch):
+        ii = idx[k:k + batch]
+        x, t = make_batch(net, S0, S1, ii, box)
+        out = net.forward(x, keep=False)
+        g = torch.empty(out.shape, device=out.device, dtype=torch.bfloat16)
+        sg.sg_mse(out, t, loss, g, scratch)
+        tot_n += float(loss.item()) * len(ii)
+        zero = torch.zeros_like(out)
+        sg.sg_mse(zero, t, loss, g, scratch)
+        tot_z += float(loss.item()) * len(ii)
+        cnt += len(ii)
+    return tot_n / cnt, tot_z / cnt
+
+
+# ---------------------------------------------------------------------------------------
+# jump driver
+# ---------------------------------------------------------------------------------------
+
+@dataclass
+class JumpConfig:
+    K: int = 200                # steps one prediction skips
+    relax: int = 50             # LBM steps after each jump
+    mass_tol: float = 1e-6      # |d sum(phi)| / sum(phi) over a cycle
+    xi_lo: float = 0.8          # interface width must stay in [xi_lo, xi_hi] * xi
+    xi_hi: float = 1.25
+
+
+def predict_into_fields(net, phi, u, p, nx, ny, nz, walls_y, phi_L, phi_H):
+    """One network prediction over the whole grid (D, H, W divisible by 8),
+    added to the FP32 fields in place."""
+    import torch
+    box = (0, 0, 0, nx, ny, nz)
+    x = torch.empty((1, nz, ny, nx, C_IN), device=phi.device, dtype=torch.bfloat16)
+    sg.sg_fields_to_input(phi, u, p, nx, ny, nz, box, net.scale_in, C_IN, x)
+    out = net.forward(x, keep=False)
+    del x
+    sg.sg_apply_prediction(out, C_OUT, net.scale_out, phi, u, p, nx, ny, nz, box, walls_y, phi_L, phi_H)
+    del out
+
+
+def run_with_jumps(net, solver, setup, total_steps, jc: JumpConfig, log=print, every_stats=None):
+    """Advance `solver` by total_steps with cycles of (jump K, relax) and
+    fallback; returns the trajectory and counts."""
+    import torch
+    nx, ny, nz = setup.nx, setup.ny, setup.nz
+    backup = solver.new_state_buffer()
+    scratch = torch.zeros(2048, device=solver.device, dtype=torch.float64)
+    done = 0
+    traj = []
+    accepted = rejected = 0
+    st = solver.stats()
+    traj.append({"step": 0, "centroid_y": st["centroid"][1], "rise_velocity": st["rise_velocity"],
+                 "mass": st["mass"]})
+    cyc = jc.K + jc.relax
+    while done + cyc <= total_steps:
+        m0 = solver.reduce_mass()
+        solver.save_state(backup)
+        phi, u, p = solver.macroscopic(torch.float32)
+        predict_into_fields(net, phi, u, p, nx, ny, nz, setup.walls_y, setup.phi_L, setup.phi_H)
+        sg.sg_mass_project(phi, m0, setup.phi_L, setup.phi_H, scratch)
+        solver.set_macroscopic(phi, u, p)
+        del phi, u, p
+        solver.step(jc.relax)
+        st = solver.stats()
+        drift = abs(st["mass"] - m0) / abs(m0)
+        ok = (math.isfinite(st["mass"]) and drift <= jc.mass_tol
+              and jc.xi_lo * setup.xi <= st["xi_eff"] <= jc.xi_hi * setup.xi)
+        if ok:
+            accepted += 1
+        else:
+            rejected += 1
+            solver.restore_state(backup)
+            solver.step(cyc)
+            st = solver.stats()
+        done += cyc
+        traj.append({"step": done, "centroid_y": st["centroid"][1], "rise_velocity": st["rise_velocity"],
+                     "mass": st["mass"], "jump": bool(ok), "drift": drift, "xi_eff": st["xi_eff"]})
+    if done < total_steps:
+        solver.step(total_steps - done)
+        st = solver.stats()
+        done = total_steps
+        traj.append({"step": done, "centroid_y": st["centroid"][1], "rise_velocity": st["rise_velocity"],
+                     "mass": st["mass"]})
+    torch.cuda.synchronize()
+    return {"trajectory": traj, "accepted": accepted, "rejected": rejected}

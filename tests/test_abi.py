@@ -39,6 +39,20 @@ def test_library_exports_every_declared_symbol():
     assert sorted(lbm.EXPORTS) == declared
 
 
+def test_surrogate_library_exports_every_declared_symbol():
+    lbm = _lbm()
+    from paper_2012_06144_amd import sg
+    declared = sorted(set(re.findall(r"\b(sg_[a-z_0-9]+)\s*\(",
+                                     re.sub(r"/\*.*?\*/", "", open(os.path.join(ROOT, "include", "sg.h")).read(),
+                                            flags=re.S))))
+    assert len(declared) >= 15
+    out = subprocess.run(["nm", "-D", "--defined-only", lbm.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r"\bT (sg_[a-z_0-9]+)$", out, flags=re.M))
+    assert not [f for f in declared if f not in exported]
+    assert sorted(sg.EXPORTS) == declared
+
+
 def test_struct_layout_matches_header(tmp_path):
     """Compile a probe against include/lbm.h with gcc and compare sizes and
     offsets with the ctypes mirrors used by the binding."""
@@ -50,7 +64,7 @@ def test_struct_layout_matches_header(tmp_path):
 #include "lbm.h"
 int main(void) {
   printf("%zu %zu %zu %zu %zu\\n", sizeof(lbm_params), offsetof(lbm_params, body_accel),
-         offsetof(lbm_params, storage), offsetof(lbm_params, phi_shift), sizeof(lbm_stats));
+         offsetof(lbm_params, storage), offsetof(lbm_params, reserved0), sizeof(lbm_stats));
   printf("%zu %zu\\n", offsetof(lbm_stats, centroid), offsetof(lbm_stats, max_speed));
   return 0;
 }
@@ -60,7 +74,7 @@ int main(void) {
     vals = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True,
                                            check=True).stdout.split()]
     P, S = lbm.LbmParams, lbm.LbmStats
-    assert vals[:5] == [C.sizeof(P), P.body_accel.offset, P.storage.offset, P.phi_shift.offset,
+    assert vals[:5] == [C.sizeof(P), P.body_accel.offset, P.storage.offset, P.reserved0.offset,
                         C.sizeof(S)]
     assert vals[5:] == [S.centroid.offset, S.max_speed.offset]
 

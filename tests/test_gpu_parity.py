@@ -134,13 +134,14 @@ def test_set_get_roundtrip(lbm):
 
 
 def _fp32_tolerances(ost, src):
-    """64 eps32 times the scale of each output: PDF outputs scale with the
-    largest PDF magnitude of the step's inputs (15- or 27-term sums), phi with
-    the 15-term sum, u with the 27 hydrodynamic PDFs it is summed from."""
+    """64 eps32 times the scale of each output.  The phase-field rest
+    population is formed as phi minus the 14 others, so H and phi scale with
+    the 15-term sum; G and u scale with the 27 hydrodynamic PDFs they are
+    summed from."""
     H0, G0, phi0, u0 = src
-    sH = max(np.abs(H0).max(), np.abs(ost[0]).max())
-    sG = max(27 * np.abs(G0).max(), np.abs(ost[1]).max())  # g_eq has no O(w) cancellation
     sphi = max(15 * np.abs(H0).max(), np.abs(ost[2]).max())
+    sH = max(np.abs(H0).max(), np.abs(ost[0]).max(), sphi)
+    sG = max(27 * np.abs(G0).max(), np.abs(ost[1]).max())  # g_eq has no O(w) cancellation
     su = max(27 * np.abs(G0).max(), np.abs(ost[3]).max())
     return [64 * EPS32 * v for v in (sH, sG, sphi, su)]
 
@@ -161,16 +162,18 @@ def test_one_step_f32_small(lbm):
 
 
 def _ulp(v, fmt):
-    """Spacing of the storage format at |v| (normal range; subnormal floor)."""
-    mant, emin = (10, -14) if fmt == "f16s" else (7, -126)
+    """Spacing of the stored format at |v| in unscaled units: FP16 values are
+    stored times 2^10, which moves the subnormal range down by 2^10."""
+    mant, emin = (10, -24) if fmt == "f16s" else (7, -126)
     e = np.floor(np.log2(np.maximum(np.abs(v), 2.0 ** emin)))
     return 2.0 ** (e - mant)
 
 
 @pytest.mark.parametrize("fmt", ["f16s", "bf16s"])
 def test_one_step_low_precision_small(lbm, fmt):
-    """Shifted low-precision storage: one step from a common state is within
-    half an ulp of the stored (shifted) value plus the FP32 bound."""
+    """16-bit storage of h_i - phi w_i and g_i / w_i: one step from a common
+    state is within half an ulp of the stored value (in stored units) plus the
+    FP32 bound plus the FP32 rounding of the decode."""
     s = SMALL["ragged_walls_bubble"]()
     o, g = _pair(lbm, s, storage=fmt)
     g.step(5)
@@ -180,11 +183,17 @@ def test_one_step_low_precision_small(lbm, fmt):
     g.step(1)
     ost, gst = o.state(), g.state()
     tol = _fp32_tolerances(ost, src)
-    e15, w15 = orc.velocity_set(15)
-    shift = 1.0 * w15.reshape(15, 1, 1, 1)
-    # stored value rounded to the format, then decoded in FP32
-    bound_H = 0.5 * _ulp(ost[0] - shift, fmt) + tol[0] + EPS32 * np.abs(ost[0])
-    bound_G = 0.5 * _ulp(ost[1], fmt) + tol[1]
+    _, w15 = orc.velocity_set(15)
+    _, w27 = orc.velocity_set(27)
+    w15 = w15.reshape(15, 1, 1, 1)
+    w27 = w27.reshape(27, 1, 1, 1)
+    shift = gst[2][None] * w15           # the GPU's new phi times w_i
+    half_ulp = 0.5 * _ulp(ost[0] - shift, fmt)
+    bound_H = half_ulp + tol[0] + EPS32 * (np.abs(ost[0]) + np.abs(shift))
+    # the rest population closes sum(h) = phi on the decoded values of the
+    # other 14, so it carries their rounding too
+    bound_H[0] += half_ulp[1:].sum(axis=0) + 15 * EPS32 * np.abs(gst[2])
+    bound_G = 0.5 * _ulp(ost[1] / w27, fmt) * w27 + tol[1] + EPS32 * np.abs(ost[1])
     fluid = np.ones(s.shape, dtype=bool)
     fluid[:, 0, :] = fluid[:, -1, :] = False
     dH = np.abs(gst[0] - ost[0])[:, fluid]

@@ -1,0 +1,283 @@
+"""GPU parity of the surrogate-network kernels (through the sg_* C ABI)
+against the FP64 CPU oracle on the same BF16-rounded operands.
+
+Bar per element: |gpu - oracle| <= half a BF16 ulp of the stored result (when
+the result is stored as BF16) + gamma_K * sum |terms|, gamma_K = K eps32 for
+an FP32 accumulation of K products (K = 27 c_in for the forward and input
+gradient, the voxel count for the weight gradient).
+"""
+import numpy as np
+import pytest
+
+from oracle import conv as oc
+
+pytestmark = pytest.mark.gpu
+
+EPS32 = float(np.finfo(np.float32).eps)
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2012_06144_amd import sg
+    return torch, sg
+
+
+def _bf16(torch, a):
+    t = torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to("cuda").to(torch.bfloat16)
+    return t, t.float().cpu().numpy().astype(np.float64)
+
+
+def _ulp_bf16(v):
+    e = np.floor(np.log2(np.maximum(np.abs(v), 2.0 ** -126)))
+    return 2.0 ** (e - 7)
+
+
+CONV_CASES = [
+    # (n, d, h, w, ci, co, n_store, act, f32_out)
+    (1, 4, 6, 8, 16, 32, 32, 1, 0),       # first-layer width, partial block of voxels
+    (2, 3, 5, 7, 32, 64, 64, 1, 0),       # ragged voxel count
+    (1, 4, 4, 4, 48, 96, 96, 0, 0),       # three column tiles
+    (1, 2, 4, 8, 64, 256, 256, 1, 0),     # two column groups of four tiles
+    (1, 4, 4, 8, 32, 32, 5, 0, 1),        # FP32 output, first 5 channels kept
+]
+
+
+@pytest.mark.parametrize("case", CONV_CASES)
+def test_conv3d_fwd(env, case):
+    torch, sg = env
+    n, d, h, w, ci, co, ns, act, f32 = case
+    rng = np.random.default_rng(hash(case) % 2 ** 32)
+    xt, x = _bf16(torch, rng.standard_normal((n, d, h, w, ci)))
+    wt, wv = _bf16(torch, rng.standard_normal((27, co, ci)) / np.sqrt(27 * ci))
+    b = rng.standard_normal(co).astype(np.float32)
+    bt = torch.from_numpy(b).cuda()
+    y = torch.empty((n, d, h, w, ns), device="cuda", dtype=torch.float32 if f32 else torch.bfloat16)
+    sg.sg_conv3d_fwd(xt, wt, bt, co, ns, act, 0.1, y, f32)
+    torch.cuda.synchronize()
+    ref = oc.conv3d(x, wv, b.astype(np.float64))
+    if act:
+        ref = oc.leaky(ref, 0.1)
+    ref = ref[..., :ns]
+    mag = oc.conv3d(np.abs(x), np.abs(wv), np.abs(b.astype(np.float64)))[..., :ns]
+    bound = 27 * ci * EPS32 * mag + (0.0 if f32 else 1.0) * 0.5 * _ulp_bf16(ref) + 1e-30
+    got = y.float().cpu().numpy().astype(np.float64)
+    assert np.all(np.abs(got - ref) <= bound), np.max(np.abs(got - ref) / bound)
+
+
+@pytest.mark.parametrize("case", [(1, 4, 6, 8, 32, 64), (2, 3, 5, 7, 64, 32), (1, 2, 4, 8, 96, 192)])
+def test_conv3d_input_gradient(env, case):
+    torch, sg = env
+    n, d, h, w, ci, co = case
+    rng = np.random.default_rng(sum(case))
+    dyt, dy = _bf16(torch, rng.standard_normal((n, d, h, w, co)))
+    wt, wv = _bf16(torch, rng.standard_normal((27, co, ci)) / np.sqrt(27 * co))
+    wm = torch.empty((27, ci, co), device="cuda", dtype=torch.bfloat16)
+    sg.sg_weight_mirror(wt, wm)
+    dx = torch.empty((n, d, h, w, ci), device="cuda", dtype=torch.bfloat16)
+    sg.sg_conv3d_fwd(dyt, wm, None, ci, ci, 0, 0.0, dx, 0)
+    torch.cuda.synchronize()
+    ref = oc.conv3d_bwd_data(dy, wv)
+    mag = oc.conv3d_bwd_data(np.abs(dy), np.abs(wv))
+    bound = 27 * co * EPS32 * mag + 0.5 * _ulp_bf16(ref) + 1e-30
+    got = dx.float().cpu().numpy().astype(np.float64)
+    assert np.all(np.abs(got - ref) <= bound), np.max(np.abs(got - ref) / bound)
+
+
+@pytest.mark.parametrize("case", [(1, 4, 6, 8, 16, 32), (2, 5, 6, 7, 32, 64), (1, 4, 4, 4, 96, 32)])
+def test_conv3d_weight_gradient(env, case):
+    torch, sg = env
+    n, d, h, w, ci, co = case
+    rng = np.random.default_rng(3 * sum(case))
+    xt, x = _bf16(torch, rng.standard_normal((n, d, h, w, ci)))
+    dyt, dy = _bf16(torch, rng.standard_normal((n, d, h, w, co)))
+    dw = torch.empty((27, co, ci), device="cuda", dtype=torch.float32)
+    db = torch.empty(co, device="cuda", dtype=torch.float32)
+    ws = torch.empty(sg.sg_bwd_weight_workspace(n, d, h, w, ci, co) // 4 + 1, device="cuda", dtype=torch.float32)
+    sg.sg_conv3d_bwd_weight(xt, dyt, dw, db, ws)
+    torch.cuda.synchronize()
+    rw, rb = oc.conv3d_bwd_weight(x, dy)
+    mw, mb = oc.conv3d_bwd_weight(np.abs(x), np.abs(dy))
+    V = n * d * h * w
+    assert np.all(np.abs(dw.cpu().numpy() - rw) <= V * EPS32 * mw + 1e-30)
+    assert np.all(np.abs(db.cpu().numpy() - rb) <= V * EPS32 * mb + 1e-30)
+
+
+def test_resampling_and_elementwise(env):
+    torch, sg = env
+    rng = np.random.default_rng(11)
+    xt, x = _bf16(torch, rng.standard_normal((2, 4, 6, 8, 16)))
+    p = torch.empty((2, 2, 3, 4, 16), device="cuda", dtype=torch.bfloat16)
+    sg.sg_pool2_fwd(xt, p)
+    ref = oc.pool2(x)
+    assert np.all(np.abs(p.float().cpu().numpy() - ref) <= 0.5 * _ulp_bf16(ref) + 8 * EPS32 * np.abs(ref))
+    u = torch.empty_like(xt)
+    sg.sg_up2_fwd(p, u)
+    assert np.array_equal(u.float().cpu().numpy(), oc.up2(p.float().cpu().numpy().astype(np.float64)))
+    dp = torch.empty_like(p)
+    sg.sg_up2_bwd(xt, dp)
+    ref_u = 8 * oc.pool2(x)
+    assert np.all(np.abs(dp.float().cpu().numpy() - ref_u) <= 0.5 * _ulp_bf16(ref_u) + 8 * EPS32 * np.abs(ref_u) * 8)
+    dx = torch.empty_like(xt)
+    sg.sg_pool2_bwd(p, dx)
+    ref_p = oc.up2(p.float().cpu().numpy().astype(np.float64)) / 8.0
+    assert np.array_equal(dx.float().cpu().numpy().astype(np.float64), ref_p)
+    a_t, a = _bf16(torch, rng.standard_normal((3, 5, 32)))
+    b_t, b = _bf16(torch, rng.standard_normal((3, 5, 64)))
+    cat = torch.empty((3, 5, 96), device="cuda", dtype=torch.bfloat16)
+    sg.sg_concat(a_t, b_t, cat)
+    assert np.array_equal(cat.float().cpu().numpy(), np.concatenate([a, b], -1))
+    a2, b2 = torch.empty_like(a_t), torch.empty_like(b_t)
+    sg.sg_split(cat, 32, 64, a2, b2)
+    assert torch.equal(a2, a_t) and torch.equal(b2, b_t)
+    s = torch.empty_like(a_t)
+    sg.sg_add(a_t, a_t, s)
+    assert np.array_equal(s.float().cpu().numpy(), 2 * a)
+    yt, y = _bf16(torch, rng.standard_normal((1000,)))
+    gt, g = _bf16(torch, rng.standard_normal((1000,)))
+    d = torch.empty_like(yt)
+    sg.sg_leaky_bwd(yt, gt, d, 0.1)
+    ref_l = np.where(y > 0, g, 0.1 * g)
+    assert np.all(np.abs(d.float().cpu().numpy() - ref_l) <= 0.5 * _ulp_bf16(ref_l))
+
+
+def test_mse_and_adam(env):
+    torch, sg = env
+    rng = np.random.default_rng(12)
+    p = rng.standard_normal(100000).astype(np.float32)
+    t = rng.standard_normal(100000).astype(np.float32)
+    loss = torch.zeros(1, device="cuda")
+    scratch = torch.zeros(1024, device="cuda")
+    g = torch.empty(100000, device="cuda", dtype=torch.bfloat16)
+    sg.sg_mse(torch.from_numpy(p).cuda(), torch.from_numpy(t).cuda(), loss, g, scratch)
+    torch.cuda.synchronize()
+    rv, rg = oc.mse(p.astype(np.float64), t.astype(np.float64))
+    assert abs(loss.item() - rv) <= 1e-5 * rv
+    assert np.all(np.abs(g.float().cpu().numpy() - rg) <= 0.5 * _ulp_bf16(rg) + 4 * EPS32 * np.abs(rg))
+    # Adam: 5 steps from the same state, FP32 vs FP64
+    w0 = rng.standard_normal(5000)
+    grads = [rng.standard_normal(5000) for _ in range(5)]
+    pw, m, v = w0.copy(), np.zeros(5000), np.zeros(5000)
+    tp = torch.from_numpy(w0.astype(np.float32)).cuda()
+    tm = torch.zeros_like(tp)
+    tv = torch.zeros_like(tp)
+    tb = torch.empty(5000, device="cuda", dtype=torch.bfloat16)
+    for k, gr in enumerate(grads, 1):
+        oc.adam(pw, gr, m, v, 1e-2, 0.9, 0.999, 1e-8, k)
+        sg.sg_adam(tp, torch.from_numpy(gr.astype(np.float32)).cuda(), tm, tv, tb, 1e-2, 0.9, 0.999, 1e-8, k)
+    torch.cuda.synchronize()
+    assert np.abs(tp.cpu().numpy() - pw).max() < 1e-5
+    assert torch.equal(tb, tp.to(torch.bfloat16))
+
+
+def test_field_packing_and_mass_projection(env):
+    torch, sg = env
+    rng = np.random.default_rng(13)
+    nx, ny, nz = 12, 10, 8
+    N = nx * ny * nz
+    phi = rng.uniform(0, 1, N).astype(np.float32)
+    u = rng.standard_normal(3 * N).astype(np.float32) * 1e-3
+    p = rng.standard_normal(N).astype(np.float32) * 1e-4
+    tphi, tu, tp = (torch.from_numpy(a).cuda() for a in (phi, u, p))
+    box = (10, 2, 6, 8, 6, 4)          # wraps in x and z
+    V = 8 * 6 * 4
+    x = torch.empty((1, 4, 6, 8, 16), device="cuda", dtype=torch.bfloat16)
+    st = torch.empty(V * 5, device="cuda", dtype=torch.float32)
+    scale = [1.0, 1e-2, 1e-2, 1e-2, 1e-4]
+    sg.sg_fields_to_input(tphi, tu, tp, nx, ny, nz, box, scale, 16, x, st)
+    torch.cuda.synchronize()
+    F = np.stack([phi, u[:N], u[N:2 * N], u[2 * N:], p], -1).reshape(nz, ny, nx, 5)
+    zi = (6 + np.arange(4)) % nz
+    yi = 2 + np.arange(6)
+    xi = (10 + np.arange(8)) % nx
+    ref = F[zi][:, yi][:, :, xi]
+    assert np.array_equal(st.cpu().numpy().reshape(4, 6, 8, 5), ref)
+    xs = x.float().cpu().numpy()
+    assert np.all(xs[..., 5:] == 0)
+    assert np.allclose(xs[..., :5], ref / np.array(scale), rtol=2 ** -8)
+    # prediction applied back (walls at y = 0, ny-1 are skipped), phi clipped
+    out = torch.from_numpy(rng.standard_normal((V, 32)).astype(np.float32)).cuda()
+    so = [0.5, 1e-3, 1e-3, 1e-3, 1e-5]
+    sg.sg_apply_prediction(out, 32, so, tphi, tu, tp, nx, ny, nz, box, 1, 0.0, 1.0)
+    torch.cuda.synchronize()
+    phi2 = tphi.cpu().numpy().reshape(nz, ny, nx)
+    o = out.cpu().numpy().reshape(4, 6, 8, 32)
+    expect = np.clip(ref[..., 0] + o[..., 0] * 0.5, 0, 1)
+    assert np.allclose(phi2[zi][:, yi][:, :, xi], expect, atol=1e-6)
+    # mass projection to a target sum
+    scratch = torch.zeros(2048, device="cuda", dtype=torch.float64)
+    target = float(phi2.sum()) + 3.0
+    sg.sg_mass_project(tphi, target, 0.0, 1.0, scratch)
+    torch.cuda.synchronize()
+    assert abs(tphi.double().sum().item() - target) < 1e-3
+
+
+def test_network_gradient_against_oracle(env):
+    """The whole encoder-decoder: loss gradient of the GPU network (BF16
+    activations, FP32 accumulation) against the same network built from the
+    oracle's FP64 operations on the same BF16-rounded weights and input.  BF16
+    rounding of every activation limits agreement; the gradients must point
+    the same way (cosine > 0.98) and agree in norm within 10 %."""
+    torch, sg = env
+    from paper_2012_06144_amd import surrogate as S
+    net = S.Net(seed=5)
+    rng = np.random.default_rng(14)
+    xt, x = _bf16(torch, rng.standard_normal((1, 8, 8, 8, 16)) * np.r_[np.ones(5), np.zeros(11)])
+    tgt = rng.standard_normal((1, 8, 8, 8, 32)).astype(np.float32)
+    tgt[..., 5:] = 0
+    out = net.forward(xt)
+    loss = torch.zeros(1, device="cuda")
+    scratch = torch.zeros(1024, device="cuda")
+    g = torch.empty(out.shape, device="cuda", dtype=torch.bfloat16)
+    sg.sg_mse(out, torch.from_numpy(tgt).cuda(), loss, g, scratch)
+    net.backward(g)
+    torch.cuda.synchronize()
+    W = {k: d["wt"].float().cpu().numpy().astype(np.float64) for k, d in net.p.items()}
+    B = {k: d["b"].cpu().numpy().astype(np.float64) for k, d in net.p.items()}
+
+    def fwd(x):
+        a = {}
+        c = lambda k, t, act=True: oc.leaky(oc.conv3d(t, W[k], B[k]), 0.1) if act else oc.conv3d(t, W[k], B[k])
+        a["x"] = x
+        a["e0a"] = c("enc0a", x); a["s0"] = c("enc0b", a["e0a"]); a["p1"] = oc.pool2(a["s0"])
+        a["e1a"] = c("enc1a", a["p1"]); a["s1"] = c("enc1b", a["e1a"]); a["p2"] = oc.pool2(a["s1"])
+        a["e2a"] = c("enc2a", a["p2"]); a["s2"] = c("enc2b", a["e2a"]); a["p3"] = oc.pool2(a["s2"])
+        a["ba"] = c("bot_a", a["p3"]); a["bb"] = c("bot_b", a["ba"])
+        a["c2"] = np.concatenate([oc.up2(a["bb"]), a["s2"]], -1)
+        a["d2a"] = c("dec2a", a["c2"]); a["t2"] = c("dec2b", a["d2a"])
+        a["c1"] = np.concatenate([oc.up2(a["t2"]), a["s1"]], -1)
+        a["d1a"] = c("dec1a", a["c1"]); a["t1"] = c("dec1b", a["d1a"])
+        a["c0"] = np.concatenate([oc.up2(a["t1"]), a["s0"]], -1)
+        a["d0a"] = c("dec0a", a["c0"]); a["t0"] = c("dec0b", a["d0a"])
+        return c("out", a["t0"], act=False), a
+
+    ref_out, a = fwd(x)
+    _, gout = oc.mse(ref_out, tgt.astype(np.float64))
+    # reverse pass with the oracle's operations
+    G = {}
+
+    def bw(k, xin, y, dy, act=True):
+        dp = dy * np.where(y > 0, 1.0, 0.1) if act else dy
+        G[k] = oc.conv3d_bwd_weight(xin, dp)[0]
+        return oc.conv3d_bwd_data(dp, W[k])
+    gt0 = bw("out", a["t0"], None, gout, act=False)
+    g = bw("dec0b", a["d0a"], a["t0"], gt0); g = bw("dec0a", a["c0"], a["d0a"], g)
+    gs0 = g[..., 64:]; g = oc.pool2(g[..., :64]) * 8
+    g = bw("dec1b", a["d1a"], a["t1"], g); g = bw("dec1a", a["c1"], a["d1a"], g)
+    gs1 = g[..., 128:]; g = oc.pool2(g[..., :128]) * 8
+    g = bw("dec2b", a["d2a"], a["t2"], g); g = bw("dec2a", a["c2"], a["d2a"], g)
+    gs2 = g[..., 128:]; g = oc.pool2(g[..., :128]) * 8
+    g = bw("bot_b", a["ba"], a["bb"], g); g = bw("bot_a", a["p3"], a["ba"], g)
+    gs2 = gs2 + oc.up2(g) / 8
+    g = bw("enc2b", a["e2a"], a["s2"], gs2); g = bw("enc2a", a["p2"], a["e2a"], g)
+    gs1 = gs1 + oc.up2(g) / 8
+    g = bw("enc1b", a["e1a"], a["s1"], gs1); g = bw("enc1a", a["p1"], a["e1a"], g)
+    gs0 = gs0 + oc.up2(g) / 8
+    g = bw("enc0b", a["e0a"], a["s0"], gs0); bw("enc0a", a["x"], a["e0a"], g)
+    for k in ("out", "dec0a", "dec2b", "bot_a", "enc1b", "enc0a"):
+        gg = net.p[k]["gw"].cpu().numpy().ravel().astype(np.float64)
+        rr = G[k].ravel()
+        cos = gg @ rr / (np.linalg.norm(gg) * np.linalg.norm(rr))
+        assert cos > 0.98, (k, cos)
+        assert abs(np.linalg.norm(gg) / np.linalg.norm(rr) - 1) < 0.1, k
