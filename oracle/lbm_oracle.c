@@ -413,6 +413,25 @@ static void iso_gradient(const orc_params *p, const double *phi, int q, int x, i
 }
 
 /* Isotropic Laplacian (eq. lap): (2/cs^2) sum_i w_i [phi(x+e_i) - phi(x)]. */
+/* Density and relaxation time of a cell (eq. density and the tau
+ * interpolation of Sec. 3.2): linear in phi between the two bulk phases.
+ * The interpolation is defined on [phi_L, phi_H]; the conservative
+ * Allen-Cahn model overshoots that interval by ~1e-3 (most in the cores of
+ * small bubbles, where |grad phi| ~ 0), and at rho_H/rho_L = 1000 an
+ * undershoot of 1e-3 would put rho near zero.  phi is therefore clamped to
+ * the interval before interpolating, which keeps rho in [rho_L, rho_H].   */
+static double phase_clamp(const orc_params *p, double phi)
+{
+    const double lo = p->phi_L < p->phi_H ? p->phi_L : p->phi_H;
+    const double hi = p->phi_L < p->phi_H ? p->phi_H : p->phi_L;
+    return phi < lo ? lo : (phi > hi ? hi : phi);
+}
+
+static double density_of(const orc_params *p, double phi)
+{
+    return p->rho_L + (phase_clamp(p, phi) - p->phi_L) * (p->rho_H - p->rho_L) / (p->phi_H - p->phi_L);
+}
+
 static double iso_laplacian(const orc_params *p, const double *phi, int q, int x, int y, int z)
 {
     const int (*E)[3] = (q == Q15) ? E15 : E27;
@@ -545,8 +564,8 @@ static void hydro_cell(orc_state *s, int x, int y, int z)
 
     const double dphi = p->phi_H - p->phi_L;
     double phi = s->phiB[c];
-    double rho = p->rho_L + (phi - p->phi_L) * (p->rho_H - p->rho_L) / dphi;
-    double tau = p->tau_L + (phi - p->phi_L) * (p->tau_H - p->tau_L) / dphi;
+    double rho = density_of(p, phi);
+    double tau = p->tau_L + (phase_clamp(p, phi) - p->phi_L) * (p->tau_H - p->tau_L) / dphi;
     double s_nu = 1.0 / (tau + 0.5);
     double nu = tau * CS2;
 
@@ -655,13 +674,12 @@ void orc_pressure(const orc_state *s, double *pout)
 {
     const orc_params *p = &s->p;
     const int64_t n = s->n;
-    const double dphi = p->phi_H - p->phi_L;
     for (int64_t c = 0; c < n; ++c) {
         int y = (int)((c / p->nx) % p->ny);
         if (is_wall_row(p, y)) { pout[c] = 0.0; continue; }
         double ps = 0.0;
         for (int i = 0; i < Q27; ++i) ps += s->G[i * n + c];
-        double rho = p->rho_L + (s->phiA[c] - p->phi_L) * (p->rho_H - p->rho_L) / dphi;
+        double rho = density_of(p, s->phiA[c]);
         pout[c] = ps * rho * CS2;
     }
 }
@@ -684,7 +702,7 @@ void orc_stats_compute(const orc_state *s, orc_stats *out)
             for (int x = 0; x < p->nx; ++x) {
                 int64_t c = cidx(p, x, y, z);
                 double phi = s->phiA[c];
-                double rho = p->rho_L + (phi - p->phi_L) * (p->rho_H - p->rho_L) / dphi;
+                double rho = density_of(p, phi);
                 double ux = s->u[c], uy = s->u[n + c], uz = s->u[2 * n + c];
                 double chi = (p->phi_H - phi) / dphi;
                 double grad[3];

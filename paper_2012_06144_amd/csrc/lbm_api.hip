@@ -117,6 +117,8 @@ Phys<R> make_phys(const lbm_params *p)
     ph.phi_H = (R)p->phi_H;
     ph.phi_0 = (R)(0.5 * (p->phi_L + p->phi_H));
     ph.inv_dphi = (R)(1.0 / (p->phi_H - p->phi_L));
+    ph.phi_lo = (R)(p->phi_L < p->phi_H ? p->phi_L : p->phi_H);
+    ph.phi_hi = (R)(p->phi_L < p->phi_H ? p->phi_H : p->phi_L);
     ph.xi = (R)p->xi;
     const double tau_phi = p->mobility / CS2;  // eq. mobility with dt = 1
     ph.omega_phi = (R)(1.0 / (tau_phi + 0.5));

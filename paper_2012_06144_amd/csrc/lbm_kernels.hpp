@@ -49,6 +49,7 @@ constexpr int kRedVals = 12;      // 11 sums + 1 max
 template <class R>
 struct Phys {
     R phi_L, phi_H, phi_0, inv_dphi;     // inv_dphi = 1/(phi_H - phi_L)
+    R phi_lo, phi_hi;                    // min and max of phi_L, phi_H
     R xi, omega_phi;                     // phase-field relaxation rate
     R rho_L, drho;                       // drho = rho_H - rho_L
     R tau_L, dtau;                       // dtau = tau_H - tau_L
@@ -57,6 +58,22 @@ struct Phys {
     R rho_ref;                           // F_b = (rho - rho_ref) accel
     R normal_eps;
 };
+
+// Density and relaxation time of a cell (eq. density, tau interpolation of
+// Sec. 3.2), linear in phi between the bulk phases.  phi is clamped to
+// [phi_L, phi_H] first: the phase field overshoots that interval by ~1e-3
+// in the cores of small bubbles, and at rho_H/rho_L = 1000 an undershoot
+// of 1e-3 would put rho near zero.
+template <class R>
+__host__ __device__ inline R phase_clamp(const Phys<R> &ph, R phi)
+{
+    return phi < ph.phi_lo ? ph.phi_lo : (phi > ph.phi_hi ? ph.phi_hi : phi);
+}
+template <class R>
+__host__ __device__ inline R density_of(const Phys<R> &ph, R phi)
+{
+    return ph.rho_L + (phase_clamp(ph, phi) - ph.phi_L) * ph.drho * ph.inv_dphi;
+}
 
 // Division by a run-time invariant d >= 1 with a multiply-high and shifts
 // (Granlund and Montgomery, "Division by invariant integers using
@@ -369,8 +386,8 @@ __global__ __launch_bounds__(kBlock) void k_hydro(const SweepArgs<S> a)
     stencil<27, R, true>(a.phi_in, c, n, grad, lap);
 
     const Phys<R> &ph = a.ph;
-    const R rho = ph.rho_L + (phi - ph.phi_L) * ph.drho * ph.inv_dphi;
-    const R tau = ph.tau_L + (phi - ph.phi_L) * ph.dtau * ph.inv_dphi;
+    const R rho = density_of(ph, phi);
+    const R tau = ph.tau_L + (phase_clamp(ph, phi) - ph.phi_L) * ph.dtau * ph.inv_dphi;
     const R s = R(1) / (tau + R(0.5));
     const R nu = tau * cs2<R>();
     R grho[3];
@@ -442,7 +459,7 @@ __global__ __launch_bounds__(kBlock) void k_equilibrium(typename S::pdf_t *__res
     R ux = wall ? R(0) : R(u_in[c]), uy = wall ? R(0) : R(u_in[N + c]), uz = wall ? R(0) : R(u_in[2 * N + c]);
     R ps = wall ? R(0) : R(p_in[c]);
     if (p_is_pressure && !wall) {
-        const R rho = ph.rho_L + (phi - ph.phi_L) * ph.drho * ph.inv_dphi;
+        const R rho = density_of(ph, phi);
         ps = ps / (rho * cs2<R>());
     }
     const R uu = ux * ux + uy * uy + uz * uz;
@@ -561,7 +578,7 @@ __global__ __launch_bounds__(kBlock) void k_get_macro(const typename S::pdf_t *_
         if (fluid)
 #pragma unroll
             for (int i = 0; i < 27; ++i) ps += dec_g<S>(G[pull_idx<27>(i, c, n)], i);
-        const R rho = ph.rho_L + (phiA[c] - ph.phi_L) * ph.drho * ph.inv_dphi;
+        const R rho = density_of(ph, phiA[c]);
         p_o[c] = fluid ? Out(ps * rho * cs2<R>()) : Out(0);
     }
 }
@@ -605,7 +622,8 @@ __global__ __launch_bounds__(kBlock) void k_reduce1(const typename S::real *__re
         const double phi = (double)phiA[c];
         v[0] += phi;
         if (mass_only) continue;
-        const double rho = (double)ph.rho_L + (phi - phiL) * (double)ph.drho * idp;
+        const double phc = phi < (double)ph.phi_lo ? (double)ph.phi_lo : (phi > (double)ph.phi_hi ? (double)ph.phi_hi : phi);
+        const double rho = (double)ph.rho_L + (phc - phiL) * (double)ph.drho * idp;
         const double ux = u[c], uy = u[g.fplane + c], uz = u[2 * g.fplane + c];
         const double chi = (phiH - phi) * idp;
         R grad[3], lapu;

@@ -252,76 +252,95 @@ class Net:
 @dataclass
 class DataConfig:
     """Rising-bubble runs on an nx x ny x nz grid with seeded diameter, Eotvos
-    number and centre offset; a crop of `box` cells around the bubble every
-    `every` steps from step `start`."""
-    n_runs: int = 32
+    number and centre offset.  Snapshots of (phi, u, p) every `every` steps
+    from step `start`; `pairs_per_run` pairs (t, t + K) per run, each cropped
+    to `box` cells with the window centred on the bubble at t (the same window
+    for both states of a pair)."""
+    n_runs: int = 200
     grid: tuple = (128, 256, 128)
     d_range: tuple = (16.0, 40.0)
     eo_range: tuple = (2.0, 20.0)
     offset: float = 8.0
-    steps: int = 3000
+    centre_y: float = 80.0
+    steps: int = 6000
+    start: int = 400
     every: int = 50
-    start: int = 200
     K: int = 200
-    box: tuple = (64, 96, 64)      # (bx, by, bz)
+    pairs_per_run: int = 10
+    box: tuple = (80, 96, 80)      # (bx, by, bz), each divisible by 8
     seed: int = 7
     storage: str = "f32"
 
 
+def _window(cent, box, grid):
+    bx, by, bz = box
+    nx, ny, nz = grid
+    y0 = int(min(max(round(cent[1]) - by // 2, 1), ny - 1 - by))
+    return (int(round(cent[0])) - bx // 2, y0, int(round(cent[2])) - bz // 2, bx, by, bz)
+
+
 def generate_snapshots(cfg: DataConfig, device="cuda:0", log=print):
-    """Runs the solver and returns FP32 crops (runs, snapshots, bz*by*bx*5) on
-    the device, with the crop box of each snapshot kept fixed per pair so the
-    target is the change inside one window."""
+    """Runs the solver and returns the FP32 crops S0, S1 (pairs, bz*by*bx*5,
+    channels last) on the device, the run index of every pair and the run
+    parameters."""
     import torch
 
     from . import inputs, lbm
     rng = np.random.default_rng(cfg.seed)
     nx, ny, nz = cfg.grid
     bx, by, bz = cfg.box
+    V = bx * by * bz
     nsnap = (cfg.steps - cfg.start) // cfg.every + 1
     lag = cfg.K // cfg.every
-    V = bx * by * bz
-    pairs_s0, pairs_s1 = [], []
+    assert lag * cfg.every == cfg.K and nsnap > lag
+    npr = min(cfg.pairs_per_run, nsnap - lag)
+    ks = sorted(set(np.linspace(0, nsnap - lag - 1, npr).round().astype(int).tolist()))
+    S0 = torch.empty((cfg.n_runs * len(ks), V * NCH), device=device, dtype=torch.float32)
+    S1 = torch.empty_like(S0)
+    xb = torch.empty(V * C_IN, device=device, dtype=torch.bfloat16)
+    run_of = []
     meta = []
+    slot = 0
+    t0 = time.perf_counter()
     for r in range(cfg.n_runs):
-        D = rng.uniform(*cfg.d_range)
-        eo = rng.uniform(*cfg.eo_range)
+        D = float(rng.uniform(*cfg.d_range))
+        eo = float(rng.uniform(*cfg.eo_range))
         off = rng.uniform(-cfg.offset, cfg.offset, 3)
-        g = eo * 1e-4 / (1.0 * D * D)
-        c = (nx / 2 + off[0], 72.0 + off[1], nz / 2 + off[2])
+        g = eo * 1e-4 / (1.0 * D * D)          # Eo = g rho_H D^2 / sigma, sigma = 1e-4, rho_H = 1
+        c = (nx / 2 + off[0], cfg.centre_y + off[1], nz / 2 + off[2])
         s = inputs.rising_bubble(nx, ny, nz, D=D, center=c, g=g)
         phi, u, ps = inputs.build_fields(s)
         sv = lbm.Solver(s.physics(), storage=cfg.storage, device=device)
         sv.init_fields(phi, u, ps)
         sv.step(cfg.start)
-        snaps = []
-        cents = []
+        pending = {}
+        y_first = None
         for k in range(nsnap):
             if k:
                 sv.step(cfg.every)
-            ph, uu, pp = sv.macroscopic(torch.float32)
-            cents.append(sv.stats()["centroid"])
-            snaps.append((ph, uu, pp))
-        # pair (k, k + lag) cropped with the window centred on the bubble at k
-        for k in range(nsnap - lag):
-            cx, cy, cz = cents[k]
-            y0 = int(min(max(round(cy) - by // 2, 1), ny - 1 - by))
-            box = (int(round(cx)) - bx // 2, y0, int(round(cz)) - bz // 2, bx, by, bz)
-            s0 = torch.empty(V * NCH, device=device, dtype=torch.float32)
-            s1 = torch.empty_like(s0)
-            xb = torch.empty(V * C_IN, device=device, dtype=torch.bfloat16)
-            sg.sg_fields_to_input(*snaps[k], nx, ny, nz, box, [1] * 5, C_IN, xb, s0)
-            sg.sg_fields_to_input(*snaps[k + lag], nx, ny, nz, box, [1] * 5, C_IN, xb, s1)
-            pairs_s0.append(s0)
-            pairs_s1.append(s1)
-        meta.append({"D": D, "Eo": eo, "g": g, "centre": list(c)})
-        log(f"[data] run {r}: D={D:.1f} Eo={eo:.1f} -> {nsnap - lag} pairs, "
-            f"rise {cents[-1][1] - cents[0][1]:.2f} cells")
-        del sv, snaps
-        torch.cuda.empty_cache()
-    S0 = torch.stack(pairs_s0)
-    S1 = torch.stack(pairs_s1)
-    return S0, S1, meta
+            if k not in ks and k not in pending:
+                continue
+            fields = sv.macroscopic(torch.float32)
+            if k in pending:
+                j, box = pending.pop(k)
+                sg.sg_fields_to_input(*fields, nx, ny, nz, box, [1.0] * NCH, C_IN, xb, S1[j])
+            if k in ks:
+                cent = sv.stats()["centroid"]
+                if y_first is None:
+                    y_first = cent[1]
+                box = _window(cent, cfg.box, cfg.grid)
+                sg.sg_fields_to_input(*fields, nx, ny, nz, box, [1.0] * NCH, C_IN, xb, S0[slot])
+                pending[k + lag] = (slot, box)
+                run_of.append(r)
+                slot += 1
+            del fields
+        y_last = sv.stats()["centroid"][1]
+        meta.append({"D": D, "Eo": eo, "g": g, "centre": [float(v) for v in c]})
+        log(f"[data] run {r}: D={D:.1f} Eo={eo:.1f}: {len(ks)} pairs, rise {y_last - y_first:.2f} cells "
+            f"({time.perf_counter() - t0:.0f}s)")
+        del sv
+    torch.cuda.synchronize()
+    return S0[:slot], S1[:slot], np.array(run_of), meta
 
 
 def channel_scales(S0, S1):
@@ -349,18 +368,25 @@ def make_batch(net, S0, S1, idx, box):
     return x, t
 
 
-def train(net, S0, S1, box, steps=500, batch=8, lr=1e-3, val_frac=0.1, seed=0, log=print):
-    """Adam on the MSE of the normalised increment; returns the loss history
-    and the validation losses of the network and of persistence (increment 0)."""
+def train(net, S0, S1, box, run_of=None, steps=500, batch=8, lr=5e-4, warmup=20, val_frac=0.1, seed=0,
+          log=print):
+    """Adam on the MSE of the normalised increment, linear warm-up over
+    `warmup` steps, then cosine learning-rate decay.  Validation pairs are whole runs held out (pairs of one run are
+    correlated).  Returns the loss history and the validation losses of the
+    network and of persistence (increment 0)."""
     import torch
     n = S0.shape[0]
     rng = np.random.default_rng(seed)
-    perm = rng.permutation(n)
-    nval = max(1, int(val_frac * n))
-    val, tr = perm[:nval], perm[nval:]
+    if run_of is None:
+        run_of = np.arange(n)
+    runs = np.unique(run_of)
+    vr = rng.permutation(runs)[:max(1, int(round(val_frac * len(runs))))]
+    val = np.nonzero(np.isin(run_of, vr))[0]
+    tr = np.nonzero(~np.isin(run_of, vr))[0]
     loss = torch.zeros(1, device=S0.device, dtype=torch.float32)
     scratch = torch.zeros(1024, device=S0.device, dtype=torch.float32)
     hist = []
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
     for it in range(steps):
         idx = rng.choice(tr, size=min(batch, len(tr)), replace=False)
@@ -369,9 +395,9 @@ def train(net, S0, S1, box, steps=500, batch=8, lr=1e-3, val_frac=0.1, seed=0, l
         g = torch.empty(out.shape, device=out.device, dtype=torch.bfloat16)
         sg.sg_mse(out, t, loss, g, scratch)
         net.backward(g)
-        cur_lr = lr * 0.5 * (1 + math.cos(math.pi * it / steps))
+        cur_lr = lr * min(1.0, (it + 1) / max(1, warmup)) * 0.5 * (1 + math.cos(math.pi * it / steps))
         net.adam(cur_lr)
-        if it % 25 == 0 or it == steps - 1:
+        if it % 50 == 0 or it == steps - 1:
             lv = float(loss.item())
             hist.append((it, lv))
             log(f"[train] step {it} loss {lv:.4e} ({time.perf_counter() - t0:.1f}s)")
@@ -379,7 +405,7 @@ def train(net, S0, S1, box, steps=500, batch=8, lr=1e-3, val_frac=0.1, seed=0, l
     wall = time.perf_counter() - t0
     v_net, v_zero = evaluate(net, S0, S1, val, box)
     return {"history": hist, "val_loss": v_net, "val_loss_persistence": v_zero, "seconds": wall,
-            "n_train": int(len(tr)), "n_val": int(nval)}
+            "n_train": int(len(tr)), "n_val": int(len(val)), "val_runs": [int(v) for v in vr]}
 
 
 def evaluate(net, S0, S1, idx, box, batch=8):
@@ -413,43 +439,60 @@ class JumpConfig:
     mass_tol: float = 1e-6      # |d sum(phi)| / sum(phi) over a cycle
     xi_lo: float = 0.8          # interface width must stay in [xi_lo, xi_hi] * xi
     xi_hi: float = 1.25
+    box: tuple = (112, 128, 112)  # prediction window around the bubble (bx, by, bz), divisible by 8
 
 
-def predict_into_fields(net, phi, u, p, nx, ny, nz, walls_y, phi_L, phi_H):
-    """One network prediction over the whole grid (D, H, W divisible by 8),
-    added to the FP32 fields in place."""
+def predict_into_fields(net, phi, u, p, setup, box):
+    """One network prediction over `box` (x0, y0, z0, bx, by, bz), added to
+    the FP32 fields in place; the fields outside the box are left as they are."""
     import torch
-    box = (0, 0, 0, nx, ny, nz)
-    x = torch.empty((1, nz, ny, nx, C_IN), device=phi.device, dtype=torch.bfloat16)
-    sg.sg_fields_to_input(phi, u, p, nx, ny, nz, box, net.scale_in, C_IN, x)
+    bx, by, bz = box[3], box[4], box[5]
+    x = torch.empty((1, bz, by, bx, C_IN), device=phi.device, dtype=torch.bfloat16)
+    sg.sg_fields_to_input(phi, u, p, setup.nx, setup.ny, setup.nz, box, net.scale_in, C_IN, x)
     out = net.forward(x, keep=False)
-    del x
-    sg.sg_apply_prediction(out, C_OUT, net.scale_out, phi, u, p, nx, ny, nz, box, walls_y, phi_L, phi_H)
-    del out
+    sg.sg_apply_prediction(out, C_OUT, net.scale_out, phi, u, p, setup.nx, setup.ny, setup.nz, box,
+                           int(setup.walls_y), setup.phi_L, setup.phi_H)
 
 
-def run_with_jumps(net, solver, setup, total_steps, jc: JumpConfig, log=print, every_stats=None):
-    """Advance `solver` by total_steps with cycles of (jump K, relax) and
-    fallback; returns the trajectory and counts."""
+def _traj_entry(step, st, **kw):
+    d = {"step": step, "centroid_y": st["centroid"][1], "rise_velocity": st["rise_velocity"], "mass": st["mass"],
+         "xi_eff": st["xi_eff"]}
+    d.update(kw)
+    return d
+
+
+def run_with_jumps(net, solver, setup, total_steps, jc: JumpConfig, log=print):
+    """Advances `solver` by total_steps in cycles of one jump (K steps
+    predicted) plus jc.relax LBM steps.  After each cycle the indicators are
+    checked (finite, mass drift over the cycle <= mass_tol, interface width in
+    [xi_lo, xi_hi] xi); if one trips, the state saved before the jump is
+    restored and the cycle's K + relax steps are run with the plain LBM.
+    With net=None the jump leaves the fields unchanged (persistence), the
+    same driver without the network."""
     import torch
-    nx, ny, nz = setup.nx, setup.ny, setup.nz
     backup = solver.new_state_buffer()
     scratch = torch.zeros(2048, device=solver.device, dtype=torch.float64)
     done = 0
-    traj = []
     accepted = rejected = 0
-    st = solver.stats()
-    traj.append({"step": 0, "centroid_y": st["centroid"][1], "rise_velocity": st["rise_velocity"],
-                 "mass": st["mass"]})
+    traj = [_traj_entry(0, solver.stats())]
     cyc = jc.K + jc.relax
+    t_pred = 0.0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
     while done + cyc <= total_steps:
         m0 = solver.reduce_mass()
+        cent = solver.stats()["centroid"]
         solver.save_state(backup)
         phi, u, p = solver.macroscopic(torch.float32)
-        predict_into_fields(net, phi, u, p, nx, ny, nz, setup.walls_y, setup.phi_L, setup.phi_H)
+        box = _window(cent, jc.box, (setup.nx, setup.ny, setup.nz))
+        tp = time.perf_counter()
+        if net is not None:
+            predict_into_fields(net, phi, u, p, setup, box)
         sg.sg_mass_project(phi, m0, setup.phi_L, setup.phi_H, scratch)
         solver.set_macroscopic(phi, u, p)
         del phi, u, p
+        torch.cuda.synchronize()
+        t_pred += time.perf_counter() - tp
         solver.step(jc.relax)
         st = solver.stats()
         drift = abs(st["mass"] - m0) / abs(m0)
@@ -463,13 +506,171 @@ def run_with_jumps(net, solver, setup, total_steps, jc: JumpConfig, log=print, e
             solver.step(cyc)
             st = solver.stats()
         done += cyc
-        traj.append({"step": done, "centroid_y": st["centroid"][1], "rise_velocity": st["rise_velocity"],
-                     "mass": st["mass"], "jump": bool(ok), "drift": drift, "xi_eff": st["xi_eff"]})
+        traj.append(_traj_entry(done, st, jump=bool(ok), drift=drift))
     if done < total_steps:
         solver.step(total_steps - done)
-        st = solver.stats()
         done = total_steps
-        traj.append({"step": done, "centroid_y": st["centroid"][1], "rise_velocity": st["rise_velocity"],
-                     "mass": st["mass"]})
+        traj.append(_traj_entry(done, solver.stats()))
     torch.cuda.synchronize()
-    return {"trajectory": traj, "accepted": accepted, "rejected": rejected}
+    wall = time.perf_counter() - t0
+    log(f"[jump] {accepted} accepted, {rejected} rejected, {wall:.1f}s ({t_pred:.1f}s predicting)")
+    return {"trajectory": traj, "accepted": accepted, "rejected": rejected, "seconds": wall,
+            "seconds_predict": t_pred}
+
+
+def run_plain(solver, total_steps, every, log=print):
+    """The plain LBM with the same statistics cadence as the jump driver."""
+    import torch
+    traj = [_traj_entry(0, solver.stats())]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    done = 0
+    while done < total_steps:
+        n = min(every, total_steps - done)
+        solver.step(n)
+        done += n
+        traj.append(_traj_entry(done, solver.stats()))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    log(f"[plain] {total_steps} steps, {wall:.1f}s")
+    return {"trajectory": traj, "seconds": wall}
+
+
+def compare_trajectories(ref, run):
+    """Rise velocity (centroid slope over the second half) and centroid
+    errors of `run` against `ref` at the steps both recorded."""
+    rs = {e["step"]: e for e in ref["trajectory"]}
+    common = [e for e in run["trajectory"] if e["step"] in rs]
+    steps = np.array([e["step"] for e in common], dtype=np.float64)
+    y = np.array([e["centroid_y"] for e in common])
+    yr = np.array([rs[e["step"]]["centroid_y"] for e in common])
+    half = len(steps) // 2
+    slope = np.polyfit(steps[half:], y[half:], 1)[0]
+    slope_r = np.polyfit(steps[half:], yr[half:], 1)[0]
+    ur = np.array([rs[e["step"]]["rise_velocity"] for e in common])
+    uu = np.array([e["rise_velocity"] for e in common])
+    return {"centroid_err_max_cells": float(np.max(np.abs(y - yr))),
+            "centroid_err_final_cells": float(abs(y[-1] - yr[-1])),
+            "rise_rel_err_centroid_slope": float(abs(slope - slope_r) / abs(slope_r)),
+            "rise_rel_err_velocity_final": float(abs(uu[-1] - ur[-1]) / abs(ur[-1])),
+            "rise_rel_err_velocity_max_2nd_half": float(np.max(np.abs(uu[half:] - ur[half:])) / np.max(np.abs(ur[half:]))),
+            "rise_ref_cells": float(yr[-1] - yr[0])}
+
+
+# ---------------------------------------------------------------------------------------
+# persistence and command line
+# ---------------------------------------------------------------------------------------
+
+def save_weights(net, path):
+    """FP32 master weights, biases and the normalisation scales (safetensors)."""
+    from safetensors.torch import save_file
+    t = {}
+    for k, d in net.p.items():
+        t[k + ".w"] = d["w"].detach().cpu().contiguous()
+        t[k + ".b"] = d["b"].detach().cpu().contiguous()
+    meta = {"scale_in": json.dumps(net.scale_in), "scale_out": json.dumps(net.scale_out),
+            "steps": str(net.step_count)}
+    save_file(t, path, metadata=meta)
+
+
+def load_weights(net, path):
+    from safetensors import safe_open
+    with safe_open(path, framework="pt") as f:
+        meta = f.metadata()
+        for k, d in net.p.items():
+            d["w"].copy_(f.get_tensor(k + ".w").to(d["w"].device))
+            d["b"].copy_(f.get_tensor(k + ".b").to(d["b"].device))
+            sg.sg_to_bf16(d["w"], d["wt"])
+    net.scale_in = json.loads(meta["scale_in"])
+    net.scale_out = json.loads(meta["scale_out"])
+    net.step_count = int(meta["steps"])
+
+
+def _cmd_train(a):
+    import torch
+    cfg = DataConfig(n_runs=a.runs, steps=a.lbm_steps, pairs_per_run=a.pairs_per_run)
+    t0 = time.perf_counter()
+    S0, S1, run_of, meta = generate_snapshots(cfg, log=_log)
+    torch.cuda.synchronize()
+    t_data = time.perf_counter() - t0
+    net = Net(seed=a.seed)
+    net.scale_in, net.scale_out = channel_scales(S0, S1)
+    res = train(net, S0, S1, cfg.box, run_of=run_of, steps=a.train_steps, batch=a.batch, lr=a.lr, log=_log)
+    res.update({"data_seconds": t_data, "pairs": int(S0.shape[0]), "runs": meta, "config": cfg.__dict__,
+                "scale_in": net.scale_in, "scale_out": net.scale_out, "params": net.n_params()})
+    _log(f"[train] val loss {res['val_loss']:.4e} vs persistence {res['val_loss_persistence']:.4e}")
+    if a.weights:
+        save_weights(net, a.weights)
+    return res
+
+
+def _cmd_jump(a):
+    import torch
+
+    from . import inputs, lbm
+    s = inputs.surrogate_jump_bubble(steps=a.steps)
+    if a.grid:
+        nx, ny, nz = (int(v) for v in a.grid.split("x"))
+        s = inputs.rising_bubble(nx, ny, nz, D=s.radius * 2, center=(nx / 2, ny / 4, nz / 2),
+                                 g=-s.accel[1], steps=a.steps)
+    phi, u, ps = inputs.build_fields(s)
+    jc = JumpConfig(K=a.K, relax=a.relax)
+    out = {"workload": s.name, "steps": a.steps, "jump": jc.__dict__, "runs": {}}
+    sv = lbm.Solver(s.physics(), storage="f32")
+    sv.init_fields(phi, u, ps)
+    out["runs"]["plain"] = run_plain(sv, a.steps, jc.K + jc.relax, log=_log)
+    del sv
+    torch.cuda.empty_cache()
+    variants = [("persistence", None)]
+    if a.weights:
+        net = Net(seed=0)
+        load_weights(net, a.weights)
+        variants.append(("surrogate", net))
+    for name, net in variants:
+        sv = lbm.Solver(s.physics(), storage="f32")
+        sv.init_fields(phi, u, ps)
+        r = run_with_jumps(net, sv, s, a.steps, jc, log=_log)
+        r["errors"] = compare_trajectories(out["runs"]["plain"], r)
+        r["speedup"] = out["runs"]["plain"]["seconds"] / r["seconds"]
+        out["runs"][name] = r
+        _log(f"[jump] {name}: speedup {r['speedup']:.2f}x, errors {r['errors']}")
+        del sv
+        torch.cuda.empty_cache()
+    return out
+
+
+def _log(msg):
+    import sys
+    print(msg, file=sys.stderr, flush=True)
+
+
+def main():
+    import argparse
+    ap = argparse.ArgumentParser(description="surrogate training data, training and jump study")
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    t = sub.add_parser("train")
+    t.add_argument("--runs", type=int, default=200)
+    t.add_argument("--lbm-steps", type=int, default=6000)
+    t.add_argument("--pairs-per-run", type=int, default=10)
+    t.add_argument("--train-steps", type=int, default=2000)
+    t.add_argument("--batch", type=int, default=8)
+    t.add_argument("--lr", type=float, default=5e-4)
+    t.add_argument("--seed", type=int, default=0)
+    t.add_argument("--weights", default=None)
+    t.add_argument("--out", default=None)
+    j = sub.add_parser("jump")
+    j.add_argument("--weights", default=None)
+    j.add_argument("--steps", type=int, default=40000)
+    j.add_argument("--K", type=int, default=200)
+    j.add_argument("--relax", type=int, default=50)
+    j.add_argument("--grid", default=None, help="override the grid, e.g. 128x512x128")
+    j.add_argument("--out", default=None)
+    a = ap.parse_args()
+    res = _cmd_train(a) if a.cmd == "train" else _cmd_jump(a)
+    if a.out:
+        with open(a.out, "w") as f:
+            json.dump(res, f, indent=1)
+
+
+if __name__ == "__main__":
+    main()

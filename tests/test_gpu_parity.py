@@ -70,6 +70,8 @@ SMALL = {
                                            accel=(1e-5, 0.0, 0.0), xi=4.0, sigma=1e-4),
     "one_fluid_row": lambda: inputs.rising_bubble(12, 3, 10, D=4.0, center=(6.0, 1.0, 5.0), g=1e-5)
     .with_grid(12, 3, 10, noise=1e-4),
+    "bubble_core_undershoot": lambda: inputs.rising_bubble(40, 40, 40, D=23.518, center=(20.438, 20.107, 20.264))
+    .with_grid(40, 40, 40, walls_y=False),
     "cube_2": lambda: inputs.static_droplet(n=2, R=0.7, noise=1e-3),
     "cube_1": lambda: inputs.Setup(name="c1", nx=1, ny=1, nz=1, walls_y=False, kind="uniform",
                                    noise=1e-3, rho_L=1.0, rho_H=10.0, tau_L=1.0, tau_H=1.0, xi=4.0),

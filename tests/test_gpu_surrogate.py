@@ -281,3 +281,22 @@ def test_network_gradient_against_oracle(env):
         cos = gg @ rr / (np.linalg.norm(gg) * np.linalg.norm(rr))
         assert cos > 0.98, (k, cos)
         assert abs(np.linalg.norm(gg) / np.linalg.norm(rr) - 1) < 0.1, k
+
+
+def test_trained_network_beats_persistence(env):
+    """What the learned part gains over the method without it: on held-out
+    rising-bubble runs the trained network's prediction of the state 200
+    steps ahead has a smaller error than persistence (the state left as it
+    is, which is what a jump without the network does)."""
+    torch, sg = env
+    from paper_2012_06144_amd import surrogate as S
+    cfg = S.DataConfig(n_runs=4, grid=(64, 128, 64), d_range=(12.0, 16.0), eo_range=(5.0, 15.0), offset=4.0,
+                       centre_y=40.0, steps=1400, start=200, every=50, K=200, pairs_per_run=6, box=(32, 48, 32))
+    S0, S1, run_of, _ = S.generate_snapshots(cfg, log=lambda m: None)
+    net = S.Net(seed=1)
+    net.scale_in, net.scale_out = S.channel_scales(S0, S1)
+    res = S.train(net, S0, S1, cfg.box, run_of=run_of, steps=150, batch=8, lr=5e-4, warmup=15, val_frac=0.25,
+                  log=print)
+    print("validation loss", res["val_loss"], "persistence", res["val_loss_persistence"])
+    assert np.isfinite(res["val_loss"])
+    assert res["val_loss"] < 0.6 * res["val_loss_persistence"]
