@@ -46,7 +46,8 @@ size_t sg_bwd_weight_workspace(int32_t n, int32_t d, int32_t h, int32_t w, int32
 
 /* dw[t][co][ci] = sum_v dy[v][co] x[v + offset(t)][ci] and db[co] = sum_v dy[v][co]
  * (FP32 outputs, overwritten), deterministic two-pass reduction through
- * `workspace` (sg_bwd_weight_workspace bytes).  db may be NULL. */
+ * `workspace` (sg_bwd_weight_workspace bytes; 0 for an invalid shape).  x and
+ * dy 16-byte aligned; db may be NULL. */
 sg_status sg_conv3d_bwd_weight(const void *x, const void *dy, int32_t n, int32_t d, int32_t h, int32_t w,
                                int32_t c_in, int32_t c_out, float *dw, float *db, void *workspace,
                                size_t workspace_bytes, void *hip_stream);

@@ -125,68 +125,127 @@ __global__ void k_weight_mirror(const bf16 *__restrict__ wt, int Co, int Ci, bf1
 }
 
 // ---- convolution weight gradient ------------------------------------------------
-// dw[t][co][ci] = sum_v dy[v][co] x[v + off(t)][ci].  A GEMM per tap with the
-// voxels as the reduction: rows co, columns ci.  Grid (chunk, tap, tile):
-// each block computes one 32x32 (co, ci) tile of one tap over one chunk of
-// voxels, its 4 waves splitting the chunk; the waves' sums are combined in
-// LDS and the block partial goes to partial[chunk][t][co][ci], summed over
-// chunks in a fixed order by k_reduce_partials.
-constexpr int kBwChunk = 16384;  // voxels per block
+// dw[t][co][ci] = sum_v dy[v][co] x[v + off(t)][ci]: per tap a GEMM with the
+// voxels as the reduction (M = co, N = ci, K = voxels).  The MFMA operands
+// need 8 consecutive voxels of one channel per lane, while activations are
+// stored channels last, so both are transposed through LDS.
+//
+// A block owns one 32 x 32 (co, ci) tile for all 27 taps and walks a chunk
+// of row tiles: 16 consecutive voxels (n, d, h, w0 .. w0+15) of one W row.
+// Per row tile it stages
+//   dys[co][k]        = dy[n][d][h][w0 + k][co0 + co]
+//   xs[s][r][ci][k]   = x[n][d + a][h + b][w0 + k + s - 1][ci0 + ci]
+// (r = 3 (a+1) + (b+1), s = c+1; zero outside the volume), i.e. the nine
+// neighbouring rows in three w-shifts, so every MFMA operand is one aligned
+// 16-byte LDS read.  Wave w accumulates taps w, w+4, ... in registers; the
+// block's sums go to partial[chunk][t][co][ci], which k_reduce_partials
+// adds over chunks in a fixed order.
+constexpr int kBwTile = 16;    // voxels per row tile (one MFMA K step)
+constexpr int kBwPitch = 24;   // LDS row pitch in bf16 (48 B: conflict-free 16-byte reads)
+constexpr int kBwTargetBlocks = 2048;
+
+struct BwPlan {
+    int64_t tiles;   // row tiles
+    int ntw;         // row tiles per W row
+    int chunks;      // blocks along the voxels
+    int64_t per;     // row tiles per chunk
+};
+
+BwPlan bw_plan(int n, int d, int h, int w, int ci, int co)
+{
+    BwPlan p;
+    p.ntw = (w + kBwTile - 1) / kBwTile;
+    p.tiles = (int64_t)n * d * h * p.ntw;
+    const int64_t mn = (int64_t)(co / 32) * ((ci + 31) / 32);
+    int64_t ch = (kBwTargetBlocks + mn - 1) / mn;
+    if (ch > p.tiles) ch = p.tiles;
+    if (ch < 1) ch = 1;
+    p.per = (p.tiles + ch - 1) / ch;
+    p.chunks = (int)((p.tiles + p.per - 1) / p.per);
+    return p;
+}
 
 __global__ __launch_bounds__(kThreads) void k_conv3d_bwd_weight(const bf16 *__restrict__ x,
                                                                 const bf16 *__restrict__ dy, int N, int D,
-                                                                int H, int W, int Ci, int Co,
+                                                                int H, int W, int Ci, int Co, int ntw,
+                                                                int64_t tiles, int64_t per,
                                                                 float *__restrict__ partial)
 {
-    __shared__ float red[4][32][33];
+    __shared__ __attribute__((aligned(16))) bf16 xs[3][9][32][kBwPitch];
+    __shared__ __attribute__((aligned(16))) bf16 dys[32][kBwPitch];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int64_t V = (int64_t)N * D * H * W;
-    const int chunk = blockIdx.x, t = blockIdx.y;
-    const int ntc = (Ci + 31) / 32;
-    const int co0 = (blockIdx.z / ntc) * 32, ci0 = (blockIdx.z % ntc) * 32;
-    const bool ci_ok = ci0 + (lane & 31) < Ci;  // a 16-channel input fills half a tile
-    const int a = t / 9 - 1, b = (t / 3) % 3 - 1, c = t % 3 - 1;
-    f32x16 acc;
-    for (int r = 0; r < 16; ++r) acc[r] = 0.f;
-    const int64_t vbeg = (int64_t)chunk * kBwChunk;
-    const int64_t vend = vbeg + kBwChunk < V ? vbeg + kBwChunk : V;
+    const int chunk = blockIdx.x;
+    const int co0 = blockIdx.y * 32, ci0 = blockIdx.z * 32;
+    const int ntap = wave < 3 ? 7 : 6;  // taps wave, wave + 4, ...
+    f32x16 acc[7];
+#pragma unroll
+    for (int j = 0; j < 7; ++j)
+        for (int r = 0; r < 16; ++r) acc[j][r] = 0.f;
+    const int64_t tbeg = (int64_t)chunk * per;
+    const int64_t tend = tbeg + per < tiles ? tbeg + per : tiles;
     const int kh = (lane >> 5) * 8;
-    // each wave walks 16-voxel K slices: wave w takes slices w, w+4, ...
-    for (int64_t k0 = vbeg + wave * 16; k0 < vend; k0 += 64) {
-        bf16x8 av, bv;
+
+    for (int64_t rt = tbeg; rt < tend; ++rt) {
+        const int wt = (int)(rt % ntw);
+        int64_t row = rt / ntw;  // (n D + d) H + h
+        const int h = (int)(row % H);
+        row /= H;
+        const int d = (int)(row % D);
+        const int n = (int)(row / D);
+        const int w0 = wt * kBwTile;
+        // x: 9 rows x (kBwTile + 2) voxels x 4 groups of 8 channels
+        for (int item = threadIdx.x; item < 9 * (kBwTile + 2) * 4; item += kThreads) {
+            const int cg = item & 3;
+            const int wv = (item >> 2) % (kBwTile + 2);
+            const int r = (item >> 2) / (kBwTile + 2);
+            const int dd = d + r / 3 - 1, hh = h + r % 3 - 1, ww = w0 - 1 + wv;
+            const int cc = ci0 + cg * 8;
+            bf16x8 v = {};
+            if (dd >= 0 && dd < D && hh >= 0 && hh < H && ww >= 0 && ww < W && cc < Ci)
+                v = *reinterpret_cast<const bf16x8 *>(x + ((((int64_t)n * D + dd) * H + hh) * W + ww) * Ci + cc);
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            const int64_t v = k0 + kh + e;
-            bf16 dval = (bf16)0.f, xval = (bf16)0.f;
-            if (v < vend) {
-                dval = dy[v * Co + co0 + (lane & 31)];
-                int64_t q = v;
-                const int ww = (int)(q % W);
-                q /= W;
-                const int hh = (int)(q % H);
-                q /= H;
-                const int dd = (int)(q % D);
-                const int nn = (int)(q / D);
-                const int d2 = dd + a, h2 = hh + b, w2 = ww + c;
-                if (ci_ok && d2 >= 0 && d2 < D && h2 >= 0 && h2 < H && w2 >= 0 && w2 < W)
-                    xval = x[((((int64_t)nn * D + d2) * H + h2) * W + w2) * Ci + ci0 + (lane & 31)];
+            for (int sft = 0; sft < 3; ++sft) {
+                const int k = wv - sft;  // w = w0 + k + sft - 1
+                if (k >= 0 && k < kBwTile) {
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) xs[sft][r][cg * 8 + e][k] = v[e];
+                }
             }
-            av[e] = dval;
-            bv[e] = xval;
         }
-        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc, 0, 0, 0);
-    }
+        // dy: kBwTile voxels x 4 groups of 8 channels
+        if (threadIdx.x < kBwTile * 4) {
+            const int cg = threadIdx.x & 3, k = threadIdx.x >> 2;
+            const int ww = w0 + k;
+            bf16x8 v = {};
+            if (ww < W) v = *reinterpret_cast<const bf16x8 *>(dy + ((((int64_t)n * D + d) * H + h) * W + ww) * Co + co0 + cg * 8);
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-        const int row = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-        red[wave][row][lane & 31] = acc[r];
+            for (int e = 0; e < 8; ++e) dys[cg * 8 + e][k] = v[e];
+        }
+        __syncthreads();
+        const bf16x8 av = *reinterpret_cast<const bf16x8 *>(&dys[lane & 31][kh]);
+#pragma unroll
+        for (int j = 0; j < 7; ++j) {
+            if (j < ntap) {
+                const int t = wave + 4 * j;
+                const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(&xs[t % 3][t / 3][lane & 31][kh]);
+                acc[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc[j], 0, 0, 0);
+            }
+        }
+        __syncthreads();
     }
-    __syncthreads();
-    for (int i = threadIdx.x; i < 32 * 32; i += kThreads) {
-        const int row = i / 32, col = i % 32;
-        if (ci0 + col >= Ci) continue;
-        const float s = (red[0][row][col] + red[1][row][col]) + (red[2][row][col] + red[3][row][col]);
-        partial[(((int64_t)chunk * 27 + t) * Co + co0 + row) * Ci + ci0 + col] = s;
+    // D layout of the 32x32 tile: column l % 32 (ci), row 8 (r/4) + 4 (l/32) + r % 4 (co)
+    const int col = lane & 31;
+    if (ci0 + col >= Ci) return;
+#pragma unroll
+    for (int j = 0; j < 7; ++j) {
+        if (j < ntap) {
+            const int t = wave + 4 * j;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int rowc = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                partial[(((int64_t)chunk * 27 + t) * Co + co0 + rowc) * Ci + ci0 + col] = acc[j][r];
+            }
+        }
     }
 }
 
@@ -200,15 +259,17 @@ __global__ void k_reduce_partials(const float *__restrict__ partial, int nchunk,
     out[i] = s;
 }
 
-// db[co] = sum_v dy[v][co]: one block per 32 channels x chunk, fixed order
+// db[co] = sum_v dy[v][co]: one block per 32 channels x chunk of kBiasChunk
+// voxels, fixed order
+constexpr int kBiasChunk = 16384;
 __global__ __launch_bounds__(kThreads) void k_bias_grad_partial(const bf16 *__restrict__ dy, int64_t V, int Co,
                                                                 float *__restrict__ partial)
 {
     __shared__ float s[kThreads];
     const int chunk = blockIdx.x;
     const int co = blockIdx.y;
-    const int64_t vbeg = (int64_t)chunk * kBwChunk;
-    const int64_t vend = vbeg + kBwChunk < V ? vbeg + kBwChunk : V;
+    const int64_t vbeg = (int64_t)chunk * kBiasChunk;
+    const int64_t vend = vbeg + kBiasChunk < V ? vbeg + kBiasChunk : V;
     float acc = 0.f;
     for (int64_t v = vbeg + threadIdx.x; v < vend; v += kThreads) acc += (float)dy[v * Co + co];
     s[threadIdx.x] = acc;
@@ -578,9 +639,11 @@ sg_status sg_weight_mirror(const void *wt, int32_t c_out, int32_t c_in, void *wm
 
 size_t sg_bwd_weight_workspace(int32_t n, int32_t d, int32_t h, int32_t w, int32_t c_in, int32_t c_out)
 {
+    if (n < 1 || d < 1 || h < 1 || w < 1 || c_in < 1 || c_out < 32) return 0;
+    const BwPlan p = bw_plan(n, d, h, w, c_in, c_out);
     const int64_t V = (int64_t)n * d * h * w;
-    const int64_t nchunk = (V + kBwChunk - 1) / kBwChunk;
-    return (size_t)nchunk * (27 * (size_t)c_in * c_out + (size_t)c_out) * sizeof(float);
+    const int64_t nb = (V + kBiasChunk - 1) / kBiasChunk;
+    return ((size_t)p.chunks * 27 * (size_t)c_in * c_out + (size_t)nb * c_out) * sizeof(float);
 }
 
 sg_status sg_conv3d_bwd_weight(const void *x, const void *dy, int32_t n, int32_t d, int32_t h, int32_t w,
@@ -588,27 +651,30 @@ sg_status sg_conv3d_bwd_weight(const void *x, const void *dy, int32_t n, int32_t
                                void *stream)
 {
     if (!x || !dy || !dw || !ws) return fail(SG_EARG, "NULL tensor");
+    if (n < 1 || d < 1 || h < 1 || w < 1) return fail(SG_EARG, "bad shape");
     if (c_in < 16 || c_in % 16) return fail(SG_EARG, "c_in must be a positive multiple of 16 (got %d)", c_in);
     if (c_out < 32 || c_out % 32) return fail(SG_EARG, "c_out must be a multiple of 32 (got %d)", c_out);
+    if (!aligned16(x) || !aligned16(dy)) return fail(SG_EARG, "x and dy must be 16-byte aligned");
     const size_t need = sg_bwd_weight_workspace(n, d, h, w, c_in, c_out);
     if (ws_bytes < need) return fail(SG_ESIZE, "workspace has %zu bytes, needs %zu", ws_bytes, need);
+    const BwPlan p = bw_plan(n, d, h, w, c_in, c_out);
     const int64_t V = (int64_t)n * d * h * w;
-    const int nchunk = (int)((V + kBwChunk - 1) / kBwChunk);
     float *part = (float *)ws;
-    float *bpart = part + (int64_t)nchunk * 27 * c_in * c_out;
+    float *bpart = part + (int64_t)p.chunks * 27 * c_in * c_out;
     hipStream_t s = (hipStream_t)stream;
-    const dim3 grid((unsigned)nchunk, 27, (unsigned)((c_out / 32) * ((c_in + 31) / 32)));
+    const dim3 grid((unsigned)p.chunks, (unsigned)(c_out / 32), (unsigned)((c_in + 31) / 32));
     hipLaunchKernelGGL(k_conv3d_bwd_weight, grid, dim3(kThreads), 0, s, (const bf16 *)x, (const bf16 *)dy, n, d,
-                       h, w, c_in, c_out, part);
+                       h, w, c_in, c_out, p.ntw, p.tiles, p.per, part);
     SG_LAUNCH_CHECK();
     const int64_t stride = (int64_t)27 * c_in * c_out;
-    hipLaunchKernelGGL(k_reduce_partials, dim3(blocks_for(stride)), dim3(kThreads), 0, s, part, nchunk, stride, dw);
+    hipLaunchKernelGGL(k_reduce_partials, dim3(blocks_for(stride)), dim3(kThreads), 0, s, part, p.chunks, stride, dw);
     SG_LAUNCH_CHECK();
     if (db) {
-        hipLaunchKernelGGL(k_bias_grad_partial, dim3((unsigned)nchunk, (unsigned)c_out), dim3(kThreads), 0, s,
+        const int nb = (int)((V + kBiasChunk - 1) / kBiasChunk);
+        hipLaunchKernelGGL(k_bias_grad_partial, dim3((unsigned)nb, (unsigned)c_out), dim3(kThreads), 0, s,
                            (const bf16 *)dy, V, c_out, bpart);
         SG_LAUNCH_CHECK();
-        hipLaunchKernelGGL(k_reduce_partials, dim3(blocks_for(c_out)), dim3(kThreads), 0, s, bpart, nchunk,
+        hipLaunchKernelGGL(k_reduce_partials, dim3(blocks_for(c_out)), dim3(kThreads), 0, s, bpart, nb,
                            (int64_t)c_out, db);
         SG_LAUNCH_CHECK();
     }

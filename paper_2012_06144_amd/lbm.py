@@ -59,6 +59,11 @@ def _load():
     if not os.path.exists(LIB_PATH):
         raise LbmError(f"HIP library not built: {LIB_PATH} is missing "
                        "(run paper_2012_06144_amd/build.py or __graft_entry__.build())")
+    # torch ships its own HIP runtime with the same soname as the system one;
+    # loading torch first makes the library bind to that runtime, so the
+    # process has one HIP runtime and torch's device pointers and streams
+    # are valid in the library.
+    import torch  # noqa: F401
     L = C.CDLL(LIB_PATH)
     vp = C.c_void_p
     sig = {

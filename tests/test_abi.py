@@ -142,3 +142,18 @@ def test_create_validates_without_device_access():
         assert lbm.lbm_steps_done(ctx) == 0
     finally:
         lbm.lbm_destroy(ctx)
+
+
+def test_one_hip_runtime_per_process():
+    """Importing the package before torch must still leave one HIP runtime in
+    the process (torch's), or the library and torch would each bring up
+    their own and the library would see no device."""
+    import subprocess
+    import sys
+    code = ("import paper_2012_06144_amd.surrogate, torch\n"
+            "m = open('/proc/self/maps').read().splitlines()\n"
+            "print(len(set(l.split()[-1] for l in m if 'libamdhip64' in l)))\n")
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300,
+                         cwd=os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    assert out.returncode == 0, out.stderr[-2000:]
+    assert out.stdout.strip().splitlines()[-1] == "1"
