@@ -30,6 +30,7 @@ def _lib():
         L.orc_mse.restype = C.c_double
         L.orc_adam.argtypes = [_D, _D, _D, _D, C.c_size_t, C.c_double, C.c_double, C.c_double,
                                C.c_double, C.c_int]
+        L.orc_advect_phase.argtypes = [_D, i, i, i, i, C.c_double, _D]
         _ready = True
     return L
 
@@ -104,3 +105,17 @@ def adam(p, g, m, v, lr, b1, b2, eps, t):
     """In-place Adam step on float64 arrays p, m, v."""
     assert p.dtype == np.float64 and p.flags.c_contiguous
     _lib().orc_adam(p, _f(g), m, v, p.size, lr, b1, b2, eps, int(t))
+
+
+def advect_phase(state, K):
+    """Semi-Lagrangian jump baseline on boxes of states shaped (count, bz, by,
+    bx, 5): phi(x - K u(x)) by trilinear interpolation (departure point
+    clamped to the box), u and p unchanged."""
+    st = _f(state)
+    if st.ndim == 4:
+        st = st[None]
+    n, bz, by, bx, c = st.shape
+    assert c == 5
+    out = np.zeros_like(st)
+    _lib().orc_advect_phase(st, n, bx, by, bz, float(K), out)
+    return out.reshape(np.shape(state))

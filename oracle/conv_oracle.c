@@ -2,7 +2,8 @@
  * Plain FP64 CPU oracle of the surrogate network's operations: 3x3x3
  * convolution (forward, gradient with respect to the input, gradient with
  * respect to the weights and bias), 2x average pooling, 2x nearest
- * upsampling, leaky ReLU, mean-squared error and the Adam update.
+ * upsampling, leaky ReLU, mean-squared error, the Adam update, and the
+ * semi-Lagrangian phase transport that serves as the jump baseline.
  *
  * TEST INFRASTRUCTURE ONLY: for the tests and the smoke check; shares no code
  * with the GPU library.
@@ -158,5 +159,48 @@ void orc_adam(double *p, const double *g, double *m, double *v, size_t n, double
         m[i] = b1 * m[i] + (1.0 - b1) * g[i];
         v[i] = b2 * v[i] + (1.0 - b2) * g[i] * g[i];
         p[i] -= lr * (m[i] / c1) / (sqrt(v[i] / c2) + eps);
+    }
+}
+
+/* Physics baseline of a jump of K steps on a box of states (5 channels per
+ * voxel, channels last: phi, u_x, u_y, u_z, p; voxel v = x + bx (y + by z)):
+ * semi-Lagrangian transport of phi by the local velocity,
+ *   phi'(x) = phi(x - K u(x))   (trilinear interpolation, the departure
+ *                                point clamped to the box),
+ * with u and p carried over unchanged.  count boxes one after another.   */
+void orc_advect_phase(const double *state, int count, int bx, int by, int bz, double K, double *out)
+{
+    const int64_t V = (int64_t)bx * by * bz;
+    for (int n = 0; n < count; ++n) {
+        const double *s = state + (int64_t)n * V * 5;
+        double *o = out + (int64_t)n * V * 5;
+        for (int z = 0; z < bz; ++z)
+            for (int y = 0; y < by; ++y)
+                for (int x = 0; x < bx; ++x) {
+                    const int64_t v = x + (int64_t)bx * (y + (int64_t)by * z);
+                    const double *sv = s + v * 5;
+                    double p[3] = {x - K * sv[1], y - K * sv[2], z - K * sv[3]};
+                    const int ext[3] = {bx, by, bz};
+                    int lo[3], hi[3];
+                    double f[3];
+                    for (int a = 0; a < 3; ++a) {
+                        if (p[a] < 0.0) p[a] = 0.0;
+                        if (p[a] > ext[a] - 1) p[a] = ext[a] - 1;
+                        lo[a] = (int)floor(p[a]);
+                        hi[a] = lo[a] + 1 < ext[a] ? lo[a] + 1 : lo[a];
+                        f[a] = p[a] - lo[a];
+                    }
+                    double phi = 0.0;
+                    for (int cz = 0; cz < 2; ++cz)
+                        for (int cy = 0; cy < 2; ++cy)
+                            for (int cx = 0; cx < 2; ++cx) {
+                                const int xx = cx ? hi[0] : lo[0], yy = cy ? hi[1] : lo[1], zz = cz ? hi[2] : lo[2];
+                                const double wgt = (cx ? f[0] : 1.0 - f[0]) * (cy ? f[1] : 1.0 - f[1]) *
+                                                   (cz ? f[2] : 1.0 - f[2]);
+                                phi += wgt * s[(xx + (int64_t)bx * (yy + (int64_t)by * zz)) * 5];
+                            }
+                    o[v * 5] = phi;
+                    for (int k = 1; k < 5; ++k) o[v * 5 + k] = sv[k];
+                }
     }
 }

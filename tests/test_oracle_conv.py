@@ -12,6 +12,9 @@ library routine or a property that does not come from the oracle itself.
   adjoint of upsampling divided by 8.
 * Adam with a constant gradient moves every parameter by exactly
   lr * g / (|g| + eps) per step (bias correction makes m_hat = g, v_hat = g^2).
+* Jump baseline (semi-Lagrangian transport of phi): identity at zero
+  velocity, an exact shift for integer displacements, exact on linear fields
+  (trilinear interpolation reproduces them), clamping at the box faces.
 """
 import numpy as np
 import pytest
@@ -137,3 +140,54 @@ def test_adam_constant_gradient():
         conv.adam(p, g, m, v, lr, 0.9, 0.999, eps, t)
         expect = p0 - t * lr * g / (np.abs(g) + eps)
         assert np.abs(p - expect).max() < 1e-12
+
+
+def _box_state(bz, by, bx, seed=0):
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal((bz, by, bx, 5))
+
+
+def test_advect_zero_velocity_is_identity():
+    s = _box_state(5, 6, 7)
+    s[..., 1:4] = 0.0
+    assert np.array_equal(conv.advect_phase(s, 200.0), s)
+
+
+def test_advect_integer_shift_moves_the_field():
+    """A uniform velocity with K u = (1, -2, 1) cells moves phi by that many
+    cells; voxels whose departure point lies inside the box match exactly."""
+    s = _box_state(6, 7, 8, seed=1)
+    K = 200.0
+    s[..., 1], s[..., 2], s[..., 3] = 1.0 / K, -2.0 / K, 1.0 / K
+    o = conv.advect_phase(s, K)
+    phi = s[..., 0]
+    # out[z, y, x] = phi[z - 1, y + 2, x - 1]
+    assert np.array_equal(o[1:, :-2, 1:, 0], phi[:-1, 2:, :-1])
+    assert np.array_equal(o[..., 1:], s[..., 1:])
+
+
+def test_advect_reproduces_linear_fields():
+    """Trilinear interpolation is exact for a linear field: with a uniform
+    non-integer displacement every interior voxel gets a + b.(x - K u)."""
+    bz, by, bx = 6, 7, 8
+    z, y, x = np.meshgrid(np.arange(bz), np.arange(by), np.arange(bx), indexing="ij")
+    a, b = 0.3, np.array([0.05, -0.02, 0.07])       # along x, y, z
+    s = np.zeros((bz, by, bx, 5))
+    s[..., 0] = a + b[0] * x + b[1] * y + b[2] * z
+    d = np.array([0.37, -1.61, 0.52])                # K u in cells, along x, y, z
+    K = 100.0
+    s[..., 1:4] = d / K
+    o = conv.advect_phase(s, K)
+    exact = a + b[0] * (x - d[0]) + b[1] * (y - d[1]) + b[2] * (z - d[2])
+    inside = (x - d[0] >= 0) & (x - d[0] <= bx - 1) & (y - d[1] >= 0) & (y - d[1] <= by - 1) & \
+             (z - d[2] >= 0) & (z - d[2] <= bz - 1)
+    assert inside.sum() > 100
+    assert np.max(np.abs(o[..., 0] - exact)[inside]) < 1e-14
+
+
+def test_advect_clamps_departure_to_the_box():
+    s = _box_state(4, 4, 4, seed=2)
+    s[..., 1:4] = 0.0
+    s[..., 1] = 10.0                                  # departure far left of x = 0
+    o = conv.advect_phase(s, 1.0)
+    assert np.array_equal(o[..., 0], np.broadcast_to(s[:, :, :1, 0], (4, 4, 4)))
