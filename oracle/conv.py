@@ -31,6 +31,8 @@ def _lib():
         L.orc_adam.argtypes = [_D, _D, _D, _D, C.c_size_t, C.c_double, C.c_double, C.c_double,
                                C.c_double, C.c_int]
         L.orc_advect_phase.argtypes = [_D, i, i, i, i, C.c_double, _D]
+        i64 = C.c_int64
+        L.orc_projective_step.argtypes = [_D, _D, i64, i64, i64, C.c_double, C.c_double, C.c_double, i, i, _D]
         _ready = True
     return L
 
@@ -119,3 +121,20 @@ def advect_phase(state, K):
     out = np.zeros_like(st)
     _lib().orc_advect_phase(st, n, bx, by, bz, float(K), out)
     return out.reshape(np.shape(state))
+
+
+def projective_step(s, s_prev, ratio, phi_lo, phi_hi, u_by_phase=True, p_step=False, layout="last"):
+    """Projective step s + ratio (s - s_prev) of field sets: layout "last"
+    (..., 5) channels last, or "planar" (5, ...) one plane per channel."""
+    a, b = _f(s), _f(s_prev)
+    assert a.shape == b.shape
+    if layout == "last":
+        n = a.size // 5
+        cs, vs = 1, 5
+    else:
+        n = a.size // 5
+        cs, vs = n, 1
+    out = np.zeros_like(a)
+    _lib().orc_projective_step(a, b, n, cs, vs, float(ratio), float(phi_lo), float(phi_hi), int(u_by_phase),
+                               int(p_step), out)
+    return out

@@ -3,7 +3,8 @@
  * convolution (forward, gradient with respect to the input, gradient with
  * respect to the weights and bias), 2x average pooling, 2x nearest
  * upsampling, leaky ReLU, mean-squared error, the Adam update, and the
- * semi-Lagrangian phase transport that serves as the jump baseline.
+ * semi-Lagrangian phase transport and the projective time step that serve as
+ * jump baselines.
  *
  * TEST INFRASTRUCTURE ONLY: for the tests and the smoke check; shares no code
  * with the GPU library.
@@ -202,5 +203,35 @@ void orc_advect_phase(const double *state, int count, int bx, int by, int bz, do
                     o[v * 5] = phi;
                     for (int k = 1; k < 5; ++k) o[v * 5 + k] = sv[k];
                 }
+    }
+}
+
+/* Projective (coarse) time step of the macroscopic fields (Gear and
+ * Kevrekidis, "Projective methods for stiff differential equations", SIAM
+ * J. Sci. Comput. 24, 2003): with s the fields now and s_prev the fields m
+ * LBM steps earlier, the fields K steps ahead are extrapolated linearly,
+ *   s' = s + (K/m) (s - s_prev),
+ * channel by channel for n points.  Element (i, k) of a field set sits at
+ * f[k * cs + i * vs] (planar: cs = n, vs = 1; channels last: cs = 1,
+ * vs = 5); channels are (phi, u_x, u_y, u_z, p).  phi' is clipped to
+ * [phi_lo, phi_hi]; with u_by_phase the velocity increment is weighted by
+ * the heavy-phase fraction clamp((phi - phi_lo)/(phi_hi - phi_lo), 0, 1) of
+ * the current phi; with p_step == 0 the pressure is carried over.        */
+void orc_projective_step(const double *s, const double *s_prev, int64_t n, int64_t cs, int64_t vs, double ratio,
+                         double phi_lo, double phi_hi, int u_by_phase, int p_step, double *out)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        const double phi = s[i * vs], dphi = phi - s_prev[i * vs];
+        double q = (phi - phi_lo) / (phi_hi - phi_lo);
+        q = q < 0.0 ? 0.0 : (q > 1.0 ? 1.0 : q);
+        double np = phi + ratio * dphi;
+        np = np < phi_lo ? phi_lo : (np > phi_hi ? phi_hi : np);
+        out[i * vs] = np;
+        for (int k = 1; k <= 3; ++k) {
+            const double v = s[k * cs + i * vs], dv = v - s_prev[k * cs + i * vs];
+            out[k * cs + i * vs] = v + (u_by_phase ? q : 1.0) * ratio * dv;
+        }
+        const double p = s[4 * cs + i * vs];
+        out[4 * cs + i * vs] = p_step ? p + ratio * (p - s_prev[4 * cs + i * vs]) : p;
     }
 }

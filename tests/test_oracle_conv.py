@@ -191,3 +191,44 @@ def test_advect_clamps_departure_to_the_box():
     s[..., 1] = 10.0                                  # departure far left of x = 0
     o = conv.advect_phase(s, 1.0)
     assert np.array_equal(o[..., 0], np.broadcast_to(s[:, :, :1, 0], (4, 4, 4)))
+
+
+def test_projective_step_exact_for_fields_linear_in_time():
+    """s(t) = a + b t for every channel: the projective step from s(t - m)
+    and s(t) lands exactly on s(t + K) (u unweighted, p stepped, phi inside
+    its bounds)."""
+    rng = np.random.default_rng(3)
+    a = rng.uniform(0.3, 0.7, (7, 5))
+    b = rng.uniform(-1e-4, 1e-4, (7, 5))
+    t, m, K = 1000.0, 25.0, 200.0
+    s_prev, s = a + b * (t - m), a + b * t
+    out = conv.projective_step(s, s_prev, K / m, 0.0, 1.0, u_by_phase=False, p_step=True)
+    assert np.max(np.abs(out - (a + b * (t + K)))) < 1e-15
+
+
+def test_projective_step_limits():
+    rng = np.random.default_rng(4)
+    s = rng.uniform(0.0, 1.0, (50, 5))
+    sp = s + rng.uniform(-0.1, 0.1, (50, 5))
+    # ratio 0: identity
+    assert np.array_equal(conv.projective_step(s, sp, 0.0, 0.0, 1.0), s)
+    out = conv.projective_step(s, sp, 8.0, 0.0, 1.0, u_by_phase=True, p_step=False)
+    # phi clipped into [0, 1]; pressure carried over
+    assert out[:, 0].min() >= 0.0 and out[:, 0].max() <= 1.0
+    assert np.array_equal(out[:, 4], s[:, 4])
+    # velocity increments scale with the heavy-phase fraction: none in the
+    # light phase (phi = 0), all of it in the heavy phase (phi = 1)
+    s2 = s.copy()
+    s2[:25, 0], s2[25:, 0] = 0.0, 1.0
+    out2 = conv.projective_step(s2, sp, 8.0, 0.0, 1.0, u_by_phase=True)
+    assert np.array_equal(out2[:25, 1:4], s2[:25, 1:4])
+    assert np.allclose(out2[25:, 1:4], s2[25:, 1:4] + 8.0 * (s2[25:, 1:4] - sp[25:, 1:4]), rtol=0, atol=1e-15)
+
+
+def test_projective_step_layouts_agree():
+    rng = np.random.default_rng(5)
+    s = rng.uniform(0.0, 1.0, (3, 4, 6, 5))
+    sp = s + rng.uniform(-0.01, 0.01, s.shape)
+    last = conv.projective_step(s, sp, 8.0, 0.0, 1.0)
+    planar = conv.projective_step(np.moveaxis(s, -1, 0), np.moveaxis(sp, -1, 0), 8.0, 0.0, 1.0, layout="planar")
+    assert np.array_equal(np.moveaxis(planar, 0, -1), last)
