@@ -116,13 +116,52 @@ sg_status sg_state_to_input(const float *state, int64_t voxels, const float *sca
 sg_status sg_make_target(const float *s0, const float *s1, int64_t voxels, const float *scale_out,
                          int32_t c_out, float *target, void *hip_stream);
 
-/* Applies a predicted increment to the fields of a box: field += out * scale_out
- * (out has c_out FP32 channels, the first 5 used); phi is clipped to
- * [phi_min, phi_max] afterwards; cells of the rows y = 0 and ny-1 are left
- * unchanged if walls_y. */
-sg_status sg_apply_prediction(const float *out, int32_t c_out, const float *scale_out, float *phi, float *u,
-                              float *p, int32_t nx, int32_t ny, int32_t nz, const int32_t *box, int32_t walls_y,
-                              float phi_min, float phi_max, void *hip_stream);
+/* Applies a predicted increment to the fields of a box: field = base + out * scale_out
+ * per channel (out has c_out FP32 channels, the first 5 used; base is a raw
+ * state of the box, 5 FP32 channels per voxel, or NULL for the field itself);
+ * phi is clipped to [phi_min, phi_max] afterwards (phi_max > phi_min); with
+ * u_by_phase the velocity increment is weighted by the heavy-phase fraction
+ * clamp((phi_base - phi_min)/(phi_max - phi_min), 0, 1); cells of the rows
+ * y = 0 and ny-1 are left unchanged if walls_y.  A zero scale leaves that
+ * channel at its base. */
+sg_status sg_apply_prediction(const float *out, int32_t c_out, const float *scale_out, const float *base,
+                              float *phi, float *u, float *p, int32_t nx, int32_t ny, int32_t nz,
+                              const int32_t *box, int32_t walls_y, float phi_min, float phi_max,
+                              int32_t u_by_phase, void *hip_stream);
+
+/* Physics baseline of a jump of K steps on `count` boxes of raw states
+ * (count x bz x by x bx voxels, 5 FP32 channels each, x fastest): phi is
+ * transported by the local velocity, phi'(x) = phi(x - K u(x)) with
+ * trilinear interpolation and the departure point clamped to the box; u and
+ * p are copied.  out must not alias state. */
+sg_status sg_advect_phase(const float *state, int64_t count, int32_t bx, int32_t by, int32_t bz, float K,
+                          float *out, void *hip_stream);
+
+/* Projective time step of field sets (Gear and Kevrekidis, SIAM J. Sci.
+ * Comput. 24, 2003): out = s + ratio (s - s_prev) per channel over n points,
+ * channels (phi, u_x, u_y, u_z, p); element (i, k) at f[k cs + i vs], either
+ * planar (cs = n, vs = 1: the solver's FP32 field planes, phi then u then p
+ * as one allocation per argument) or channels last (cs = 1, vs = 5: box
+ * states).  phi is clipped to [phi_lo, phi_hi]; with u_by_phase the velocity
+ * increment is weighted by the heavy-phase fraction of the current phi;
+ * with p_step == 0 the pressure is carried over.  out may alias s. */
+sg_status sg_projective_step(const float *s, const float *s_prev, int64_t n, int64_t cs, int64_t vs, float ratio,
+                             float phi_lo, float phi_hi, int32_t u_by_phase, int32_t p_step, float *out,
+                             void *hip_stream);
+
+/* Network input of a box state s and the same box m steps earlier (5 FP32
+ * channels per voxel each): channels 0-4 = s / scale_in, 5-9 =
+ * (s - s_prev) * trend_scale (both HOST arrays of 5 floats), zeros up to
+ * c_in (>= 10) channels, BF16. */
+sg_status sg_pair_to_input(const float *state, const float *state_prev, int64_t voxels, const float *scale_in,
+                           const float *trend_scale, int32_t c_in, void *x_bf16, void *hip_stream);
+
+/* Per-channel sums: out[c] = sum_r a[r][c] and out[8 + c] = sum_r a[r][c]^2
+ * in FP64 over a (rows, C) FP32 array, C <= 8 (out has 16 doubles; unused
+ * channels are 0); deterministic fixed-order reduction through `scratch`
+ * (512 x 16 doubles). */
+sg_status sg_channel_moments(const float *a, int64_t rows, int32_t c, double *out, double *scratch,
+                             void *hip_stream);
 
 /* Mass projection of a phase field over ncells cells: phi += c * 4 phi' (1 - phi')
  * with phi' = (phi - phi_min)/(phi_max - phi_min), c chosen (FP64, fixed-order

@@ -522,9 +522,9 @@ __global__ void k_make_target(const float *__restrict__ s0, const float *__restr
 }
 
 __global__ void k_apply_prediction(const float *__restrict__ out, int c_out, float q0, float q1, float q2,
-                                   float q3, float q4, float *__restrict__ phi, float *__restrict__ u,
-                                   float *__restrict__ p, int nx, int ny, int nz, Box b, int walls, float pmin,
-                                   float pmax)
+                                   float q3, float q4, const float *__restrict__ base, float *__restrict__ phi,
+                                   float *__restrict__ u, float *__restrict__ p, int nx, int ny, int nz, Box b,
+                                   int walls, float pmin, float pmax, int u_by_phase)
 {
     const int64_t V = (int64_t)b.bx * b.by * b.bz;
     const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -534,12 +534,131 @@ __global__ void k_apply_prediction(const float *__restrict__ out, int c_out, flo
     if (walls && (yy == 0 || yy == ny - 1)) return;
     const int64_t N = (int64_t)nx * ny * nz;
     const float *o = out + v * c_out;
-    const float f = phi[c] + o[0] * q0;
-    phi[c] = fminf(fmaxf(f, pmin), pmax);
-    u[c] += o[1] * q1;
-    u[N + c] += o[2] * q2;
-    u[2 * N + c] += o[3] * q3;
-    p[c] += o[4] * q4;
+    const float f0 = base ? base[v * 5 + 0] : phi[c];
+    const float f1 = base ? base[v * 5 + 1] : u[c];
+    const float f2 = base ? base[v * 5 + 2] : u[N + c];
+    const float f3 = base ? base[v * 5 + 3] : u[2 * N + c];
+    const float f4 = base ? base[v * 5 + 4] : p[c];
+    // velocity increments weighted by the heavy-phase fraction of the base
+    // phi when u_by_phase (the light phase carries no momentum to speak of)
+    float wu = 1.f;
+    if (u_by_phase) wu = fminf(fmaxf((f0 - pmin) / (pmax - pmin), 0.f), 1.f);
+    phi[c] = fminf(fmaxf(f0 + o[0] * q0, pmin), pmax);
+    u[c] = f1 + wu * (o[1] * q1);
+    u[N + c] = f2 + wu * (o[2] * q2);
+    u[2 * N + c] = f3 + wu * (o[3] * q3);
+    p[c] = f4 + o[4] * q4;
+}
+
+// Jump baseline on boxes of raw states (5 FP32 channels per voxel):
+// phi'(x) = phi(x - K u(x)) by trilinear interpolation, the departure point
+// clamped to the box; u and p copied.
+__global__ void k_advect_phase(const float *__restrict__ s, int64_t count, int bx, int by, int bz, float K,
+                               float *__restrict__ o)
+{
+    const int64_t V = (int64_t)bx * by * bz;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= V * count) return;
+    const int64_t n = i / V, v = i % V;
+    const float *sb = s + n * V * 5;
+    const int x = (int)(v % bx), y = (int)((v / bx) % by), z = (int)(v / ((int64_t)bx * by));
+    const float *sv = sb + v * 5;
+    float px = (float)x - K * sv[1], py = (float)y - K * sv[2], pz = (float)z - K * sv[3];
+    px = fminf(fmaxf(px, 0.f), (float)(bx - 1));
+    py = fminf(fmaxf(py, 0.f), (float)(by - 1));
+    pz = fminf(fmaxf(pz, 0.f), (float)(bz - 1));
+    const int x0 = (int)floorf(px), y0 = (int)floorf(py), z0 = (int)floorf(pz);
+    const int x1 = x0 + 1 < bx ? x0 + 1 : x0, y1 = y0 + 1 < by ? y0 + 1 : y0, z1 = z0 + 1 < bz ? z0 + 1 : z0;
+    const float fx = px - (float)x0, fy = py - (float)y0, fz = pz - (float)z0;
+    auto at = [&](int xx, int yy, int zz) { return sb[(xx + (int64_t)bx * (yy + (int64_t)by * zz)) * 5]; };
+    const float c00 = at(x0, y0, z0) * (1.f - fx) + at(x1, y0, z0) * fx;
+    const float c10 = at(x0, y1, z0) * (1.f - fx) + at(x1, y1, z0) * fx;
+    const float c01 = at(x0, y0, z1) * (1.f - fx) + at(x1, y0, z1) * fx;
+    const float c11 = at(x0, y1, z1) * (1.f - fx) + at(x1, y1, z1) * fx;
+    const float c0 = c00 * (1.f - fy) + c10 * fy, c1 = c01 * (1.f - fy) + c11 * fy;
+    float *ov = o + n * V * 5 + v * 5;
+    ov[0] = c0 * (1.f - fz) + c1 * fz;
+    ov[1] = sv[1];
+    ov[2] = sv[2];
+    ov[3] = sv[3];
+    ov[4] = sv[4];
+}
+
+// Projective time step of field sets: s' = s + ratio (s - s_prev) per
+// channel, element (i, k) at f[k cs + i vs]; phi clipped to [lo, hi];
+// velocity increments weighted by the heavy-phase fraction of the current
+// phi if u_by_phase; pressure stepped only if p_step.  out may alias s.
+__global__ void k_projective(const float *__restrict__ s, const float *__restrict__ sp, int64_t n, int64_t cs,
+                             int64_t vs, float ratio, float lo, float hi, int u_by_phase, int p_step, float *out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float phi = s[i * vs], dphi = phi - sp[i * vs];
+    const float q = fminf(fmaxf((phi - lo) / (hi - lo), 0.f), 1.f);
+    const float wu = u_by_phase ? q : 1.f;
+    float v[3], dv[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        v[k] = s[(k + 1) * cs + i * vs];
+        dv[k] = v[k] - sp[(k + 1) * cs + i * vs];
+    }
+    const float p = s[4 * cs + i * vs], dp = p - sp[4 * cs + i * vs];
+    out[i * vs] = fminf(fmaxf(phi + ratio * dphi, lo), hi);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) out[(k + 1) * cs + i * vs] = v[k] + wu * (ratio * dv[k]);
+    out[4 * cs + i * vs] = p_step ? p + ratio * dp : p;
+}
+
+// Network input of a state and its recent change: channels 0-4 = s /
+// scale_in, channels 5-9 = (s - s_prev) * trend_scale, zeros up to c_in.
+__global__ void k_pair_to_input(const float *__restrict__ s, const float *__restrict__ sp, int64_t V, float q0,
+                                float q1, float q2, float q3, float q4, float t0, float t1, float t2, float t3,
+                                float t4, int c_in, bf16 *__restrict__ x)
+{
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= V) return;
+    const float sc[5] = {q0, q1, q2, q3, q4}, tr[5] = {t0, t1, t2, t3, t4};
+    for (int k = 0; k < c_in; ++k) {
+        float val = 0.f;
+        if (k < 5) val = s[v * 5 + k] / sc[k];
+        else if (k < 10) val = (s[v * 5 + k - 5] - sp[v * 5 + k - 5]) * tr[k - 5];
+        x[v * c_in + k] = (bf16)val;
+    }
+}
+
+// Per-channel sum and sum of squares (FP64) of a (rows, C) FP32 array,
+// C <= 8: fixed grid of kMomBlocks blocks with fixed-order trees, then one
+// block combining the partials in order.
+constexpr int kMomBlocks = 512;
+__global__ __launch_bounds__(kThreads) void k_moments1(const float *__restrict__ a, int64_t rows, int C,
+                                                       double *__restrict__ part)
+{
+    __shared__ double sh[16][kThreads];
+    double acc[16];
+    for (int k = 0; k < 16; ++k) acc[k] = 0.0;
+    for (int64_t r = (int64_t)blockIdx.x * kThreads + threadIdx.x; r < rows; r += (int64_t)kMomBlocks * kThreads)
+        for (int c = 0; c < C; ++c) {
+            const double v = a[r * C + c];
+            acc[c] += v;
+            acc[8 + c] += v * v;
+        }
+    for (int k = 0; k < 16; ++k) sh[k][threadIdx.x] = acc[k];
+    __syncthreads();
+    for (int st = kThreads / 2; st > 0; st >>= 1) {
+        if (threadIdx.x < st)
+            for (int k = 0; k < 16; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x < 16) part[(int64_t)blockIdx.x * 16 + threadIdx.x] = sh[threadIdx.x][0];
+}
+
+__global__ void k_moments2(const double *__restrict__ part, double *__restrict__ out)
+{
+    const int k = threadIdx.x;
+    if (k >= 16) return;
+    double s = 0.0;
+    for (int b = 0; b < kMomBlocks; ++b) s += part[b * 16 + k];
+    out[k] = s;
 }
 
 constexpr int kProjBlocks = 1024;
@@ -838,17 +957,64 @@ sg_status sg_make_target(const float *s0, const float *s1, int64_t V, const floa
     return SG_OK;
 }
 
-sg_status sg_apply_prediction(const float *out, int32_t c_out, const float *so, float *phi, float *u, float *p,
-                              int32_t nx, int32_t ny, int32_t nz, const int32_t *box, int32_t walls_y,
-                              float pmin, float pmax, void *stream)
+sg_status sg_apply_prediction(const float *out, int32_t c_out, const float *so, const float *base, float *phi,
+                              float *u, float *p, int32_t nx, int32_t ny, int32_t nz, const int32_t *box,
+                              int32_t walls_y, float pmin, float pmax, int32_t u_by_phase, void *stream)
 {
     if (!out || !so || !phi || !u || !p || c_out < 5) return fail(SG_EARG, "bad arguments");
+    if (!(pmax > pmin)) return fail(SG_EARG, "phi_max must exceed phi_min");
     Box b;
     sg_status st = read_box(box, nx, ny, nz, b);
     if (st != SG_OK) return st;
     const int64_t V = (int64_t)b.bx * b.by * b.bz;
     hipLaunchKernelGGL(k_apply_prediction, dim3(blocks_for(V)), dim3(kThreads), 0, (hipStream_t)stream, out, c_out,
-                       so[0], so[1], so[2], so[3], so[4], phi, u, p, nx, ny, nz, b, walls_y, pmin, pmax);
+                       so[0], so[1], so[2], so[3], so[4], base, phi, u, p, nx, ny, nz, b, walls_y, pmin, pmax,
+                       u_by_phase);
+    SG_LAUNCH_CHECK();
+    return SG_OK;
+}
+
+sg_status sg_advect_phase(const float *state, int64_t count, int32_t bx, int32_t by, int32_t bz, float K,
+                          float *out, void *stream)
+{
+    if (!state || !out || count < 1 || bx < 1 || by < 1 || bz < 1) return fail(SG_EARG, "bad arguments");
+    if (state == out) return fail(SG_EARG, "sg_advect_phase cannot run in place");
+    const int64_t n = count * bx * (int64_t)by * bz;
+    hipLaunchKernelGGL(k_advect_phase, dim3(blocks_for(n)), dim3(kThreads), 0, (hipStream_t)stream, state, count,
+                       bx, by, bz, K, out);
+    SG_LAUNCH_CHECK();
+    return SG_OK;
+}
+
+sg_status sg_projective_step(const float *s, const float *s_prev, int64_t n, int64_t cs, int64_t vs, float ratio,
+                             float phi_lo, float phi_hi, int32_t u_by_phase, int32_t p_step, float *out,
+                             void *stream)
+{
+    if (!s || !s_prev || !out || n < 1 || cs < 1 || vs < 1 || !(phi_hi > phi_lo)) return fail(SG_EARG, "bad arguments");
+    if (!((cs == n && vs == 1) || (cs == 1 && vs == 5))) return fail(SG_EARG, "layout must be planar or channels last");
+    hipLaunchKernelGGL(k_projective, dim3(blocks_for(n)), dim3(kThreads), 0, (hipStream_t)stream, s, s_prev, n, cs,
+                       vs, ratio, phi_lo, phi_hi, u_by_phase, p_step, out);
+    SG_LAUNCH_CHECK();
+    return SG_OK;
+}
+
+sg_status sg_pair_to_input(const float *s, const float *s_prev, int64_t V, const float *si, const float *ts,
+                           int32_t c_in, void *x, void *stream)
+{
+    if (!s || !s_prev || !si || !ts || !x || c_in < 10) return fail(SG_EARG, "bad arguments");
+    hipLaunchKernelGGL(k_pair_to_input, dim3(blocks_for(V)), dim3(kThreads), 0, (hipStream_t)stream, s, s_prev, V,
+                       si[0], si[1], si[2], si[3], si[4], ts[0], ts[1], ts[2], ts[3], ts[4], c_in, (bf16 *)x);
+    SG_LAUNCH_CHECK();
+    return SG_OK;
+}
+
+sg_status sg_channel_moments(const float *a, int64_t rows, int32_t c, double *out, double *scratch, void *stream)
+{
+    if (!a || !out || !scratch || rows < 1 || c < 1 || c > 8) return fail(SG_EARG, "bad arguments");
+    hipStream_t s = (hipStream_t)stream;
+    hipLaunchKernelGGL(k_moments1, dim3(kMomBlocks), dim3(kThreads), 0, s, a, rows, c, scratch);
+    SG_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_moments2, dim3(1), dim3(64), 0, s, scratch, out);
     SG_LAUNCH_CHECK();
     return SG_OK;
 }

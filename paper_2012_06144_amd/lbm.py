@@ -283,13 +283,20 @@ class Solver:
     def stats(self) -> dict:
         return lbm_reduce_stats(self.ctx)
 
-    def macroscopic(self, dtype=None):
+    def macroscopic(self, dtype=None, out=None):
+        """(phi, u, p) as new tensors, or as views of `out`, a (5, nz, ny, nx)
+        tensor holding phi, u_x, u_y, u_z, p as consecutive planes."""
         t = self.torch
-        dtype = dtype or t.float64
+        if out is not None:
+            assert out.shape == (5,) + self.shape and out.is_contiguous()
+            dtype = out.dtype
+            phi, u, p = out[0], out[1:4], out[4]
+        else:
+            dtype = dtype or t.float64
+            phi = t.empty(self.shape, dtype=dtype, device=self.device)
+            u = t.empty((3,) + self.shape, dtype=dtype, device=self.device)
+            p = t.empty(self.shape, dtype=dtype, device=self.device)
         code = DTYPE_F64 if dtype == t.float64 else DTYPE_F32
-        phi = t.empty(self.shape, dtype=dtype, device=self.device)
-        u = t.empty((3,) + self.shape, dtype=dtype, device=self.device)
-        p = t.empty(self.shape, dtype=dtype, device=self.device)
         lbm_get_macroscopic(self.ctx, code, phi, u, p)
         return phi, u, p
 

@@ -15,7 +15,9 @@ EXPORTS = [
     "sg_conv3d_fwd", "sg_weight_mirror", "sg_bwd_weight_workspace", "sg_conv3d_bwd_weight",
     "sg_leaky_bwd", "sg_pool2_fwd", "sg_pool2_bwd", "sg_up2_fwd", "sg_up2_bwd", "sg_concat",
     "sg_split", "sg_mse", "sg_adam", "sg_to_bf16", "sg_to_f32", "sg_add", "sg_fields_to_input",
-    "sg_state_to_input", "sg_make_target", "sg_apply_prediction", "sg_mass_project", "sg_last_error",
+    "sg_state_to_input", "sg_make_target", "sg_apply_prediction", "sg_advect_phase", "sg_projective_step",
+    "sg_pair_to_input", "sg_channel_moments",
+    "sg_mass_project", "sg_last_error",
 ]
 
 _vp, _i, _i64, _f, _sz = C.c_void_p, C.c_int32, C.c_int64, C.c_float, C.c_size_t
@@ -39,7 +41,11 @@ _SIG = {
     "sg_fields_to_input": [_vp, _vp, _vp, _i, _i, _i, _vp, _vp, _i, _vp, _vp, _vp],
     "sg_state_to_input": [_vp, _i64, _vp, _i, _vp, _vp],
     "sg_make_target": [_vp, _vp, _i64, _vp, _i, _vp, _vp],
-    "sg_apply_prediction": [_vp, _i, _vp, _vp, _vp, _vp, _i, _i, _i, _vp, _i, _f, _f, _vp],
+    "sg_apply_prediction": [_vp, _i, _vp, _vp, _vp, _vp, _vp, _i, _i, _i, _vp, _i, _f, _f, _i, _vp],
+    "sg_advect_phase": [_vp, _i64, _i, _i, _i, _f, _vp, _vp],
+    "sg_projective_step": [_vp, _vp, _i64, _i64, _i64, _f, _f, _f, _i, _i, _vp, _vp],
+    "sg_pair_to_input": [_vp, _vp, _i64, _vp, _vp, _i, _vp, _vp],
+    "sg_channel_moments": [_vp, _i64, _i, _vp, _vp, _vp],
     "sg_mass_project": [_vp, _i64, C.c_double, _f, _f, _vp, _vp],
     "sg_last_error": [],
 }
@@ -177,10 +183,33 @@ def sg_make_target(s0, s1, scale_out, c_out, target, stream=None):
 
 
 def sg_apply_prediction(out, c_out, scale_out, phi, u, p, nx, ny, nz, box, walls_y, phi_min, phi_max,
-                        stream=None):
-    _check(_L.sg_apply_prediction(_p(out), c_out, _f5(scale_out), _p(phi), _p(u), _p(p), nx, ny, nz, _box(box),
-                                  int(walls_y), float(phi_min), float(phi_max), _stream(stream)),
+                        base=None, u_by_phase=False, stream=None):
+    _check(_L.sg_apply_prediction(_p(out), c_out, _f5(scale_out), _p(base), _p(phi), _p(u), _p(p), nx, ny, nz,
+                                  _box(box), int(walls_y), float(phi_min), float(phi_max), int(u_by_phase),
+                                  _stream(stream)),
            "sg_apply_prediction")
+
+
+def sg_advect_phase(state, count, bx, by, bz, K, out, stream=None):
+    _check(_L.sg_advect_phase(_p(state), int(count), bx, by, bz, float(K), _p(out), _stream(stream)),
+           "sg_advect_phase")
+
+
+def sg_projective_step(s, s_prev, n, cs, vs, ratio, phi_lo, phi_hi, u_by_phase, p_step, out, stream=None):
+    _check(_L.sg_projective_step(_p(s), _p(s_prev), int(n), int(cs), int(vs), float(ratio), float(phi_lo),
+                                 float(phi_hi), int(u_by_phase), int(p_step), _p(out), _stream(stream)),
+           "sg_projective_step")
+
+
+def sg_pair_to_input(state, state_prev, scale_in, trend_scale, c_in, x, stream=None):
+    v = state.numel() // 5
+    _check(_L.sg_pair_to_input(_p(state), _p(state_prev), v, _f5(scale_in), _f5(trend_scale), c_in, _p(x),
+                               _stream(stream)), "sg_pair_to_input")
+
+
+def sg_channel_moments(a, rows, c, out, scratch, stream=None):
+    _check(_L.sg_channel_moments(_p(a), int(rows), int(c), _p(out), _p(scratch), _stream(stream)),
+           "sg_channel_moments")
 
 
 def sg_mass_project(phi, target_mass, phi_min, phi_max, scratch, stream=None):

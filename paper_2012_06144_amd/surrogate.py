@@ -253,9 +253,9 @@ class Net:
 class DataConfig:
     """Rising-bubble runs on an nx x ny x nz grid with seeded diameter, Eotvos
     number and centre offset.  Snapshots of (phi, u, p) every `every` steps
-    from step `start`; `pairs_per_run` pairs (t, t + K) per run, each cropped
-    to `box` cells with the window centred on the bubble at t (the same window
-    for both states of a pair)."""
+    from step `start`; `pairs_per_run` samples per run, each the triplet of
+    states (t - m, t, t + K) cropped to `box` cells with the window centred
+    on the bubble at t - m (the same window for all three)."""
     n_runs: int = 200
     grid: tuple = (128, 256, 128)
     d_range: tuple = (16.0, 40.0)
@@ -266,6 +266,7 @@ class DataConfig:
     start: int = 400
     every: int = 50
     K: int = 200
+    m: int = 25                    # steps between the two states the trend is taken from
     pairs_per_run: int = 10
     box: tuple = (80, 96, 80)      # (bx, by, bz), each divisible by 8
     seed: int = 7
@@ -279,10 +280,23 @@ def _window(cent, box, grid):
     return (int(round(cent[0])) - bx // 2, y0, int(round(cent[2])) - bz // 2, bx, by, bz)
 
 
+class _Stepper:
+    """Advances a solver to absolute step counts."""
+
+    def __init__(self, solver):
+        self.sv, self.t = solver, 0
+
+    def to(self, t):
+        assert t >= self.t
+        if t > self.t:
+            self.sv.step(t - self.t)
+            self.t = t
+
+
 def generate_snapshots(cfg: DataConfig, device="cuda:0", log=print):
-    """Runs the solver and returns the FP32 crops S0, S1 (pairs, bz*by*bx*5,
-    channels last) on the device, the run index of every pair and the run
-    parameters."""
+    """Runs the solver and returns the FP32 crops Sm, S0, S1 (samples,
+    bz*by*bx*5, channels last) of the states at t - m, t and t + K on the
+    device, the run index of every sample and the run parameters."""
     import torch
 
     from . import inputs, lbm
@@ -292,14 +306,15 @@ def generate_snapshots(cfg: DataConfig, device="cuda:0", log=print):
     V = bx * by * bz
     nsnap = (cfg.steps - cfg.start) // cfg.every + 1
     lag = cfg.K // cfg.every
-    assert lag * cfg.every == cfg.K and nsnap > lag
+    assert lag * cfg.every == cfg.K and nsnap > lag and 0 < cfg.m <= cfg.start
     npr = min(cfg.pairs_per_run, nsnap - lag)
     ks = sorted(set(np.linspace(0, nsnap - lag - 1, npr).round().astype(int).tolist()))
-    S0 = torch.empty((cfg.n_runs * len(ks), V * NCH), device=device, dtype=torch.float32)
-    S1 = torch.empty_like(S0)
+    total = cfg.n_runs * len(ks)
+    Sm = torch.empty((total, V * NCH), device=device, dtype=torch.float32)
+    S0, S1 = torch.empty_like(Sm), torch.empty_like(Sm)
     xb = torch.empty(V * C_IN, device=device, dtype=torch.bfloat16)
-    run_of = []
-    meta = []
+    one = [1.0] * NCH
+    run_of, meta = [], []
     slot = 0
     t0 = time.perf_counter()
     for r in range(cfg.n_runs):
@@ -312,68 +327,115 @@ def generate_snapshots(cfg: DataConfig, device="cuda:0", log=print):
         phi, u, ps = inputs.build_fields(s)
         sv = lbm.Solver(s.physics(), storage=cfg.storage, device=device)
         sv.init_fields(phi, u, ps)
-        sv.step(cfg.start)
-        pending = {}
+        st = _Stepper(sv)
         y_first = None
-        for k in range(nsnap):
-            if k:
-                sv.step(cfg.every)
-            if k not in ks and k not in pending:
-                continue
-            fields = sv.macroscopic(torch.float32)
-            if k in pending:
-                j, box = pending.pop(k)
-                sg.sg_fields_to_input(*fields, nx, ny, nz, box, [1.0] * NCH, C_IN, xb, S1[j])
-            if k in ks:
+        # the three states of each sample, in time order (samples may overlap)
+        events = []
+        for j, k in enumerate(ks):
+            t = cfg.start + k * cfg.every
+            events += [(t - cfg.m, 0, j), (t, 1, j), (t + cfg.K, 2, j)]
+        boxes = {}
+        for t, kind, j in sorted(events):
+            st.to(t)
+            if kind == 0:
                 cent = sv.stats()["centroid"]
                 if y_first is None:
                     y_first = cent[1]
-                box = _window(cent, cfg.box, cfg.grid)
-                sg.sg_fields_to_input(*fields, nx, ny, nz, box, [1.0] * NCH, C_IN, xb, S0[slot])
-                pending[k + lag] = (slot, box)
-                run_of.append(r)
-                slot += 1
-            del fields
+                boxes[j] = _window(cent, cfg.box, cfg.grid)
+            f = sv.macroscopic(torch.float32)
+            dst = (Sm, S0, S1)[kind][slot + j]
+            sg.sg_fields_to_input(*f, nx, ny, nz, boxes[j], one, C_IN, xb, dst)
+            del f
+        run_of += [r] * len(ks)
+        slot += len(ks)
         y_last = sv.stats()["centroid"][1]
         meta.append({"D": D, "Eo": eo, "g": g, "centre": [float(v) for v in c]})
-        log(f"[data] run {r}: D={D:.1f} Eo={eo:.1f}: {len(ks)} pairs, rise {y_last - y_first:.2f} cells "
+        log(f"[data] run {r}: D={D:.1f} Eo={eo:.1f}: {len(ks)} samples, rise {y_last - y_first:.2f} cells "
             f"({time.perf_counter() - t0:.0f}s)")
         del sv
     torch.cuda.synchronize()
-    return S0[:slot], S1[:slot], np.array(run_of), meta
+    return Sm[:slot], S0[:slot], S1[:slot], np.array(run_of), meta
 
 
-def channel_scales(S0, S1):
-    """Per-channel input scale (max |value|) and output scale (std of the
-    increment) of the (phi, u_x, u_y, u_z, p) crops, used to normalise."""
-    a = S0.view(-1, NCH)
-    d = (S1 - S0).view(-1, NCH)
-    sin = a.abs().amax(0).clamp_min(1e-12).tolist()
-    sout = d.std(0).clamp_min(1e-12).tolist()
-    sin[0] = 1.0
+def _moments(a, rows, scratch, out):
+    sg.sg_channel_moments(a, rows, NCH, out, scratch)
+    m = out.tolist()
+    mean = [m[c] / rows for c in range(NCH)]
+    var = [max(m[8 + c] / rows - mean[c] ** 2, 0.0) for c in range(NCH)]
+    rms = [math.sqrt(m[8 + c] / rows) for c in range(NCH)]
+    return mean, var, rms
+
+
+def _projective_crop(net_or_none, Sm_i, S0_i, ratio, out):
+    """Baseline of one crop: projective step s + ratio (s - s_prev) (channels
+    last; phi clipped to [0, 1]; velocity increments weighted by the heavy
+    fraction; pressure carried over)."""
+    V = S0_i.numel() // NCH
+    sg.sg_projective_step(S0_i, Sm_i, V, 1, NCH, ratio, 0.0, 1.0, 1, 0, out)
+
+
+def channel_scales(Sm, S0, S1, box, K, m):
+    """Per-channel input scale (root mean square of the state; 1 for phi)
+    and output scale (standard deviation of the target S1 - baseline, the
+    baseline being the projective step from (S(t - m), S(t))), over all
+    samples.  FP64 moments from sg_channel_moments."""
+    import torch
+    bx, by, bz = box
+    V = bx * by * bz
+    n = S0.shape[0]
+    out = torch.zeros(16, device=S0.device, dtype=torch.float64)
+    scratch = torch.zeros(512 * 16, device=S0.device, dtype=torch.float64)
+    _, _, rms = _moments(S0, n * V, scratch, out)
+    sin = [1.0] + [max(r, 1e-12) for r in rms[1:]]
+    acc = np.zeros(16)
+    base = torch.empty((V * NCH,), device=S0.device, dtype=torch.float32)
+    diff = torch.empty((V * NCH,), device=S0.device, dtype=torch.float32)
+    for i in range(n):
+        _projective_crop(None, Sm[i], S0[i], K / m, base)
+        sg.sg_make_target(base, S1[i], [1.0] * NCH, NCH, diff)
+        sg.sg_channel_moments(diff, V, NCH, out, scratch)
+        acc += out.cpu().numpy()
+    rows = n * V
+    var = [max(acc[8 + c] / rows - (acc[c] / rows) ** 2, 0.0) for c in range(NCH)]
+    sout = [max(math.sqrt(v), 1e-12) for v in var]
     return [float(v) for v in sin], [float(v) for v in sout]
 
 
-def make_batch(net, S0, S1, idx, box):
-    """Network input (BF16) and target (FP32) of the pairs `idx`."""
+def trend_scale(net, K, m):
+    """Input scale of the trend channels: the projected increment (K/m)(s -
+    s_prev) in units of the output scale."""
+    return [(K / m) / q for q in net.scale_out]
+
+
+def make_batch(net, Sm, S0, S1, idx, box, K, m, target_from="baseline"):
+    """Network input (BF16: state and trend) and target (FP32) of the samples
+    `idx`.  The target is (S1 - base) / scale_out with base the projective
+    step, or base = S0 (persistence) with target_from="state"."""
     import torch
     bx, by, bz = box
     V = bx * by * bz
     n = len(idx)
     x = torch.empty((n, bz, by, bx, C_IN), device=S0.device, dtype=torch.bfloat16)
     t = torch.empty((n, bz, by, bx, C_OUT), device=S0.device, dtype=torch.float32)
+    base = torch.empty((V * NCH,), device=S0.device, dtype=torch.float32)
+    ts = trend_scale(net, K, m)
     for j, i in enumerate(idx):
-        sg.sg_state_to_input(S0[i], net.scale_in, C_IN, x[j])
-        sg.sg_make_target(S0[i], S1[i], net.scale_out, C_OUT, t[j])
+        sg.sg_pair_to_input(S0[i], Sm[i], net.scale_in, ts, C_IN, x[j])
+        if target_from == "baseline":
+            _projective_crop(net, Sm[i], S0[i], K / m, base)
+            sg.sg_make_target(base, S1[i], net.scale_out, C_OUT, t[j])
+        else:
+            sg.sg_make_target(S0[i], S1[i], net.scale_out, C_OUT, t[j])
     return x, t
 
 
-def train(net, S0, S1, box, run_of=None, steps=500, batch=8, lr=5e-4, warmup=20, val_frac=0.1, seed=0,
-          log=print):
-    """Adam on the MSE of the normalised increment, linear warm-up over
-    `warmup` steps, then cosine learning-rate decay.  Validation pairs are whole runs held out (pairs of one run are
+def train(net, Sm, S0, S1, box, K, m, run_of=None, steps=500, batch=8, lr=5e-4, warmup=20, val_frac=0.1,
+          seed=0, log=print):
+    """Adam on the MSE of the normalised residual of the projective step,
+    linear warm-up over `warmup` steps, then cosine learning-rate decay.
+    Validation samples are whole runs held out (samples of one run are
     correlated).  Returns the loss history and the validation losses of the
-    network and of persistence (increment 0)."""
+    network, of the projective step alone and of persistence."""
     import torch
     n = S0.shape[0]
     rng = np.random.default_rng(seed)
@@ -390,7 +452,7 @@ def train(net, S0, S1, box, run_of=None, steps=500, batch=8, lr=5e-4, warmup=20,
     t0 = time.perf_counter()
     for it in range(steps):
         idx = rng.choice(tr, size=min(batch, len(tr)), replace=False)
-        x, t = make_batch(net, S0, S1, idx, box)
+        x, t = make_batch(net, Sm, S0, S1, idx, box, K, m)
         out = net.forward(x)
         g = torch.empty(out.shape, device=out.device, dtype=torch.bfloat16)
         sg.sg_mse(out, t, loss, g, scratch)
@@ -403,29 +465,36 @@ def train(net, S0, S1, box, run_of=None, steps=500, batch=8, lr=5e-4, warmup=20,
             log(f"[train] step {it} loss {lv:.4e} ({time.perf_counter() - t0:.1f}s)")
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    v_net, v_zero = evaluate(net, S0, S1, val, box)
-    return {"history": hist, "val_loss": v_net, "val_loss_persistence": v_zero, "seconds": wall,
+    v = evaluate(net, Sm, S0, S1, val, box, K, m)
+    return {"history": hist, "val_loss": v["network"], "val_loss_baseline": v["baseline"],
+            "val_loss_persistence": v["persistence"], "seconds": wall,
             "n_train": int(len(tr)), "n_val": int(len(val)), "val_runs": [int(v) for v in vr]}
 
 
-def evaluate(net, S0, S1, idx, box, batch=8):
-    """Mean validation MSE of the network and of the zero increment."""
+def evaluate(net, Sm, S0, S1, idx, box, K, m, batch=8):
+    """Mean validation MSE (normalised units) of the jump with the network
+    (projective step + network residual), of the projective step alone
+    (network output 0) and of persistence (state left unchanged)."""
     import torch
     loss = torch.zeros(1, device=S0.device, dtype=torch.float32)
     scratch = torch.zeros(1024, device=S0.device, dtype=torch.float32)
-    tot_n, tot_z, cnt = 0.0, 0.0, 0
+    tot = {"network": 0.0, "baseline": 0.0, "persistence": 0.0}
+    cnt = 0
     for k in range(0, len(idx), batch):
         ii = idx[k:k + batch]
-        x, t = make_batch(net, S0, S1, ii, box)
+        x, t = make_batch(net, Sm, S0, S1, ii, box, K, m)
         out = net.forward(x, keep=False)
         g = torch.empty(out.shape, device=out.device, dtype=torch.bfloat16)
         sg.sg_mse(out, t, loss, g, scratch)
-        tot_n += float(loss.item()) * len(ii)
+        tot["network"] += float(loss.item()) * len(ii)
         zero = torch.zeros_like(out)
         sg.sg_mse(zero, t, loss, g, scratch)
-        tot_z += float(loss.item()) * len(ii)
+        tot["baseline"] += float(loss.item()) * len(ii)
+        _, tp = make_batch(net, Sm, S0, S1, ii, box, K, m, target_from="state")
+        sg.sg_mse(zero, tp, loss, g, scratch)
+        tot["persistence"] += float(loss.item()) * len(ii)
         cnt += len(ii)
-    return tot_n / cnt, tot_z / cnt
+    return {k: v / cnt for k, v in tot.items()}
 
 
 # ---------------------------------------------------------------------------------------
@@ -434,77 +503,148 @@ def evaluate(net, S0, S1, idx, box, batch=8):
 
 @dataclass
 class JumpConfig:
-    K: int = 200                # steps one prediction skips
+    K: int = 200                # steps one jump skips
     relax: int = 50             # LBM steps after each jump
+    m: int = 25                 # the trend is taken over the last m relaxation steps (m <= relax), or
+                                # between consecutive cycle ends (m = K + relax)
     mass_tol: float = 1e-6      # |d sum(phi)| / sum(phi) over a cycle
     xi_lo: float = 0.8          # interface width must stay in [xi_lo, xi_hi] * xi
     xi_hi: float = 1.25
-    box: tuple = (112, 128, 112)  # prediction window around the bubble (bx, by, bz), divisible by 8
-
-
-def predict_into_fields(net, phi, u, p, setup, box):
-    """One network prediction over `box` (x0, y0, z0, bx, by, bz), added to
-    the FP32 fields in place; the fields outside the box are left as they are."""
-    import torch
-    bx, by, bz = box[3], box[4], box[5]
-    x = torch.empty((1, bz, by, bx, C_IN), device=phi.device, dtype=torch.bfloat16)
-    sg.sg_fields_to_input(phi, u, p, setup.nx, setup.ny, setup.nz, box, net.scale_in, C_IN, x)
-    out = net.forward(x, keep=False)
-    sg.sg_apply_prediction(out, C_OUT, net.scale_out, phi, u, p, setup.nx, setup.ny, setup.nz, box,
-                           int(setup.walls_y), setup.phi_L, setup.phi_H)
+    u_max: float = 0.05         # indicator: max |u| after the relaxation (lattice units)
+    box: tuple = (112, 128, 112)  # network window around the bubble (bx, by, bz), divisible by 8
+    predict_pressure: bool = False  # apply the network's pressure residual (else p follows the baseline)
+    u_by_phase: bool = True     # weight velocity increments by the heavy-phase fraction
 
 
 def _traj_entry(step, st, **kw):
     d = {"step": step, "centroid_y": st["centroid"][1], "rise_velocity": st["rise_velocity"], "mass": st["mass"],
-         "xi_eff": st["xi_eff"]}
+         "xi_eff": st["xi_eff"], "max_speed": st["max_speed"]}
     d.update(kw)
     return d
 
 
-def run_with_jumps(net, solver, setup, total_steps, jc: JumpConfig, log=print):
-    """Advances `solver` by total_steps in cycles of one jump (K steps
-    predicted) plus jc.relax LBM steps.  After each cycle the indicators are
-    checked (finite, mass drift over the cycle <= mass_tol, interface width in
-    [xi_lo, xi_hi] xi); if one trips, the state saved before the jump is
-    restored and the cycle's K + relax steps are run with the plain LBM.
-    With net=None the jump leaves the fields unchanged (persistence), the
-    same driver without the network."""
+def _jump(net, mode, F_now, F_prev, setup, box, jc: JumpConfig, diagnostics=False):
+    """Writes the state K steps ahead into F_now ((5, nz, ny, nx) FP32 planes:
+    phi, u, p) from F_now and F_prev (m steps earlier).  mode "persistence":
+    unchanged; "transport": phi moved by the local velocity; "projective":
+    projective step; "network": projective step plus the network's residual
+    in the window around the bubble."""
     import torch
+    nx, ny, nz = setup.nx, setup.ny, setup.nz
+    N = nx * ny * nz
+    if mode == "persistence":
+        return None
+    if mode == "transport":
+        bx, by, bz = box[3], box[4], box[5]
+        V = bx * by * bz
+        st = torch.empty(V * NCH, device=F_now.device, dtype=torch.float32)
+        base = torch.empty_like(st)
+        x = torch.empty(V * C_IN, device=F_now.device, dtype=torch.bfloat16)
+        sg.sg_fields_to_input(F_now[0], F_now[1:4], F_now[4], nx, ny, nz, box, [1.0] * NCH, C_IN, x, st)
+        sg.sg_advect_phase(st, 1, bx, by, bz, jc.K, base)
+        zero = torch.zeros((V, C_OUT), device=F_now.device, dtype=torch.float32)
+        sg.sg_apply_prediction(zero, C_OUT, [0.0] * NCH, F_now[0], F_now[1:4], F_now[4], nx, ny, nz, box,
+                               int(setup.walls_y), setup.phi_L, setup.phi_H, base=base)
+        return None
+    inc = None
+    out = None
+    if mode == "network":
+        bx, by, bz = box[3], box[4], box[5]
+        V = bx * by * bz
+        s0 = torch.empty(V * NCH, device=F_now.device, dtype=torch.float32)
+        sm = torch.empty_like(s0)
+        x = torch.empty((1, bz, by, bx, C_IN), device=F_now.device, dtype=torch.bfloat16)
+        one = [1.0] * NCH
+        sg.sg_fields_to_input(F_now[0], F_now[1:4], F_now[4], nx, ny, nz, box, one, C_IN, x, s0)
+        sg.sg_fields_to_input(F_prev[0], F_prev[1:4], F_prev[4], nx, ny, nz, box, one, C_IN, x, sm)
+        sg.sg_pair_to_input(s0, sm, net.scale_in, trend_scale(net, jc.K, jc.m), C_IN, x)
+        out = net.forward(x, keep=False)
+    lo, hi = min(setup.phi_L, setup.phi_H), max(setup.phi_L, setup.phi_H)
+    sg.sg_projective_step(F_now, F_prev, N, N, 1, jc.K / jc.m, lo, hi, int(jc.u_by_phase), 0, F_now)
+    if out is not None:
+        so = list(net.scale_out)
+        if not jc.predict_pressure:
+            so[4] = 0.0
+        sg.sg_apply_prediction(out, C_OUT, so, F_now[0], F_now[1:4], F_now[4], nx, ny, nz, box,
+                               int(setup.walls_y), lo, hi, u_by_phase=jc.u_by_phase)
+        if diagnostics:
+            mx = out.view(-1, C_OUT)[:, :NCH].abs().amax(0).tolist()
+            inc = [float(a * b) for a, b in zip(mx, so)]
+    return inc
+
+
+def run_with_jumps(net, solver, setup, total_steps, jc: JumpConfig, log=print, mode="network"):
+    """Advances `solver` by total_steps: m plain steps to start the trend,
+    then cycles of one jump (K steps, see _jump) plus jc.relax LBM steps,
+    the fields being taken m steps before the end of each relaxation and at
+    its end.  After each cycle the indicators are checked (finite, mass drift
+    over the cycle <= mass_tol, interface width in [xi_lo, xi_hi] xi, max |u|
+    <= u_max); if one trips, the state saved before the jump is restored and
+    the cycle's K + relax steps are run with the plain LBM."""
+    import torch
+    nx, ny, nz = setup.nx, setup.ny, setup.nz
+    shape = (5, nz, ny, nx)
+    F_now = torch.empty(shape, device=solver.device, dtype=torch.float32)
+    F_prev = torch.empty_like(F_now)
     backup = solver.new_state_buffer()
     scratch = torch.zeros(2048, device=solver.device, dtype=torch.float64)
-    done = 0
+    cyc = jc.K + jc.relax
     accepted = rejected = 0
     traj = [_traj_entry(0, solver.stats())]
-    cyc = jc.K + jc.relax
-    t_pred = 0.0
+    t_jump = 0.0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    across = jc.m == cyc               # trend between consecutive cycle ends
+    assert across or 0 < jc.m <= jc.relax
+    solver.macroscopic(out=F_prev)
+    solver.step(jc.m)
+    done = jc.m
+    solver.macroscopic(out=F_now)
+    F_keep = torch.empty_like(F_now) if across else None
     while done + cyc <= total_steps:
         m0 = solver.reduce_mass()
         cent = solver.stats()["centroid"]
         solver.save_state(backup)
-        phi, u, p = solver.macroscopic(torch.float32)
-        box = _window(cent, jc.box, (setup.nx, setup.ny, setup.nz))
+        box = _window(cent, jc.box, (nx, ny, nz))
         tp = time.perf_counter()
-        if net is not None:
-            predict_into_fields(net, phi, u, p, setup, box)
-        sg.sg_mass_project(phi, m0, setup.phi_L, setup.phi_H, scratch)
-        solver.set_macroscopic(phi, u, p)
-        del phi, u, p
+        if across:
+            F_keep.copy_(F_now)
+        inc = _jump(net, mode, F_now, F_prev, setup, box, jc, diagnostics=len(traj) <= 4)
+        sg.sg_mass_project(F_now[0], m0, setup.phi_L, setup.phi_H, scratch)
+        solver.set_macroscopic(F_now[0], F_now[1:4], F_now[4])
         torch.cuda.synchronize()
-        t_pred += time.perf_counter() - tp
-        solver.step(jc.relax)
-        st = solver.stats()
-        drift = abs(st["mass"] - m0) / abs(m0)
-        ok = (math.isfinite(st["mass"]) and drift <= jc.mass_tol
-              and jc.xi_lo * setup.xi <= st["xi_eff"] <= jc.xi_hi * setup.xi)
+        t_jump += time.perf_counter() - tp
+        if across:
+            F_prev, F_keep = F_keep, F_prev
+            solver.step(jc.relax)
+        else:
+            solver.step(jc.relax - jc.m)
+            solver.macroscopic(out=F_prev)
+            solver.step(jc.m)
+        try:
+            st = solver.stats()
+            drift = abs(st["mass"] - m0) / abs(m0)
+            ok = (drift <= jc.mass_tol and jc.xi_lo * setup.xi <= st["xi_eff"] <= jc.xi_hi * setup.xi
+                  and st["max_speed"] <= jc.u_max)
+        except Exception as e:          # non-finite state after the jump
+            st, drift, ok = None, float("nan"), False
+            log(f"[jump] cycle at step {done}: {e}")
+        if inc is not None:
+            log(f"[jump] cycle at step {done}: max network residual {['%.2e' % v for v in inc]}, "
+                f"drift {drift:.2e}, xi_eff {st['xi_eff'] if st else float('nan'):.3f}")
         if ok:
             accepted += 1
         else:
             rejected += 1
             solver.restore_state(backup)
-            solver.step(cyc)
+            if across:
+                solver.step(cyc)
+            else:
+                solver.step(cyc - jc.m)
+                solver.macroscopic(out=F_prev)
+                solver.step(jc.m)
             st = solver.stats()
+        solver.macroscopic(out=F_now)
         done += cyc
         traj.append(_traj_entry(done, st, jump=bool(ok), drift=drift))
     if done < total_steps:
@@ -513,18 +653,23 @@ def run_with_jumps(net, solver, setup, total_steps, jc: JumpConfig, log=print):
         traj.append(_traj_entry(done, solver.stats()))
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    log(f"[jump] {accepted} accepted, {rejected} rejected, {wall:.1f}s ({t_pred:.1f}s predicting)")
+    log(f"[jump] {mode}: {accepted} accepted, {rejected} rejected, {wall:.1f}s ({t_jump:.2f}s in jumps)")
     return {"trajectory": traj, "accepted": accepted, "rejected": rejected, "seconds": wall,
-            "seconds_predict": t_pred}
+            "seconds_jump": t_jump}
 
 
-def run_plain(solver, total_steps, every, log=print):
-    """The plain LBM with the same statistics cadence as the jump driver."""
+def run_plain(solver, total_steps, every, first=None, log=print):
+    """The plain LBM with the statistics cadence of the jump driver: at step
+    0, at `first`, then every `every` steps, and at the end."""
     import torch
     traj = [_traj_entry(0, solver.stats())]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     done = 0
+    if first:
+        solver.step(first)
+        done = first
+        traj.append(_traj_entry(done, solver.stats()))
     while done < total_steps:
         n = min(every, total_steps - done)
         solver.step(n)
@@ -590,15 +735,17 @@ def _cmd_train(a):
     import torch
     cfg = DataConfig(n_runs=a.runs, steps=a.lbm_steps, pairs_per_run=a.pairs_per_run)
     t0 = time.perf_counter()
-    S0, S1, run_of, meta = generate_snapshots(cfg, log=_log)
+    Sm, S0, S1, run_of, meta = generate_snapshots(cfg, log=_log)
     torch.cuda.synchronize()
     t_data = time.perf_counter() - t0
     net = Net(seed=a.seed)
-    net.scale_in, net.scale_out = channel_scales(S0, S1)
-    res = train(net, S0, S1, cfg.box, run_of=run_of, steps=a.train_steps, batch=a.batch, lr=a.lr, log=_log)
-    res.update({"data_seconds": t_data, "pairs": int(S0.shape[0]), "runs": meta, "config": cfg.__dict__,
+    net.scale_in, net.scale_out = channel_scales(Sm, S0, S1, cfg.box, cfg.K, cfg.m)
+    res = train(net, Sm, S0, S1, cfg.box, cfg.K, cfg.m, run_of=run_of, steps=a.train_steps, batch=a.batch,
+                lr=a.lr, log=_log)
+    res.update({"data_seconds": t_data, "samples": int(S0.shape[0]), "runs": meta, "config": cfg.__dict__,
                 "scale_in": net.scale_in, "scale_out": net.scale_out, "params": net.n_params()})
-    _log(f"[train] val loss {res['val_loss']:.4e} vs persistence {res['val_loss_persistence']:.4e}")
+    _log(f"[train] val loss {res['val_loss']:.4e}; projective step alone {res['val_loss_baseline']:.4e}; "
+         f"persistence {res['val_loss_persistence']:.4e}")
     if a.weights:
         save_weights(net, a.weights)
     return res
@@ -611,25 +758,31 @@ def _cmd_jump(a):
     s = inputs.surrogate_jump_bubble(steps=a.steps)
     if a.grid:
         nx, ny, nz = (int(v) for v in a.grid.split("x"))
-        s = inputs.rising_bubble(nx, ny, nz, D=s.radius * 2, center=(nx / 2, ny / 4, nz / 2),
-                                 g=-s.accel[1], steps=a.steps)
+        D = a.D if a.D else s.radius * 2
+        g = a.eo * 1e-4 / (D * D)          # Eo = g rho_H D^2 / sigma, sigma = 1e-4, rho_H = 1
+        s = inputs.rising_bubble(nx, ny, nz, D=D, center=(nx / 2, ny / 4, nz / 2), g=g, steps=a.steps)
+        s.name = f"rising_bubble_{nx}x{ny}x{nz}_D{D:g}_Eo{a.eo:g}"
     phi, u, ps = inputs.build_fields(s)
-    jc = JumpConfig(K=a.K, relax=a.relax)
+    jc = JumpConfig(K=a.K, relax=a.relax, m=a.m)
+    if a.box:
+        jc.box = tuple(int(v) for v in a.box.split("x"))
     out = {"workload": s.name, "steps": a.steps, "jump": jc.__dict__, "runs": {}}
     sv = lbm.Solver(s.physics(), storage="f32")
     sv.init_fields(phi, u, ps)
-    out["runs"]["plain"] = run_plain(sv, a.steps, jc.K + jc.relax, log=_log)
+    out["runs"]["plain"] = run_plain(sv, a.steps, jc.K + jc.relax, first=jc.m, log=_log)
     del sv
     torch.cuda.empty_cache()
-    variants = [("persistence", None)]
-    if a.weights:
+    modes = a.modes.split(",")
+    variants = [(mname, None, mname) for mname in ("persistence", "transport", "projective") if mname in modes]
+    if a.weights and "network" in modes:
         net = Net(seed=0)
         load_weights(net, a.weights)
-        variants.append(("surrogate", net))
-    for name, net in variants:
+        variants.append(("surrogate", net, "network"))
+    jc.predict_pressure = bool(a.predict_pressure)
+    for name, net, mode in variants:
         sv = lbm.Solver(s.physics(), storage="f32")
         sv.init_fields(phi, u, ps)
-        r = run_with_jumps(net, sv, s, a.steps, jc, log=_log)
+        r = run_with_jumps(net, sv, s, a.steps, jc, log=_log, mode=mode)
         r["errors"] = compare_trajectories(out["runs"]["plain"], r)
         r["speedup"] = out["runs"]["plain"]["seconds"] / r["seconds"]
         out["runs"][name] = r
@@ -663,7 +816,13 @@ def main():
     j.add_argument("--steps", type=int, default=40000)
     j.add_argument("--K", type=int, default=200)
     j.add_argument("--relax", type=int, default=50)
+    j.add_argument("--m", type=int, default=25, help="trend window (<= relax, or K + relax for cycle ends)")
+    j.add_argument("--modes", default="persistence,transport,projective,network")
     j.add_argument("--grid", default=None, help="override the grid, e.g. 128x512x128")
+    j.add_argument("--D", type=float, default=None, help="bubble diameter with --grid")
+    j.add_argument("--eo", type=float, default=10.0, help="Eotvos number with --grid")
+    j.add_argument("--box", default=None, help="prediction window bx x by x bz, e.g. 80x96x80")
+    j.add_argument("--predict-pressure", action="store_true")
     j.add_argument("--out", default=None)
     a = ap.parse_args()
     res = _cmd_train(a) if a.cmd == "train" else _cmd_jump(a)
