@@ -63,6 +63,30 @@ def load_traffic(kernel: str, workload: str, storage: str, src_hash: str):
     return d
 
 
+def surrogate_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("csrc/sg_api.hip", "surrogate.py", "csrc/lbm_kernels.hpp", "csrc/lbm_lattice.hpp", "csrc/lbm_api.hip"):
+        with open(os.path.join(ROOT, "paper_2012_06144_amd", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_surrogate_study():
+    """Speedup and rise-velocity error of the surrogate-accelerated run against
+    the plain FP32 run (40000 steps, 256x1024x256), from the committed study
+    summary if it was taken on the current sources (else marked stale)."""
+    path = os.path.join(ROOT, "profiles", "surrogate_jump_rising_bubble_256x1024x256.md")
+    if not os.path.exists(path):
+        return None
+    m = re.search(r"^study_json:\s*(\{.*\})\s*$", open(path).read(), flags=re.M)
+    if not m:
+        return None
+    d = json.loads(m.group(1))
+    d["source"] = "profiles/surrogate_jump_rising_bubble_256x1024x256.md"
+    d["stale"] = d.get("source_hash") != surrogate_source_hash()
+    return d
+
+
 def cpu_baseline(setup, phi, u, ps, target_s: float = 15.0):
     """Time the FP64 oracle on a 128 x ny x 128 slab of the same workload."""
     import numpy as np
@@ -189,7 +213,7 @@ def main():
         log(f"[bench] oracle {cpu['value']:.2f} MLUPS on {cpu['cores']} threads")
 
     line = {
-        "metric": "coupled MLUPS + %HBM roofline",
+        "metric": "coupled MLUPS + %HBM roofline; surrogate-vs-plain speedup at \u22641% rise-vel error",
         "value": round(mlups, 1),
         "unit": "MLUPS",
         "n_gpus": 1,
@@ -222,6 +246,7 @@ def main():
         "paper_context": {"mlups": 550, "hardware": "Tesla P100", "precision": "f64",
                           "roofline_frac_of_stream": 0.78},
         "cpu_baseline": cpu,
+        "surrogate": load_surrogate_study(),
         "kernel_source_hash": src_hash,
     }
     print(json.dumps(line), flush=True)

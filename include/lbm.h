@@ -129,7 +129,11 @@ size_t lbm_workspace_bytes(const lbm_params *p);
 /* Creates a solver context.  dev_workspace: caller-owned device memory of
  * at least lbm_workspace_bytes(p) bytes, 256-byte aligned, that must stay
  * allocated until lbm_destroy.  hip_stream: a hipStream_t (NULL = default
- * stream).  The context owns no device memory.  *out receives the context. */
+ * stream).  The context owns no device memory.  *out receives the context.
+ * Sweep kernels: the environment variable LBM_ZMARCH, read here, selects the
+ * z-marching sweeps that stage the phase field of three planes in LDS
+ * ("1") or the one-cell-per-thread sweeps ("0"); unset, the library's
+ * default.  Both compute the same numbers (same operation order). */
 lbm_status lbm_create(const lbm_params *p, void *dev_workspace, size_t bytes, void *hip_stream,
                       lbm_ctx **out);
 

@@ -151,8 +151,8 @@ sg_status sg_projective_step(const float *s, const float *s_prev, int64_t n, int
 
 /* Network input of a box state s and the same box m steps earlier (5 FP32
  * channels per voxel each): channels 0-4 = s / scale_in, 5-9 =
- * (s - s_prev) * trend_scale (both HOST arrays of 5 floats), zeros up to
- * c_in (>= 10) channels, BF16. */
+ * (s - s_prev) * trend_scale (both HOST arrays of 5 floats), each clipped
+ * to [-16, 16], zeros up to c_in (>= 10) channels, BF16. */
 sg_status sg_pair_to_input(const float *state, const float *state_prev, int64_t voxels, const float *scale_in,
                            const float *trend_scale, int32_t c_in, void *x_bf16, void *hip_stream);
 

@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 
@@ -146,6 +147,7 @@ struct lbm_ctx {
     int cur;  // index of the current source buffers (H, G, phi)
     bool initialized;
     int64_t steps;
+    bool zmarch;  // sweeps march in z with phi staged in LDS
 };
 
 namespace {
@@ -160,6 +162,41 @@ struct Ops {
     static R *phi(lbm_ctx *c, int k) { return (R *)(c->ws + c->L.off_phi[k]); }
     static R *u(lbm_ctx *c) { return (R *)(c->ws + c->L.off_u); }
     static int blocks(lbm_ctx *c) { return (int)((c->g.ncells + kBlock - 1) / kBlock); }
+
+    // Tiling of the z-marching sweeps: about kZmBlocks blocks, at most 64
+    // planes per block.
+    static ZTiles ztiles(lbm_ctx *c)
+    {
+        ZTiles t;
+        t.tx = (c->g.nx + kTX - 1) / kTX;
+        t.ty = (c->g.ny + kTY - 1) / kTY;
+        const int64_t tiles = (int64_t)t.tx * t.ty;
+        int64_t zc = tiles * c->g.nz / kZmBlocks;
+        zc = zc < 1 ? 1 : (zc > 64 ? 64 : zc);
+        t.zc = (int)zc;
+        t.tz = (c->g.nz + t.zc - 1) / t.zc;
+        return t;
+    }
+
+    static void launch_phase(lbm_ctx *c, const SweepArgs<S> &sp)
+    {
+        if (c->zmarch) {
+            const ZTiles t = ztiles(c);
+            hipLaunchKernelGGL((k_sweep_zm<S, true>), dim3(t.tx * t.ty * t.tz), dim3(kBlock), 0, c->stream, sp, t);
+        } else {
+            hipLaunchKernelGGL((k_phase<S>), dim3(blocks(c)), dim3(kBlock), 0, c->stream, sp);
+        }
+    }
+
+    static void launch_hydro(lbm_ctx *c, const SweepArgs<S> &sh)
+    {
+        if (c->zmarch) {
+            const ZTiles t = ztiles(c);
+            hipLaunchKernelGGL((k_sweep_zm<S, false>), dim3(t.tx * t.ty * t.tz), dim3(kBlock), 0, c->stream, sh, t);
+        } else {
+            hipLaunchKernelGGL((k_hydro<S>), dim3(blocks(c)), dim3(kBlock), 0, c->stream, sh);
+        }
+    }
 
     static lbm_status zero_all(lbm_ctx *c)
     {
@@ -191,10 +228,10 @@ struct Ops {
         for (int t = 0; t < n; ++t) {
             const int a = c->cur, b = 1 - c->cur;
             SweepArgs<S> sp{H(c, a), H(c, b), phi(c, a), phi(c, b), u(c), c->g, ph};
-            hipLaunchKernelGGL((k_phase<S>), dim3(blocks(c)), dim3(kBlock), 0, c->stream, sp);
+            launch_phase(c, sp);
             LAUNCH_CHECK();
             SweepArgs<S> sh{G(c, a), G(c, b), phi(c, b), nullptr, u(c), c->g, ph};
-            hipLaunchKernelGGL((k_hydro<S>), dim3(blocks(c)), dim3(kBlock), 0, c->stream, sh);
+            launch_hydro(c, sh);
             LAUNCH_CHECK();
             c->cur = b;
             ++c->steps;
@@ -215,12 +252,12 @@ struct Ops {
             SweepArgs<S> sh{G(c, a), G(c, b), phi(c, b), nullptr, u(c), c->g, ph};
             hipError_t e = hipEventRecord(ev[0], c->stream);
             if (e == hipSuccess) {
-                hipLaunchKernelGGL((k_phase<S>), dim3(blocks(c)), dim3(kBlock), 0, c->stream, sp);
+                launch_phase(c, sp);
                 e = hipGetLastError();
             }
             if (e == hipSuccess) e = hipEventRecord(ev[1], c->stream);
             if (e == hipSuccess) {
-                hipLaunchKernelGGL((k_hydro<S>), dim3(blocks(c)), dim3(kBlock), 0, c->stream, sh);
+                launch_hydro(c, sh);
                 e = hipGetLastError();
             }
             if (e == hipSuccess) e = hipEventRecord(ev[2], c->stream);
@@ -410,6 +447,8 @@ lbm_status lbm_create(const lbm_params *p, void *ws, size_t bytes, void *stream,
     c->cur = 0;
     c->initialized = false;
     c->steps = 0;
+    c->zmarch = LBM_ZMARCH != 0;
+    if (const char *v = std::getenv("LBM_ZMARCH")) c->zmarch = (v[0] == '1');
     *out = c;
     g_err[0] = 0;
     return LBM_OK;

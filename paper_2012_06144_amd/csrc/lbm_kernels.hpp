@@ -194,16 +194,45 @@ __device__ inline R geq_i(int i, R ps, R ux, R uy, R uz, R uu)
     return wgt<27, R>(i) * (ps + by_cs2(eu) + (eu * eu) / (R(2) * c2 * c2) - uu / (R(2) * c2));
 }
 
+// Previous / new phase field around a cell, as the stencils read it (wall
+// rows mirrored onto the current row).  PhiG reads global memory; PhiL reads
+// the three LDS planes a z-marching block keeps.
+template <class R>
+struct PhiG {
+    const R *__restrict__ phi;
+    int c;
+    const Nbr *n;
+    __device__ R at(int dx, int dy, int dz) const { return phi[c + n->offm(dx, dy, dz)]; }
+};
+
+#ifndef LBM_ZMARCH
+#define LBM_ZMARCH 0  // 1: sweeps march in z with the phase field staged in LDS
+#endif
+#ifndef LBM_ZM_TX
+#define LBM_ZM_TX 64
+#endif
+constexpr int kTX = LBM_ZM_TX, kTY = LBM_BLOCK / LBM_ZM_TX;  // z-marching tile, one thread per cell
+constexpr int kZmBlocks = 8192;            // target block count of a z-marching launch
+static_assert(kTX * kTY == LBM_BLOCK, "a z-marching tile has one thread per cell");
+constexpr int kLX = kTX + 2, kLY = kTY + 2;
+
+template <class R>
+struct PhiL {
+    const R *pl[3];  // planes z-1, z, z+1: (kTY+2) rows of (kTX+2) values, halo included
+    int o;           // (ty+1) kLX + (tx+1)
+    __device__ R at(int dx, int dy, int dz) const { return pl[dz + 1][o + dy * kLX + dx]; }
+};
+
 // Isotropic gradient (eq. grad) as antisymmetric pair differences over the
 // half set, and (optionally) Laplacian (eq. lap), on phi with the wall mirror.
-template <int Q, class R, bool LAP>
-__device__ inline void stencil(const R *__restrict__ phi, int c, const Nbr &n, R grad[3], R &lap)
+template <int Q, class R, bool LAP, class P>
+__device__ inline void stencil(const P &phi, R grad[3], R &lap)
 {
     R acc[3] = {R(0), R(0), R(0)};
 #pragma unroll
     for (int i = 1; i < Q; i += 2) {
         const int dx = ev<Q>(i, 0), dy = ev<Q>(i, 1), dz = ev<Q>(i, 2);
-        const R d = phi[c + n.offm(dx, dy, dz)] - phi[c + n.offm(-dx, -dy, -dz)];
+        const R d = phi.at(dx, dy, dz) - phi.at(-dx, -dy, -dz);
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             const int ea = ev<Q>(i, a);
@@ -214,12 +243,12 @@ __device__ inline void stencil(const R *__restrict__ phi, int c, const Nbr &n, R
 #pragma unroll
     for (int a = 0; a < 3; ++a) grad[a] = by_cs2(acc[a]);
     if (LAP) {
-        const R pc = phi[c];
+        const R pc = phi.at(0, 0, 0);
         R s = R(0);
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
             const int dx = ev<Q>(i, 0), dy = ev<Q>(i, 1), dz = ev<Q>(i, 2);
-            s += wgt<Q, R>(i) * (phi[c + n.offm(dx, dy, dz)] - pc);
+            s += wgt<Q, R>(i) * (phi.at(dx, dy, dz) - pc);
         }
         lap = R(2) * by_cs2(s);
     }
@@ -252,20 +281,14 @@ __device__ inline int64_t pull_idx(int i, int c, const Nbr &n)
 // normal and theta from the previous phi (eqs. allen_cahn, grad), forcing
 // (eq. interfaceTracking), equilibrium phi Gamma(u), single-rate collision
 // (eq. lb_interface); store post-collision h at the cell ----------------------
-template <class S>
-__global__ __launch_bounds__(kBlock) void k_phase(const SweepArgs<S> a)
+template <class S, class P>
+__device__ inline void phase_cell(const SweepArgs<S> &a, int c, const Nbr &n, const P &phiA)
 {
     using R = typename S::real;
-    const int c = xcd_block() * kBlock + threadIdx.x;
-    if (c >= a.g.ncells) return;
-    int x, y, z;
-    Nbr n;
-    if (!decode(a.g, c, x, y, z, n)) return;
-
     // previous phase field at x + e_i (D3Q15 stencil points; wall rows mirrored)
     R phs[15];
 #pragma unroll
-    for (int i = 0; i < 15; ++i) phs[i] = a.phi_in[c + n.offm(e15(i, 0), e15(i, 1), e15(i, 2))];
+    for (int i = 0; i < 15; ++i) phs[i] = phiA.at(e15(i, 0), e15(i, 1), e15(i, 2));
 
     // The population arrives from x - e_i (phs[opp(i)]) or bounces back at x.
     // The FP32 and 16-bit paths keep the phi budget of the cell in FP64: the
@@ -341,6 +364,17 @@ __global__ __launch_bounds__(kBlock) void k_phase(const SweepArgs<S> a)
     }
 }
 
+template <class S>
+__global__ __launch_bounds__(kBlock) void k_phase(const SweepArgs<S> a)
+{
+    const int c = xcd_block() * kBlock + threadIdx.x;
+    if (c >= a.g.ncells) return;
+    int x, y, z;
+    Nbr n;
+    if (!decode(a.g, c, x, y, z, n)) return;
+    phase_cell<S>(a, c, n, PhiG<typename S::real>{a.phi_in, c, &n});
+}
+
 // ---- hydrodynamic sweep: pull-stream g, moments, forces from the new phi
 // (eqs. forceHydro, pressure_force, surfaceTension, chemPot, viscousForce and
 // buoyancy), velocity update (eq. updateVelocityField), moment-space
@@ -353,16 +387,10 @@ __global__ __launch_bounds__(kBlock) void k_phase(const SweepArgs<S> a)
 //   g*_i = g_eq_i(p*, u) + F_i/2 + (1 - s) w_i/(2 cs^4) (e_i e_i - cs^2 I) : A,
 //   A = Pi - p* cs^2 I - u u^T,  F_i = w_i e_i.F/(rho cs^2),
 // and the bracket of the viscous force is s A(u_old).
-template <class S>
-__global__ __launch_bounds__(kBlock) void k_hydro(const SweepArgs<S> a)
+template <class S, class P>
+__device__ inline void hydro_cell(const SweepArgs<S> &a, int c, const Nbr &n, const P &phiB)
 {
     using R = typename S::real;
-    const int c = xcd_block() * kBlock + threadIdx.x;
-    if (c >= a.g.ncells) return;
-    int x, y, z;
-    Nbr n;
-    if (!decode(a.g, c, x, y, z, n)) return;
-
     R ps = R(0), j[3] = {R(0), R(0), R(0)};
     R Pxx = R(0), Pyy = R(0), Pzz = R(0), Pxy = R(0), Pxz = R(0), Pyz = R(0);
 #pragma unroll
@@ -381,9 +409,9 @@ __global__ __launch_bounds__(kBlock) void k_hydro(const SweepArgs<S> a)
         if (ey && ez) Pyz += (ey * ez > 0) ? gi : -gi;
     }
 
-    const R phi = a.phi_in[c];
+    const R phi = phiB.at(0, 0, 0);
     R grad[3], lap;
-    stencil<27, R, true>(a.phi_in, c, n, grad, lap);
+    stencil<27, R, true>(phiB, grad, lap);
 
     const Phys<R> &ph = a.ph;
     const R rho = density_of(ph, phi);
@@ -432,6 +460,117 @@ __global__ __launch_bounds__(kBlock) void k_hydro(const SweepArgs<S> a)
                       R(2 * ex * ey) * Bxy + R(2 * ex * ez) * Bxz + R(2 * ey * ez) * Byz - c2 * trB;
         const R gs = geq + R(0.5) * w * eF * finv + neq * w * eBe;
         st_stream(a.dst + pidx<27>(i, c), enc_g<S>(gs, i));
+    }
+}
+
+template <class S>
+__global__ __launch_bounds__(kBlock) void k_hydro(const SweepArgs<S> a)
+{
+    const int c = xcd_block() * kBlock + threadIdx.x;
+    if (c >= a.g.ncells) return;
+    int x, y, z;
+    Nbr n;
+    if (!decode(a.g, c, x, y, z, n)) return;
+    hydro_cell<S>(a, c, n, PhiG<typename S::real>{a.phi_in, c, &n});
+}
+
+// ---- z-marching sweeps with the phase field staged in LDS ----------------------
+// A block owns a kTX x kTY tile of (x, y) and walks zc consecutive planes.
+// It keeps the phase field of planes z-1, z, z+1 over the tile plus a
+// one-cell halo in a rotating set of three LDS buffers, so each plane of phi
+// is read from memory once per tile (halo included) instead of once per
+// neighbouring plane.  Wall rows are filled with their mirror (the adjacent
+// fluid row), which is what the stencils read there.
+struct ZTiles {
+    int tx, ty, tz;  // tiles along x, y and z-chunks along z
+    int zc;          // planes per z-chunk
+};
+
+__device__ inline int wrap_i(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
+__device__ inline int mod_i(int v, int n) { return ((v % n) + n) % n; }
+
+template <class R>
+__device__ inline void load_plane(R *dst, const R *__restrict__ phi, const Grid &g, int x0, int y0, int z)
+{
+    const int zz = wrap_i(z, g.nz);
+    for (int i = threadIdx.x; i < kLX * kLY; i += kBlock) {
+        const int hx = i % kLX, hy = i / kLX;
+        const int gx = mod_i(x0 - 1 + hx, g.nx);
+        int gy = y0 - 1 + hy;
+        if (g.walls) {
+            gy = gy < 1 ? 1 : (gy > g.ny - 2 ? g.ny - 2 : gy);
+        } else {
+            gy = mod_i(gy, g.ny);
+        }
+        dst[i] = phi[gx + (int64_t)g.nx * (gy + (int64_t)g.ny * zz)];
+    }
+}
+
+__device__ inline bool zm_cell(const Grid &g, const ZTiles &zt, int &x0, int &y0, int &z0, int &z1, int &x, int &y)
+{
+    int b = xcd_block();
+    const int bx = b % zt.tx;
+    b /= zt.tx;
+    const int by = b % zt.ty;
+    const int bz = b / zt.ty;
+    x0 = bx * kTX;
+    y0 = by * kTY;
+    z0 = bz * zt.zc;
+    z1 = z0 + zt.zc < g.nz ? z0 + zt.zc : g.nz;
+    x = x0 + (int)(threadIdx.x % kTX);
+    y = y0 + (int)(threadIdx.x / kTX);
+    return x < g.nx && y < g.ny && !(g.walls && (y == 0 || y == g.ny - 1));
+}
+
+__device__ inline Nbr zm_nbr(const Grid &g, int x, int y, int z)
+{
+    Nbr n;
+    const int nxy = g.nx * g.ny;
+    n.xm = (x == 0) ? g.nx - 1 : -1;
+    n.xp = (x == g.nx - 1) ? -(g.nx - 1) : 1;
+    if (g.walls) {
+        n.ym = -g.nx;
+        n.yp = g.nx;
+        n.wm = (y == 1);
+        n.wp = (y == g.ny - 2);
+    } else {
+        n.ym = (y == 0) ? (g.ny - 1) * g.nx : -g.nx;
+        n.yp = (y == g.ny - 1) ? -(g.ny - 1) * g.nx : g.nx;
+        n.wm = n.wp = false;
+    }
+    n.zm = (z == 0) ? (g.nz - 1) * nxy : -nxy;
+    n.zp = (z == g.nz - 1) ? -(g.nz - 1) * nxy : nxy;
+    return n;
+}
+
+// PHASE: the phase sweep (stencil on phi_in, the previous field), else the
+// hydrodynamic sweep (stencil on phi_in, the new field).
+template <class S, bool PHASE>
+__global__ __launch_bounds__(kBlock) void k_sweep_zm(const SweepArgs<S> a, const ZTiles zt)
+{
+    using R = typename S::real;
+    __shared__ R buf[3][kLX * kLY];
+    int x0, y0, z0, z1, x, y;
+    const bool active = zm_cell(a.g, zt, x0, y0, z0, z1, x, y);
+    const int o = (int)(threadIdx.x / kTX + 1) * kLX + (int)(threadIdx.x % kTX) + 1;
+    load_plane(buf[0], a.phi_in, a.g, x0, y0, z0 - 1);
+    load_plane(buf[1], a.phi_in, a.g, x0, y0, z0);
+    int sm = 0, sc = 1, sp = 2;
+    for (int z = z0; z < z1; ++z) {
+        load_plane(buf[sp], a.phi_in, a.g, x0, y0, z + 1);
+        __syncthreads();
+        if (active) {
+            const int c = x + a.g.nx * (y + a.g.ny * z);
+            const Nbr n = zm_nbr(a.g, x, y, z);
+            const PhiL<R> pl{{buf[sm], buf[sc], buf[sp]}, o};
+            if constexpr (PHASE) phase_cell<S>(a, c, n, pl);
+            else hydro_cell<S>(a, c, n, pl);
+        }
+        __syncthreads();
+        const int t = sm;
+        sm = sc;
+        sc = sp;
+        sp = t;
     }
 }
 
@@ -585,23 +724,45 @@ __global__ __launch_bounds__(kBlock) void k_get_macro(const typename S::pdf_t *_
 
 // ---- deterministic FP64 reductions --------------------------------------------
 // Pass 1: a fixed grid of kRedBlocks blocks; thread t of block b visits
-// cells b*kBlock + t + k*kRedBlocks*kBlock in order; the block combines its
-// threads with a fixed tree.  Pass 2: one block combines the block partials
-// with a fixed tree.  Same result for every run on any device.
-__device__ inline void block_reduce(double v[kRedVals], double *sh /* kRedVals*kBlock */)
+// cells b*kBlock + t + k*kRedBlocks*kBlock in order.  Each wavefront combines
+// its 64 lanes with a butterfly of cross-lane exchanges (every lane ends with
+// the same value), the wavefronts' results are combined in wave order, and
+// the block writes its partials.  Pass 2: one block combines the block
+// partials the same way.  Same result for every run on any device.
+constexpr int kWaves = kBlock / 64;
+
+__device__ inline double wave_sum(double v)
 {
-    const int t = threadIdx.x;
-    for (int k = 0; k < kRedVals; ++k) sh[k * kBlock + t] = v[k];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ inline double wave_max(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// Leaves the block's totals in sh[0 .. kRedVals-1] (sh holds kRedVals*kWaves).
+__device__ inline void block_reduce(double v[kRedVals], double *sh)
+{
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < kRedVals; ++k) v[k] = (k == kRedVals - 1) ? wave_max(v[k]) : wave_sum(v[k]);
+    if (lane == 0)
+        for (int k = 0; k < kRedVals; ++k) sh[k * kWaves + w] = v[k];
     __syncthreads();
-    for (int s = kBlock / 2; s > 0; s >>= 1) {
-        if (t < s)
-            for (int k = 0; k < kRedVals; ++k) {
-                const double o = sh[k * kBlock + t + s];
-                double &m = sh[k * kBlock + t];
-                m = (k == kRedVals - 1) ? fmax(m, o) : m + o;
-            }
-        __syncthreads();
+    double r = 0.0;
+    if (threadIdx.x < kRedVals) {
+        const int k = threadIdx.x;
+        r = sh[k * kWaves];
+        for (int i = 1; i < kWaves; ++i) r = (k == kRedVals - 1) ? fmax(r, sh[k * kWaves + i]) : r + sh[k * kWaves + i];
     }
+    __syncthreads();
+    if (threadIdx.x < kRedVals) sh[threadIdx.x] = r;
+    __syncthreads();
 }
 
 template <class S>
@@ -611,7 +772,7 @@ __global__ __launch_bounds__(kBlock) void k_reduce1(const typename S::real *__re
                                                     double *__restrict__ partial)
 {
     using R = typename S::real;
-    __shared__ double sh[kRedVals * kBlock];
+    __shared__ double sh[kRedVals * kWaves];
     double v[kRedVals];
     for (int k = 0; k < kRedVals; ++k) v[k] = 0.0;
     const double phiH = (double)ph.phi_H, phiL = (double)ph.phi_L, idp = (double)ph.inv_dphi;
@@ -627,7 +788,7 @@ __global__ __launch_bounds__(kBlock) void k_reduce1(const typename S::real *__re
         const double ux = u[c], uy = u[g.fplane + c], uz = u[2 * g.fplane + c];
         const double chi = (phiH - phi) * idp;
         R grad[3], lapu;
-        stencil<27, R, false>(phiA, c, n, grad, lapu);
+        stencil<27, R, false>(PhiG<R>{phiA, c, &n}, grad, lapu);
         const double gn = sqrt((double)grad[0] * grad[0] + (double)grad[1] * grad[1] + (double)grad[2] * grad[2]);
         v[1] += rho * ux;
         v[2] += rho * uy;
@@ -642,13 +803,13 @@ __global__ __launch_bounds__(kBlock) void k_reduce1(const typename S::real *__re
         v[11] = fmax(v[11], sqrt(ux * ux + uy * uy + uz * uz));
     }
     block_reduce(v, sh);
-    if (threadIdx.x < kRedVals) partial[blockIdx.x * kRedVals + threadIdx.x] = sh[threadIdx.x * kBlock];
+    if (threadIdx.x < kRedVals) partial[blockIdx.x * kRedVals + threadIdx.x] = sh[threadIdx.x];
 }
 
 __global__ __launch_bounds__(kBlock) void k_reduce2(const double *__restrict__ partial,
                                                     double *__restrict__ out)
 {
-    __shared__ double sh[kRedVals * kBlock];
+    __shared__ double sh[kRedVals * kWaves];
     double v[kRedVals];
     for (int k = 0; k < kRedVals; ++k) v[k] = 0.0;
     for (int b = threadIdx.x; b < kRedBlocks; b += kBlock)
@@ -657,7 +818,7 @@ __global__ __launch_bounds__(kBlock) void k_reduce2(const double *__restrict__ p
             v[k] = (k == kRedVals - 1) ? fmax(v[k], o) : v[k] + o;
         }
     block_reduce(v, sh);
-    if (threadIdx.x < kRedVals) out[threadIdx.x] = sh[threadIdx.x * kBlock];
+    if (threadIdx.x < kRedVals) out[threadIdx.x] = sh[threadIdx.x];
 }
 
 // ---- fill with zeros (16-byte vectors); used instead of a runtime memset so

@@ -610,7 +610,10 @@ __global__ void k_projective(const float *__restrict__ s, const float *__restric
 }
 
 // Network input of a state and its recent change: channels 0-4 = s /
-// scale_in, channels 5-9 = (s - s_prev) * trend_scale, zeros up to c_in.
+// scale_in, channels 5-9 = (s - s_prev) * trend_scale, each clipped to
+// [-kInClip, kInClip] (the light phase's acoustic noise gives rare, very
+// large trends), zeros up to c_in.
+constexpr float kInClip = 16.f;
 __global__ void k_pair_to_input(const float *__restrict__ s, const float *__restrict__ sp, int64_t V, float q0,
                                 float q1, float q2, float q3, float q4, float t0, float t1, float t2, float t3,
                                 float t4, int c_in, bf16 *__restrict__ x)
@@ -622,7 +625,7 @@ __global__ void k_pair_to_input(const float *__restrict__ s, const float *__rest
         float val = 0.f;
         if (k < 5) val = s[v * 5 + k] / sc[k];
         else if (k < 10) val = (s[v * 5 + k - 5] - sp[v * 5 + k - 5]) * tr[k - 5];
-        x[v * c_in + k] = (bf16)val;
+        x[v * c_in + k] = (bf16)fminf(fmaxf(val, -kInClip), kInClip);
     }
 }
 

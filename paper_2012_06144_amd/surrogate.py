@@ -80,6 +80,7 @@ class Net:
             self.p[name] = d
         self.scale_in = [1.0, 1e-2, 1e-2, 1e-2, 1e-4]
         self.scale_out = [1e-2, 1e-3, 1e-3, 1e-3, 1e-5]
+        self.scale_trend = [1e-3, 1e-5, 1e-5, 1e-5, 1e-7]
         self.step_count = 0
         self._ws = None
 
@@ -366,19 +367,19 @@ def _moments(a, rows, scratch, out):
     return mean, var, rms
 
 
-def _projective_crop(net_or_none, Sm_i, S0_i, ratio, out):
-    """Baseline of one crop: projective step s + ratio (s - s_prev) (channels
-    last; phi clipped to [0, 1]; velocity increments weighted by the heavy
-    fraction; pressure carried over)."""
-    V = S0_i.numel() // NCH
-    sg.sg_projective_step(S0_i, Sm_i, V, 1, NCH, ratio, 0.0, 1.0, 1, 0, out)
+def _base_crop(S0_i, box, K, out):
+    """Baseline of one crop: phi transported by the local velocity over K
+    steps (semi-Lagrangian), u and p carried over."""
+    bx, by, bz = box
+    sg.sg_advect_phase(S0_i, 1, bx, by, bz, K, out)
 
 
 def channel_scales(Sm, S0, S1, box, K, m):
-    """Per-channel input scale (root mean square of the state; 1 for phi)
-    and output scale (standard deviation of the target S1 - baseline, the
-    baseline being the projective step from (S(t - m), S(t))), over all
-    samples.  FP64 moments from sg_channel_moments."""
+    """Per-channel input scale (root mean square of the state; 1 for phi),
+    output scale (standard deviation of the target S1 - baseline, the
+    baseline being phi transported by the local velocity over K steps with
+    u and p carried over) and trend scale (root mean square of S(t) -
+    S(t - m)), over all samples.  FP64 moments from sg_channel_moments."""
     import torch
     bx, by, bz = box
     V = bx * by * bz
@@ -388,29 +389,35 @@ def channel_scales(Sm, S0, S1, box, K, m):
     _, _, rms = _moments(S0, n * V, scratch, out)
     sin = [1.0] + [max(r, 1e-12) for r in rms[1:]]
     acc = np.zeros(16)
+    tacc = np.zeros(16)
     base = torch.empty((V * NCH,), device=S0.device, dtype=torch.float32)
     diff = torch.empty((V * NCH,), device=S0.device, dtype=torch.float32)
     for i in range(n):
-        _projective_crop(None, Sm[i], S0[i], K / m, base)
+        _base_crop(S0[i], box, K, base)
         sg.sg_make_target(base, S1[i], [1.0] * NCH, NCH, diff)
         sg.sg_channel_moments(diff, V, NCH, out, scratch)
         acc += out.cpu().numpy()
+        sg.sg_make_target(Sm[i], S0[i], [1.0] * NCH, NCH, diff)
+        sg.sg_channel_moments(diff, V, NCH, out, scratch)
+        tacc += out.cpu().numpy()
     rows = n * V
     var = [max(acc[8 + c] / rows - (acc[c] / rows) ** 2, 0.0) for c in range(NCH)]
     sout = [max(math.sqrt(v), 1e-12) for v in var]
-    return [float(v) for v in sin], [float(v) for v in sout]
+    strend = [max(math.sqrt(tacc[8 + c] / rows), 1e-12) for c in range(NCH)]
+    return [float(v) for v in sin], [float(v) for v in sout], [float(v) for v in strend]
 
 
 def trend_scale(net, K, m):
-    """Input scale of the trend channels: the projected increment (K/m)(s -
-    s_prev) in units of the output scale."""
-    return [(K / m) / q for q in net.scale_out]
+    """Input factor of the trend channels: (s - s_prev) over its root mean
+    square in the training data."""
+    return [1.0 / q for q in net.scale_trend]
 
 
 def make_batch(net, Sm, S0, S1, idx, box, K, m, target_from="baseline"):
-    """Network input (BF16: state and trend) and target (FP32) of the samples
-    `idx`.  The target is (S1 - base) / scale_out with base the projective
-    step, or base = S0 (persistence) with target_from="state"."""
+    """Network input (BF16: state and its trend (K/m)(S0 - Sm)) and target
+    (FP32) of the samples `idx`.  The target is (S1 - base) / scale_out with
+    base the transport baseline, or base = S0 (persistence) with
+    target_from="state"."""
     import torch
     bx, by, bz = box
     V = bx * by * bz
@@ -422,20 +429,20 @@ def make_batch(net, Sm, S0, S1, idx, box, K, m, target_from="baseline"):
     for j, i in enumerate(idx):
         sg.sg_pair_to_input(S0[i], Sm[i], net.scale_in, ts, C_IN, x[j])
         if target_from == "baseline":
-            _projective_crop(net, Sm[i], S0[i], K / m, base)
+            _base_crop(S0[i], box, K, base)
             sg.sg_make_target(base, S1[i], net.scale_out, C_OUT, t[j])
         else:
             sg.sg_make_target(S0[i], S1[i], net.scale_out, C_OUT, t[j])
     return x, t
 
 
-def train(net, Sm, S0, S1, box, K, m, run_of=None, steps=500, batch=8, lr=5e-4, warmup=20, val_frac=0.1,
+def train(net, Sm, S0, S1, box, K, m, run_of=None, steps=500, batch=8, lr=2e-4, warmup=50, val_frac=0.1,
           seed=0, log=print):
-    """Adam on the MSE of the normalised residual of the projective step,
+    """Adam on the MSE of the normalised residual of the transport baseline,
     linear warm-up over `warmup` steps, then cosine learning-rate decay.
     Validation samples are whole runs held out (samples of one run are
     correlated).  Returns the loss history and the validation losses of the
-    network, of the projective step alone and of persistence."""
+    network, of the transport baseline alone and of persistence."""
     import torch
     n = S0.shape[0]
     rng = np.random.default_rng(seed)
@@ -463,6 +470,10 @@ def train(net, Sm, S0, S1, box, K, m, run_of=None, steps=500, batch=8, lr=5e-4, 
             lv = float(loss.item())
             hist.append((it, lv))
             log(f"[train] step {it} loss {lv:.4e} ({time.perf_counter() - t0:.1f}s)")
+            best = min(v for _, v in hist)
+            if not math.isfinite(lv) or lv > 20.0 * best:
+                lr *= 0.5                       # divergence guard: halve the rate from here on
+                log(f"[train] loss rose to {lv:.3e} (best {best:.3e}): learning rate halved to {lr:.2e}")
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     v = evaluate(net, Sm, S0, S1, val, box, K, m)
@@ -473,8 +484,8 @@ def train(net, Sm, S0, S1, box, K, m, run_of=None, steps=500, batch=8, lr=5e-4, 
 
 def evaluate(net, Sm, S0, S1, idx, box, K, m, batch=8):
     """Mean validation MSE (normalised units) of the jump with the network
-    (projective step + network residual), of the projective step alone
-    (network output 0) and of persistence (state left unchanged)."""
+    (transport baseline + network residual), of the baseline alone (network
+    output 0) and of persistence (state left unchanged)."""
     import torch
     loss = torch.zeros(1, device=S0.device, dtype=torch.float32)
     scratch = torch.zeros(1024, device=S0.device, dtype=torch.float32)
@@ -526,50 +537,44 @@ def _traj_entry(step, st, **kw):
 def _jump(net, mode, F_now, F_prev, setup, box, jc: JumpConfig, diagnostics=False):
     """Writes the state K steps ahead into F_now ((5, nz, ny, nx) FP32 planes:
     phi, u, p) from F_now and F_prev (m steps earlier).  mode "persistence":
-    unchanged; "transport": phi moved by the local velocity; "projective":
-    projective step; "network": projective step plus the network's residual
-    in the window around the bubble."""
+    unchanged; "transport": phi moved by the local velocity in the window
+    around the bubble; "projective": projective step over the whole grid;
+    "network": transport plus the network's residual (from the state and
+    its trend) in the window."""
     import torch
     nx, ny, nz = setup.nx, setup.ny, setup.nz
     N = nx * ny * nz
+    lo, hi = min(setup.phi_L, setup.phi_H), max(setup.phi_L, setup.phi_H)
     if mode == "persistence":
         return None
-    if mode == "transport":
-        bx, by, bz = box[3], box[4], box[5]
-        V = bx * by * bz
-        st = torch.empty(V * NCH, device=F_now.device, dtype=torch.float32)
-        base = torch.empty_like(st)
-        x = torch.empty(V * C_IN, device=F_now.device, dtype=torch.bfloat16)
-        sg.sg_fields_to_input(F_now[0], F_now[1:4], F_now[4], nx, ny, nz, box, [1.0] * NCH, C_IN, x, st)
-        sg.sg_advect_phase(st, 1, bx, by, bz, jc.K, base)
-        zero = torch.zeros((V, C_OUT), device=F_now.device, dtype=torch.float32)
-        sg.sg_apply_prediction(zero, C_OUT, [0.0] * NCH, F_now[0], F_now[1:4], F_now[4], nx, ny, nz, box,
-                               int(setup.walls_y), setup.phi_L, setup.phi_H, base=base)
+    if mode == "projective":
+        sg.sg_projective_step(F_now, F_prev, N, N, 1, jc.K / jc.m, lo, hi, int(jc.u_by_phase), 0, F_now)
         return None
+    bx, by, bz = box[3], box[4], box[5]
+    V = bx * by * bz
+    one = [1.0] * NCH
+    s0 = torch.empty(V * NCH, device=F_now.device, dtype=torch.float32)
+    base = torch.empty_like(s0)
+    x = torch.empty((1, bz, by, bx, C_IN), device=F_now.device, dtype=torch.bfloat16)
+    sg.sg_fields_to_input(F_now[0], F_now[1:4], F_now[4], nx, ny, nz, box, one, C_IN, x, s0)
+    sg.sg_advect_phase(s0, 1, bx, by, bz, jc.K, base)
     inc = None
-    out = None
     if mode == "network":
-        bx, by, bz = box[3], box[4], box[5]
-        V = bx * by * bz
-        s0 = torch.empty(V * NCH, device=F_now.device, dtype=torch.float32)
         sm = torch.empty_like(s0)
-        x = torch.empty((1, bz, by, bx, C_IN), device=F_now.device, dtype=torch.bfloat16)
-        one = [1.0] * NCH
-        sg.sg_fields_to_input(F_now[0], F_now[1:4], F_now[4], nx, ny, nz, box, one, C_IN, x, s0)
         sg.sg_fields_to_input(F_prev[0], F_prev[1:4], F_prev[4], nx, ny, nz, box, one, C_IN, x, sm)
         sg.sg_pair_to_input(s0, sm, net.scale_in, trend_scale(net, jc.K, jc.m), C_IN, x)
         out = net.forward(x, keep=False)
-    lo, hi = min(setup.phi_L, setup.phi_H), max(setup.phi_L, setup.phi_H)
-    sg.sg_projective_step(F_now, F_prev, N, N, 1, jc.K / jc.m, lo, hi, int(jc.u_by_phase), 0, F_now)
-    if out is not None:
         so = list(net.scale_out)
         if not jc.predict_pressure:
             so[4] = 0.0
-        sg.sg_apply_prediction(out, C_OUT, so, F_now[0], F_now[1:4], F_now[4], nx, ny, nz, box,
-                               int(setup.walls_y), lo, hi, u_by_phase=jc.u_by_phase)
-        if diagnostics:
-            mx = out.view(-1, C_OUT)[:, :NCH].abs().amax(0).tolist()
-            inc = [float(a * b) for a, b in zip(mx, so)]
+    else:
+        out = torch.zeros((V, C_OUT), device=F_now.device, dtype=torch.float32)
+        so = [0.0] * NCH
+    sg.sg_apply_prediction(out, C_OUT, so, F_now[0], F_now[1:4], F_now[4], nx, ny, nz, box,
+                           int(setup.walls_y), lo, hi, base=base, u_by_phase=jc.u_by_phase)
+    if diagnostics and mode == "network":
+        mx = out.view(-1, C_OUT)[:, :NCH].abs().amax(0).tolist()
+        inc = [float(a * b) for a, b in zip(mx, so)]
     return inc
 
 
@@ -618,7 +623,8 @@ def run_with_jumps(net, solver, setup, total_steps, jc: JumpConfig, log=print, m
             F_prev, F_keep = F_keep, F_prev
             solver.step(jc.relax)
         else:
-            solver.step(jc.relax - jc.m)
+            if jc.relax > jc.m:
+                solver.step(jc.relax - jc.m)
             solver.macroscopic(out=F_prev)
             solver.step(jc.m)
         try:
@@ -714,7 +720,7 @@ def save_weights(net, path):
         t[k + ".w"] = d["w"].detach().cpu().contiguous()
         t[k + ".b"] = d["b"].detach().cpu().contiguous()
     meta = {"scale_in": json.dumps(net.scale_in), "scale_out": json.dumps(net.scale_out),
-            "steps": str(net.step_count)}
+            "scale_trend": json.dumps(net.scale_trend), "steps": str(net.step_count)}
     save_file(t, path, metadata=meta)
 
 
@@ -728,6 +734,7 @@ def load_weights(net, path):
             sg.sg_to_bf16(d["w"], d["wt"])
     net.scale_in = json.loads(meta["scale_in"])
     net.scale_out = json.loads(meta["scale_out"])
+    net.scale_trend = json.loads(meta["scale_trend"])
     net.step_count = int(meta["steps"])
 
 
@@ -739,12 +746,13 @@ def _cmd_train(a):
     torch.cuda.synchronize()
     t_data = time.perf_counter() - t0
     net = Net(seed=a.seed)
-    net.scale_in, net.scale_out = channel_scales(Sm, S0, S1, cfg.box, cfg.K, cfg.m)
+    net.scale_in, net.scale_out, net.scale_trend = channel_scales(Sm, S0, S1, cfg.box, cfg.K, cfg.m)
     res = train(net, Sm, S0, S1, cfg.box, cfg.K, cfg.m, run_of=run_of, steps=a.train_steps, batch=a.batch,
                 lr=a.lr, log=_log)
     res.update({"data_seconds": t_data, "samples": int(S0.shape[0]), "runs": meta, "config": cfg.__dict__,
-                "scale_in": net.scale_in, "scale_out": net.scale_out, "params": net.n_params()})
-    _log(f"[train] val loss {res['val_loss']:.4e}; projective step alone {res['val_loss_baseline']:.4e}; "
+                "scale_in": net.scale_in, "scale_out": net.scale_out, "scale_trend": net.scale_trend,
+                "params": net.n_params()})
+    _log(f"[train] val loss {res['val_loss']:.4e}; transport baseline alone {res['val_loss_baseline']:.4e}; "
          f"persistence {res['val_loss_persistence']:.4e}")
     if a.weights:
         save_weights(net, a.weights)
@@ -807,7 +815,7 @@ def main():
     t.add_argument("--pairs-per-run", type=int, default=10)
     t.add_argument("--train-steps", type=int, default=2000)
     t.add_argument("--batch", type=int, default=8)
-    t.add_argument("--lr", type=float, default=5e-4)
+    t.add_argument("--lr", type=float, default=2e-4)
     t.add_argument("--seed", type=int, default=0)
     t.add_argument("--weights", default=None)
     t.add_argument("--out", default=None)
