@@ -524,7 +524,7 @@ __global__ void k_make_target(const float *__restrict__ s0, const float *__restr
 __global__ void k_apply_prediction(const float *__restrict__ out, int c_out, float q0, float q1, float q2,
                                    float q3, float q4, const float *__restrict__ base, float *__restrict__ phi,
                                    float *__restrict__ u, float *__restrict__ p, int nx, int ny, int nz, Box b,
-                                   int walls, float pmin, float pmax, int u_by_phase)
+                                   int walls, float pmin, float pmax, int flags)
 {
     const int64_t V = (int64_t)b.bx * b.by * b.bz;
     const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -539,11 +539,14 @@ __global__ void k_apply_prediction(const float *__restrict__ out, int c_out, flo
     const float f2 = base ? base[v * 5 + 2] : u[N + c];
     const float f3 = base ? base[v * 5 + 3] : u[2 * N + c];
     const float f4 = base ? base[v * 5 + 4] : p[c];
-    // velocity increments weighted by the heavy-phase fraction of the base
-    // phi when u_by_phase (the light phase carries no momentum to speak of)
-    float wu = 1.f;
-    if (u_by_phase) wu = fminf(fmaxf((f0 - pmin) / (pmax - pmin), 0.f), 1.f);
-    phi[c] = fminf(fmaxf(f0 + o[0] * q0, pmin), pmax);
+    // flags & 1: velocity increments weighted by the heavy-phase fraction q
+    // of the base phi (the light phase carries no momentum to speak of);
+    // flags & 2: phi increments weighted by 4 q (1 - q), which vanishes in
+    // both bulk phases (phi only moves at interfaces)
+    const float q = fminf(fmaxf((f0 - pmin) / (pmax - pmin), 0.f), 1.f);
+    const float wu = (flags & 1) ? q : 1.f;
+    const float wp = (flags & 2) ? 4.f * q * (1.f - q) : 1.f;
+    phi[c] = fminf(fmaxf(f0 + wp * (o[0] * q0), pmin), pmax);
     u[c] = f1 + wu * (o[1] * q1);
     u[N + c] = f2 + wu * (o[2] * q2);
     u[2 * N + c] = f3 + wu * (o[3] * q3);
@@ -962,7 +965,7 @@ sg_status sg_make_target(const float *s0, const float *s1, int64_t V, const floa
 
 sg_status sg_apply_prediction(const float *out, int32_t c_out, const float *so, const float *base, float *phi,
                               float *u, float *p, int32_t nx, int32_t ny, int32_t nz, const int32_t *box,
-                              int32_t walls_y, float pmin, float pmax, int32_t u_by_phase, void *stream)
+                              int32_t walls_y, float pmin, float pmax, int32_t flags, void *stream)
 {
     if (!out || !so || !phi || !u || !p || c_out < 5) return fail(SG_EARG, "bad arguments");
     if (!(pmax > pmin)) return fail(SG_EARG, "phi_max must exceed phi_min");
@@ -972,7 +975,7 @@ sg_status sg_apply_prediction(const float *out, int32_t c_out, const float *so, 
     const int64_t V = (int64_t)b.bx * b.by * b.bz;
     hipLaunchKernelGGL(k_apply_prediction, dim3(blocks_for(V)), dim3(kThreads), 0, (hipStream_t)stream, out, c_out,
                        so[0], so[1], so[2], so[3], so[4], base, phi, u, p, nx, ny, nz, b, walls_y, pmin, pmax,
-                       u_by_phase);
+                       flags);
     SG_LAUNCH_CHECK();
     return SG_OK;
 }

@@ -525,6 +525,7 @@ class JumpConfig:
     box: tuple = (112, 128, 112)  # network window around the bubble (bx, by, bz), divisible by 8
     predict_pressure: bool = False  # apply the network's pressure residual (else p follows the baseline)
     u_by_phase: bool = True     # weight velocity increments by the heavy-phase fraction
+    phi_at_interface: bool = True  # weight phi increments by 4 q (1 - q): none in the bulk phases
 
 
 def _traj_entry(step, st, **kw):
@@ -571,7 +572,8 @@ def _jump(net, mode, F_now, F_prev, setup, box, jc: JumpConfig, diagnostics=Fals
         out = torch.zeros((V, C_OUT), device=F_now.device, dtype=torch.float32)
         so = [0.0] * NCH
     sg.sg_apply_prediction(out, C_OUT, so, F_now[0], F_now[1:4], F_now[4], nx, ny, nz, box,
-                           int(setup.walls_y), lo, hi, base=base, u_by_phase=jc.u_by_phase)
+                           int(setup.walls_y), lo, hi, base=base, u_by_phase=jc.u_by_phase,
+                           phi_at_interface=jc.phi_at_interface)
     if diagnostics and mode == "network":
         mx = out.view(-1, C_OUT)[:, :NCH].abs().amax(0).tolist()
         inc = [float(a * b) for a, b in zip(mx, so)]
@@ -599,6 +601,7 @@ def run_with_jumps(net, solver, setup, total_steps, jc: JumpConfig, log=print, m
     t_jump = 0.0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    t_log = t0
     across = jc.m == cyc               # trend between consecutive cycle ends
     assert across or 0 < jc.m <= jc.relax
     solver.macroscopic(out=F_prev)
@@ -653,6 +656,10 @@ def run_with_jumps(net, solver, setup, total_steps, jc: JumpConfig, log=print, m
         solver.macroscopic(out=F_now)
         done += cyc
         traj.append(_traj_entry(done, st, jump=bool(ok), drift=drift))
+        if time.perf_counter() - t_log > 30.0:
+            t_log = time.perf_counter()
+            log(f"[jump] {mode} step {done}: centroid y {st['centroid'][1]:.3f}, {accepted} accepted, "
+                f"{rejected} rejected")
     if done < total_steps:
         solver.step(total_steps - done)
         done = total_steps
@@ -676,11 +683,15 @@ def run_plain(solver, total_steps, every, first=None, log=print):
         solver.step(first)
         done = first
         traj.append(_traj_entry(done, solver.stats()))
+    last_log = time.perf_counter()
     while done < total_steps:
         n = min(every, total_steps - done)
         solver.step(n)
         done += n
         traj.append(_traj_entry(done, solver.stats()))
+        if time.perf_counter() - last_log > 30.0:
+            last_log = time.perf_counter()
+            log(f"[plain] step {done}: centroid y {traj[-1]['centroid_y']:.3f}")
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     log(f"[plain] {total_steps} steps, {wall:.1f}s")
@@ -775,11 +786,15 @@ def _cmd_jump(a):
     if a.box:
         jc.box = tuple(int(v) for v in a.box.split("x"))
     out = {"workload": s.name, "steps": a.steps, "jump": jc.__dict__, "runs": {}}
-    sv = lbm.Solver(s.physics(), storage="f32")
-    sv.init_fields(phi, u, ps)
-    out["runs"]["plain"] = run_plain(sv, a.steps, jc.K + jc.relax, first=jc.m, log=_log)
-    del sv
-    torch.cuda.empty_cache()
+    if a.plain_from:
+        out["runs"]["plain"] = json.load(open(a.plain_from))["runs"]["plain"]
+        _log(f"[plain] reference trajectory from {a.plain_from}")
+    else:
+        sv = lbm.Solver(s.physics(), storage="f32")
+        sv.init_fields(phi, u, ps)
+        out["runs"]["plain"] = run_plain(sv, a.steps, jc.K + jc.relax, first=jc.m, log=_log)
+        del sv
+        torch.cuda.empty_cache()
     modes = a.modes.split(",")
     variants = [(mname, None, mname) for mname in ("persistence", "transport", "projective") if mname in modes]
     if a.weights and "network" in modes:
@@ -787,6 +802,7 @@ def _cmd_jump(a):
         load_weights(net, a.weights)
         variants.append(("surrogate", net, "network"))
     jc.predict_pressure = bool(a.predict_pressure)
+    jc.phi_at_interface = not a.no_phi_at_interface
     for name, net, mode in variants:
         sv = lbm.Solver(s.physics(), storage="f32")
         sv.init_fields(phi, u, ps)
@@ -831,6 +847,8 @@ def main():
     j.add_argument("--eo", type=float, default=10.0, help="Eotvos number with --grid")
     j.add_argument("--box", default=None, help="prediction window bx x by x bz, e.g. 80x96x80")
     j.add_argument("--predict-pressure", action="store_true")
+    j.add_argument("--plain-from", default=None, help="reuse the plain run of an earlier study (same setup)")
+    j.add_argument("--no-phi-at-interface", action="store_true")
     j.add_argument("--out", default=None)
     a = ap.parse_args()
     res = _cmd_train(a) if a.cmd == "train" else _cmd_jump(a)

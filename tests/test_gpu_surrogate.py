@@ -449,3 +449,26 @@ def test_pair_to_input(env):
     ref = np.clip(np.concatenate([r1, r2, np.zeros((V, 6), np.float32)], 1), -16, 16)
     ref = torch.from_numpy(ref).to(torch.bfloat16).float()
     assert np.array_equal(got, ref.numpy())
+
+
+def test_apply_prediction_phi_increment_at_interface(env):
+    torch, sg = env
+    rng = np.random.default_rng(27)
+    nx, ny, nz = 8, 6, 4
+    N = nx * ny * nz
+    phi = torch.zeros(N, device="cuda")
+    u = torch.zeros(3 * N, device="cuda")
+    p = torch.zeros(N, device="cuda")
+    base = rng.uniform(-0.1, 1.1, (N, 5)).astype(np.float32)
+    base[:10, 0], base[10:20, 0] = 0.0, 1.0                    # bulk light and heavy phase
+    out = (rng.standard_normal((N, 32)) * 0.1).astype(np.float32)
+    so = [1.0, 0.0, 0.0, 0.0, 0.0]
+    sg.sg_apply_prediction(torch.from_numpy(out).cuda(), 32, so, phi, u, p, nx, ny, nz, (0, 0, 0, nx, ny, nz), 0,
+                           0.0, 1.0, base=torch.from_numpy(base).cuda(), phi_at_interface=True)
+    torch.cuda.synchronize()
+    q = np.clip(base[:, 0], 0, 1).astype(np.float32)
+    w = np.float32(4) * q * (np.float32(1) - q)
+    ref = np.clip(base[:, 0] + w * out[:, 0], 0, 1)
+    got = phi.cpu().numpy()
+    assert np.array_equal(got[:20], base[:20, 0])            # bulk phases unchanged
+    assert np.allclose(got, ref, rtol=0, atol=2 * np.finfo(np.float32).eps)
