@@ -133,7 +133,10 @@ size_t lbm_workspace_bytes(const lbm_params *p);
  * Sweep kernels: the environment variable LBM_ZMARCH, read here, selects the
  * z-marching sweeps that stage the phase field of three planes in LDS
  * ("1") or the one-cell-per-thread sweeps ("0"); unset, the library's
- * default.  Both compute the same numbers (same operation order). */
+ * default.  With 16-bit storage and even nz the sweeps process cells z and
+ * z + nz/2 together from shared 32-bit words; LBM_PAIR=0 selects the
+ * one-cell-per-thread sweeps instead.  All variants compute the same
+ * numbers (same operation order). */
 lbm_status lbm_create(const lbm_params *p, void *dev_workspace, size_t bytes, void *hip_stream,
                       lbm_ctx **out);
 

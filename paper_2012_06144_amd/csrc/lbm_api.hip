@@ -56,6 +56,7 @@ size_t real_bytes(int storage) { return storage == LBM_F64 ? 8 : 4; }
 
 struct Layout {
     int64_t ncells, nblk, fplane;
+    int64_t pdf_elems;  // elements per direction of a PDF buffer
     size_t off_H[2], off_G[2], off_phi[2], off_u, off_red, off_out, total;
 };
 
@@ -85,15 +86,22 @@ Layout layout(const lbm_params *p)
     L.ncells = (int64_t)p->nx * p->ny * p->nz;
     L.nblk = (L.ncells + kB - 1) / kB;  // blocked PDF layout, kB cells per block
     L.fplane = (int64_t)align_up((size_t)L.ncells, 512) + kPlanePadElems;
+    if (pdf_bytes(p->storage) == 2) {
+        // paired 16-bit storage: ceil(N/2) words of two cells, in blocks of kB words
+        const int64_t half = (L.ncells + 1) / 2;
+        L.pdf_elems = 2 * ((half + kB - 1) / kB) * kB;
+    } else {
+        L.pdf_elems = L.nblk * kB;
+    }
     const size_t pb = pdf_bytes(p->storage), rb = real_bytes(p->storage);
     size_t off = 0;
     for (int k = 0; k < 2; ++k) {
         L.off_H[k] = off;
-        off = align_up(off + 15 * (size_t)L.nblk * kB * pb, kAlign);
+        off = align_up(off + 15 * (size_t)L.pdf_elems * pb, kAlign);
     }
     for (int k = 0; k < 2; ++k) {
         L.off_G[k] = off;
-        off = align_up(off + 27 * (size_t)L.nblk * kB * pb, kAlign);
+        off = align_up(off + 27 * (size_t)L.pdf_elems * pb, kAlign);
     }
     for (int k = 0; k < 2; ++k) {
         L.off_phi[k] = off;
@@ -121,6 +129,7 @@ Phys<R> make_phys(const lbm_params *p)
     ph.phi_lo = (R)(p->phi_L < p->phi_H ? p->phi_L : p->phi_H);
     ph.phi_hi = (R)(p->phi_L < p->phi_H ? p->phi_H : p->phi_L);
     ph.xi = (R)p->xi;
+    ph.inv_xi = (R)(1.0 / p->xi);
     const double tau_phi = p->mobility / CS2;  // eq. mobility with dt = 1
     ph.omega_phi = (R)(1.0 / (tau_phi + 0.5));
     ph.rho_L = (R)p->rho_L;
@@ -148,6 +157,7 @@ struct lbm_ctx {
     bool initialized;
     int64_t steps;
     bool zmarch;  // sweeps march in z with phi staged in LDS
+    bool pair16;  // 16-bit storage with even nz: one thread per pair of cells
 };
 
 namespace {
@@ -178,8 +188,18 @@ struct Ops {
         return t;
     }
 
+    // paired 16-bit sweeps: one thread per two cells (needs even nz)
+    static bool paired(lbm_ctx *c) { return S::paired && c->pair16 && c->g.nz % 2 == 0; }
+    static int pair_blocks(lbm_ctx *c) { return (c->g.half + kBlock - 1) / kBlock; }
+
     static void launch_phase(lbm_ctx *c, const SweepArgs<S> &sp)
     {
+        if constexpr (S::paired) {
+            if (paired(c)) {
+                hipLaunchKernelGGL((k_sweep_pair<S, true>), dim3(pair_blocks(c)), dim3(kBlock), 0, c->stream, sp);
+                return;
+            }
+        }
         if (c->zmarch) {
             const ZTiles t = ztiles(c);
             hipLaunchKernelGGL((k_sweep_zm<S, true>), dim3(t.tx * t.ty * t.tz), dim3(kBlock), 0, c->stream, sp, t);
@@ -190,6 +210,12 @@ struct Ops {
 
     static void launch_hydro(lbm_ctx *c, const SweepArgs<S> &sh)
     {
+        if constexpr (S::paired) {
+            if (paired(c)) {
+                hipLaunchKernelGGL((k_sweep_pair<S, false>), dim3(pair_blocks(c)), dim3(kBlock), 0, c->stream, sh);
+                return;
+            }
+        }
         if (c->zmarch) {
             const ZTiles t = ztiles(c);
             hipLaunchKernelGGL((k_sweep_zm<S, false>), dim3(t.tx * t.ty * t.tz), dim3(kBlock), 0, c->stream, sh, t);
@@ -441,6 +467,7 @@ lbm_status lbm_create(const lbm_params *p, void *ws, size_t bytes, void *stream,
     c->g.nz = p->nz;
     c->g.walls = p->walls_y ? 1 : 0;
     c->g.ncells = (int)L.ncells;
+    c->g.half = (int)((L.ncells + 1) / 2);
     c->g.fplane = L.fplane;
     c->g.dnx = make_fastdiv((uint32_t)p->nx);
     c->g.dny = make_fastdiv((uint32_t)p->ny);
@@ -449,6 +476,8 @@ lbm_status lbm_create(const lbm_params *p, void *ws, size_t bytes, void *stream,
     c->steps = 0;
     c->zmarch = LBM_ZMARCH != 0;
     if (const char *v = std::getenv("LBM_ZMARCH")) c->zmarch = (v[0] == '1');
+    c->pair16 = true;
+    if (const char *v = std::getenv("LBM_PAIR")) c->pair16 = (v[0] != '0');
     *out = c;
     g_err[0] = 0;
     return LBM_OK;
@@ -579,8 +608,8 @@ lbm_status lbm_stream_copy(const void *src, void *dst, size_t bytes, void *strea
 static void state_parts(const lbm_ctx *c, size_t sz[4], size_t off_dst[5])
 {
     const size_t pb = pdf_bytes(c->p.storage), rb = real_bytes(c->p.storage);
-    sz[0] = 15 * (size_t)c->L.nblk * kB * pb;
-    sz[1] = 27 * (size_t)c->L.nblk * kB * pb;
+    sz[0] = 15 * (size_t)c->L.pdf_elems * pb;
+    sz[1] = 27 * (size_t)c->L.pdf_elems * pb;
     sz[2] = (size_t)c->L.fplane * rb;
     sz[3] = 3 * (size_t)c->L.fplane * rb;
     off_dst[0] = 0;

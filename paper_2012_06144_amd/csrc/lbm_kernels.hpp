@@ -50,7 +50,7 @@ template <class R>
 struct Phys {
     R phi_L, phi_H, phi_0, inv_dphi;     // inv_dphi = 1/(phi_H - phi_L)
     R phi_lo, phi_hi;                    // min and max of phi_L, phi_H
-    R xi, omega_phi;                     // phase-field relaxation rate
+    R xi, inv_xi, omega_phi;             // interface width, its inverse, phase-field relaxation rate
     R rho_L, drho;                       // drho = rho_H - rho_L
     R tau_L, dtau;                       // dtau = tau_H - tau_L
     R beta, kappa;                       // 12 sigma/xi, 3 sigma xi/2
@@ -103,6 +103,7 @@ struct Grid {
     int nx, ny, nz;
     int walls;
     int ncells;
+    int half;        // ceil(ncells / 2): paired 16-bit storage keeps cells c and c + half in one word
     int64_t fplane;  // field plane stride (elements) of u
     FastDiv dnx, dny;
 };
@@ -179,8 +180,14 @@ template <int Q, class R>
 __device__ inline R gamma_i(int i, R ux, R uy, R uz, R uu)
 {
     const R eu = R(ev<Q>(i, 0)) * ux + R(ev<Q>(i, 1)) * uy + R(ev<Q>(i, 2)) * uz;
-    const R c2 = cs2<R>();
-    return wgt<Q, R>(i) * (R(1) + by_cs2(eu) + (eu * eu) / (R(2) * c2 * c2) - uu / (R(2) * c2));
+    if constexpr (std::is_same<R, float>::value) {
+        // 1/(2 cs^4) = 4.5 and 1/(2 cs^2) = 1.5 exactly: multiplications, where
+        // a division by the rounded constants costs ~10 VALU instructions each
+        return wgt<Q, R>(i) * (R(1) + by_cs2(eu) + (eu * eu) * R(4.5) - uu * R(1.5));
+    } else {
+        const R c2 = cs2<R>();
+        return wgt<Q, R>(i) * (R(1) + by_cs2(eu) + (eu * eu) / (R(2) * c2 * c2) - uu / (R(2) * c2));
+    }
 }
 
 // Hydrodynamic equilibrium g_eq_i = p* w_i + (Gamma_i - w_i) (Sec. 3.2), with
@@ -190,8 +197,12 @@ template <class R>
 __device__ inline R geq_i(int i, R ps, R ux, R uy, R uz, R uu)
 {
     const R eu = R(e27(i, 0)) * ux + R(e27(i, 1)) * uy + R(e27(i, 2)) * uz;
-    const R c2 = cs2<R>();
-    return wgt<27, R>(i) * (ps + by_cs2(eu) + (eu * eu) / (R(2) * c2 * c2) - uu / (R(2) * c2));
+    if constexpr (std::is_same<R, float>::value) {
+        return wgt<27, R>(i) * (ps + by_cs2(eu) + (eu * eu) * R(4.5) - uu * R(1.5));
+    } else {
+        const R c2 = cs2<R>();
+        return wgt<27, R>(i) * (ps + by_cs2(eu) + (eu * eu) / (R(2) * c2 * c2) - uu / (R(2) * c2));
+    }
 }
 
 // Previous / new phase field around a cell, as the stencils read it (wall
@@ -265,24 +276,61 @@ struct SweepArgs {
     Phys<typename S::real> ph;
 };
 
+// Element index of population q of cell c in a PDF buffer of storage S.
+// 16-bit storage is paired: cells c and c + half (half = ceil(N/2); for even
+// nz, (x, y, z) and (x, y, z + nz/2)) share the 32-bit word at the blocked
+// index of the lower cell, the lower cell in the low half.
+template <class S, int Q>
+__device__ inline int64_t pdf_index(int q, int c, const Grid &g)
+{
+    if constexpr (S::paired) {
+        const int h = c >= g.half ? 1 : 0;
+        return 2 * pidx<Q>(q, c - h * g.half) + h;
+    } else {
+        return pidx<Q>(q, c);
+    }
+}
+
 // Storage index of the population of direction i arriving at cell c: the
 // post-collision value of the upstream cell c - e_i or, when that cell is a
 // wall, the value of the opposite direction at c itself (halfway
 // bounce-back: what left c towards the wall comes back reversed).
-template <int Q>
-__device__ inline int64_t pull_idx(int i, int c, const Nbr &n)
+template <class S, int Q>
+__device__ inline int64_t pull_idx(int i, int c, const Nbr &n, const Grid &g)
 {
     const int dx = ev<Q>(i, 0), dy = ev<Q>(i, 1), dz = ev<Q>(i, 2);
     const bool bb = (dy > 0 && n.wm) || (dy < 0 && n.wp);
-    return bb ? pidx<Q>(opp(i), c) : pidx<Q>(i, c + n.off(-dx, -dy, -dz));
+    return bb ? pdf_index<S, Q>(opp(i), c, g) : pdf_index<S, Q>(i, c + n.off(-dx, -dy, -dz), g);
 }
+
+// Population I/O of the per-cell sweep bodies.  IOGlobal pulls from and
+// stores to global memory for one cell; IORegs reads and writes register
+// arrays that a paired kernel fills from and drains to 32-bit words.
+template <class S, int Q>
+struct IOGlobal {
+    const typename S::pdf_t *__restrict__ src;
+    typename S::pdf_t *__restrict__ dst;
+    int c;
+    const Nbr *n;
+    const Grid *g;
+    __device__ typename S::pdf_t load(int i) const { return ld_stream(src + pull_idx<S, Q>(i, c, *n, *g)); }
+    __device__ void store(int i, typename S::pdf_t v) const { st_stream(dst + pdf_index<S, Q>(i, c, *g), v); }
+};
+
+template <class S, int Q>
+struct IORegs {
+    const typename S::pdf_t *in;
+    typename S::pdf_t *out;
+    __device__ typename S::pdf_t load(int i) const { return in[i]; }
+    __device__ void store(int i, typename S::pdf_t v) const { out[i] = v; }
+};
 
 // ---- phase-field sweep: pull-stream h, phi = sum h (eq. updatePhaseField),
 // normal and theta from the previous phi (eqs. allen_cahn, grad), forcing
 // (eq. interfaceTracking), equilibrium phi Gamma(u), single-rate collision
 // (eq. lb_interface); store post-collision h at the cell ----------------------
-template <class S, class P>
-__device__ inline void phase_cell(const SweepArgs<S> &a, int c, const Nbr &n, const P &phiA)
+template <class S, class P, class IO>
+__device__ inline void phase_cell(const SweepArgs<S> &a, int c, const Nbr &n, const P &phiA, const IO &io)
 {
     using R = typename S::real;
     // previous phase field at x + e_i (D3Q15 stencil points; wall rows mirrored)
@@ -299,7 +347,7 @@ __device__ inline void phase_cell(const SweepArgs<S> &a, int c, const Nbr &n, co
 #pragma unroll
     for (int i = 0; i < 15; ++i) {
         const bool bb = (e15(i, 1) > 0 && n.wm) || (e15(i, 1) < 0 && n.wp);
-        const typename S::pdf_t v = ld_stream(a.src + pull_idx<15>(i, c, n));
+        const typename S::pdf_t v = io.load(i);
         const R up = bb ? phs[0] : phs[opp(i)];
         if constexpr (std::is_same<R, double>::value) {
             Pi[i] = dec_h<S>(v, up, i);
@@ -329,10 +377,18 @@ __device__ inline void phase_cell(const SweepArgs<S> &a, int c, const Nbr &n, co
     for (int k = 0; k < 3; ++k) grad[k] = by_cs2(acc[k]);
     const R gn = sqrt(grad[0] * grad[0] + grad[1] * grad[1] + grad[2] * grad[2]);
     R nrm[3];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) nrm[k] = grad[k] / (gn + a.ph.normal_eps);
     const R dp = phs[0] - a.ph.phi_0;
-    const R theta = (R(1) - R(4) * dp * dp) / a.ph.xi;
+    R theta;
+    if constexpr (std::is_same<R, float>::value) {
+        const R inv = R(1) / (gn + a.ph.normal_eps);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) nrm[k] = grad[k] * inv;
+        theta = (R(1) - R(4) * dp * dp) * a.ph.inv_xi;
+    } else {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) nrm[k] = grad[k] / (gn + a.ph.normal_eps);
+        theta = (R(1) - R(4) * dp * dp) / a.ph.xi;
+    }
 
     const R ux = a.u[c], uy = a.u[a.g.fplane + c], uz = a.u[2 * a.g.fplane + c];
     const R uu = ux * ux + uy * uy + uz * uz;
@@ -347,7 +403,7 @@ __device__ inline void phase_cell(const SweepArgs<S> &a, int c, const Nbr &n, co
     }
     if constexpr (std::is_same<R, double>::value) {
 #pragma unroll
-        for (int i = 0; i < 15; ++i) st_stream(a.dst + pidx<15>(i, c), enc_h<S>(hs[i], phi, i));
+        for (int i = 0; i < 15; ++i) io.store(i, enc_h<S>(hs[i], phi, i));
     } else {
         // The collision conserves phi exactly; in FP32 the rounded weights do
         // not sum to one and 16-bit storage rounds every population, which
@@ -358,9 +414,9 @@ __device__ inline void phase_cell(const SweepArgs<S> &a, int c, const Nbr &n, co
         for (int i = 1; i < 15; ++i) {
             const typename S::pdf_t v = enc_h<S>(hs[i], phi, i);
             rest -= dec_h64<S>(v, phi, i);
-            st_stream(a.dst + pidx<15>(i, c), v);
+            io.store(i, v);
         }
-        st_stream(a.dst + pidx<15>(0, c), enc_h64<S>(rest, phi, 0));
+        io.store(0, enc_h64<S>(rest, phi, 0));
     }
 }
 
@@ -372,7 +428,7 @@ __global__ __launch_bounds__(kBlock) void k_phase(const SweepArgs<S> a)
     int x, y, z;
     Nbr n;
     if (!decode(a.g, c, x, y, z, n)) return;
-    phase_cell<S>(a, c, n, PhiG<typename S::real>{a.phi_in, c, &n});
+    phase_cell<S>(a, c, n, PhiG<typename S::real>{a.phi_in, c, &n}, IOGlobal<S, 15>{a.src, a.dst, c, &n, &a.g});
 }
 
 // ---- hydrodynamic sweep: pull-stream g, moments, forces from the new phi
@@ -387,15 +443,15 @@ __global__ __launch_bounds__(kBlock) void k_phase(const SweepArgs<S> a)
 //   g*_i = g_eq_i(p*, u) + F_i/2 + (1 - s) w_i/(2 cs^4) (e_i e_i - cs^2 I) : A,
 //   A = Pi - p* cs^2 I - u u^T,  F_i = w_i e_i.F/(rho cs^2),
 // and the bracket of the viscous force is s A(u_old).
-template <class S, class P>
-__device__ inline void hydro_cell(const SweepArgs<S> &a, int c, const Nbr &n, const P &phiB)
+template <class S, class P, class IO>
+__device__ inline void hydro_cell(const SweepArgs<S> &a, int c, const Nbr &n, const P &phiB, const IO &io)
 {
     using R = typename S::real;
     R ps = R(0), j[3] = {R(0), R(0), R(0)};
     R Pxx = R(0), Pyy = R(0), Pzz = R(0), Pxy = R(0), Pxz = R(0), Pyz = R(0);
 #pragma unroll
     for (int i = 0; i < 27; ++i) {
-        const R gi = dec_g<S>(ld_stream(a.src + pull_idx<27>(i, c, n)), i);
+        const R gi = dec_g<S>(io.load(i), i);
         const int ex = e27(i, 0), ey = e27(i, 1), ez = e27(i, 2);
         ps += gi;
         if (ex) j[0] += ex > 0 ? gi : -gi;
@@ -428,7 +484,7 @@ __device__ inline void hydro_cell(const SweepArgs<S> &a, int c, const Nbr &n, co
     // A(u_old) = Pi - p* cs^2 I - u_old u_old^T; viscous bracket = s A
     const R Axx = Pxx - ps * c2 - uox * uox, Ayy = Pyy - ps * c2 - uoy * uoy, Azz = Pzz - ps * c2 - uoz * uoz;
     const R Axy = Pxy - uox * uoy, Axz = Pxz - uox * uoz, Ayz = Pyz - uoy * uoz;
-    const R vf = -nu / c2 * s;
+    const R vf = std::is_same<R, float>::value ? -tau * s : -nu / c2 * s;  // nu / cs^2 = tau
     const R rb = rho - ph.rho_ref;
     R F[3];
     F[0] = -ps * c2 * grho[0] + mu * grad[0] + vf * (Axx * grho[0] + Axy * grho[1] + Axz * grho[2]) +
@@ -438,7 +494,19 @@ __device__ inline void hydro_cell(const SweepArgs<S> &a, int c, const Nbr &n, co
     F[2] = -ps * c2 * grho[2] + mu * grad[2] + vf * (Axz * grho[0] + Ayz * grho[1] + Azz * grho[2]) +
            rb * ph.accel[2];
 
-    const R ux = j[0] + F[0] / (R(2) * rho), uy = j[1] + F[1] / (R(2) * rho), uz = j[2] + F[2] / (R(2) * rho);
+    R ux, uy, uz;
+    R inv_rho = R(0);
+    if constexpr (std::is_same<R, float>::value) {
+        inv_rho = R(1) / rho;
+        const R h = R(0.5) * inv_rho;
+        ux = j[0] + F[0] * h;
+        uy = j[1] + F[1] * h;
+        uz = j[2] + F[2] * h;
+    } else {
+        ux = j[0] + F[0] / (R(2) * rho);
+        uy = j[1] + F[1] / (R(2) * rho);
+        uz = j[2] + F[2] / (R(2) * rho);
+    }
     st_field(a.u + c, ux);
     st_field(a.u + a.g.fplane + c, uy);
     st_field(a.u + 2 * a.g.fplane + c, uz);
@@ -447,8 +515,8 @@ __device__ inline void hydro_cell(const SweepArgs<S> &a, int c, const Nbr &n, co
     const R Bxx = Pxx - ps * c2 - ux * ux, Byy = Pyy - ps * c2 - uy * uy, Bzz = Pzz - ps * c2 - uz * uz;
     const R Bxy = Pxy - ux * uy, Bxz = Pxz - ux * uz, Byz = Pyz - uy * uz;
     const R trB = Bxx + Byy + Bzz;
-    const R neq = (R(1) - s) / (R(2) * c2 * c2);
-    const R finv = R(1) / (rho * c2);
+    const R neq = std::is_same<R, float>::value ? (R(1) - s) * R(4.5) : (R(1) - s) / (R(2) * c2 * c2);
+    const R finv = std::is_same<R, float>::value ? R(3) * inv_rho : R(1) / (rho * c2);
 #pragma unroll
     for (int i = 0; i < 27; ++i) {
         const int ex = e27(i, 0), ey = e27(i, 1), ez = e27(i, 2);
@@ -459,7 +527,7 @@ __device__ inline void hydro_cell(const SweepArgs<S> &a, int c, const Nbr &n, co
         const R eBe = R(ex * ex) * Bxx + R(ey * ey) * Byy + R(ez * ez) * Bzz +
                       R(2 * ex * ey) * Bxy + R(2 * ex * ez) * Bxz + R(2 * ey * ez) * Byz - c2 * trB;
         const R gs = geq + R(0.5) * w * eF * finv + neq * w * eBe;
-        st_stream(a.dst + pidx<27>(i, c), enc_g<S>(gs, i));
+        io.store(i, enc_g<S>(gs, i));
     }
 }
 
@@ -471,7 +539,7 @@ __global__ __launch_bounds__(kBlock) void k_hydro(const SweepArgs<S> a)
     int x, y, z;
     Nbr n;
     if (!decode(a.g, c, x, y, z, n)) return;
-    hydro_cell<S>(a, c, n, PhiG<typename S::real>{a.phi_in, c, &n});
+    hydro_cell<S>(a, c, n, PhiG<typename S::real>{a.phi_in, c, &n}, IOGlobal<S, 27>{a.src, a.dst, c, &n, &a.g});
 }
 
 // ---- z-marching sweeps with the phase field staged in LDS ----------------------
@@ -563,14 +631,90 @@ __global__ __launch_bounds__(kBlock) void k_sweep_zm(const SweepArgs<S> a, const
             const int c = x + a.g.nx * (y + a.g.ny * z);
             const Nbr n = zm_nbr(a.g, x, y, z);
             const PhiL<R> pl{{buf[sm], buf[sc], buf[sp]}, o};
-            if constexpr (PHASE) phase_cell<S>(a, c, n, pl);
-            else hydro_cell<S>(a, c, n, pl);
+            if constexpr (PHASE) phase_cell<S>(a, c, n, pl, IOGlobal<S, 15>{a.src, a.dst, c, &n, &a.g});
+            else hydro_cell<S>(a, c, n, pl, IOGlobal<S, 27>{a.src, a.dst, c, &n, &a.g});
         }
         __syncthreads();
         const int t = sm;
         sm = sc;
         sc = sp;
         sp = t;
+    }
+}
+
+// ---- paired sweeps for 16-bit storage ---------------------------------------
+// One thread per pair of cells (x, y, z) and (x, y, z + nz/2) (nz even): the
+// pair's 15 or 27 populations arrive as 32-bit words from the upstream pair
+// in the half domain, so every load and store is 4 bytes instead of 2.
+// Where the z pull wraps across the half domain (z = 0 pulling from below,
+// z = nz/2 - 1 pulling from above) the upstream word holds the two cells the
+// other way round and its halves are swapped.  Each cell then runs the same
+// per-cell body as the one-cell-per-thread sweeps.
+template <class S, bool PHASE>
+__global__ __launch_bounds__(kBlock) void k_sweep_pair(const SweepArgs<S> a)
+{
+    static_assert(S::paired, "paired sweeps need 16-bit storage");
+    constexpr int Q = PHASE ? 15 : 27;
+    using pdf_t = typename S::pdf_t;
+    using R = typename S::real;
+    const Grid &g = a.g;
+    const int p = xcd_block() * kBlock + threadIdx.x;
+    if (p >= g.half) return;
+    const int t = (int)g.dnx.div((uint32_t)p);
+    const int x = p - t * g.nx;
+    const int z2 = (int)g.dny.div((uint32_t)t);
+    const int y = t - z2 * g.ny;
+    if (g.walls && (y == 0 || y == g.ny - 1)) return;
+    const int nz2 = g.nz / 2, nxy = g.nx * g.ny;
+    const int xm = (x == 0) ? g.nx - 1 : -1, xp = (x == g.nx - 1) ? -(g.nx - 1) : 1;
+    int ym, yp;
+    bool wm = false, wp = false;
+    if (g.walls) {
+        ym = -g.nx;
+        yp = g.nx;
+        wm = (y == 1);
+        wp = (y == g.ny - 2);
+    } else {
+        ym = (y == 0) ? (g.ny - 1) * g.nx : -g.nx;
+        yp = (y == g.ny - 1) ? -(g.ny - 1) * g.nx : g.nx;
+    }
+    const int zm = (z2 == 0) ? (nz2 - 1) * nxy : -nxy, zp = (z2 == nz2 - 1) ? -(nz2 - 1) * nxy : nxy;
+    const uint32_t *__restrict__ W = reinterpret_cast<const uint32_t *>(a.src);
+    uint32_t *__restrict__ Wd = reinterpret_cast<uint32_t *>(a.dst);
+    pdf_t in0[Q], in1[Q], out0[Q], out1[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const int ex = ev<Q>(i, 0), ey = ev<Q>(i, 1), ez = ev<Q>(i, 2);
+        const bool bb = (ey > 0 && wm) || (ey < 0 && wp);
+        int64_t w;
+        bool sw = false;
+        if (bb) {
+            w = pidx<Q>(opp(i), p);
+        } else {
+            const int off = (ex > 0 ? xm : ex < 0 ? xp : 0) + (ey > 0 ? ym : ey < 0 ? yp : 0) +
+                            (ez > 0 ? zm : ez < 0 ? zp : 0);
+            w = pidx<Q>(i, p + off);
+            sw = (z2 == 0 && ez > 0) || (z2 == nz2 - 1 && ez < 0);
+        }
+        uint32_t v = ld_stream(W + w);
+        if (sw) v = (v >> 16) | (v << 16);
+        in0[i] = __builtin_bit_cast(pdf_t, (uint16_t)(v & 0xffffu));
+        in1[i] = __builtin_bit_cast(pdf_t, (uint16_t)(v >> 16));
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int c = p + h * g.half;
+        const Nbr n = zm_nbr(g, x, y, z2 + h * nz2);
+        const PhiG<R> ph{a.phi_in, c, &n};
+        const IORegs<S, Q> io{h ? in1 : in0, h ? out1 : out0};
+        if constexpr (PHASE) phase_cell<S>(a, c, n, ph, io);
+        else hydro_cell<S>(a, c, n, ph, io);
+    }
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const uint32_t v = (uint32_t)__builtin_bit_cast(uint16_t, out0[i]) |
+                           ((uint32_t)__builtin_bit_cast(uint16_t, out1[i]) << 16);
+        st_stream(Wd + pidx<Q>(i, p), v);
     }
 }
 
@@ -605,12 +749,12 @@ __global__ __launch_bounds__(kBlock) void k_equilibrium(typename S::pdf_t *__res
 #pragma unroll
     for (int i = 0; i < 15; ++i) {
         const R h = wall ? R(0) : phi * gamma_i<15, R>(i, ux, uy, uz, uu);
-        H[pidx<15>(i, c)] = enc_h<S>(h, phi, i);
+        H[pdf_index<S, 15>(i, c, g)] = enc_h<S>(h, phi, i);
     }
 #pragma unroll
     for (int i = 0; i < 27; ++i) {
         const R ge = wall ? R(0) : geq_i<R>(i, ps, ux, uy, uz, uu);
-        Gc[pidx<27>(i, c)] = enc_g<S>(ge, i);
+        Gc[pdf_index<S, 27>(i, c, g)] = enc_g<S>(ge, i);
     }
     phiA[c] = phi;
     u[c] = ux;
@@ -635,8 +779,8 @@ __global__ __launch_bounds__(kBlock) void k_unpull27(const typename S::pdf_t *__
     for (int j = 0; j < 27; ++j) {
         const int dx = e27(j, 0), dy = e27(j, 1), dz = e27(j, 2);
         const bool bb = (dy > 0 && n.wp) || (dy < 0 && n.wm);  // y + e_j is a wall row
-        const int64_t from = bb ? pidx<27>(opp(j), c) : pidx<27>(j, c + n.off(dx, dy, dz));
-        G[pidx<27>(j, c)] = Gc[from];
+        const int64_t from = bb ? pdf_index<S, 27>(opp(j), c, g) : pdf_index<S, 27>(j, c + n.off(dx, dy, dz), g);
+        G[pdf_index<S, 27>(j, c, g)] = Gc[from];
     }
 }
 
@@ -658,11 +802,11 @@ __global__ __launch_bounds__(kBlock) void k_get_pdfs(const typename S::pdf_t *__
     if (Ho)
 #pragma unroll
         for (int i = 0; i < 15; ++i)
-            Ho[i * N + c] = fluid ? (double)dec_h<S>(H[pidx<15>(i, c)], phiA[c], i) : 0.0;
+            Ho[i * N + c] = fluid ? (double)dec_h<S>(H[pdf_index<S, 15>(i, c, g)], phiA[c], i) : 0.0;
     if (Go)
 #pragma unroll
         for (int i = 0; i < 27; ++i)
-            Go[i * N + c] = fluid ? (double)dec_g<S>(G[pull_idx<27>(i, c, n)], i) : 0.0;
+            Go[i * N + c] = fluid ? (double)dec_g<S>(G[pull_idx<S, 27>(i, c, n, g)], i) : 0.0;
 }
 
 // Storage from canonical FP64 planes: H stored directly, G (pre-collision)
@@ -686,10 +830,10 @@ __global__ __launch_bounds__(kBlock) void k_set_pdfs(typename S::pdf_t *__restri
     const int64_t N = g.ncells;
 #pragma unroll
     for (int i = 0; i < 15; ++i) {
-        H[pidx<15>(i, c)] = enc_h<S>(wall ? R(0) : R(Hi[i * N + c]), wall ? R(0) : R(phi_i[c]), i);
+        H[pdf_index<S, 15>(i, c, g)] = enc_h<S>(wall ? R(0) : R(Hi[i * N + c]), wall ? R(0) : R(phi_i[c]), i);
     }
 #pragma unroll
-    for (int i = 0; i < 27; ++i) Gc[pidx<27>(i, c)] = enc_g<S>(wall ? R(0) : R(Gi[i * N + c]), i);
+    for (int i = 0; i < 27; ++i) Gc[pdf_index<S, 27>(i, c, g)] = enc_g<S>(wall ? R(0) : R(Gi[i * N + c]), i);
     phiA[c] = wall ? R(0) : R(phi_i[c]);
     for (int k = 0; k < 3; ++k) u[k * g.fplane + c] = wall ? R(0) : R(u_i[k * N + c]);
 }
@@ -716,7 +860,7 @@ __global__ __launch_bounds__(kBlock) void k_get_macro(const typename S::pdf_t *_
         R ps = R(0);
         if (fluid)
 #pragma unroll
-            for (int i = 0; i < 27; ++i) ps += dec_g<S>(G[pull_idx<27>(i, c, n)], i);
+            for (int i = 0; i < 27; ++i) ps += dec_g<S>(G[pull_idx<S, 27>(i, c, n, g)], i);
         const R rho = density_of(ph, phiA[c]);
         p_o[c] = fluid ? Out(ps * rho * cs2<R>()) : Out(0);
     }

@@ -80,6 +80,7 @@ struct StoreF64 {
     using pdf_t = double;
     using real = double;
     static constexpr bool lowp = false;
+    static constexpr bool paired = false;  // cell c and c + half share a 32-bit word
     __device__ static real ld(pdf_t v) { return v; }
     __device__ static pdf_t st(real v) { return v; }
 };
@@ -88,6 +89,7 @@ struct StoreF32 {
     using pdf_t = float;
     using real = float;
     static constexpr bool lowp = false;
+    static constexpr bool paired = false;  // cell c and c + half share a 32-bit word
     __device__ static real ld(pdf_t v) { return v; }
     __device__ static pdf_t st(real v) { return v; }
 };
@@ -96,6 +98,7 @@ struct StoreF16S {
     using pdf_t = __half;
     using real = float;
     static constexpr bool lowp = true;
+    static constexpr bool paired = true;  // cell c and c + half share a 32-bit word
     __device__ static real ld(pdf_t v) { return __half2float(v) * 0x1p-10f; }
     __device__ static pdf_t st(real v) { return __float2half_rn(v * 0x1p10f); }
 };
@@ -104,6 +107,7 @@ struct StoreBF16S {
     using pdf_t = __hip_bfloat16;
     using real = float;
     static constexpr bool lowp = true;
+    static constexpr bool paired = true;  // cell c and c + half share a 32-bit word
     __device__ static real ld(pdf_t v) { return __bfloat162float(v); }
     __device__ static pdf_t st(real v) { return __float2bfloat16(v); }
 };
@@ -158,7 +162,7 @@ template <class S>
 __device__ inline typename S::real dec_g(typename S::pdf_t v, int i)
 {
     using R = typename S::real;
-    if constexpr (S::lowp) return S::ld(v) / inv_w27<R>(i);
+    if constexpr (S::lowp) return S::ld(v) * wgt<27, R>(i);  // stored g / w_i, decoded with the rounded w_i
     else return S::ld(v);
 }
 
