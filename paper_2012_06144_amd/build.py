@@ -10,17 +10,20 @@ LIBDIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(LIBDIR, "liblbm.so")
 ARCH = "gfx950"
 
-SOURCES = [os.path.join(CSRC, "lbm_api.hip"), os.path.join(CSRC, "sg_api.hip")]
+SOURCES = [os.path.join(CSRC, "lbm_api.hip"), os.path.join(CSRC, "lbm_sweeps_f32.hip"),
+           os.path.join(CSRC, "sg_api.hip")]
 HEADERS = [os.path.join(CSRC, f) for f in ("lbm_kernels.hpp", "lbm_lattice.hpp")] + [
     os.path.join(ROOT, "include", "lbm.h")]
+# Per-source contraction of a*b+c into fused multiply-adds: off where FP64
+# kernels follow the rounding of the formulas as written, on (within an
+# expression) for the sweeps that compute in FP32.
+CONTRACT = {"lbm_sweeps_f32.hip": "on"}
 
 
-def hipcc_flags():
+def hipcc_flags(contract: str = "off"):
     return [
-        f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
-        # no contraction of a*b+c: the FP64 sweeps follow the rounding of the
-        # formulas as written
-        "-ffp-contract=off",
+        f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
+        f"-ffp-contract={contract}",
         # keep the compiler from forming packed FP32 instructions
         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
         "-Wall", "-Wno-unused-result",
@@ -28,14 +31,25 @@ def hipcc_flags():
     ]
 
 
-def build(verbose: bool = False) -> str:
+def build(verbose: bool = False, extra=()) -> str:
     os.makedirs(LIBDIR, exist_ok=True)
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    objs = []
+    for src in SOURCES:
+        obj = os.path.join(LIBDIR, os.path.basename(src) + ".o")
+        cmd = ([hipcc] + hipcc_flags(CONTRACT.get(os.path.basename(src), "off")) + list(extra) +
+               ["-c", "-o", obj, src])
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.run(cmd, check=True)
+        objs.append(obj)
     tmp = LIB + ".tmp"
-    cmd = [hipcc] + hipcc_flags() + ["-o", tmp] + SOURCES
+    cmd = [hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
+    for o in objs:
+        os.remove(o)
     os.replace(tmp, LIB)
     return LIB
 

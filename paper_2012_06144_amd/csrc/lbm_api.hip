@@ -12,6 +12,13 @@
 #include "lbm.h"
 #include "lbm_kernels.hpp"
 
+// FP32-arithmetic sweeps live in lbm_sweeps_f32.hip (compiled with FMA contraction)
+namespace lbm {
+#define LBM_EXTERN_SWEEP(S, P) extern template void launch_sweep<S, P>(const SweepArgs<S> &, const SweepLaunch &, hipStream_t);
+LBM_FP32_SWEEPS(LBM_EXTERN_SWEEP)
+#undef LBM_EXTERN_SWEEP
+}  // namespace lbm
+
 using namespace lbm;
 
 namespace {
@@ -190,38 +197,32 @@ struct Ops {
 
     // paired 16-bit sweeps: one thread per two cells (needs even nz)
     static bool paired(lbm_ctx *c) { return S::paired && c->pair16 && c->g.nz % 2 == 0; }
-    static int pair_blocks(lbm_ctx *c) { return (c->g.half + kBlock - 1) / kBlock; }
+
+    static SweepLaunch sweep_launch(lbm_ctx *c)
+    {
+        SweepLaunch L{};
+        if (paired(c)) {
+            L.mode = 2;
+            L.blocks = (c->g.half + kBlock - 1) / kBlock;
+        } else if (c->zmarch) {
+            L.mode = 1;
+            L.zt = ztiles(c);
+            L.blocks = L.zt.tx * L.zt.ty * L.zt.tz;
+        } else {
+            L.mode = 0;
+            L.blocks = blocks(c);
+        }
+        return L;
+    }
 
     static void launch_phase(lbm_ctx *c, const SweepArgs<S> &sp)
     {
-        if constexpr (S::paired) {
-            if (paired(c)) {
-                hipLaunchKernelGGL((k_sweep_pair<S, true>), dim3(pair_blocks(c)), dim3(kBlock), 0, c->stream, sp);
-                return;
-            }
-        }
-        if (c->zmarch) {
-            const ZTiles t = ztiles(c);
-            hipLaunchKernelGGL((k_sweep_zm<S, true>), dim3(t.tx * t.ty * t.tz), dim3(kBlock), 0, c->stream, sp, t);
-        } else {
-            hipLaunchKernelGGL((k_phase<S>), dim3(blocks(c)), dim3(kBlock), 0, c->stream, sp);
-        }
+        launch_sweep<S, true>(sp, sweep_launch(c), c->stream);
     }
 
     static void launch_hydro(lbm_ctx *c, const SweepArgs<S> &sh)
     {
-        if constexpr (S::paired) {
-            if (paired(c)) {
-                hipLaunchKernelGGL((k_sweep_pair<S, false>), dim3(pair_blocks(c)), dim3(kBlock), 0, c->stream, sh);
-                return;
-            }
-        }
-        if (c->zmarch) {
-            const ZTiles t = ztiles(c);
-            hipLaunchKernelGGL((k_sweep_zm<S, false>), dim3(t.tx * t.ty * t.tz), dim3(kBlock), 0, c->stream, sh, t);
-        } else {
-            hipLaunchKernelGGL((k_hydro<S>), dim3(blocks(c)), dim3(kBlock), 0, c->stream, sh);
-        }
+        launch_sweep<S, false>(sh, sweep_launch(c), c->stream);
     }
 
     static lbm_status zero_all(lbm_ctx *c)

@@ -449,20 +449,62 @@ __device__ inline void hydro_cell(const SweepArgs<S> &a, int c, const Nbr &n, co
     using R = typename S::real;
     R ps = R(0), j[3] = {R(0), R(0), R(0)};
     R Pxx = R(0), Pyy = R(0), Pzz = R(0), Pxy = R(0), Pxz = R(0), Pyz = R(0);
+    if constexpr (S::lowp) {
+        // g_i = w_i x stored_i / kScale: sum the stored values per weight
+        // class (rest, axis, edge, corner) and apply each class weight once
+        R m[4][10];
 #pragma unroll
-    for (int i = 0; i < 27; ++i) {
-        const R gi = dec_g<S>(io.load(i), i);
-        const int ex = e27(i, 0), ey = e27(i, 1), ez = e27(i, 2);
-        ps += gi;
-        if (ex) j[0] += ex > 0 ? gi : -gi;
-        if (ey) j[1] += ey > 0 ? gi : -gi;
-        if (ez) j[2] += ez > 0 ? gi : -gi;
-        if (ex) Pxx += gi;
-        if (ey) Pyy += gi;
-        if (ez) Pzz += gi;
-        if (ex && ey) Pxy += (ex * ey > 0) ? gi : -gi;
-        if (ex && ez) Pxz += (ex * ez > 0) ? gi : -gi;
-        if (ey && ez) Pyz += (ey * ez > 0) ? gi : -gi;
+        for (int k = 0; k < 4; ++k)
+#pragma unroll
+            for (int q = 0; q < 10; ++q) m[k][q] = R(0);
+#pragma unroll
+        for (int i = 0; i < 27; ++i) {
+            const R v = S::raw_ld(io.load(i));
+            const int ex = e27(i, 0), ey = e27(i, 1), ez = e27(i, 2), k = l1<27>(i);
+            m[k][0] += v;
+            if (ex) m[k][1] += ex > 0 ? v : -v;
+            if (ey) m[k][2] += ey > 0 ? v : -v;
+            if (ez) m[k][3] += ez > 0 ? v : -v;
+            if (ex) m[k][4] += v;
+            if (ey) m[k][5] += v;
+            if (ez) m[k][6] += v;
+            if (ex && ey) m[k][7] += (ex * ey > 0) ? v : -v;
+            if (ex && ez) m[k][8] += (ex * ez > 0) ? v : -v;
+            if (ey && ez) m[k][9] += (ey * ez > 0) ? v : -v;
+        }
+        R mom[10];
+#pragma unroll
+        for (int q = 0; q < 10; ++q) {
+            mom[q] = R(0);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) mom[q] += m[k][q] * (class_w27<R>(k) * (R(1) / R(S::kScale)));
+        }
+        ps = mom[0];
+        j[0] = mom[1];
+        j[1] = mom[2];
+        j[2] = mom[3];
+        Pxx = mom[4];
+        Pyy = mom[5];
+        Pzz = mom[6];
+        Pxy = mom[7];
+        Pxz = mom[8];
+        Pyz = mom[9];
+    } else {
+#pragma unroll
+        for (int i = 0; i < 27; ++i) {
+            const R gi = dec_g<S>(io.load(i), i);
+            const int ex = e27(i, 0), ey = e27(i, 1), ez = e27(i, 2);
+            ps += gi;
+            if (ex) j[0] += ex > 0 ? gi : -gi;
+            if (ey) j[1] += ey > 0 ? gi : -gi;
+            if (ez) j[2] += ez > 0 ? gi : -gi;
+            if (ex) Pxx += gi;
+            if (ey) Pyy += gi;
+            if (ez) Pzz += gi;
+            if (ex && ey) Pxy += (ex * ey > 0) ? gi : -gi;
+            if (ex && ez) Pxz += (ex * ez > 0) ? gi : -gi;
+            if (ey && ez) Pyz += (ey * ez > 0) ? gi : -gi;
+        }
     }
 
     const R phi = phiB.at(0, 0, 0);
@@ -517,17 +559,38 @@ __device__ inline void hydro_cell(const SweepArgs<S> &a, int c, const Nbr &n, co
     const R trB = Bxx + Byy + Bzz;
     const R neq = std::is_same<R, float>::value ? (R(1) - s) * R(4.5) : (R(1) - s) / (R(2) * c2 * c2);
     const R finv = std::is_same<R, float>::value ? R(3) * inv_rho : R(1) / (rho * c2);
+    if constexpr (std::is_same<R, float>::value) {
+        // g*_i / w_i = (p* - 1.5 u.u) + e.u (3 + 4.5 e.u) + e.F / (2 rho cs^2) + neq (e e - cs^2 I) : B,
+        // times kScale for 16-bit storage (which stores g / w_i) or w_i for FP32
+        const R sc = S::lowp ? R(S::kScale) : R(1);
+        const R P0 = (ps - R(1.5) * uu) * sc, A = R(0.5) * finv * sc, Nq = neq * sc;
+        const R c3 = R(3) * sc, c45 = R(4.5) * sc;
+        const R ct = trB * (R(1) / R(3));
+        const R Bxy2 = R(2) * Bxy, Bxz2 = R(2) * Bxz, Byz2 = R(2) * Byz;
 #pragma unroll
-    for (int i = 0; i < 27; ++i) {
-        const int ex = e27(i, 0), ey = e27(i, 1), ez = e27(i, 2);
-        const R w = wgt<27, R>(i);
-        const R geq = geq_i<R>(i, ps, ux, uy, uz, uu);
-        const R eF = R(ex) * F[0] + R(ey) * F[1] + R(ez) * F[2];
-        // (e e - cs^2 I) : B
-        const R eBe = R(ex * ex) * Bxx + R(ey * ey) * Byy + R(ez * ez) * Bzz +
-                      R(2 * ex * ey) * Bxy + R(2 * ex * ez) * Bxz + R(2 * ey * ez) * Byz - c2 * trB;
-        const R gs = geq + R(0.5) * w * eF * finv + neq * w * eBe;
-        io.store(i, enc_g<S>(gs, i));
+        for (int i = 0; i < 27; ++i) {
+            const int ex = e27(i, 0), ey = e27(i, 1), ez = e27(i, 2);
+            const R eu = R(ex) * ux + R(ey) * uy + R(ez) * uz;
+            const R eF = R(ex) * F[0] + R(ey) * F[1] + R(ez) * F[2];
+            const R eBe = R(ex * ex) * Bxx + R(ey * ey) * Byy + R(ez * ez) * Bzz + R(ex * ey) * Bxy2 +
+                          R(ex * ez) * Bxz2 + R(ey * ez) * Byz2 - ct;
+            const R sv = P0 + eu * (c3 + c45 * eu) + eF * A + eBe * Nq;
+            if constexpr (S::lowp) io.store(i, S::raw_st(sv));
+            else io.store(i, S::st(sv * wgt<27, R>(i)));
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < 27; ++i) {
+            const int ex = e27(i, 0), ey = e27(i, 1), ez = e27(i, 2);
+            const R w = wgt<27, R>(i);
+            const R geq = geq_i<R>(i, ps, ux, uy, uz, uu);
+            const R eF = R(ex) * F[0] + R(ey) * F[1] + R(ez) * F[2];
+            // (e e - cs^2 I) : B
+            const R eBe = R(ex * ex) * Bxx + R(ey * ey) * Byy + R(ez * ez) * Bzz +
+                          R(2 * ex * ey) * Bxy + R(2 * ex * ez) * Bxz + R(2 * ey * ez) * Byz - c2 * trB;
+            const R gs = geq + R(0.5) * w * eF * finv + neq * w * eBe;
+            io.store(i, enc_g<S>(gs, i));
+        }
     }
 }
 
@@ -717,6 +780,39 @@ __global__ __launch_bounds__(kBlock) void k_sweep_pair(const SweepArgs<S> a)
         st_stream(Wd + pidx<Q>(i, p), v);
     }
 }
+
+// ---- launch of one sweep ------------------------------------------------------
+// The sweeps for FP32 arithmetic (FP32 and 16-bit storage) are instantiated in
+// their own translation unit, compiled with contraction of a*b+c into fused
+// multiply-adds; the FP64 sweeps are instantiated with the rest of the
+// library, without contraction.
+struct SweepLaunch {
+    int mode;    // 0: one cell per thread, 1: z-marching with LDS, 2: paired 16-bit
+    int blocks;  // grid size
+    ZTiles zt;   // tiling of mode 1
+};
+
+template <class S, bool PHASE>
+void launch_sweep(const SweepArgs<S> &a, const SweepLaunch &L, hipStream_t stream)
+{
+    if constexpr (S::paired) {
+        if (L.mode == 2) {
+            hipLaunchKernelGGL((k_sweep_pair<S, PHASE>), dim3(L.blocks), dim3(kBlock), 0, stream, a);
+            return;
+        }
+    }
+    if (L.mode == 1) {
+        hipLaunchKernelGGL((k_sweep_zm<S, PHASE>), dim3(L.blocks), dim3(kBlock), 0, stream, a, L.zt);
+    } else if constexpr (PHASE) {
+        hipLaunchKernelGGL((k_phase<S>), dim3(L.blocks), dim3(kBlock), 0, stream, a);
+    } else {
+        hipLaunchKernelGGL((k_hydro<S>), dim3(L.blocks), dim3(kBlock), 0, stream, a);
+    }
+}
+
+#define LBM_FP32_SWEEPS(X)                                                                          \
+    X(StoreF32, true) X(StoreF32, false) X(StoreF16S, true) X(StoreF16S, false) X(StoreBF16S, true) \
+    X(StoreBF16S, false)
 
 // ---- initial / equilibrium state from (phi, u, p*) ---------------------------
 // Writes the phase-field PDFs (post-collision, stored as is), the canonical
@@ -950,6 +1046,7 @@ __global__ __launch_bounds__(kBlock) void k_reduce1(const typename S::real *__re
     if (threadIdx.x < kRedVals) partial[blockIdx.x * kRedVals + threadIdx.x] = sh[threadIdx.x];
 }
 
+#ifndef LBM_SWEEPS_ONLY  // non-template kernels: defined once, in the translation unit of the C ABI
 __global__ __launch_bounds__(kBlock) void k_reduce2(const double *__restrict__ partial,
                                                     double *__restrict__ out)
 {
@@ -981,5 +1078,7 @@ __global__ __launch_bounds__(kBlock) void k_copy(const uint4 *__restrict__ src, 
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i < n) dst[i] = src[i];
 }
+
+#endif  // LBM_SWEEPS_ONLY
 
 }  // namespace lbm

@@ -81,6 +81,7 @@ struct StoreF64 {
     using real = double;
     static constexpr bool lowp = false;
     static constexpr bool paired = false;  // cell c and c + half share a 32-bit word
+    static constexpr real kScale = 1;
     __device__ static real ld(pdf_t v) { return v; }
     __device__ static pdf_t st(real v) { return v; }
 };
@@ -90,6 +91,7 @@ struct StoreF32 {
     using real = float;
     static constexpr bool lowp = false;
     static constexpr bool paired = false;  // cell c and c + half share a 32-bit word
+    static constexpr real kScale = 1;
     __device__ static real ld(pdf_t v) { return v; }
     __device__ static pdf_t st(real v) { return v; }
 };
@@ -99,8 +101,11 @@ struct StoreF16S {
     using real = float;
     static constexpr bool lowp = true;
     static constexpr bool paired = true;  // cell c and c + half share a 32-bit word
-    __device__ static real ld(pdf_t v) { return __half2float(v) * 0x1p-10f; }
-    __device__ static pdf_t st(real v) { return __float2half_rn(v * 0x1p10f); }
+    static constexpr float kScale = 0x1p10f;  // stored = value * kScale
+    __device__ static real raw_ld(pdf_t v) { return __half2float(v); }
+    __device__ static pdf_t raw_st(real v) { return __float2half_rn(v); }
+    __device__ static real ld(pdf_t v) { return raw_ld(v) * (1.0f / kScale); }
+    __device__ static pdf_t st(real v) { return raw_st(v * kScale); }
 };
 
 struct StoreBF16S {
@@ -108,8 +113,11 @@ struct StoreBF16S {
     using real = float;
     static constexpr bool lowp = true;
     static constexpr bool paired = true;  // cell c and c + half share a 32-bit word
-    __device__ static real ld(pdf_t v) { return __bfloat162float(v); }
-    __device__ static pdf_t st(real v) { return __float2bfloat16(v); }
+    static constexpr float kScale = 1.0f;
+    __device__ static real raw_ld(pdf_t v) { return __bfloat162float(v); }
+    __device__ static pdf_t raw_st(real v) { return __float2bfloat16(v); }
+    __device__ static real ld(pdf_t v) { return raw_ld(v); }
+    __device__ static pdf_t st(real v) { return raw_st(v); }
 };
 
 // 1/w_i of D3Q27 (all exact in binary): 27/8, 27/2, 54, 216.
@@ -117,6 +125,13 @@ template <class R>
 __host__ __device__ constexpr R inv_w27(int i)
 {
     return l1<27>(i) == 0 ? R(3.375) : l1<27>(i) == 1 ? R(13.5) : l1<27>(i) == 2 ? R(54) : R(216);
+}
+
+// D3Q27 weight of the class of directions with k non-zero components.
+template <class R>
+__host__ __device__ constexpr R class_w27(int k)
+{
+    return k == 0 ? R(8) / R(27) : k == 1 ? R(2) / R(27) : k == 2 ? R(1) / R(54) : R(1) / R(216);
 }
 
 // Phase-field population i stored at a cell whose phase field is phi_cell.
