@@ -41,8 +41,9 @@ def log(msg):
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("lbm_kernels.hpp", "lbm_lattice.hpp", "lbm_api.hip"):
-        with open(os.path.join(ROOT, "paper_2012_06144_amd", "csrc", f), "rb") as fh:
+    for f in ("csrc/lbm_kernels.hpp", "csrc/lbm_lattice.hpp", "csrc/lbm_api.hip", "csrc/lbm_sweeps_f32.hip",
+              "build.py"):
+        with open(os.path.join(ROOT, "paper_2012_06144_amd", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
@@ -65,7 +66,8 @@ def load_traffic(kernel: str, workload: str, storage: str, src_hash: str):
 
 def surrogate_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("csrc/sg_api.hip", "surrogate.py", "csrc/lbm_kernels.hpp", "csrc/lbm_lattice.hpp", "csrc/lbm_api.hip"):
+    for f in ("csrc/sg_api.hip", "surrogate.py", "csrc/lbm_kernels.hpp", "csrc/lbm_lattice.hpp", "csrc/lbm_api.hip",
+              "csrc/lbm_sweeps_f32.hip", "build.py"):
         with open(os.path.join(ROOT, "paper_2012_06144_amd", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
