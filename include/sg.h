@@ -139,6 +139,29 @@ sg_status sg_apply_prediction(const float *out, int32_t c_out, const float *scal
 sg_status sg_advect_phase(const float *state, int64_t count, int32_t bx, int32_t by, int32_t bz, float K,
                           float *out, void *hip_stream);
 
+/* Co-moving baseline of a jump on `count` boxes of raw states (layout as in
+ * sg_advect_phase): every channel is translated, out(x) = state(x - d_n)
+ * with d_n = (shift[4n], shift[4n+1], shift[4n+2]) in cells, trilinear
+ * interpolation, the departure point clamped to the box; the velocity
+ * channels are then multiplied by f_n = shift[4n+3].  shift is a DEVICE
+ * array of 4 count floats.  A bubble rising at constant speed U is steady
+ * in its own frame, so d = K U (f = 1) moves its whole neighbourhood K
+ * steps ahead; a slowly accelerating one is followed to first order by
+ * d = K U + K^2 a / 2 and f = 1 + K a.U / |U|^2.  out must not alias
+ * state. */
+sg_status sg_shift_boxes(const float *state, int64_t count, int32_t bx, int32_t by, int32_t bz, const float *shift,
+                         float *out, void *hip_stream);
+
+/* Gas-indicator moments of `count` boxes of raw states: with chi =
+ * clamp((phi_heavy - phi)/(phi_heavy - phi_light), 0, 1) (the indicator of
+ * the statistics in lbm.h), out[8n + k] (DEVICE, 8 count doubles) holds
+ * k = 0: sum chi; 1-3: sum chi x, chi y, chi z (box coordinates, x
+ * fastest); 4-6: sum chi u_x, chi u_y, chi u_z; 7: 0.  FP64, one block per
+ * box, fixed-order reduction (deterministic).  Gives the gas centroid and
+ * the gas-weighted velocity of each box. */
+sg_status sg_box_moments(const float *state, int64_t count, int32_t bx, int32_t by, int32_t bz, float phi_heavy,
+                         float phi_light, double *out, void *hip_stream);
+
 /* Projective time step of field sets (Gear and Kevrekidis, SIAM J. Sci.
  * Comput. 24, 2003): out = s + ratio (s - s_prev) per channel over n points,
  * channels (phi, u_x, u_y, u_z, p); element (i, k) at f[k cs + i vs], either

@@ -31,6 +31,8 @@ def _lib():
         L.orc_adam.argtypes = [_D, _D, _D, _D, C.c_size_t, C.c_double, C.c_double, C.c_double,
                                C.c_double, C.c_int]
         L.orc_advect_phase.argtypes = [_D, i, i, i, i, C.c_double, _D]
+        L.orc_shift_boxes.argtypes = [_D, i, i, i, i, _D, _D]
+        L.orc_box_moments.argtypes = [_D, i, i, i, i, C.c_double, C.c_double, _D]
         i64 = C.c_int64
         L.orc_projective_step.argtypes = [_D, _D, i64, i64, i64, C.c_double, C.c_double, C.c_double, i, i, _D]
         _ready = True
@@ -121,6 +123,41 @@ def advect_phase(state, K):
     out = np.zeros_like(st)
     _lib().orc_advect_phase(st, n, bx, by, bz, float(K), out)
     return out.reshape(np.shape(state))
+
+
+def shift_boxes(state, shift):
+    """Co-moving jump baseline on boxes of states shaped (count, bz, by, bx, 5):
+    every channel translated by the box's displacement (dx, dy, dz), s(x - d)
+    by trilinear interpolation with the departure point clamped to the box,
+    then the velocity channels multiplied by f; shift shaped (count, 4) rows
+    (dx, dy, dz, f), or (count, 3) for f = 1."""
+    st = _f(state)
+    if st.ndim == 4:
+        st = st[None]
+    n, bz, by, bx, c = st.shape
+    assert c == 5
+    d = _f(np.reshape(shift, (n, -1)))
+    if d.shape[1] == 3:
+        d = np.concatenate([d, np.ones((n, 1))], axis=1)
+    d = _f(d)
+    out = np.zeros_like(st)
+    _lib().orc_shift_boxes(st, n, bx, by, bz, d, out)
+    return out.reshape(np.shape(state))
+
+
+def box_moments(state, phi_heavy, phi_light):
+    """Gas-indicator moments of boxes of states (count, bz, by, bx, 5):
+    rows of (sum chi, sum chi x, sum chi y, sum chi z, sum chi u_x,
+    sum chi u_y, sum chi u_z, 0), chi = (phi_heavy - phi)/(phi_heavy -
+    phi_light) clipped to [0, 1]."""
+    st = _f(state)
+    if st.ndim == 4:
+        st = st[None]
+    n, bz, by, bx, c = st.shape
+    assert c == 5
+    out = np.zeros((n, 8))
+    _lib().orc_box_moments(st, n, bx, by, bz, float(phi_heavy), float(phi_light), out)
+    return out
 
 
 def projective_step(s, s_prev, ratio, phi_lo, phi_hi, u_by_phase=True, p_step=False, layout="last"):

@@ -206,6 +206,81 @@ void orc_advect_phase(const double *state, int count, int bx, int by, int bz, do
     }
 }
 
+/* Co-moving baseline of a jump on boxes of states (layout as above): the
+ * whole state is translated by the box's displacement d_n = shift[4n..4n+2],
+ *   s'(x) = s(x - d_n)   (trilinear interpolation of every channel, the
+ *                         departure point clamped to the box),
+ * and the velocity channels are multiplied by f_n = shift[4n+3].  A bubble
+ * rising at a constant speed U is steady in its own frame, so d = K U,
+ * f = 1 is the exact jump of K steps in that limit.                       */
+void orc_shift_boxes(const double *state, int count, int bx, int by, int bz, const double *shift, double *out)
+{
+    const int64_t V = (int64_t)bx * by * bz;
+    const int ext[3] = {bx, by, bz};
+    for (int n = 0; n < count; ++n) {
+        const double *s = state + (int64_t)n * V * 5;
+        double *o = out + (int64_t)n * V * 5;
+        for (int z = 0; z < bz; ++z)
+            for (int y = 0; y < by; ++y)
+                for (int x = 0; x < bx; ++x) {
+                    const int64_t v = x + (int64_t)bx * (y + (int64_t)by * z);
+                    double p[3] = {x - shift[4 * n], y - shift[4 * n + 1], z - shift[4 * n + 2]};
+                    int lo[3], hi[3];
+                    double f[3];
+                    for (int a = 0; a < 3; ++a) {
+                        if (p[a] < 0.0) p[a] = 0.0;
+                        if (p[a] > ext[a] - 1) p[a] = ext[a] - 1;
+                        lo[a] = (int)floor(p[a]);
+                        hi[a] = lo[a] + 1 < ext[a] ? lo[a] + 1 : lo[a];
+                        f[a] = p[a] - lo[a];
+                    }
+                    for (int k = 0; k < 5; ++k) {
+                        double acc = 0.0;
+                        for (int cz = 0; cz < 2; ++cz)
+                            for (int cy = 0; cy < 2; ++cy)
+                                for (int cx = 0; cx < 2; ++cx) {
+                                    const int xx = cx ? hi[0] : lo[0], yy = cy ? hi[1] : lo[1];
+                                    const int zz = cz ? hi[2] : lo[2];
+                                    const double wgt = (cx ? f[0] : 1.0 - f[0]) * (cy ? f[1] : 1.0 - f[1]) *
+                                                       (cz ? f[2] : 1.0 - f[2]);
+                                    acc += wgt * s[(xx + (int64_t)bx * (yy + (int64_t)by * zz)) * 5 + k];
+                                }
+                        o[v * 5 + k] = (k >= 1 && k <= 3) ? acc * shift[4 * n + 3] : acc;
+                    }
+                }
+    }
+}
+
+/* Gas-indicator moments of boxes of states: chi = (phi_heavy - phi) /
+ * (phi_heavy - phi_light) clipped to [0, 1] (the gas indicator of the
+ * statistics, whose centroid and chi-weighted u_y define the rise of a
+ * bubble); out[8n + k] = sum chi, sum chi x, sum chi y, sum chi z,
+ * sum chi u_x, sum chi u_y, sum chi u_z, 0 over box n.                   */
+void orc_box_moments(const double *state, int count, int bx, int by, int bz, double pheavy, double plight,
+                     double *out)
+{
+    const int64_t V = (int64_t)bx * by * bz;
+    for (int n = 0; n < count; ++n) {
+        double *o = out + 8 * n;
+        for (int k = 0; k < 8; ++k) o[k] = 0.0;
+        for (int z = 0; z < bz; ++z)
+            for (int y = 0; y < by; ++y)
+                for (int x = 0; x < bx; ++x) {
+                    const double *sv = state + ((int64_t)n * V + x + (int64_t)bx * (y + (int64_t)by * z)) * 5;
+                    double chi = (pheavy - sv[0]) / (pheavy - plight);
+                    if (chi < 0.0) chi = 0.0;
+                    if (chi > 1.0) chi = 1.0;
+                    o[0] += chi;
+                    o[1] += chi * x;
+                    o[2] += chi * y;
+                    o[3] += chi * z;
+                    o[4] += chi * sv[1];
+                    o[5] += chi * sv[2];
+                    o[6] += chi * sv[3];
+                }
+    }
+}
+
 /* Projective (coarse) time step of the macroscopic fields (Gear and
  * Kevrekidis, "Projective methods for stiff differential equations", SIAM
  * J. Sci. Comput. 24, 2003): with s the fields now and s_prev the fields m

@@ -587,6 +587,80 @@ __global__ void k_advect_phase(const float *__restrict__ s, int64_t count, int b
     ov[4] = sv[4];
 }
 
+// Uniform translation of box states: out(x) = s(x - d_n) for all five
+// channels by trilinear interpolation, d_n = (shift[4n], shift[4n+1],
+// shift[4n+2]) the displacement of box n, the departure point clamped to the
+// box; the velocity channels are then multiplied by shift[4n+3].  At steady
+// translation (a bubble rising at constant speed) the whole state moves with
+// the bubble, so this is the jump of a co-moving frame; the factor carries a
+// slowly growing flow amplitude along.
+__global__ void k_shift_boxes(const float *__restrict__ s, int64_t count, int bx, int by, int bz,
+                              const float *__restrict__ shift, float *__restrict__ o)
+{
+    const int64_t V = (int64_t)bx * by * bz;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= V * count) return;
+    const int64_t n = i / V, v = i % V;
+    const float *sb = s + n * V * 5;
+    const int x = (int)(v % bx), y = (int)((v / bx) % by), z = (int)(v / ((int64_t)bx * by));
+    float px = (float)x - shift[4 * n], py = (float)y - shift[4 * n + 1], pz = (float)z - shift[4 * n + 2];
+    const float fu = shift[4 * n + 3];
+    px = fminf(fmaxf(px, 0.f), (float)(bx - 1));
+    py = fminf(fmaxf(py, 0.f), (float)(by - 1));
+    pz = fminf(fmaxf(pz, 0.f), (float)(bz - 1));
+    const int x0 = (int)floorf(px), y0 = (int)floorf(py), z0 = (int)floorf(pz);
+    const int x1 = x0 + 1 < bx ? x0 + 1 : x0, y1 = y0 + 1 < by ? y0 + 1 : y0, z1 = z0 + 1 < bz ? z0 + 1 : z0;
+    const float fx = px - (float)x0, fy = py - (float)y0, fz = pz - (float)z0;
+    const int64_t r00 = (int64_t)bx * (y0 + (int64_t)by * z0), r10 = (int64_t)bx * (y1 + (int64_t)by * z0);
+    const int64_t r01 = (int64_t)bx * (y0 + (int64_t)by * z1), r11 = (int64_t)bx * (y1 + (int64_t)by * z1);
+    float *ov = o + n * V * 5 + v * 5;
+    for (int k = 0; k < 5; ++k) {
+        auto at = [&](int64_t row, int xx) { return sb[(row + xx) * 5 + k]; };
+        const float c00 = at(r00, x0) * (1.f - fx) + at(r00, x1) * fx;
+        const float c10 = at(r10, x0) * (1.f - fx) + at(r10, x1) * fx;
+        const float c01 = at(r01, x0) * (1.f - fx) + at(r01, x1) * fx;
+        const float c11 = at(r11, x0) * (1.f - fx) + at(r11, x1) * fx;
+        const float c0 = c00 * (1.f - fy) + c10 * fy, c1 = c01 * (1.f - fy) + c11 * fy;
+        const float val = c0 * (1.f - fz) + c1 * fz;
+        ov[k] = (k >= 1 && k <= 3) ? val * fu : val;
+    }
+}
+
+// Gas-indicator moments of box states, one block per box: with
+// chi = clamp((phi_heavy - phi) / (phi_heavy - phi_light), 0, 1),
+// out[8n + 0] = sum chi, 1..3 = sum chi (x, y, z) (box coordinates),
+// 4..6 = sum chi (u_x, u_y, u_z), 7 = 0; FP64, fixed-order reduction.
+constexpr int kBoxThreads = 256;
+__global__ __launch_bounds__(kBoxThreads) void k_box_moments(const float *__restrict__ s, int bx, int by, int bz,
+                                                            float pheavy, float plight, double *__restrict__ out)
+{
+    __shared__ double sh[7][kBoxThreads];
+    const int64_t V = (int64_t)bx * by * bz;
+    const float *sb = s + (int64_t)blockIdx.x * V * 5;
+    const double inv = 1.0 / ((double)pheavy - (double)plight);
+    double acc[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int64_t v = threadIdx.x; v < V; v += kBoxThreads) {
+        const float *sv = sb + v * 5;
+        const double chi = fmin(fmax(((double)pheavy - (double)sv[0]) * inv, 0.0), 1.0);
+        const int x = (int)(v % bx), y = (int)((v / bx) % by), z = (int)(v / ((int64_t)bx * by));
+        acc[0] += chi;
+        acc[1] += chi * x;
+        acc[2] += chi * y;
+        acc[3] += chi * z;
+        acc[4] += chi * sv[1];
+        acc[5] += chi * sv[2];
+        acc[6] += chi * sv[3];
+    }
+    for (int k = 0; k < 7; ++k) sh[k][threadIdx.x] = acc[k];
+    __syncthreads();
+    for (int st = kBoxThreads / 2; st > 0; st >>= 1) {
+        if (threadIdx.x < st)
+            for (int k = 0; k < 7; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x < 8) out[(int64_t)blockIdx.x * 8 + threadIdx.x] = threadIdx.x < 7 ? sh[threadIdx.x][0] : 0.0;
+}
+
 // Projective time step of field sets: s' = s + ratio (s - s_prev) per
 // channel, element (i, k) at f[k cs + i vs]; phi clipped to [lo, hi];
 // velocity increments weighted by the heavy-phase fraction of the current
@@ -988,6 +1062,29 @@ sg_status sg_advect_phase(const float *state, int64_t count, int32_t bx, int32_t
     const int64_t n = count * bx * (int64_t)by * bz;
     hipLaunchKernelGGL(k_advect_phase, dim3(blocks_for(n)), dim3(kThreads), 0, (hipStream_t)stream, state, count,
                        bx, by, bz, K, out);
+    SG_LAUNCH_CHECK();
+    return SG_OK;
+}
+
+sg_status sg_shift_boxes(const float *state, int64_t count, int32_t bx, int32_t by, int32_t bz, const float *shift,
+                         float *out, void *stream)
+{
+    if (!state || !shift || !out || count < 1 || bx < 1 || by < 1 || bz < 1) return fail(SG_EARG, "bad arguments");
+    if (state == out) return fail(SG_EARG, "sg_shift_boxes cannot run in place");
+    const int64_t n = count * bx * (int64_t)by * bz;
+    hipLaunchKernelGGL(k_shift_boxes, dim3(blocks_for(n)), dim3(kThreads), 0, (hipStream_t)stream, state, count,
+                       bx, by, bz, shift, out);
+    SG_LAUNCH_CHECK();
+    return SG_OK;
+}
+
+sg_status sg_box_moments(const float *state, int64_t count, int32_t bx, int32_t by, int32_t bz, float phi_heavy,
+                         float phi_light, double *out, void *stream)
+{
+    if (!state || !out || count < 1 || count > INT32_MAX || bx < 1 || by < 1 || bz < 1 || !(phi_heavy != phi_light))
+        return fail(SG_EARG, "bad arguments");
+    hipLaunchKernelGGL(k_box_moments, dim3((unsigned)count), dim3(kBoxThreads), 0, (hipStream_t)stream, state, bx, by,
+                       bz, phi_heavy, phi_light, out);
     SG_LAUNCH_CHECK();
     return SG_OK;
 }

@@ -16,7 +16,7 @@ EXPORTS = [
     "sg_leaky_bwd", "sg_pool2_fwd", "sg_pool2_bwd", "sg_up2_fwd", "sg_up2_bwd", "sg_concat",
     "sg_split", "sg_mse", "sg_adam", "sg_to_bf16", "sg_to_f32", "sg_add", "sg_fields_to_input",
     "sg_state_to_input", "sg_make_target", "sg_apply_prediction", "sg_advect_phase", "sg_projective_step",
-    "sg_pair_to_input", "sg_channel_moments",
+    "sg_pair_to_input", "sg_channel_moments", "sg_shift_boxes", "sg_box_moments",
     "sg_mass_project", "sg_last_error",
 ]
 
@@ -46,6 +46,8 @@ _SIG = {
     "sg_projective_step": [_vp, _vp, _i64, _i64, _i64, _f, _f, _f, _i, _i, _vp, _vp],
     "sg_pair_to_input": [_vp, _vp, _i64, _vp, _vp, _i, _vp, _vp],
     "sg_channel_moments": [_vp, _i64, _i, _vp, _vp, _vp],
+    "sg_shift_boxes": [_vp, _i64, _i, _i, _i, _vp, _vp, _vp],
+    "sg_box_moments": [_vp, _i64, _i, _i, _i, _f, _f, _vp, _vp],
     "sg_mass_project": [_vp, _i64, C.c_double, _f, _f, _vp, _vp],
     "sg_last_error": [],
 }
@@ -215,6 +217,16 @@ def sg_pair_to_input(state, state_prev, scale_in, trend_scale, c_in, x, stream=N
 def sg_channel_moments(a, rows, c, out, scratch, stream=None):
     _check(_L.sg_channel_moments(_p(a), int(rows), int(c), _p(out), _p(scratch), _stream(stream)),
            "sg_channel_moments")
+
+
+def sg_shift_boxes(state, count, bx, by, bz, shift, out, stream=None):
+    _check(_L.sg_shift_boxes(_p(state), int(count), bx, by, bz, _p(shift), _p(out), _stream(stream)),
+           "sg_shift_boxes")
+
+
+def sg_box_moments(state, count, bx, by, bz, phi_heavy, phi_light, out, stream=None):
+    _check(_L.sg_box_moments(_p(state), int(count), bx, by, bz, float(phi_heavy), float(phi_light), _p(out),
+                             _stream(stream)), "sg_box_moments")
 
 
 def sg_mass_project(phi, target_mass, phi_min, phi_max, scratch, stream=None):

@@ -81,6 +81,7 @@ class Net:
         self.scale_in = [1.0, 1e-2, 1e-2, 1e-2, 1e-4]
         self.scale_out = [1e-2, 1e-3, 1e-3, 1e-3, 1e-5]
         self.scale_trend = [1e-3, 1e-5, 1e-5, 1e-5, 1e-7]
+        self.base = "comoving"          # baseline whose residual the network predicts (see jump_base)
         self.step_count = 0
         self._ws = None
 
@@ -367,19 +368,77 @@ def _moments(a, rows, scratch, out):
     return mean, var, rms
 
 
-def _base_crop(S0_i, box, K, out):
-    """Baseline of one crop: phi transported by the local velocity over K
-    steps (semi-Lagrangian), u and p carried over."""
+PHI_HEAVY, PHI_LIGHT = 1.0, 0.0      # phase-field values of liquid and gas in the rising-bubble runs
+
+
+def _gas_velocity(states, count, box, phi_heavy, phi_light):
+    """Gas volume and gas-weighted velocity sum(chi u) / sum(chi) of each of
+    `count` box states (sg_box_moments, FP64), as numpy arrays."""
+    import torch
     bx, by, bz = box
-    sg.sg_advect_phase(S0_i, 1, bx, by, bz, K, out)
+    mom = torch.empty(count * 8, device=states.device, dtype=torch.float64)
+    sg.sg_box_moments(states, count, bx, by, bz, phi_heavy, phi_light, mom)
+    M = mom.view(count, 8).cpu().numpy()
+    vol = M[:, 0]
+    return vol, M[:, 4:7] / np.maximum(vol, 1e-30)[:, None]
 
 
-def channel_scales(Sm, S0, S1, box, K, m):
+def comoving_shift(states, count, box, K, prev=None, m=None, phi_heavy=PHI_HEAVY, phi_light=PHI_LIGHT,
+                   max_gain=0.5):
+    """Co-moving jump of each of `count` box states (contiguous, 5 FP32
+    channels per voxel) over K steps: the bubble's gas-weighted velocity U
+    and, given the same boxes `prev` m steps earlier, its acceleration
+    a = (U - U_prev) / m give the displacement d = K U + K^2 a / 2 and the
+    velocity factor f = 1 + K a.U / |U|^2 (the flow around the bubble keeps
+    its shape and grows with U), f clipped to 1 +- max_gain.  Returns a
+    (count, 4) FP32 device tensor of rows (dx, dy, dz, f); a box without
+    gas stays put."""
+    import torch
+    vol, U = _gas_velocity(states, count, box, phi_heavy, phi_light)
+    a = np.zeros_like(U)
+    if prev is not None:
+        vol_p, Up = _gas_velocity(prev, count, box, phi_heavy, phi_light)
+        a = np.where((vol_p > 0.5)[:, None], (U - Up) / float(m), 0.0)
+    d = K * U + 0.5 * K * K * a
+    uu = (U * U).sum(1)
+    f = 1.0 + K * np.where(uu > 0, (a * U).sum(1) / np.maximum(uu, 1e-300), 0.0)
+    f = np.clip(f, 1.0 - max_gain, 1.0 + max_gain)
+    out = np.concatenate([d, f[:, None]], axis=1)
+    out[vol <= 0.5] = (0.0, 0.0, 0.0, 1.0)
+    return torch.from_numpy(out.astype(np.float32)).to(states.device)
+
+
+def jump_base(kind, s0, box, K, out, shift=None):
+    """Baseline state K steps ahead of one box state s0 (into out):
+    "transport": phi moved by the local velocity (semi-Lagrangian), u and p
+    carried over; "comoving": every channel translated with the bubble and
+    the velocity scaled (`shift`, a (4,) device tensor from comoving_shift:
+    the exact jump of a bubble rising steadily, followed to first order
+    while it accelerates)."""
+    bx, by, bz = box
+    if kind == "comoving":
+        sg.sg_shift_boxes(s0, 1, bx, by, bz, shift, out)
+    else:
+        sg.sg_advect_phase(s0, 1, bx, by, bz, K, out)
+
+
+def _base_crop(S0, i, box, K, out, base, shifts, Sm=None, m=None):
+    """Baseline of sample i; the co-moving displacement comes from `shifts`
+    (all samples, comoving_shift) or is measured on the sample itself (and
+    its state m steps earlier, Sm[i])."""
+    if base == "comoving" and shifts is None:
+        shift = comoving_shift(S0[i], 1, box, K, prev=None if Sm is None else Sm[i], m=m)[0]
+    else:
+        shift = None if shifts is None else shifts[i]
+    jump_base(base, S0[i], box, K, out, shift)
+
+
+def channel_scales(Sm, S0, S1, box, K, m, base_kind="comoving", shifts=None):
     """Per-channel input scale (root mean square of the state; 1 for phi),
     output scale (standard deviation of the target S1 - baseline, the
-    baseline being phi transported by the local velocity over K steps with
-    u and p carried over) and trend scale (root mean square of S(t) -
-    S(t - m)), over all samples.  FP64 moments from sg_channel_moments."""
+    baseline of kind `base_kind`, see jump_base) and trend scale (root mean
+    square of S(t) - S(t - m)), over all samples.  FP64 moments from
+    sg_channel_moments."""
     import torch
     bx, by, bz = box
     V = bx * by * bz
@@ -393,7 +452,7 @@ def channel_scales(Sm, S0, S1, box, K, m):
     base = torch.empty((V * NCH,), device=S0.device, dtype=torch.float32)
     diff = torch.empty((V * NCH,), device=S0.device, dtype=torch.float32)
     for i in range(n):
-        _base_crop(S0[i], box, K, base)
+        _base_crop(S0, i, box, K, base, base_kind, shifts, Sm, m)
         sg.sg_make_target(base, S1[i], [1.0] * NCH, NCH, diff)
         sg.sg_channel_moments(diff, V, NCH, out, scratch)
         acc += out.cpu().numpy()
@@ -413,10 +472,12 @@ def trend_scale(net, K, m):
     return [1.0 / q for q in net.scale_trend]
 
 
-def make_batch(net, Sm, S0, S1, idx, box, K, m, target_from="baseline"):
-    """Network input (BF16: state and its trend (K/m)(S0 - Sm)) and target
-    (FP32) of the samples `idx`.  The target is (S1 - base) / scale_out with
-    base the transport baseline, or base = S0 (persistence) with
+def make_batch(net, Sm, S0, S1, idx, box, K, m, target_from="baseline", shifts=None):
+    """Network input (BF16: state and its trend S0 - Sm, normalised) and
+    target (FP32) of the samples `idx`.  The target is (S1 - base) /
+    scale_out with base the network's baseline (net.base; `shifts` holds
+    the co-moving displacements of all samples), the transport baseline
+    with target_from="transport", or base = S0 (persistence) with
     target_from="state"."""
     import torch
     bx, by, bz = box
@@ -428,8 +489,9 @@ def make_batch(net, Sm, S0, S1, idx, box, K, m, target_from="baseline"):
     ts = trend_scale(net, K, m)
     for j, i in enumerate(idx):
         sg.sg_pair_to_input(S0[i], Sm[i], net.scale_in, ts, C_IN, x[j])
-        if target_from == "baseline":
-            _base_crop(S0[i], box, K, base)
+        if target_from in ("baseline", "transport"):
+            kind = net.base if target_from == "baseline" else "transport"
+            _base_crop(S0, i, box, K, base, kind, shifts, Sm, m)
             sg.sg_make_target(base, S1[i], net.scale_out, C_OUT, t[j])
         else:
             sg.sg_make_target(S0[i], S1[i], net.scale_out, C_OUT, t[j])
@@ -437,12 +499,13 @@ def make_batch(net, Sm, S0, S1, idx, box, K, m, target_from="baseline"):
 
 
 def train(net, Sm, S0, S1, box, K, m, run_of=None, steps=500, batch=8, lr=2e-4, warmup=50, val_frac=0.1,
-          seed=0, log=print):
-    """Adam on the MSE of the normalised residual of the transport baseline,
+          seed=0, log=print, shifts=None):
+    """Adam on the MSE of the normalised residual of the network's baseline,
     linear warm-up over `warmup` steps, then cosine learning-rate decay.
     Validation samples are whole runs held out (samples of one run are
     correlated).  Returns the loss history and the validation losses of the
-    network, of the transport baseline alone and of persistence."""
+    network, of its baseline alone, of the transport baseline and of
+    persistence."""
     import torch
     n = S0.shape[0]
     rng = np.random.default_rng(seed)
@@ -459,7 +522,7 @@ def train(net, Sm, S0, S1, box, K, m, run_of=None, steps=500, batch=8, lr=2e-4, 
     t0 = time.perf_counter()
     for it in range(steps):
         idx = rng.choice(tr, size=min(batch, len(tr)), replace=False)
-        x, t = make_batch(net, Sm, S0, S1, idx, box, K, m)
+        x, t = make_batch(net, Sm, S0, S1, idx, box, K, m, shifts=shifts)
         out = net.forward(x)
         g = torch.empty(out.shape, device=out.device, dtype=torch.bfloat16)
         sg.sg_mse(out, t, loss, g, scratch)
@@ -476,24 +539,26 @@ def train(net, Sm, S0, S1, box, K, m, run_of=None, steps=500, batch=8, lr=2e-4, 
                 log(f"[train] loss rose to {lv:.3e} (best {best:.3e}): learning rate halved to {lr:.2e}")
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    v = evaluate(net, Sm, S0, S1, val, box, K, m)
+    v = evaluate(net, Sm, S0, S1, val, box, K, m, shifts=shifts)
     return {"history": hist, "val_loss": v["network"], "val_loss_baseline": v["baseline"],
-            "val_loss_persistence": v["persistence"], "seconds": wall,
+            "val_loss_transport": v["transport"], "val_loss_persistence": v["persistence"], "seconds": wall,
+            "base": net.base,
             "n_train": int(len(tr)), "n_val": int(len(val)), "val_runs": [int(v) for v in vr]}
 
 
-def evaluate(net, Sm, S0, S1, idx, box, K, m, batch=8):
+def evaluate(net, Sm, S0, S1, idx, box, K, m, batch=8, shifts=None):
     """Mean validation MSE (normalised units) of the jump with the network
-    (transport baseline + network residual), of the baseline alone (network
-    output 0) and of persistence (state left unchanged)."""
+    (its baseline + network residual), of that baseline alone (network
+    output 0), of the transport baseline and of persistence (state left
+    unchanged)."""
     import torch
     loss = torch.zeros(1, device=S0.device, dtype=torch.float32)
     scratch = torch.zeros(1024, device=S0.device, dtype=torch.float32)
-    tot = {"network": 0.0, "baseline": 0.0, "persistence": 0.0}
+    tot = {"network": 0.0, "baseline": 0.0, "transport": 0.0, "persistence": 0.0}
     cnt = 0
     for k in range(0, len(idx), batch):
         ii = idx[k:k + batch]
-        x, t = make_batch(net, Sm, S0, S1, ii, box, K, m)
+        x, t = make_batch(net, Sm, S0, S1, ii, box, K, m, shifts=shifts)
         out = net.forward(x, keep=False)
         g = torch.empty(out.shape, device=out.device, dtype=torch.bfloat16)
         sg.sg_mse(out, t, loss, g, scratch)
@@ -501,9 +566,10 @@ def evaluate(net, Sm, S0, S1, idx, box, K, m, batch=8):
         zero = torch.zeros_like(out)
         sg.sg_mse(zero, t, loss, g, scratch)
         tot["baseline"] += float(loss.item()) * len(ii)
-        _, tp = make_batch(net, Sm, S0, S1, ii, box, K, m, target_from="state")
-        sg.sg_mse(zero, tp, loss, g, scratch)
-        tot["persistence"] += float(loss.item()) * len(ii)
+        for name in ("transport", "state"):
+            _, tp = make_batch(net, Sm, S0, S1, ii, box, K, m, target_from=name, shifts=shifts)
+            sg.sg_mse(zero, tp, loss, g, scratch)
+            tot["transport" if name == "transport" else "persistence"] += float(loss.item()) * len(ii)
         cnt += len(ii)
     return {k: v / cnt for k, v in tot.items()}
 
@@ -526,6 +592,7 @@ class JumpConfig:
     predict_pressure: bool = False  # apply the network's pressure residual (else p follows the baseline)
     u_by_phase: bool = True     # weight velocity increments by the heavy-phase fraction
     phi_at_interface: bool = True  # weight phi increments by 4 q (1 - q): none in the bulk phases
+    accel: bool = True          # co-moving jumps follow the bubble's acceleration over the trend window
 
 
 def _traj_entry(step, st, **kw):
@@ -539,9 +606,10 @@ def _jump(net, mode, F_now, F_prev, setup, box, jc: JumpConfig, diagnostics=Fals
     """Writes the state K steps ahead into F_now ((5, nz, ny, nx) FP32 planes:
     phi, u, p) from F_now and F_prev (m steps earlier).  mode "persistence":
     unchanged; "transport": phi moved by the local velocity in the window
-    around the bubble; "projective": projective step over the whole grid;
-    "network": transport plus the network's residual (from the state and
-    its trend) in the window."""
+    around the bubble; "comoving": the window translated by K times the
+    bubble's gas-weighted velocity; "projective": projective step over the
+    whole grid; "network": the network's baseline (net.base) plus its
+    residual (from the state and its trend) in the window."""
     import torch
     nx, ny, nz = setup.nx, setup.ny, setup.nz
     N = nx * ny * nz
@@ -558,11 +626,16 @@ def _jump(net, mode, F_now, F_prev, setup, box, jc: JumpConfig, diagnostics=Fals
     base = torch.empty_like(s0)
     x = torch.empty((1, bz, by, bx, C_IN), device=F_now.device, dtype=torch.bfloat16)
     sg.sg_fields_to_input(F_now[0], F_now[1:4], F_now[4], nx, ny, nz, box, one, C_IN, x, s0)
-    sg.sg_advect_phase(s0, 1, bx, by, bz, jc.K, base)
+    kind = net.base if mode == "network" else mode
+    sm = torch.empty_like(s0)
+    sg.sg_fields_to_input(F_prev[0], F_prev[1:4], F_prev[4], nx, ny, nz, box, one, C_IN, x, sm)
+    shift = None
+    if kind == "comoving":
+        shift = comoving_shift(s0, 1, (bx, by, bz), jc.K, prev=sm if jc.accel else None, m=jc.m,
+                               phi_heavy=setup.phi_H, phi_light=setup.phi_L)[0]
+    jump_base(kind, s0, (bx, by, bz), jc.K, base, shift)
     inc = None
     if mode == "network":
-        sm = torch.empty_like(s0)
-        sg.sg_fields_to_input(F_prev[0], F_prev[1:4], F_prev[4], nx, ny, nz, box, one, C_IN, x, sm)
         sg.sg_pair_to_input(s0, sm, net.scale_in, trend_scale(net, jc.K, jc.m), C_IN, x)
         out = net.forward(x, keep=False)
         so = list(net.scale_out)
@@ -731,7 +804,7 @@ def save_weights(net, path):
         t[k + ".w"] = d["w"].detach().cpu().contiguous()
         t[k + ".b"] = d["b"].detach().cpu().contiguous()
     meta = {"scale_in": json.dumps(net.scale_in), "scale_out": json.dumps(net.scale_out),
-            "scale_trend": json.dumps(net.scale_trend), "steps": str(net.step_count)}
+            "scale_trend": json.dumps(net.scale_trend), "steps": str(net.step_count), "base": net.base}
     save_file(t, path, metadata=meta)
 
 
@@ -747,6 +820,7 @@ def load_weights(net, path):
     net.scale_out = json.loads(meta["scale_out"])
     net.scale_trend = json.loads(meta["scale_trend"])
     net.step_count = int(meta["steps"])
+    net.base = meta.get("base", "transport")
 
 
 def _cmd_train(a):
@@ -757,14 +831,18 @@ def _cmd_train(a):
     torch.cuda.synchronize()
     t_data = time.perf_counter() - t0
     net = Net(seed=a.seed)
-    net.scale_in, net.scale_out, net.scale_trend = channel_scales(Sm, S0, S1, cfg.box, cfg.K, cfg.m)
+    net.base = a.base
+    shifts = (comoving_shift(S0, S0.shape[0], cfg.box, cfg.K, prev=Sm, m=cfg.m) if a.base == "comoving"
+              else None)
+    net.scale_in, net.scale_out, net.scale_trend = channel_scales(Sm, S0, S1, cfg.box, cfg.K, cfg.m,
+                                                                  base_kind=a.base, shifts=shifts)
     res = train(net, Sm, S0, S1, cfg.box, cfg.K, cfg.m, run_of=run_of, steps=a.train_steps, batch=a.batch,
-                lr=a.lr, log=_log)
+                lr=a.lr, log=_log, shifts=shifts)
     res.update({"data_seconds": t_data, "samples": int(S0.shape[0]), "runs": meta, "config": cfg.__dict__,
                 "scale_in": net.scale_in, "scale_out": net.scale_out, "scale_trend": net.scale_trend,
                 "params": net.n_params()})
-    _log(f"[train] val loss {res['val_loss']:.4e}; transport baseline alone {res['val_loss_baseline']:.4e}; "
-         f"persistence {res['val_loss_persistence']:.4e}")
+    _log(f"[train] val loss {res['val_loss']:.4e}; {a.base} baseline alone {res['val_loss_baseline']:.4e}; "
+         f"transport {res['val_loss_transport']:.4e}; persistence {res['val_loss_persistence']:.4e}")
     if a.weights:
         save_weights(net, a.weights)
     return res
@@ -796,7 +874,8 @@ def _cmd_jump(a):
         del sv
         torch.cuda.empty_cache()
     modes = a.modes.split(",")
-    variants = [(mname, None, mname) for mname in ("persistence", "transport", "projective") if mname in modes]
+    variants = [(mname, None, mname) for mname in ("persistence", "transport", "comoving", "projective")
+                if mname in modes]
     if a.weights and "network" in modes:
         net = Net(seed=0)
         load_weights(net, a.weights)
@@ -833,6 +912,8 @@ def main():
     t.add_argument("--batch", type=int, default=8)
     t.add_argument("--lr", type=float, default=2e-4)
     t.add_argument("--seed", type=int, default=0)
+    t.add_argument("--base", default="comoving", choices=["comoving", "transport"],
+                   help="baseline whose residual the network learns")
     t.add_argument("--weights", default=None)
     t.add_argument("--out", default=None)
     j = sub.add_parser("jump")
@@ -841,7 +922,7 @@ def main():
     j.add_argument("--K", type=int, default=200)
     j.add_argument("--relax", type=int, default=50)
     j.add_argument("--m", type=int, default=25, help="trend window (<= relax, or K + relax for cycle ends)")
-    j.add_argument("--modes", default="persistence,transport,projective,network")
+    j.add_argument("--modes", default="persistence,transport,comoving,network")
     j.add_argument("--grid", default=None, help="override the grid, e.g. 128x512x128")
     j.add_argument("--D", type=float, default=None, help="bubble diameter with --grid")
     j.add_argument("--eo", type=float, default=10.0, help="Eotvos number with --grid")

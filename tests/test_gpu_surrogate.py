@@ -283,23 +283,35 @@ def test_network_gradient_against_oracle(env):
         assert abs(np.linalg.norm(gg) / np.linalg.norm(rr) - 1) < 0.1, k
 
 
-def test_trained_network_beats_the_method_without_it(env):
-    """What the learned part gains over the method without it: on held-out
-    rising-bubble runs the jump of 200 steps with the trained network
-    (transport baseline + learned residual, from the state and its recent
-    trend) has a smaller error than the transport baseline alone, which in
-    turn beats persistence (the state left as it is)."""
-    torch, sg = env
+@pytest.fixture(scope="module")
+def gain_data(env):
     from paper_2012_06144_amd import surrogate as S
     cfg = S.DataConfig(n_runs=4, grid=(64, 128, 64), d_range=(12.0, 16.0), eo_range=(5.0, 15.0), offset=4.0,
                        centre_y=40.0, steps=1400, start=200, every=50, K=200, pairs_per_run=6, box=(32, 48, 32))
     Sm, S0, S1, run_of, _ = S.generate_snapshots(cfg, log=lambda m: None)
+    return cfg, Sm, S0, S1, run_of
+
+
+@pytest.mark.parametrize("base", ["transport", "comoving"])
+def test_trained_network_beats_the_method_without_it(env, gain_data, base):
+    """What the learned part gains over the method without it: on held-out
+    rising-bubble runs the jump of 200 steps with the trained network
+    (baseline + learned residual, from the state and its recent trend) has
+    a smaller error than its baseline alone, which in turn beats
+    persistence (the state left as it is).  Baselines: phi transported by
+    the local velocity, or the whole window translated with the bubble."""
+    torch, sg = env
+    from paper_2012_06144_amd import surrogate as S
+    cfg, Sm, S0, S1, run_of = gain_data
     net = S.Net(seed=1)
-    net.scale_in, net.scale_out, net.scale_trend = S.channel_scales(Sm, S0, S1, cfg.box, cfg.K, cfg.m)
+    net.base = base
+    shifts = S.comoving_shift(S0, S0.shape[0], cfg.box, cfg.K, prev=Sm, m=cfg.m) if base == "comoving" else None
+    net.scale_in, net.scale_out, net.scale_trend = S.channel_scales(Sm, S0, S1, cfg.box, cfg.K, cfg.m,
+                                                                    base_kind=base, shifts=shifts)
     res = S.train(net, Sm, S0, S1, cfg.box, cfg.K, cfg.m, run_of=run_of, steps=150, batch=8, lr=5e-4,
-                  warmup=15, val_frac=0.25, log=print)
-    print("validation loss: network", res["val_loss"], "transport baseline alone", res["val_loss_baseline"],
-          "persistence", res["val_loss_persistence"])
+                  warmup=15, val_frac=0.25, log=print, shifts=shifts)
+    print(f"validation loss: network {res['val_loss']:.4e}, {base} baseline alone {res['val_loss_baseline']:.4e}, "
+          f"transport {res['val_loss_transport']:.4e}, persistence {res['val_loss_persistence']:.4e}")
     assert np.isfinite(res["val_loss"])
     assert res["val_loss_baseline"] < res["val_loss_persistence"]
     assert res["val_loss"] < 0.8 * res["val_loss_baseline"]
@@ -333,6 +345,58 @@ def test_advect_phase_matches_oracle(env):
 
 def conv_oracle_advect(st, K):
     return oc.advect_phase(st, K)
+
+
+def test_shift_boxes_matches_oracle(env):
+    """Co-moving baseline on three boxes with different displacements (one
+    pushing departure points out of the box) and velocity factors, FP32 on
+    the GPU vs the FP64 oracle: the departure point x - d carries at most
+    2 eps32 (max extent + |d|) cells of error, moving the value by that
+    times the largest neighbour difference, plus 8 eps32 |s| for the blend
+    and the factor, all times the largest factor."""
+    torch, sg = env
+    rng = np.random.default_rng(26)
+    n, bz, by, bx = 3, 9, 11, 13
+    st = rng.standard_normal((n, bz, by, bx, 5)).astype(np.float32)
+    d = np.array([[0.37, -1.61, 0.52, 1.0], [0.0, 0.41, 0.0, 1.37], [-3.2, 20.0, 2.75, 0.5]], dtype=np.float32)
+    ts = torch.from_numpy(st).cuda()
+    out = torch.empty_like(ts)
+    sg.sg_shift_boxes(ts, n, bx, by, bz, torch.from_numpy(d).cuda(), out)
+    torch.cuda.synchronize()
+    ref = oc.shift_boxes(st.astype(np.float64), d.astype(np.float64))
+    got = out.cpu().numpy().astype(np.float64)
+    s64 = st.astype(np.float64)
+    jump = max(np.abs(np.diff(s64, axis=a)).max() for a in (1, 2, 3))
+    bound = (2 * EPS32 * (max(bx, by, bz) + np.abs(d[:, :3]).max()) * jump + 8 * EPS32 * np.abs(s64).max()) * 1.37
+    assert np.abs(got - ref).max() <= bound
+    # an in-place call is refused
+    with pytest.raises(sg.SgError):
+        sg.sg_shift_boxes(ts, n, bx, by, bz, torch.from_numpy(d).cuda(), ts)
+
+
+def test_box_moments_matches_oracle(env):
+    """FP64 sums of FP32 inputs: |error| <= V eps64 x (sum of |terms|) per
+    entry (ordering only); phi spans beyond [0, 1] to exercise the clip."""
+    torch, sg = env
+    rng = np.random.default_rng(27)
+    n, bz, by, bx = 3, 17, 19, 21
+    st = rng.uniform(-0.1, 1.1, (n, bz, by, bx, 5)).astype(np.float32)
+    st[..., 1:4] = rng.standard_normal((n, bz, by, bx, 3)) * 1e-3
+    out = torch.zeros(n * 8, device="cuda", dtype=torch.float64)
+    sg.sg_box_moments(torch.from_numpy(st).cuda(), n, bx, by, bz, 1.0, 0.0, out)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy().reshape(n, 8)
+    ref = oc.box_moments(st.astype(np.float64), 1.0, 0.0)
+    V = bx * by * bz
+    z, y, x = np.meshgrid(np.arange(bz), np.arange(by), np.arange(bx), indexing="ij")
+    chi = np.clip(1.0 - st[..., 0].astype(np.float64), 0, 1)
+    for k in range(n):
+        c = chi[k]
+        scale = np.array([c.sum(), (c * x).sum(), (c * y).sum(), (c * z).sum(),
+                          np.abs(c * st[k, ..., 1]).sum(), np.abs(c * st[k, ..., 2]).sum(),
+                          np.abs(c * st[k, ..., 3]).sum(), 0.0])
+        assert np.all(np.abs(got[k] - ref[k]) <= 4 * V * np.finfo(np.float64).eps * scale)
+    assert np.all(got[:, 7] == 0)
 
 
 def test_channel_moments(env):
@@ -472,3 +536,43 @@ def test_apply_prediction_phi_increment_at_interface(env):
     got = phi.cpu().numpy()
     assert np.array_equal(got[:20], base[:20, 0])            # bulk phases unchanged
     assert np.allclose(got, ref, rtol=0, atol=2 * np.finfo(np.float32).eps)
+
+
+def test_jump_driver_comoving_cycles(env):
+    """Three cycles of the jump driver on a small rising bubble, started from
+    the same developed state as a plain run: every cycle is either accepted
+    or rolled back, the statistics stay finite, the phase-field mass is that
+    of the plain run (the mass projection restores it after each jump), and
+    the co-moving jump (window translated with the bubble, flow amplitude
+    following its acceleration) ends closer to the plain run's rise than
+    persistence (fields left as they are during each jump)."""
+    torch, sg = env
+    from paper_2012_06144_amd import inputs, lbm
+    from paper_2012_06144_amd import surrogate as S
+    D, Eo = 12.0, 10.0
+    s = inputs.rising_bubble(48, 96, 48, D=D, center=(24.0, 30.0, 24.0), g=Eo * 1e-4 / (D * D))
+    jc = S.JumpConfig(K=100, relax=40, m=20, box=(32, 48, 32))
+    total = jc.m + 3 * (jc.K + jc.relax)
+    sv = lbm.Solver(s.physics(), storage="f32")
+    sv.init_fields(*inputs.build_fields(s))
+    sv.step(800)
+    start = sv.new_state_buffer()
+    sv.save_state(start)
+    y0 = sv.stats()["centroid"][1]
+    sv.step(total)
+    plain = sv.stats()
+    rise_p = plain["centroid"][1] - y0
+    res = {}
+    for mode in ("persistence", "comoving"):
+        sv.restore_state(start)
+        r = S.run_with_jumps(None, sv, s, total, jc, log=print, mode=mode)
+        st = sv.stats()
+        assert r["accepted"] + r["rejected"] == 3
+        for e in r["trajectory"]:
+            assert all(np.isfinite(e[k]) for k in ("centroid_y", "rise_velocity", "mass", "xi_eff"))
+        assert abs(st["mass"] - plain["mass"]) <= 1e-5 * abs(plain["mass"])
+        res[mode] = st["centroid"][1] - y0
+    print(f"rise over {total} steps: plain {rise_p:.4f}, persistence {res['persistence']:.4f}, "
+          f"co-moving {res['comoving']:.4f} cells")
+    assert rise_p > 0
+    assert abs(res["comoving"] - rise_p) < 0.5 * abs(res["persistence"] - rise_p)

@@ -193,6 +193,90 @@ def test_advect_clamps_departure_to_the_box():
     assert np.array_equal(o[..., 0], np.broadcast_to(s[:, :, :1, 0], (4, 4, 4)))
 
 
+def test_shift_boxes_integer_shift_moves_every_channel():
+    s = _box_state(6, 7, 8, seed=4)
+    d = np.array([[1.0, -2.0, 1.0]])                 # along x, y, z
+    o = conv.shift_boxes(s, d)
+    # out[z, y, x, :] = s[z - 1, y + 2, x - 1, :]
+    assert np.array_equal(o[1:, :-2, 1:, :], s[:-1, 2:, :-1, :])
+    assert np.array_equal(conv.shift_boxes(s, np.zeros((1, 3))), s)
+    # the velocity factor scales u only
+    o2 = conv.shift_boxes(s, np.array([[1.0, -2.0, 1.0, 1.5]]))
+    assert np.array_equal(o2[..., 0], o[..., 0]) and np.array_equal(o2[..., 4], o[..., 4])
+    assert np.allclose(o2[..., 1:4], 1.5 * o[..., 1:4], rtol=1e-15, atol=0)
+
+
+def test_shift_boxes_reproduces_linear_fields_per_box():
+    """Two boxes with different non-integer displacements: every channel of
+    a linear field is translated exactly wherever the departure point lies
+    inside the box."""
+    bz, by, bx = 6, 7, 8
+    z, y, x = np.meshgrid(np.arange(bz), np.arange(by), np.arange(bx), indexing="ij")
+    rng = np.random.default_rng(5)
+    a, B = rng.standard_normal(5), rng.standard_normal((5, 3)) * 0.1
+    s = np.stack([a[k] + B[k, 0] * x + B[k, 1] * y + B[k, 2] * z for k in range(5)], axis=-1)
+    d = np.array([[0.37, -1.61, 0.52], [-0.8, 0.25, 1.3]])
+    o = conv.shift_boxes(np.stack([s, s]), d)
+    for n in range(2):
+        dx, dy, dz = d[n]
+        inside = (x - dx >= 0) & (x - dx <= bx - 1) & (y - dy >= 0) & (y - dy <= by - 1) & \
+                 (z - dz >= 0) & (z - dz <= bz - 1)
+        assert inside.sum() > 50
+        for k in range(5):
+            exact = a[k] + B[k, 0] * (x - dx) + B[k, 1] * (y - dy) + B[k, 2] * (z - dz)
+            assert np.max(np.abs(o[n, ..., k] - exact)[inside]) < 1e-13
+
+
+def _bubble_box(dims, c, R, xi, u=(0.0, 0.0, 0.0)):
+    """Box state (bz, by, bx, 5) (dims = (bx, by, bz)) with a gas bubble
+    (phi = 0 inside, 1 outside, tanh profile of width xi) centred at c
+    (x, y, z) and uniform velocity u."""
+    bx, by, bz = dims
+    z, y, x = np.meshgrid(np.arange(bz), np.arange(by), np.arange(bx), indexing="ij")
+    r = np.sqrt((x - c[0]) ** 2 + (y - c[1]) ** 2 + (z - c[2]) ** 2)
+    s = np.zeros((bz, by, bx, 5))
+    s[..., 0] = 0.5 + 0.5 * np.tanh(2.0 * (r - R) / xi)
+    s[..., 1:4] = u
+    return s
+
+
+def test_box_moments_of_a_bubble():
+    """A bubble centred on a grid point has its gas centroid there (mirror
+    symmetry); its gas volume is that of the tanh profile,
+    4/3 pi R^3 + 8 pi R (xi/2)^2 pi^2/24 (the profile is odd about r = R, so
+    only the 2 R s part of r^2 = (R + s)^2 adds, with the integral of
+    t (1 - tanh t) over t > 0 equal to pi^2/24); the gas-weighted velocity
+    of a uniform flow is that flow; phi outside [phi_light, phi_heavy]
+    counts as pure phase."""
+    R, xi = 6.0, 3.0
+    # box extents odd and the centre in the middle: each axis is mirror-symmetric
+    s = _bubble_box((27, 23, 25), (13.0, 11.0, 12.0), R, xi, u=(1e-3, -2e-3, 5e-4))
+    m = conv.box_moments(s, 1.0, 0.0)[0]
+    vol = 4.0 / 3.0 * np.pi * R ** 3 + 8.0 * np.pi * R * (xi / 2) ** 2 * np.pi ** 2 / 24
+    assert abs(m[0] - vol) < 2e-3 * vol
+    assert np.allclose(m[1:4] / m[0], [13.0, 11.0, 12.0], atol=1e-12, rtol=0)
+    assert np.allclose(m[4:7] / m[0], [1e-3, -2e-3, 5e-4], atol=1e-15, rtol=1e-13)
+    assert m[7] == 0.0
+    t = s.copy()
+    t[..., 0] = np.where(t[..., 0] < 0.5, -0.3, 1.4)  # overshoots clip to chi = 1 / 0
+    mt = conv.box_moments(t, 1.0, 0.0)[0]
+    assert mt[0] == np.count_nonzero(s[..., 0] < 0.5)
+    # phi_heavy < phi_light flips the indicator: chi counts the other phase
+    mf = conv.box_moments(s, 0.0, 1.0)[0]
+    assert abs(mf[0] + m[0] - 27 * 23 * 25) < 1e-9
+
+
+def test_shift_moves_the_gas_centroid_by_the_displacement():
+    """Linear interpolation keeps the first moment of a blob away from the
+    box edges: the centroid of the shifted box moves by exactly d."""
+    s = _bubble_box((32, 34, 30), (15.5, 17.0, 14.0), 5.0, 2.0)  # tails ~1e-10 at the box faces
+    d = np.array([[0.3, 0.41, -0.27]])
+    m0 = conv.box_moments(s, 1.0, 0.0)[0]
+    m1 = conv.box_moments(conv.shift_boxes(s, d), 1.0, 0.0)[0]
+    assert abs(m1[0] - m0[0]) < 1e-9 * m0[0]
+    assert np.allclose(m1[1:4] / m1[0] - m0[1:4] / m0[0], d[0], atol=1e-6, rtol=0)  # tails at the faces: ~1e-8
+
+
 def test_projective_step_exact_for_fields_linear_in_time():
     """s(t) = a + b t for every channel: the projective step from s(t - m)
     and s(t) lands exactly on s(t + K) (u unweighted, p stepped, phi inside
