@@ -179,6 +179,20 @@ lbm_status lbm_get_macroscopic(lbm_ctx *ctx, int32_t dtype, void *phi, void *u, 
 lbm_status lbm_set_macroscopic(lbm_ctx *ctx, int32_t dtype, const void *phi, const void *u,
                                const void *p);
 
+/* Moves the state to the given macroscopic fields (device arrays as in
+ * lbm_set_macroscopic) while keeping every population's non-equilibrium
+ * part: each population gains the change of its equilibrium (the
+ * equilibria of Section 3: h^eq = phi Gamma(u), g^eq(p*, u)),
+ *   H_i += phi' Gamma_i(u') - phi Gamma_i(u),
+ *   G_i += g^eq_i(p*', u') - g^eq_i(p*, u)   (canonical pre-collision G),
+ * where phi, u are the current fields, p* = sum_i G_i the current
+ * normalised pressure and p*' = p'/(rho(phi') c_s^2).  Unlike
+ * lbm_set_macroscopic, the viscous stress and the interface flux carried by
+ * the populations survive, so no start-up transient follows.  Wall cells
+ * are unchanged.  Requires an initialised state; asynchronous. */
+lbm_status lbm_shift_equilibrium(lbm_ctx *ctx, int32_t dtype, const void *phi, const void *u,
+                                 const void *p);
+
 /* Canonical state as FP64 device arrays, independent of the storage format:
  * H = post-collision phase-field PDFs (15 planes, not yet streamed),
  * G = pre-collision hydrodynamic PDFs (27 planes, already streamed).  The

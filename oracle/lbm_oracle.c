@@ -669,6 +669,40 @@ void orc_set_state(orc_state *s, const double *H, const double *G, const double 
     if (u) memcpy(s->u, u, sizeof(double) * 3 * n);
 }
 
+/* Moves the state to new macroscopic fields phi', u' and pressure p'
+ * keeping each population's non-equilibrium part (its distance from the
+ * equilibria of Section 3): in every fluid cell
+ *   H_i += phi' Gamma_i(u') - phi Gamma_i(u),
+ *   G_i += g^eq_i(p*', u') - g^eq_i(p*, u),
+ * with phi, u the current phase field and velocity, p* = sum_i G_i and
+ * p*' = p' / (rho(phi') cs^2); then phi_A = phi', u = u'.  Wall cells are
+ * unchanged.                                                            */
+void orc_shift_equilibrium(orc_state *s, const double *phi, const double *u, const double *pres)
+{
+    const orc_params *p = &s->p;
+    const int64_t n = s->n;
+    for (int z = 0; z < p->nz; ++z)
+        for (int y = 0; y < p->ny; ++y)
+            for (int x = 0; x < p->nx; ++x) {
+                if (is_wall_row(p, y)) continue;
+                const int64_t c = cidx(p, x, y, z);
+                const double u0[3] = {s->u[c], s->u[n + c], s->u[2 * n + c]};
+                const double u1[3] = {u[c], u[n + c], u[2 * n + c]};
+                const double phi0 = s->phiA[c], phi1 = phi[c];
+                for (int i = 0; i < Q15; ++i)
+                    s->H[i * n + c] += phi1 * gamma_i(E15[i], W15[i], u1) - phi0 * gamma_i(E15[i], W15[i], u0);
+                double ps0 = 0.0;
+                for (int i = 0; i < Q27; ++i) ps0 += s->G[i * n + c];
+                const double ps1 = pres[c] / (density_of(p, phi1) * CS2);
+                double e0[Q27], e1[Q27];
+                hydro_equilibrium(ps0, u0, e0);
+                hydro_equilibrium(ps1, u1, e1);
+                for (int i = 0; i < Q27; ++i) s->G[i * n + c] += e1[i] - e0[i];
+                s->phiA[c] = phi1;
+                for (int a = 0; a < 3; ++a) s->u[a * n + c] = u1[a];
+            }
+}
+
 /* Pressure p = p* rho cs^2 with p* = sum_i g_i (Section 3.2). */
 void orc_pressure(const orc_state *s, double *pout)
 {

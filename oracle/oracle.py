@@ -77,6 +77,7 @@ def lib():
     L.orc_get_state.argtypes = [C.c_void_p] + [C.c_void_p] * 4
     L.orc_set_state.argtypes = [C.c_void_p] + [C.c_void_p] * 4
     L.orc_pressure.argtypes = [C.c_void_p, _D]
+    L.orc_shift_equilibrium.argtypes = [C.c_void_p, _D, _D, _D]
     L.orc_stats_compute.argtypes = [C.c_void_p, C.POINTER(OrcStats)]
     L.orc_num_threads.argtypes = []
     L.orc_num_threads.restype = C.c_int
@@ -230,6 +231,14 @@ class Oracle:
         arrs = [np.ascontiguousarray(a, dtype=np.float64) if a is not None else None
                 for a in (H, G, phi, u)]
         lib().orc_set_state(self._h, *[_ptr(a) for a in arrs])
+
+    def shift_equilibrium(self, phi, u, p):
+        """Moves the state to the fields (phi, u, pressure p) keeping every
+        population's non-equilibrium part."""
+        phi = np.ascontiguousarray(phi, dtype=np.float64).reshape(self.shape)
+        u = np.ascontiguousarray(u, dtype=np.float64).reshape((3,) + self.shape)
+        p = np.ascontiguousarray(p, dtype=np.float64).reshape(self.shape)
+        lib().orc_shift_equilibrium(self._h, phi, u, p)
 
     def pressure(self):
         p = np.zeros(self.shape)

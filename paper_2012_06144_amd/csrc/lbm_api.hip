@@ -249,6 +249,22 @@ struct Ops {
         return LBM_OK;
     }
 
+    template <class In>
+    static lbm_status shift_equilibrium(lbm_ctx *c, const In *phi_in, const In *u_in, const In *p_in)
+    {
+        const int a = c->cur, b = 1 - c->cur;
+        const Phys<R> ph = make_phys<R>(&c->p);
+        hipLaunchKernelGGL((k_shift_eq_g<S, In>), dim3(blocks(c)), dim3(kBlock), 0, c->stream, G(c, a), G(c, b),
+                           u(c), phi_in, u_in, p_in, c->g, ph);
+        LAUNCH_CHECK();
+        hipLaunchKernelGGL((k_unpull27<S>), dim3(blocks(c)), dim3(kBlock), 0, c->stream, G(c, b), G(c, a), c->g);
+        LAUNCH_CHECK();
+        hipLaunchKernelGGL((k_shift_eq_h<S, In>), dim3(blocks(c)), dim3(kBlock), 0, c->stream, H(c, a), phi(c, a),
+                           u(c), phi_in, u_in, c->g);
+        LAUNCH_CHECK();
+        return LBM_OK;
+    }
+
     static lbm_status step(lbm_ctx *c, int n)
     {
         const Phys<R> ph = make_phys<R>(&c->p);
@@ -399,6 +415,15 @@ template <class S> struct DoSetMacro {
             return Ops<S>::template equilibrium<double>(c, (const double *)phi, (const double *)u,
                                                         (const double *)p, 1);
         return Ops<S>::template equilibrium<float>(c, (const float *)phi, (const float *)u, (const float *)p, 1);
+    }
+};
+template <class S> struct DoShiftEq {
+    static lbm_status run(lbm_ctx *c, int dtype, const void *phi, const void *u, const void *p)
+    {
+        if (dtype == LBM_DTYPE_F64)
+            return Ops<S>::template shift_equilibrium<double>(c, (const double *)phi, (const double *)u,
+                                                              (const double *)p);
+        return Ops<S>::template shift_equilibrium<float>(c, (const float *)phi, (const float *)u, (const float *)p);
     }
 };
 template <class S> struct DoGetMacro {
@@ -574,6 +599,15 @@ lbm_status lbm_set_macroscopic(lbm_ctx *c, int32_t dtype, const void *phi, const
     if (dtype != LBM_DTYPE_F64 && dtype != LBM_DTYPE_F32) return fail(LBM_EARG, "unknown dtype %d", dtype);
     if (!phi || !u || !p) return fail(LBM_EARG, "NULL field pointer");
     return dispatch<DoSetMacro>(c->p.storage, c, (int)dtype, phi, u, p);
+}
+
+lbm_status lbm_shift_equilibrium(lbm_ctx *c, int32_t dtype, const void *phi, const void *u, const void *p)
+{
+    lbm_status s = check_ctx(c, true);
+    if (s != LBM_OK) return s;
+    if (dtype != LBM_DTYPE_F64 && dtype != LBM_DTYPE_F32) return fail(LBM_EARG, "unknown dtype %d", dtype);
+    if (!phi || !u || !p) return fail(LBM_EARG, "NULL field pointer");
+    return dispatch<DoShiftEq>(c->p.storage, c, (int)dtype, phi, u, p);
 }
 
 lbm_status lbm_get_pdfs(lbm_ctx *c, double *H, double *G)

@@ -888,7 +888,6 @@ __global__ __launch_bounds__(kBlock) void k_get_pdfs(const typename S::pdf_t *__
                                                      double *__restrict__ Ho, double *__restrict__ Go,
                                                      Grid g, Phys<typename S::real> ph)
 {
-    using R = typename S::real;
     const int c = blockIdx.x * kBlock + threadIdx.x;
     if (c >= g.ncells) return;
     const int64_t N = g.ncells;
@@ -932,6 +931,81 @@ __global__ __launch_bounds__(kBlock) void k_set_pdfs(typename S::pdf_t *__restri
     for (int i = 0; i < 27; ++i) Gc[pdf_index<S, 27>(i, c, g)] = enc_g<S>(wall ? R(0) : R(Gi[i * N + c]), i);
     phiA[c] = wall ? R(0) : R(phi_i[c]);
     for (int k = 0; k < 3; ++k) u[k * g.fplane + c] = wall ? R(0) : R(u_i[k * N + c]);
+}
+
+// Moving the state to new macroscopic fields (phi', u', p') while keeping
+// every population's non-equilibrium part: the populations gain the change
+// of their equilibria, h_i += phi' Gamma_i(u') - phi Gamma_i(u) and
+// g_i += g^eq_i(p*', u') - g^eq_i(p*, u), with phi, u the stored fields and
+// p* = sum_i g_i.  First the canonical pre-collision G (pulled, as in the
+// hydrodynamic sweep) with its increment into Gc, which k_unpull27 turns
+// back into the stored form; it reads the old u, so it runs before
+// k_shift_eq_h.  Wall cells are left as they are.
+template <class S, class In>
+__global__ __launch_bounds__(kBlock) void k_shift_eq_g(const typename S::pdf_t *__restrict__ G,
+                                                       typename S::pdf_t *__restrict__ Gc,
+                                                       const typename S::real *__restrict__ u,
+                                                       const In *__restrict__ phi_in, const In *__restrict__ u_in,
+                                                       const In *__restrict__ p_in, Grid g,
+                                                       Phys<typename S::real> ph)
+{
+    using R = typename S::real;
+    const int c = blockIdx.x * kBlock + threadIdx.x;
+    if (c >= g.ncells) return;
+    int x, y, z;
+    Nbr n;
+    if (!decode(g, c, x, y, z, n)) return;
+    const int64_t N = g.ncells;
+    R gc[27], ps = R(0);
+#pragma unroll
+    for (int i = 0; i < 27; ++i) {
+        gc[i] = dec_g<S>(G[pull_idx<S, 27>(i, c, n, g)], i);
+        ps += gc[i];
+    }
+    const R ux = u[c], uy = u[g.fplane + c], uz = u[2 * g.fplane + c];
+    const R uu = ux * ux + uy * uy + uz * uz;
+    const R vx = R(u_in[c]), vy = R(u_in[N + c]), vz = R(u_in[2 * N + c]);
+    const R vv = vx * vx + vy * vy + vz * vz;
+    const R qs = R(p_in[c]) / (density_of(ph, R(phi_in[c])) * cs2<R>());
+#pragma unroll
+    for (int i = 0; i < 27; ++i) {
+        const R gn = gc[i] + (geq_i<R>(i, qs, vx, vy, vz, vv) - geq_i<R>(i, ps, ux, uy, uz, uu));
+        Gc[pdf_index<S, 27>(i, c, g)] = enc_g<S>(gn, i);
+    }
+}
+
+// Second part of the move: h (post-collision, stored at the cell) gains the
+// change of phi Gamma(u); then phi_A and u take the new values.
+template <class S, class In>
+__global__ __launch_bounds__(kBlock) void k_shift_eq_h(typename S::pdf_t *__restrict__ H,
+                                                       typename S::real *__restrict__ phiA,
+                                                       typename S::real *__restrict__ u,
+                                                       const In *__restrict__ phi_in, const In *__restrict__ u_in,
+                                                       Grid g)
+{
+    using R = typename S::real;
+    const int c = blockIdx.x * kBlock + threadIdx.x;
+    if (c >= g.ncells) return;
+    const int y = (c / g.nx) % g.ny;
+    if (g.walls && (y == 0 || y == g.ny - 1)) return;
+    const int64_t N = g.ncells;
+    const R phi = phiA[c];
+    const R ux = u[c], uy = u[g.fplane + c], uz = u[2 * g.fplane + c];
+    const R uu = ux * ux + uy * uy + uz * uz;
+    const R phn = R(phi_in[c]);
+    const R vx = R(u_in[c]), vy = R(u_in[N + c]), vz = R(u_in[2 * N + c]);
+    const R vv = vx * vx + vy * vy + vz * vz;
+#pragma unroll
+    for (int i = 0; i < 15; ++i) {
+        const int64_t k = pdf_index<S, 15>(i, c, g);
+        const R h = dec_h<S>(H[k], phi, i) +
+                    (phn * gamma_i<15, R>(i, vx, vy, vz, vv) - phi * gamma_i<15, R>(i, ux, uy, uz, uu));
+        H[k] = enc_h<S>(h, phn, i);
+    }
+    phiA[c] = phn;
+    u[c] = vx;
+    u[g.fplane + c] = vy;
+    u[2 * g.fplane + c] = vz;
 }
 
 template <class S, class Out>

@@ -26,7 +26,7 @@ DTYPE_F64, DTYPE_F32 = 0, 1
 EXPORTS = [
     "lbm_velocity_set", "lbm_workspace_bytes", "lbm_create", "lbm_set_stream", "lbm_init_fields",
     "lbm_step", "lbm_step_timed", "lbm_reduce_mass", "lbm_reduce_stats", "lbm_get_macroscopic",
-    "lbm_set_macroscopic", "lbm_get_pdfs", "lbm_set_pdfs", "lbm_stream_copy", "lbm_steps_done",
+    "lbm_set_macroscopic", "lbm_shift_equilibrium", "lbm_get_pdfs", "lbm_set_pdfs", "lbm_stream_copy", "lbm_steps_done",
     "lbm_state_bytes", "lbm_save_state", "lbm_restore_state", "lbm_destroy", "lbm_last_error",
 ]
 
@@ -78,6 +78,7 @@ def _load():
         "lbm_reduce_stats": ([vp, C.POINTER(LbmStats)], C.c_int),
         "lbm_get_macroscopic": ([vp, C.c_int32, vp, vp, vp], C.c_int),
         "lbm_set_macroscopic": ([vp, C.c_int32, vp, vp, vp], C.c_int),
+        "lbm_shift_equilibrium": ([vp, C.c_int32, vp, vp, vp], C.c_int),
         "lbm_get_pdfs": ([vp, vp, vp], C.c_int),
         "lbm_set_pdfs": ([vp, vp, vp, vp, vp], C.c_int),
         "lbm_stream_copy": ([vp, vp, C.c_size_t, vp], C.c_int),
@@ -174,6 +175,10 @@ def lbm_get_macroscopic(ctx, dtype: int, phi, u, p):
 
 def lbm_set_macroscopic(ctx, dtype: int, phi, u, p):
     _check(_lib.lbm_set_macroscopic(ctx, dtype, _ptr(phi), _ptr(u), _ptr(p)), "lbm_set_macroscopic")
+
+
+def lbm_shift_equilibrium(ctx, dtype: int, phi, u, p):
+    _check(_lib.lbm_shift_equilibrium(ctx, dtype, _ptr(phi), _ptr(u), _ptr(p)), "lbm_shift_equilibrium")
 
 
 def lbm_get_pdfs(ctx, H, G):
@@ -300,11 +305,15 @@ class Solver:
         lbm_get_macroscopic(self.ctx, code, phi, u, p)
         return phi, u, p
 
-    def set_macroscopic(self, phi, u, p):
+    def set_macroscopic(self, phi, u, p, keep_neq=False):
+        """Equilibrium state of the fields (lbm_set_macroscopic), or with
+        keep_neq the current state moved to them with every population's
+        non-equilibrium part kept (lbm_shift_equilibrium)."""
         t = self.torch
         dtype = phi.dtype if hasattr(phi, "dtype") and phi.dtype in (t.float32, t.float64) else t.float64
         code = DTYPE_F64 if dtype == t.float64 else DTYPE_F32
-        lbm_set_macroscopic(self.ctx, code, phi.contiguous(), u.contiguous(), p.contiguous())
+        fn = lbm_shift_equilibrium if keep_neq else lbm_set_macroscopic
+        fn(self.ctx, code, phi.contiguous(), u.contiguous(), p.contiguous())
 
     def pdfs(self):
         t = self.torch

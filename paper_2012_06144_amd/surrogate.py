@@ -371,35 +371,47 @@ def _moments(a, rows, scratch, out):
 PHI_HEAVY, PHI_LIGHT = 1.0, 0.0      # phase-field values of liquid and gas in the rising-bubble runs
 
 
-def _gas_velocity(states, count, box, phi_heavy, phi_light):
-    """Gas volume and gas-weighted velocity sum(chi u) / sum(chi) of each of
-    `count` box states (sg_box_moments, FP64), as numpy arrays."""
+def _gas_moments(states, count, box, phi_heavy, phi_light):
+    """Gas volume, centroid (box coordinates) and gas-weighted velocity
+    sum(chi u) / sum(chi) of each of `count` box states (sg_box_moments,
+    FP64), as numpy arrays."""
     import torch
     bx, by, bz = box
     mom = torch.empty(count * 8, device=states.device, dtype=torch.float64)
     sg.sg_box_moments(states, count, bx, by, bz, phi_heavy, phi_light, mom)
     M = mom.view(count, 8).cpu().numpy()
     vol = M[:, 0]
-    return vol, M[:, 4:7] / np.maximum(vol, 1e-30)[:, None]
+    inv = 1.0 / np.maximum(vol, 1e-30)[:, None]
+    return vol, M[:, 1:4] * inv, M[:, 4:7] * inv
 
 
 def comoving_shift(states, count, box, K, prev=None, m=None, phi_heavy=PHI_HEAVY, phi_light=PHI_LIGHT,
-                   max_gain=0.5):
+                   max_gain=0.02, velocity="gas"):
     """Co-moving jump of each of `count` box states (contiguous, 5 FP32
-    channels per voxel) over K steps: the bubble's gas-weighted velocity U
-    and, given the same boxes `prev` m steps earlier, its acceleration
-    a = (U - U_prev) / m give the displacement d = K U + K^2 a / 2 and the
+    channels per voxel) over K steps.  velocity="gas": the bubble's
+    gas-weighted velocity U and, given the same boxes `prev` m steps
+    earlier, its acceleration a = (U - U_prev) / m give the displacement
+    d = K U + K^2 a / 2 (the acceleration term at most K |U| / 2) and the
     velocity factor f = 1 + K a.U / |U|^2 (the flow around the bubble keeps
-    its shape and grows with U), f clipped to 1 +- max_gain.  Returns a
-    (count, 4) FP32 device tensor of rows (dx, dy, dz, f); a box without
-    gas stays put."""
+    its shape and grows with U), f clipped to 1 +- max_gain.
+    velocity="centroid": U is the displacement of the gas centroid since
+    `prev` over m, and f = 1.  Returns a (count, 4) FP32 device tensor of
+    rows (dx, dy, dz, f); a box without gas stays put."""
     import torch
-    vol, U = _gas_velocity(states, count, box, phi_heavy, phi_light)
+    vol, cen, U = _gas_moments(states, count, box, phi_heavy, phi_light)
     a = np.zeros_like(U)
     if prev is not None:
-        vol_p, Up = _gas_velocity(prev, count, box, phi_heavy, phi_light)
-        a = np.where((vol_p > 0.5)[:, None], (U - Up) / float(m), 0.0)
-    d = K * U + 0.5 * K * K * a
+        vol_p, cen_p, Up = _gas_moments(prev, count, box, phi_heavy, phi_light)
+        has = (vol_p > 0.5)[:, None]
+        if velocity == "centroid":
+            U = np.where(has, (cen - cen_p) / float(m), U)
+        else:
+            a = np.where(has, (U - Up) / float(m), 0.0)
+    acc = 0.5 * K * K * a
+    lim = 0.5 * K * np.linalg.norm(U, axis=1, keepdims=True)
+    nacc = np.linalg.norm(acc, axis=1, keepdims=True)
+    acc = np.where(nacc > lim, acc * lim / np.maximum(nacc, 1e-300), acc)
+    d = K * U + acc
     uu = (U * U).sum(1)
     f = 1.0 + K * np.where(uu > 0, (a * U).sum(1) / np.maximum(uu, 1e-300), 0.0)
     f = np.clip(f, 1.0 - max_gain, 1.0 + max_gain)
@@ -592,7 +604,14 @@ class JumpConfig:
     predict_pressure: bool = False  # apply the network's pressure residual (else p follows the baseline)
     u_by_phase: bool = True     # weight velocity increments by the heavy-phase fraction
     phi_at_interface: bool = True  # weight phi increments by 4 q (1 - q): none in the bulk phases
-    accel: bool = True          # co-moving jumps follow the bubble's acceleration over the trend window
+    accel: bool = True          # co-moving jumps use the state of the trend window (acceleration or
+                                # centroid displacement, see comoving_shift)
+    velocity: str = "gas"       # bubble velocity of co-moving jumps: "gas" (gas-weighted u) or "centroid"
+    max_gain: float = 0.02      # co-moving velocity factor limited to 1 +- max_gain
+    keep_neq: bool = False      # after a jump keep the populations' non-equilibrium parts
+                                # (lbm_shift_equilibrium) instead of rebuilding them at equilibrium;
+                                # they stay at their cells while the interface moves, which
+                                # destabilised long runs at a density ratio of 1000
 
 
 def _traj_entry(step, st, **kw):
@@ -632,7 +651,8 @@ def _jump(net, mode, F_now, F_prev, setup, box, jc: JumpConfig, diagnostics=Fals
     shift = None
     if kind == "comoving":
         shift = comoving_shift(s0, 1, (bx, by, bz), jc.K, prev=sm if jc.accel else None, m=jc.m,
-                               phi_heavy=setup.phi_H, phi_light=setup.phi_L)[0]
+                               phi_heavy=setup.phi_H, phi_light=setup.phi_L, max_gain=jc.max_gain,
+                               velocity=jc.velocity)[0]
     jump_base(kind, s0, (bx, by, bz), jc.K, base, shift)
     inc = None
     if mode == "network":
@@ -660,7 +680,10 @@ def run_with_jumps(net, solver, setup, total_steps, jc: JumpConfig, log=print, m
     its end.  After each cycle the indicators are checked (finite, mass drift
     over the cycle <= mass_tol, interface width in [xi_lo, xi_hi] xi, max |u|
     <= u_max); if one trips, the state saved before the jump is restored and
-    the cycle's K + relax steps are run with the plain LBM."""
+    the cycle's K + relax steps are run with the plain LBM.  The jumped
+    fields enter the solver through lbm_shift_equilibrium (populations keep
+    their non-equilibrium parts) or, with jc.keep_neq False, are rebuilt at
+    equilibrium."""
     import torch
     nx, ny, nz = setup.nx, setup.ny, setup.nz
     shape = (5, nz, ny, nx)
@@ -692,7 +715,7 @@ def run_with_jumps(net, solver, setup, total_steps, jc: JumpConfig, log=print, m
             F_keep.copy_(F_now)
         inc = _jump(net, mode, F_now, F_prev, setup, box, jc, diagnostics=len(traj) <= 4)
         sg.sg_mass_project(F_now[0], m0, setup.phi_L, setup.phi_H, scratch)
-        solver.set_macroscopic(F_now[0], F_now[1:4], F_now[4])
+        solver.set_macroscopic(F_now[0], F_now[1:4], F_now[4], keep_neq=jc.keep_neq)
         torch.cuda.synchronize()
         t_jump += time.perf_counter() - tp
         if across:
@@ -825,7 +848,7 @@ def load_weights(net, path):
 
 def _cmd_train(a):
     import torch
-    cfg = DataConfig(n_runs=a.runs, steps=a.lbm_steps, pairs_per_run=a.pairs_per_run)
+    cfg = DataConfig(n_runs=a.runs, steps=a.lbm_steps, pairs_per_run=a.pairs_per_run, m=a.m)
     t0 = time.perf_counter()
     Sm, S0, S1, run_of, meta = generate_snapshots(cfg, log=_log)
     torch.cuda.synchronize()
@@ -870,7 +893,8 @@ def _cmd_jump(a):
     else:
         sv = lbm.Solver(s.physics(), storage="f32")
         sv.init_fields(phi, u, ps)
-        out["runs"]["plain"] = run_plain(sv, a.steps, jc.K + jc.relax, first=jc.m, log=_log)
+        # statistics every plain_every steps, so that runs with other cycles find common steps
+        out["runs"]["plain"] = run_plain(sv, a.steps, a.plain_every, log=_log)
         del sv
         torch.cuda.empty_cache()
     modes = a.modes.split(",")
@@ -881,6 +905,10 @@ def _cmd_jump(a):
         load_weights(net, a.weights)
         variants.append(("surrogate", net, "network"))
     jc.predict_pressure = bool(a.predict_pressure)
+    jc.velocity = a.velocity
+    jc.max_gain = a.max_gain
+    jc.accel = not a.no_accel
+    jc.keep_neq = bool(a.keep_neq)
     jc.phi_at_interface = not a.no_phi_at_interface
     for name, net, mode in variants:
         sv = lbm.Solver(s.physics(), storage="f32")
@@ -912,6 +940,7 @@ def main():
     t.add_argument("--batch", type=int, default=8)
     t.add_argument("--lr", type=float, default=2e-4)
     t.add_argument("--seed", type=int, default=0)
+    t.add_argument("--m", type=int, default=25, help="steps between the trend states (<= 400)")
     t.add_argument("--base", default="comoving", choices=["comoving", "transport"],
                    help="baseline whose residual the network learns")
     t.add_argument("--weights", default=None)
@@ -930,6 +959,12 @@ def main():
     j.add_argument("--predict-pressure", action="store_true")
     j.add_argument("--plain-from", default=None, help="reuse the plain run of an earlier study (same setup)")
     j.add_argument("--no-phi-at-interface", action="store_true")
+    j.add_argument("--plain-every", type=int, default=25, help="statistics cadence of the plain run")
+    j.add_argument("--velocity", default="gas", choices=["gas", "centroid"], help="co-moving jump velocity")
+    j.add_argument("--max-gain", type=float, default=0.02, help="co-moving velocity factor limit")
+    j.add_argument("--no-accel", action="store_true", help="co-moving jumps without the trend window")
+    j.add_argument("--keep-neq", action="store_true",
+                   help="keep the populations' non-equilibrium parts after a jump (default: rebuild at equilibrium)")
     j.add_argument("--out", default=None)
     a = ap.parse_args()
     res = _cmd_train(a) if a.cmd == "train" else _cmd_jump(a)

@@ -171,6 +171,20 @@ def _ulp(v, fmt):
     return 2.0 ** (e - mant)
 
 
+def _w(q):
+    return orc.velocity_set(q)[1].reshape(q, 1, 1, 1)
+
+
+def _lowp_bounds(ost, gst, tol, fmt):
+    """Per-population bounds for 16-bit storage of h_i - phi w_i and g_i / w_i:
+    half an ulp of the stored value (in stored units), the FP32 bound and
+    the FP32 rounding of the decode."""
+    shift = gst[2][None] * _w(15)            # the GPU's new phi times w_i
+    bound_H = 0.5 * _ulp(ost[0] - shift, fmt) + tol[0] + EPS32 * (np.abs(ost[0]) + np.abs(shift))
+    bound_G = 0.5 * _ulp(ost[1] / _w(27), fmt) * _w(27) + tol[1] + EPS32 * np.abs(ost[1])
+    return bound_H, bound_G
+
+
 LOWP_GRIDS = {
     # odd nz: one-cell-per-thread sweeps on the paired storage layout
     "ragged_walls_bubble": SMALL["ragged_walls_bubble"],
@@ -196,17 +210,10 @@ def test_one_step_low_precision_small(lbm, fmt, grid):
     g.step(1)
     ost, gst = o.state(), g.state()
     tol = _fp32_tolerances(ost, src)
-    _, w15 = orc.velocity_set(15)
-    _, w27 = orc.velocity_set(27)
-    w15 = w15.reshape(15, 1, 1, 1)
-    w27 = w27.reshape(27, 1, 1, 1)
-    shift = gst[2][None] * w15           # the GPU's new phi times w_i
-    half_ulp = 0.5 * _ulp(ost[0] - shift, fmt)
-    bound_H = half_ulp + tol[0] + EPS32 * (np.abs(ost[0]) + np.abs(shift))
+    bound_H, bound_G = _lowp_bounds(ost, gst, tol, fmt)
     # the rest population closes sum(h) = phi on the decoded values of the
     # other 14, so it carries their rounding too
-    bound_H[0] += half_ulp[1:].sum(axis=0) + 15 * EPS32 * np.abs(gst[2])
-    bound_G = 0.5 * _ulp(ost[1] / w27, fmt) * w27 + tol[1] + EPS32 * np.abs(ost[1])
+    bound_H[0] += 0.5 * _ulp(ost[0][1:] - gst[2][None] * _w(15)[1:], fmt).sum(axis=0) + 15 * EPS32 * np.abs(gst[2])
     fluid = np.ones(s.shape, dtype=bool)
     if s.walls_y:
         fluid[:, 0, :] = fluid[:, -1, :] = False
@@ -239,6 +246,51 @@ def test_paired_sweeps_match_per_cell_sweeps(lbm, fmt, grid, monkeypatch):
         states.append(g.state())
     for a, b in zip(*states):
         assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16s", "bf16s"])
+@pytest.mark.parametrize("case", ["ragged_walls_bubble", "walls_bubble_even_nz", "periodic_droplet"])
+def test_shift_equilibrium_matches_oracle(lbm, storage, case):
+    """Moving a developed state to perturbed macroscopic fields with the
+    non-equilibrium parts kept (lbm_shift_equilibrium) against the oracle
+    applied to the GPU's own canonical state: FP64 to rounding, FP32 within
+    the FP32 bounds of the sweeps, 16-bit within half an ulp of the stored
+    format on top."""
+    import torch
+    s = (LOWP_GRIDS[case] if case in LOWP_GRIDS else SMALL[case])()
+    _say(f"[gpu] shift_equilibrium {storage} {case} {s.shape}")
+    o, g = _pair(lbm, s, storage=storage)
+    g.step(5)
+    src = g.state()
+    o.set_state(*src)
+    rng = np.random.default_rng(41)
+    phi1 = src[2] + 0.02 * rng.standard_normal(s.shape)
+    u1 = src[3] + 1e-3 * rng.standard_normal((3,) + s.shape)
+    p1 = o.pressure() + 1e-4 * rng.standard_normal(s.shape)
+    o.shift_equilibrium(phi1, u1, p1)
+    ost = o.state()
+    dt = torch.float64 if storage == "f64" else torch.float32
+    if dt == torch.float32:                  # the oracle sees the fields the GPU is given
+        phi1, u1, p1 = (a.astype(np.float32).astype(np.float64) for a in (phi1, u1, p1))
+        o.set_state(*src)
+        o.shift_equilibrium(phi1, u1, p1)
+        ost = o.state()
+    g.set_macroscopic(*(torch.from_numpy(a).to(dt).cuda() for a in (phi1, u1, p1)), keep_neq=True)
+    gst = g.state()
+    d = _maxdiff(ost, gst)
+    _say(f"  max|dH|,|dG|,|dphi|,|du| = {d}")
+    if storage == "f64":
+        assert max(d) <= 1e-14, d
+        return
+    tol = _fp32_tolerances(ost, src)
+    if storage == "f32":
+        assert all(x <= t for x, t in zip(d, tol)), (d, tol)
+        return
+    # the source state holds the decoded stored values, so the move rounds once
+    bound_H, bound_G = _lowp_bounds(ost, gst, tol, storage)
+    assert np.all(np.abs(gst[0] - ost[0]) <= bound_H)
+    assert np.all(np.abs(gst[1] - ost[1]) <= bound_G)
+    assert d[2] <= tol[2] and d[3] <= tol[3]
 
 
 def test_stream_copy(lbm):

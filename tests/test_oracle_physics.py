@@ -339,3 +339,67 @@ def test_density_stays_between_the_phases_in_a_bubble_core():
         u_max = max(u_max, float(np.sqrt((uu ** 2).sum(0)).max()))
     assert phi_min < -5e-4          # the undershoot happens
     assert u_max < 1e-2             # and does not drive the light fluid
+
+
+def test_shift_equilibrium_of_an_equilibrium_state_is_the_new_equilibrium():
+    """A state at equilibrium has no non-equilibrium part: moving it to new
+    fields gives exactly the equilibrium state of those fields (orc_init with
+    p* = p / (rho cs^2)), walls untouched."""
+    s = inputs.rising_bubble(9, 12, 7, D=5.0, center=(4.0, 5.0, 3.0), g=1e-5).with_grid(9, 12, 7, noise=1e-4)
+    P = orc.Params(**s.physics())
+    phi0, u0, ps0 = inputs.build_fields(s)
+    a = orc.Oracle(P)
+    a.init(phi0, u0, ps0)
+    rng = np.random.default_rng(5)
+    phi1 = phi0 + 0.05 * rng.standard_normal(phi0.shape)
+    u1 = u0 + 1e-3 * rng.standard_normal(u0.shape)
+    ps1 = 1e-3 * rng.standard_normal(phi0.shape)
+    lo, hi = min(s.phi_L, s.phi_H), max(s.phi_L, s.phi_H)
+    rho1 = s.rho_L + (np.clip(phi1, lo, hi) - s.phi_L) * (s.rho_H - s.rho_L) / (s.phi_H - s.phi_L)
+    a.shift_equilibrium(phi1, u1, ps1 * rho1 / 3.0)
+    b = orc.Oracle(P)
+    b.init(phi1, u1, ps1)
+    fluid = np.ones(phi0.shape, dtype=bool)
+    fluid[:, 0, :] = fluid[:, -1, :] = False
+    for x, y in zip(a.state(), b.state()):
+        if x.ndim == 4:
+            x, y = x[:, fluid], y[:, fluid]
+        else:
+            x, y = x[fluid], y[fluid]
+        assert np.abs(x - y).max() <= 1e-15
+
+
+def test_shift_equilibrium_moments_and_identity():
+    """On a developed state: moving to the current fields changes nothing
+    (to rounding); moving to new fields gives sum_i G_i = p*' and
+    sum_i G_i e_i = j + (u' - u) (the equilibrium moments of Section 3),
+    sum_i H_i changes by phi' - phi, and phi_A, u take the new values."""
+    s = inputs.rising_bubble(9, 12, 7, D=5.0, center=(4.0, 5.0, 3.0), g=1e-5).with_grid(9, 12, 7, noise=1e-4)
+    P = orc.Params(**s.physics())
+    o = orc.Oracle(P)
+    o.init(*inputs.build_fields(s))
+    o.step(6)
+    H0, G0, phi0, u0 = o.state()
+    p0 = o.pressure()
+    o.shift_equilibrium(phi0, u0, p0)
+    for x, y in zip(o.state(), (H0, G0, phi0, u0)):
+        assert np.abs(x - y).max() <= 1e-16
+    rng = np.random.default_rng(6)
+    phi1 = phi0 + 0.05 * rng.standard_normal(phi0.shape)
+    u1 = u0 + 1e-3 * rng.standard_normal(u0.shape)
+    p1 = p0 + 1e-4 * rng.standard_normal(p0.shape)
+    o.set_state(H0, G0, phi0, u0)
+    o.shift_equilibrium(phi1, u1, p1)
+    H1, G1, phi_a, u_a = o.state()
+    e27, _ = orc.velocity_set(27)
+    fl = np.ones(phi0.shape, dtype=bool)
+    fl[:, 0, :] = fl[:, -1, :] = False
+    lo, hi = min(s.phi_L, s.phi_H), max(s.phi_L, s.phi_H)
+    rho1 = s.rho_L + (np.clip(phi1, lo, hi) - s.phi_L) * (s.rho_H - s.rho_L) / (s.phi_H - s.phi_L)
+    assert np.abs(G1.sum(0) - p1 / (rho1 / 3.0))[fl].max() <= 1e-15
+    j0 = np.tensordot(e27.T.astype(float), G0, axes=1)
+    j1 = np.tensordot(e27.T.astype(float), G1, axes=1)
+    assert np.abs(j1 - j0 - (u1 - u0))[:, fl].max() <= 1e-15
+    assert np.abs(H1.sum(0) - H0.sum(0) - (phi1 - phi0))[fl].max() <= 1e-15
+    assert np.array_equal(phi_a[fl], phi1[fl]) and np.array_equal(u_a[:, fl], u1[:, fl])
+    assert np.array_equal(H1[:, ~fl], H0[:, ~fl]) and np.array_equal(G1[:, ~fl], G0[:, ~fl])
