@@ -119,13 +119,14 @@ sg_status sg_make_target(const float *s0, const float *s1, int64_t voxels, const
 /* Applies a predicted increment to the fields of a box: field = base + out * scale_out
  * per channel (out has c_out FP32 channels, the first 5 used; base is a raw
  * state of the box, 5 FP32 channels per voxel, or NULL for the field itself);
- * phi is clipped to [phi_min, phi_max] afterwards (phi_max > phi_min).  With
+ * phi is clipped to [phi_min, phi_max] afterwards (phi_max > phi_min) unless
+ * flags & 4 (SG_APPLY_NO_CLIP).  With
  * q = clamp((phi_base - phi_min)/(phi_max - phi_min), 0, 1): flags & 1
  * (SG_APPLY_U_BY_PHASE) weights the velocity increment by q, flags & 2
  * (SG_APPLY_PHI_AT_INTERFACE) weights the phi increment by 4 q (1 - q).
  * Cells of the rows y = 0 and ny-1 are left unchanged if walls_y.  A zero
  * scale leaves that channel at its base. */
-enum { SG_APPLY_U_BY_PHASE = 1, SG_APPLY_PHI_AT_INTERFACE = 2 };
+enum { SG_APPLY_U_BY_PHASE = 1, SG_APPLY_PHI_AT_INTERFACE = 2, SG_APPLY_NO_CLIP = 4 };
 sg_status sg_apply_prediction(const float *out, int32_t c_out, const float *scale_out, const float *base,
                               float *phi, float *u, float *p, int32_t nx, int32_t ny, int32_t nz,
                               const int32_t *box, int32_t walls_y, float phi_min, float phi_max,

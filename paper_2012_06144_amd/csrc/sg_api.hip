@@ -546,7 +546,9 @@ __global__ void k_apply_prediction(const float *__restrict__ out, int c_out, flo
     const float q = fminf(fmaxf((f0 - pmin) / (pmax - pmin), 0.f), 1.f);
     const float wu = (flags & 1) ? q : 1.f;
     const float wp = (flags & 2) ? 4.f * q * (1.f - q) : 1.f;
-    phi[c] = fminf(fmaxf(f0 + wp * (o[0] * q0), pmin), pmax);
+    // flags & 4: phi is not clipped to [pmin, pmax]
+    const float ph = f0 + wp * (o[0] * q0);
+    phi[c] = (flags & 4) ? ph : fminf(fmaxf(ph, pmin), pmax);
     u[c] = f1 + wu * (o[1] * q1);
     u[N + c] = f2 + wu * (o[2] * q2);
     u[2 * N + c] = f3 + wu * (o[3] * q3);

@@ -186,11 +186,13 @@ def sg_make_target(s0, s1, scale_out, c_out, target, stream=None):
 
 SG_APPLY_U_BY_PHASE = 1
 SG_APPLY_PHI_AT_INTERFACE = 2
+SG_APPLY_NO_CLIP = 4
 
 
 def sg_apply_prediction(out, c_out, scale_out, phi, u, p, nx, ny, nz, box, walls_y, phi_min, phi_max,
-                        base=None, u_by_phase=False, phi_at_interface=False, stream=None):
-    flags = (SG_APPLY_U_BY_PHASE if u_by_phase else 0) | (SG_APPLY_PHI_AT_INTERFACE if phi_at_interface else 0)
+                        base=None, u_by_phase=False, phi_at_interface=False, clip=True, stream=None):
+    flags = ((SG_APPLY_U_BY_PHASE if u_by_phase else 0) | (SG_APPLY_PHI_AT_INTERFACE if phi_at_interface else 0)
+             | (0 if clip else SG_APPLY_NO_CLIP))
     _check(_L.sg_apply_prediction(_p(out), c_out, _f5(scale_out), _p(base), _p(phi), _p(u), _p(p), nx, ny, nz,
                                   _box(box), int(walls_y), float(phi_min), float(phi_max), flags,
                                   _stream(stream)),

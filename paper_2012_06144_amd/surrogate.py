@@ -608,6 +608,9 @@ class JumpConfig:
                                 # centroid displacement, see comoving_shift)
     velocity: str = "gas"       # bubble velocity of co-moving jumps: "gas" (gas-weighted u) or "centroid"
     max_gain: float = 0.02      # co-moving velocity factor limited to 1 +- max_gain
+    clip_phi: bool = True       # clip the jumped phi to [phi_L, phi_H] (removes the phase field's own
+                                # small over- and undershoots, which the mass projection then moves
+                                # into the interface)
     keep_neq: bool = False      # after a jump keep the populations' non-equilibrium parts
                                 # (lbm_shift_equilibrium) instead of rebuilding them at equilibrium;
                                 # they stay at their cells while the interface moves, which
@@ -666,7 +669,7 @@ def _jump(net, mode, F_now, F_prev, setup, box, jc: JumpConfig, diagnostics=Fals
         so = [0.0] * NCH
     sg.sg_apply_prediction(out, C_OUT, so, F_now[0], F_now[1:4], F_now[4], nx, ny, nz, box,
                            int(setup.walls_y), lo, hi, base=base, u_by_phase=jc.u_by_phase,
-                           phi_at_interface=jc.phi_at_interface)
+                           phi_at_interface=jc.phi_at_interface, clip=jc.clip_phi)
     if diagnostics and mode == "network":
         mx = out.view(-1, C_OUT)[:, :NCH].abs().amax(0).tolist()
         inc = [float(a * b) for a, b in zip(mx, so)]
@@ -795,8 +798,12 @@ def run_plain(solver, total_steps, every, first=None, log=print):
 
 
 def compare_trajectories(ref, run):
-    """Rise velocity (centroid slope over the second half) and centroid
-    errors of `run` against `ref` at the steps both recorded."""
+    """Rise-velocity and centroid errors of `run` against `ref` at the steps
+    both recorded.  The rise velocity is the gas-weighted u_y (the
+    statistics' rise_velocity); its mean relative error over the second
+    half is the headline figure.  The slope of the gas centroid is reported
+    too, but the plain run's centroid wanders by a cell or more over a few
+    thousand steps while the gas-weighted velocity stays smooth."""
     rs = {e["step"]: e for e in ref["trajectory"]}
     common = [e for e in run["trajectory"] if e["step"] in rs]
     steps = np.array([e["step"] for e in common], dtype=np.float64)
@@ -812,6 +819,8 @@ def compare_trajectories(ref, run):
             "rise_rel_err_centroid_slope": float(abs(slope - slope_r) / abs(slope_r)),
             "rise_rel_err_velocity_final": float(abs(uu[-1] - ur[-1]) / abs(ur[-1])),
             "rise_rel_err_velocity_max_2nd_half": float(np.max(np.abs(uu[half:] - ur[half:])) / np.max(np.abs(ur[half:]))),
+            "rise_rel_err_velocity_mean_2nd_half": float(np.mean(np.abs(uu[half:] - ur[half:])) /
+                                                         np.mean(np.abs(ur[half:]))),
             "rise_ref_cells": float(yr[-1] - yr[0])}
 
 
@@ -909,6 +918,7 @@ def _cmd_jump(a):
     jc.max_gain = a.max_gain
     jc.accel = not a.no_accel
     jc.keep_neq = bool(a.keep_neq)
+    jc.clip_phi = not a.no_clip
     jc.phi_at_interface = not a.no_phi_at_interface
     for name, net, mode in variants:
         sv = lbm.Solver(s.physics(), storage="f32")
@@ -963,6 +973,7 @@ def main():
     j.add_argument("--velocity", default="gas", choices=["gas", "centroid"], help="co-moving jump velocity")
     j.add_argument("--max-gain", type=float, default=0.02, help="co-moving velocity factor limit")
     j.add_argument("--no-accel", action="store_true", help="co-moving jumps without the trend window")
+    j.add_argument("--no-clip", action="store_true", help="do not clip the jumped phi to [phi_L, phi_H]")
     j.add_argument("--keep-neq", action="store_true",
                    help="keep the populations' non-equilibrium parts after a jump (default: rebuild at equilibrium)")
     j.add_argument("--out", default=None)

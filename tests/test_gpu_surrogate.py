@@ -443,6 +443,14 @@ def test_apply_prediction_onto_a_base(env):
     assert np.array_equal(pp, base[:, 4])            # zero scale: the base value
     # planes z = 2, 3 lie outside the box (z = 4, 5, 0, 1): unchanged
     assert torch.equal(p.view(nz, ny, nx)[2:4], p0.view(nz, ny, nx)[2:4])
+    # without the clip phi keeps its over- and undershoots
+    sg.sg_apply_prediction(torch.from_numpy(out).cuda(), 32, so, phi, u, p, nx, ny, nz, box, 0, 0.0, 1.0,
+                           base=torch.from_numpy(base).cuda(), clip=False)
+    torch.cuda.synchronize()
+    ph = phi.cpu().numpy().reshape(nz, ny, nx)[zi][:, yi][:, :, xi].reshape(-1)
+    raw = base[:, 0] + out[:, 0] * f32(0.1)
+    assert (raw < 0).any() and (raw > 1).any()
+    assert np.array_equal(ph, raw)
 
 
 def test_apply_prediction_velocity_weighted_by_phase(env):
