@@ -386,7 +386,7 @@ def _gas_moments(states, count, box, phi_heavy, phi_light):
 
 
 def comoving_shift(states, count, box, K, prev=None, m=None, phi_heavy=PHI_HEAVY, phi_light=PHI_LIGHT,
-                   max_gain=0.02, velocity="gas"):
+                   max_gain=0.02, velocity="gas", memory=None, smooth=1.0):
     """Co-moving jump of each of `count` box states (contiguous, 5 FP32
     channels per voxel) over K steps.  velocity="gas": the bubble's
     gas-weighted velocity U and, given the same boxes `prev` m steps
@@ -395,8 +395,10 @@ def comoving_shift(states, count, box, K, prev=None, m=None, phi_heavy=PHI_HEAVY
     velocity factor f = 1 + K a.U / |U|^2 (the flow around the bubble keeps
     its shape and grows with U), f clipped to 1 +- max_gain.
     velocity="centroid": U is the displacement of the gas centroid since
-    `prev` over m, and f = 1.  Returns a (count, 4) FP32 device tensor of
-    rows (dx, dy, dz, f); a box without gas stays put."""
+    `prev` over m, and f = 1.  With a dict `memory` (kept by the caller
+    between calls on the same boxes) the acceleration is smoothed over calls,
+    a <- smooth a + (1 - smooth) a_previous.  Returns a (count, 4) FP32
+    device tensor of rows (dx, dy, dz, f); a box without gas stays put."""
     import torch
     vol, cen, U = _gas_moments(states, count, box, phi_heavy, phi_light)
     a = np.zeros_like(U)
@@ -407,6 +409,10 @@ def comoving_shift(states, count, box, K, prev=None, m=None, phi_heavy=PHI_HEAVY
             U = np.where(has, (cen - cen_p) / float(m), U)
         else:
             a = np.where(has, (U - Up) / float(m), 0.0)
+    if memory is not None:
+        if "a" in memory and memory["a"].shape == a.shape:
+            a = smooth * a + (1.0 - smooth) * memory["a"]
+        memory["a"] = a
     acc = 0.5 * K * K * a
     lim = 0.5 * K * np.linalg.norm(U, axis=1, keepdims=True)
     nacc = np.linalg.norm(acc, axis=1, keepdims=True)
@@ -608,6 +614,8 @@ class JumpConfig:
                                 # centroid displacement, see comoving_shift)
     velocity: str = "gas"       # bubble velocity of co-moving jumps: "gas" (gas-weighted u) or "centroid"
     max_gain: float = 0.02      # co-moving velocity factor limited to 1 +- max_gain
+    accel_smooth: float = 1.0   # weight of the newest acceleration estimate (1: no smoothing)
+    warmup: int = 0             # plain LBM steps before the first jump (the start-up from rest)
     clip_phi: bool = True       # clip the jumped phi to [phi_L, phi_H] (removes the phase field's own
                                 # small over- and undershoots, which the mass projection then moves
                                 # into the interface)
@@ -624,7 +632,7 @@ def _traj_entry(step, st, **kw):
     return d
 
 
-def _jump(net, mode, F_now, F_prev, setup, box, jc: JumpConfig, diagnostics=False):
+def _jump(net, mode, F_now, F_prev, setup, box, jc: JumpConfig, diagnostics=False, memory=None):
     """Writes the state K steps ahead into F_now ((5, nz, ny, nx) FP32 planes:
     phi, u, p) from F_now and F_prev (m steps earlier).  mode "persistence":
     unchanged; "transport": phi moved by the local velocity in the window
@@ -655,7 +663,7 @@ def _jump(net, mode, F_now, F_prev, setup, box, jc: JumpConfig, diagnostics=Fals
     if kind == "comoving":
         shift = comoving_shift(s0, 1, (bx, by, bz), jc.K, prev=sm if jc.accel else None, m=jc.m,
                                phi_heavy=setup.phi_H, phi_light=setup.phi_L, max_gain=jc.max_gain,
-                               velocity=jc.velocity)[0]
+                               velocity=jc.velocity, memory=memory, smooth=jc.accel_smooth)[0]
     jump_base(kind, s0, (bx, by, bz), jc.K, base, shift)
     inc = None
     if mode == "network":
@@ -677,7 +685,8 @@ def _jump(net, mode, F_now, F_prev, setup, box, jc: JumpConfig, diagnostics=Fals
 
 
 def run_with_jumps(net, solver, setup, total_steps, jc: JumpConfig, log=print, mode="network"):
-    """Advances `solver` by total_steps: m plain steps to start the trend,
+    """Advances `solver` by total_steps: jc.warmup plain steps (the start-up
+    from rest), m plain steps to start the trend,
     then cycles of one jump (K steps, see _jump) plus jc.relax LBM steps,
     the fields being taken m steps before the end of each relaxation and at
     its end.  After each cycle the indicators are checked (finite, mass drift
@@ -702,10 +711,14 @@ def run_with_jumps(net, solver, setup, total_steps, jc: JumpConfig, log=print, m
     t0 = time.perf_counter()
     t_log = t0
     across = jc.m == cyc               # trend between consecutive cycle ends
+    memory = {}                         # acceleration estimate carried between cycles
     assert across or 0 < jc.m <= jc.relax
+    if jc.warmup:                       # plain steps before the first jump
+        solver.step(jc.warmup)
+        traj.append(_traj_entry(jc.warmup, solver.stats()))
     solver.macroscopic(out=F_prev)
     solver.step(jc.m)
-    done = jc.m
+    done = jc.warmup + jc.m
     solver.macroscopic(out=F_now)
     F_keep = torch.empty_like(F_now) if across else None
     while done + cyc <= total_steps:
@@ -716,7 +729,7 @@ def run_with_jumps(net, solver, setup, total_steps, jc: JumpConfig, log=print, m
         tp = time.perf_counter()
         if across:
             F_keep.copy_(F_now)
-        inc = _jump(net, mode, F_now, F_prev, setup, box, jc, diagnostics=len(traj) <= 4)
+        inc = _jump(net, mode, F_now, F_prev, setup, box, jc, diagnostics=len(traj) <= 4, memory=memory)
         sg.sg_mass_project(F_now[0], m0, setup.phi_L, setup.phi_H, scratch)
         solver.set_macroscopic(F_now[0], F_now[1:4], F_now[4], keep_neq=jc.keep_neq)
         torch.cuda.synchronize()
@@ -916,6 +929,8 @@ def _cmd_jump(a):
     jc.predict_pressure = bool(a.predict_pressure)
     jc.velocity = a.velocity
     jc.max_gain = a.max_gain
+    jc.accel_smooth = a.accel_smooth
+    jc.warmup = a.warmup
     jc.accel = not a.no_accel
     jc.keep_neq = bool(a.keep_neq)
     jc.clip_phi = not a.no_clip
@@ -972,6 +987,9 @@ def main():
     j.add_argument("--plain-every", type=int, default=25, help="statistics cadence of the plain run")
     j.add_argument("--velocity", default="gas", choices=["gas", "centroid"], help="co-moving jump velocity")
     j.add_argument("--max-gain", type=float, default=0.02, help="co-moving velocity factor limit")
+    j.add_argument("--warmup", type=int, default=0, help="plain LBM steps before the first jump")
+    j.add_argument("--accel-smooth", type=float, default=1.0,
+                   help="weight of the newest acceleration estimate in its running average")
     j.add_argument("--no-accel", action="store_true", help="co-moving jumps without the trend window")
     j.add_argument("--no-clip", action="store_true", help="do not clip the jumped phi to [phi_L, phi_H]")
     j.add_argument("--keep-neq", action="store_true",
