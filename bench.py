@@ -134,7 +134,7 @@ def main():
     if args.gpus != 1 or world != 1:
         print(f"bench.py measures one GPU: the coupled step is built and measured on a single "
               f"MI355X (requested --gpus {args.gpus}, WORLD_SIZE {world}); multi-GPU domain "
-              f"decomposition is not part of this build.", file=sys.stderr)
+              f"decomposition is not implemented.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
