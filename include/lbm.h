@@ -135,8 +135,10 @@ size_t lbm_workspace_bytes(const lbm_params *p);
  * ("1") or the one-cell-per-thread sweeps ("0"); unset, the library's
  * default.  With 16-bit storage and even nz the sweeps process cells z and
  * z + nz/2 together from shared 32-bit words; LBM_PAIR=0 selects the
- * one-cell-per-thread sweeps instead.  All variants compute the same
- * numbers (same operation order). */
+ * one-cell-per-thread sweeps instead.  LBM_FUSE=1 makes lbm_step run the
+ * hydrodynamic sweep of each step and the phase-field sweep of the next in
+ * one kernel (FP32 and FP64 storage, one-cell-per-thread sweeps).  All
+ * variants compute the same numbers (same operation order). */
 lbm_status lbm_create(const lbm_params *p, void *dev_workspace, size_t bytes, void *hip_stream,
                       lbm_ctx **out);
 

@@ -17,6 +17,8 @@ namespace lbm {
 #define LBM_EXTERN_SWEEP(S, P) extern template void launch_sweep<S, P>(const SweepArgs<S> &, const SweepLaunch &, hipStream_t);
 LBM_FP32_SWEEPS(LBM_EXTERN_SWEEP)
 #undef LBM_EXTERN_SWEEP
+extern template void launch_fused<StoreF32>(const SweepArgs<StoreF32> &, const SweepArgs<StoreF32> &,
+                                            const SweepLaunch &, hipStream_t);
 }  // namespace lbm
 
 using namespace lbm;
@@ -165,6 +167,7 @@ struct lbm_ctx {
     int64_t steps;
     bool zmarch;  // sweeps march in z with phi staged in LDS
     bool pair16;  // 16-bit storage with even nz: one thread per pair of cells
+    bool fuse;    // lbm_step runs the hydrodynamic sweep of one step with the phase sweep of the next
 };
 
 namespace {
@@ -268,6 +271,31 @@ struct Ops {
     static lbm_status step(lbm_ctx *c, int n)
     {
         const Phys<R> ph = make_phys<R>(&c->p);
+        if constexpr (!S::paired) {
+            const SweepLaunch L = sweep_launch(c);
+            if (c->fuse && n >= 2 && L.mode == 0) {
+                // phase(0); then hydro(t - 1) fused with phase(t); then hydro(n - 1)
+                int a = c->cur, b = 1 - c->cur;
+                SweepArgs<S> sp{H(c, a), H(c, b), phi(c, a), phi(c, b), u(c), c->g, ph};
+                launch_phase(c, sp);
+                LAUNCH_CHECK();
+                for (int t = 1; t < n; ++t) {
+                    SweepArgs<S> sh{G(c, a), G(c, b), phi(c, b), nullptr, u(c), c->g, ph};
+                    SweepArgs<S> sq{H(c, b), H(c, a), phi(c, b), phi(c, a), u(c), c->g, ph};
+                    launch_fused<S>(sh, sq, L, c->stream);
+                    LAUNCH_CHECK();
+                    a = b;
+                    b = 1 - b;
+                    ++c->steps;
+                }
+                SweepArgs<S> sh{G(c, a), G(c, b), phi(c, b), nullptr, u(c), c->g, ph};
+                launch_hydro(c, sh);
+                LAUNCH_CHECK();
+                c->cur = b;
+                ++c->steps;
+                return LBM_OK;
+            }
+        }
         for (int t = 0; t < n; ++t) {
             const int a = c->cur, b = 1 - c->cur;
             SweepArgs<S> sp{H(c, a), H(c, b), phi(c, a), phi(c, b), u(c), c->g, ph};
@@ -504,6 +532,8 @@ lbm_status lbm_create(const lbm_params *p, void *ws, size_t bytes, void *stream,
     if (const char *v = std::getenv("LBM_ZMARCH")) c->zmarch = (v[0] == '1');
     c->pair16 = true;
     if (const char *v = std::getenv("LBM_PAIR")) c->pair16 = (v[0] != '0');
+    c->fuse = false;
+    if (const char *v = std::getenv("LBM_FUSE")) c->fuse = (v[0] == '1');
     *out = c;
     g_err[0] = 0;
     return LBM_OK;

@@ -330,7 +330,8 @@ struct IORegs {
 // (eq. interfaceTracking), equilibrium phi Gamma(u), single-rate collision
 // (eq. lb_interface); store post-collision h at the cell ----------------------
 template <class S, class P, class IO>
-__device__ inline void phase_cell(const SweepArgs<S> &a, int c, const Nbr &n, const P &phiA, const IO &io)
+__device__ inline void phase_cell(const SweepArgs<S> &a, int c, const Nbr &n, const P &phiA, const IO &io,
+                                  const typename S::real *u_reg = nullptr)
 {
     using R = typename S::real;
     // previous phase field at x + e_i (D3Q15 stencil points; wall rows mirrored)
@@ -390,7 +391,10 @@ __device__ inline void phase_cell(const SweepArgs<S> &a, int c, const Nbr &n, co
         theta = (R(1) - R(4) * dp * dp) / a.ph.xi;
     }
 
-    const R ux = a.u[c], uy = a.u[a.g.fplane + c], uz = a.u[2 * a.g.fplane + c];
+    // u of the cell: from memory, or from the registers of a fused hydrodynamic sweep that just wrote it
+    const R ux = u_reg ? u_reg[0] : a.u[c];
+    const R uy = u_reg ? u_reg[1] : a.u[a.g.fplane + c];
+    const R uz = u_reg ? u_reg[2] : a.u[2 * a.g.fplane + c];
     const R uu = ux * ux + uy * uy + uz * uz;
     const R om = a.ph.omega_phi;
     R hs[15];
@@ -444,7 +448,8 @@ __global__ __launch_bounds__(kBlock) void k_phase(const SweepArgs<S> a)
 //   A = Pi - p* cs^2 I - u u^T,  F_i = w_i e_i.F/(rho cs^2),
 // and the bracket of the viscous force is s A(u_old).
 template <class S, class P, class IO>
-__device__ inline void hydro_cell(const SweepArgs<S> &a, int c, const Nbr &n, const P &phiB, const IO &io)
+__device__ inline void hydro_cell(const SweepArgs<S> &a, int c, const Nbr &n, const P &phiB, const IO &io,
+                                  typename S::real *u_new = nullptr)
 {
     using R = typename S::real;
     R ps = R(0), j[3] = {R(0), R(0), R(0)};
@@ -552,6 +557,11 @@ __device__ inline void hydro_cell(const SweepArgs<S> &a, int c, const Nbr &n, co
     st_field(a.u + c, ux);
     st_field(a.u + a.g.fplane + c, uy);
     st_field(a.u + 2 * a.g.fplane + c, uz);
+    if (u_new) {
+        u_new[0] = ux;
+        u_new[1] = uy;
+        u_new[2] = uz;
+    }
 
     const R uu = ux * ux + uy * uy + uz * uz;
     const R Bxx = Pxx - ps * c2 - ux * ux, Byy = Pyy - ps * c2 - uy * uy, Bzz = Pzz - ps * c2 - uz * uz;
@@ -791,6 +801,34 @@ struct SweepLaunch {
     int blocks;  // grid size
     ZTiles zt;   // tiling of mode 1
 };
+
+// The hydrodynamic sweep of step n and the phase-field sweep of step n + 1 on
+// the same cell.  Step n + 1's phase sweep reads the h populations and the
+// phase field that step n's phase sweep wrote (complete before this launch)
+// and u at the cell only, which the hydrodynamic body has just computed and
+// hands over in registers; the two bodies read the same phase field (the
+// hydrodynamic one as the new field, the phase one as the previous field of
+// its gradient) and touch disjoint buffers otherwise.  Same arithmetic as the
+// two separate sweeps, one pass over the cells instead of two.
+template <class S>
+__global__ __launch_bounds__(kBlock) void k_fused(const SweepArgs<S> ah, const SweepArgs<S> ap)
+{
+    using R = typename S::real;
+    const int c = xcd_block() * kBlock + threadIdx.x;
+    if (c >= ah.g.ncells) return;
+    int x, y, z;
+    Nbr n;
+    if (!decode(ah.g, c, x, y, z, n)) return;
+    R un[3];
+    hydro_cell<S>(ah, c, n, PhiG<R>{ah.phi_in, c, &n}, IOGlobal<S, 27>{ah.src, ah.dst, c, &n, &ah.g}, un);
+    phase_cell<S>(ap, c, n, PhiG<R>{ap.phi_in, c, &n}, IOGlobal<S, 15>{ap.src, ap.dst, c, &n, &ap.g}, un);
+}
+
+template <class S>
+void launch_fused(const SweepArgs<S> &ah, const SweepArgs<S> &ap, const SweepLaunch &L, hipStream_t stream)
+{
+    hipLaunchKernelGGL((k_fused<S>), dim3(L.blocks), dim3(kBlock), 0, stream, ah, ap);
+}
 
 template <class S, bool PHASE>
 void launch_sweep(const SweepArgs<S> &a, const SweepLaunch &L, hipStream_t stream)

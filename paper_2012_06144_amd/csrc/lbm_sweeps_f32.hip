@@ -12,4 +12,6 @@ namespace lbm {
 #define LBM_INSTANTIATE_SWEEP(S, P) template void launch_sweep<S, P>(const SweepArgs<S> &, const SweepLaunch &, hipStream_t);
 LBM_FP32_SWEEPS(LBM_INSTANTIATE_SWEEP)
 #undef LBM_INSTANTIATE_SWEEP
+template void launch_fused<StoreF32>(const SweepArgs<StoreF32> &, const SweepArgs<StoreF32> &, const SweepLaunch &,
+                                     hipStream_t);
 }  // namespace lbm
