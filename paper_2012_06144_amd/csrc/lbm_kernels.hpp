@@ -329,7 +329,7 @@ struct IORegs {
 // normal and theta from the previous phi (eqs. allen_cahn, grad), forcing
 // (eq. interfaceTracking), equilibrium phi Gamma(u), single-rate collision
 // (eq. lb_interface); store post-collision h at the cell ----------------------
-template <class S, class P, class IO>
+template <class S, class P, class IO, bool U_REG = false>
 __device__ inline void phase_cell(const SweepArgs<S> &a, int c, const Nbr &n, const P &phiA, const IO &io,
                                   const typename S::real *u_reg = nullptr)
 {
@@ -391,10 +391,17 @@ __device__ inline void phase_cell(const SweepArgs<S> &a, int c, const Nbr &n, co
         theta = (R(1) - R(4) * dp * dp) / a.ph.xi;
     }
 
-    // u of the cell: from memory, or from the registers of a fused hydrodynamic sweep that just wrote it
-    const R ux = u_reg ? u_reg[0] : a.u[c];
-    const R uy = u_reg ? u_reg[1] : a.u[a.g.fplane + c];
-    const R uz = u_reg ? u_reg[2] : a.u[2 * a.g.fplane + c];
+    // u of the cell: from memory, or (U_REG) from the registers of a fused hydrodynamic sweep that just wrote it
+    R ux, uy, uz;
+    if constexpr (U_REG) {
+        ux = u_reg[0];
+        uy = u_reg[1];
+        uz = u_reg[2];
+    } else {
+        ux = a.u[c];
+        uy = a.u[a.g.fplane + c];
+        uz = a.u[2 * a.g.fplane + c];
+    }
     const R uu = ux * ux + uy * uy + uz * uz;
     const R om = a.ph.omega_phi;
     R hs[15];
@@ -447,7 +454,7 @@ __global__ __launch_bounds__(kBlock) void k_phase(const SweepArgs<S> a)
 //   g*_i = g_eq_i(p*, u) + F_i/2 + (1 - s) w_i/(2 cs^4) (e_i e_i - cs^2 I) : A,
 //   A = Pi - p* cs^2 I - u u^T,  F_i = w_i e_i.F/(rho cs^2),
 // and the bracket of the viscous force is s A(u_old).
-template <class S, class P, class IO>
+template <class S, class P, class IO, bool U_OUT = false>
 __device__ inline void hydro_cell(const SweepArgs<S> &a, int c, const Nbr &n, const P &phiB, const IO &io,
                                   typename S::real *u_new = nullptr)
 {
@@ -557,7 +564,7 @@ __device__ inline void hydro_cell(const SweepArgs<S> &a, int c, const Nbr &n, co
     st_field(a.u + c, ux);
     st_field(a.u + a.g.fplane + c, uy);
     st_field(a.u + 2 * a.g.fplane + c, uz);
-    if (u_new) {
+    if constexpr (U_OUT) {
         u_new[0] = ux;
         u_new[1] = uy;
         u_new[2] = uz;
@@ -820,8 +827,10 @@ __global__ __launch_bounds__(kBlock) void k_fused(const SweepArgs<S> ah, const S
     Nbr n;
     if (!decode(ah.g, c, x, y, z, n)) return;
     R un[3];
-    hydro_cell<S>(ah, c, n, PhiG<R>{ah.phi_in, c, &n}, IOGlobal<S, 27>{ah.src, ah.dst, c, &n, &ah.g}, un);
-    phase_cell<S>(ap, c, n, PhiG<R>{ap.phi_in, c, &n}, IOGlobal<S, 15>{ap.src, ap.dst, c, &n, &ap.g}, un);
+    hydro_cell<S, PhiG<R>, IOGlobal<S, 27>, true>(ah, c, n, PhiG<R>{ah.phi_in, c, &n},
+                                                  IOGlobal<S, 27>{ah.src, ah.dst, c, &n, &ah.g}, un);
+    phase_cell<S, PhiG<R>, IOGlobal<S, 15>, true>(ap, c, n, PhiG<R>{ap.phi_in, c, &n},
+                                                  IOGlobal<S, 15>{ap.src, ap.dst, c, &n, &ap.g}, un);
 }
 
 template <class S>
