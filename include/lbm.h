@@ -135,10 +135,11 @@ size_t lbm_workspace_bytes(const lbm_params *p);
  * ("1") or the one-cell-per-thread sweeps ("0"); unset, the library's
  * default.  With 16-bit storage and even nz the sweeps process cells z and
  * z + nz/2 together from shared 32-bit words; LBM_PAIR=0 selects the
- * one-cell-per-thread sweeps instead.  LBM_FUSE=1 makes lbm_step run the
- * hydrodynamic sweep of each step and the phase-field sweep of the next in
- * one kernel (FP32 and FP64 storage, one-cell-per-thread sweeps).  All
- * variants compute the same numbers (same operation order). */
+ * one-cell-per-thread sweeps instead.  With FP32 and FP64 storage and the
+ * one-cell-per-thread sweeps, lbm_step runs the hydrodynamic sweep of each
+ * step and the phase-field sweep of the next in one kernel; LBM_FUSE=0
+ * keeps them separate.  All variants compute the same numbers (same
+ * operation order). */
 lbm_status lbm_create(const lbm_params *p, void *dev_workspace, size_t bytes, void *hip_stream,
                       lbm_ctx **out);
 
@@ -164,6 +165,13 @@ lbm_status lbm_step(lbm_ctx *ctx, int32_t n);
  * mean duration of one phase-field sweep and of one hydrodynamic sweep in
  * milliseconds (host outputs).  1 <= n <= 4096.  For measurement only. */
 lbm_status lbm_step_timed(lbm_ctx *ctx, int32_t n, double *phase_ms, double *hydro_ms);
+
+/* Measurement only: n (2..4096) steps exactly as lbm_step runs them with the
+ * fused kernel (one phase-field sweep, n - 1 fused kernels, one
+ * hydrodynamic sweep), with HIP events around every fused launch; the mean
+ * fused-kernel time in ms (host output); synchronises.  LBM_EARG for 16-bit
+ * storage and the z-marching sweeps, which have no fused kernel. */
+lbm_status lbm_step_timed_fused(lbm_ctx *ctx, int32_t n, double *fused_ms);
 
 /* sum of phi over fluid cells in FP64 (host output); synchronises. */
 lbm_status lbm_reduce_mass(lbm_ctx *ctx, double *sum_phi);

@@ -352,6 +352,55 @@ struct Ops {
         return LBM_OK;
     }
 
+    // n >= 2 steps as lbm_step runs them with fused sweeps, HIP events around
+    // every fused launch; mean fused-kernel time in ms.
+    static lbm_status step_timed_fused(lbm_ctx *c, int n, double *fused_ms)
+    {
+        if constexpr (S::paired) {
+            return fail(LBM_EARG, "16-bit storage has no fused sweep kernel");
+        } else {
+            const SweepLaunch L = sweep_launch(c);
+            if (L.mode != 0) return fail(LBM_EARG, "the fused sweep kernel needs the one-cell-per-thread sweeps");
+            const Phys<R> ph = make_phys<R>(&c->p);
+            hipEvent_t ev[2];
+            for (int k = 0; k < 2; ++k) HIP_TRY(hipEventCreate(&ev[k]));
+            int a = c->cur, b = 1 - c->cur;
+            SweepArgs<S> sp{H(c, a), H(c, b), phi(c, a), phi(c, b), u(c), c->g, ph};
+            launch_phase(c, sp);
+            hipError_t e = hipGetLastError();
+            double tf = 0.0;
+            for (int t = 1; t < n && e == hipSuccess; ++t) {
+                SweepArgs<S> sh{G(c, a), G(c, b), phi(c, b), nullptr, u(c), c->g, ph};
+                SweepArgs<S> sq{H(c, b), H(c, a), phi(c, b), phi(c, a), u(c), c->g, ph};
+                e = hipEventRecord(ev[0], c->stream);
+                if (e == hipSuccess) {
+                    launch_fused<S>(sh, sq, L, c->stream);
+                    e = hipGetLastError();
+                }
+                if (e == hipSuccess) e = hipEventRecord(ev[1], c->stream);
+                if (e == hipSuccess) e = hipEventSynchronize(ev[1]);
+                float m = 0.f;
+                if (e == hipSuccess) e = hipEventElapsedTime(&m, ev[0], ev[1]);
+                tf += m;
+                a = b;
+                b = 1 - b;
+                ++c->steps;
+            }
+            if (e == hipSuccess) {
+                SweepArgs<S> sh{G(c, a), G(c, b), phi(c, b), nullptr, u(c), c->g, ph};
+                launch_hydro(c, sh);
+                e = hipGetLastError();
+                c->cur = b;
+                ++c->steps;
+            }
+            if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+            for (int k = 0; k < 2; ++k) (void)hipEventDestroy(ev[k]);
+            if (e != hipSuccess) return fail(LBM_EHIP, "timed fused steps failed: %s", hipGetErrorString(e));
+            *fused_ms = tf / (n - 1);
+            return LBM_OK;
+        }
+    }
+
     static lbm_status reduce(lbm_ctx *c, int mass_only, double out[kRedVals])
     {
         double *partial = (double *)(c->ws + c->L.off_red);
@@ -417,6 +466,9 @@ template <class S> struct DoStep {
 };
 template <class S> struct DoStepTimed {
     static lbm_status run(lbm_ctx *c, int n, double *a, double *b) { return Ops<S>::step_timed(c, n, a, b); }
+};
+template <class S> struct DoStepTimedFused {
+    static lbm_status run(lbm_ctx *c, int n, double *f) { return Ops<S>::step_timed_fused(c, n, f); }
 };
 template <class S> struct DoReduce {
     static lbm_status run(lbm_ctx *c, int m, double *o) { return Ops<S>::reduce(c, m, o); }
@@ -532,8 +584,8 @@ lbm_status lbm_create(const lbm_params *p, void *ws, size_t bytes, void *stream,
     if (const char *v = std::getenv("LBM_ZMARCH")) c->zmarch = (v[0] == '1');
     c->pair16 = true;
     if (const char *v = std::getenv("LBM_PAIR")) c->pair16 = (v[0] != '0');
-    c->fuse = false;
-    if (const char *v = std::getenv("LBM_FUSE")) c->fuse = (v[0] == '1');
+    c->fuse = true;
+    if (const char *v = std::getenv("LBM_FUSE")) c->fuse = (v[0] != '0');
     *out = c;
     g_err[0] = 0;
     return LBM_OK;
@@ -570,6 +622,15 @@ lbm_status lbm_step_timed(lbm_ctx *c, int32_t n, double *phase_ms, double *hydro
     if (n < 1 || n > 4096) return fail(LBM_EARG, "n must be in [1, 4096] (got %d)", n);
     if (!phase_ms || !hydro_ms) return fail(LBM_EARG, "NULL output");
     return dispatch<DoStepTimed>(c->p.storage, c, (int)n, phase_ms, hydro_ms);
+}
+
+lbm_status lbm_step_timed_fused(lbm_ctx *c, int32_t n, double *fused_ms)
+{
+    lbm_status s = check_ctx(c, true);
+    if (s != LBM_OK) return s;
+    if (n < 2 || n > 4096) return fail(LBM_EARG, "n must be in [2, 4096] (got %d)", n);
+    if (!fused_ms) return fail(LBM_EARG, "NULL output");
+    return dispatch<DoStepTimedFused>(c->p.storage, c, (int)n, fused_ms);
 }
 
 lbm_status lbm_reduce_mass(lbm_ctx *c, double *sum_phi)

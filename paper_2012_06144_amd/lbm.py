@@ -25,7 +25,7 @@ DTYPE_F64, DTYPE_F32 = 0, 1
 
 EXPORTS = [
     "lbm_velocity_set", "lbm_workspace_bytes", "lbm_create", "lbm_set_stream", "lbm_init_fields",
-    "lbm_step", "lbm_step_timed", "lbm_reduce_mass", "lbm_reduce_stats", "lbm_get_macroscopic",
+    "lbm_step", "lbm_step_timed", "lbm_step_timed_fused", "lbm_reduce_mass", "lbm_reduce_stats", "lbm_get_macroscopic",
     "lbm_set_macroscopic", "lbm_shift_equilibrium", "lbm_get_pdfs", "lbm_set_pdfs", "lbm_stream_copy", "lbm_steps_done",
     "lbm_state_bytes", "lbm_save_state", "lbm_restore_state", "lbm_destroy", "lbm_last_error",
 ]
@@ -74,6 +74,7 @@ def _load():
         "lbm_init_fields": ([vp, vp, vp, vp], C.c_int),
         "lbm_step": ([vp, C.c_int32], C.c_int),
         "lbm_step_timed": ([vp, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_double)], C.c_int),
+        "lbm_step_timed_fused": ([vp, C.c_int32, C.POINTER(C.c_double)], C.c_int),
         "lbm_reduce_mass": ([vp, C.POINTER(C.c_double)], C.c_int),
         "lbm_reduce_stats": ([vp, C.POINTER(LbmStats)], C.c_int),
         "lbm_get_macroscopic": ([vp, C.c_int32, vp, vp, vp], C.c_int),
@@ -143,6 +144,12 @@ def lbm_init_fields(ctx, phi, u, p_star):
 
 def lbm_step(ctx, n: int):
     _check(_lib.lbm_step(ctx, int(n)), "lbm_step")
+
+
+def lbm_step_timed_fused(ctx, n: int) -> float:
+    f = C.c_double()
+    _check(_lib.lbm_step_timed_fused(ctx, int(n), C.byref(f)), "lbm_step_timed_fused")
+    return f.value
 
 
 def lbm_step_timed(ctx, n: int):
@@ -281,6 +288,10 @@ class Solver:
 
     def step_timed(self, n: int):
         return lbm_step_timed(self.ctx, n)
+
+    def step_timed_fused(self, n: int) -> float:
+        """Mean fused-kernel time (ms) over n steps run as lbm_step runs them."""
+        return lbm_step_timed_fused(self.ctx, n)
 
     def reduce_mass(self) -> float:
         return lbm_reduce_mass(self.ctx)

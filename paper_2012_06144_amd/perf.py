@@ -31,6 +31,9 @@ def bytes_per_cell(storage: str) -> dict:
         "phase_read": phase_r, "phase_write": phase_w, "phase": phase_r + phase_w,
         "hydro_read": hydro_r, "hydro_write": hydro_w, "hydro": hydro_r + hydro_w,
         "total": phase_r + phase_w + hydro_r + hydro_w,
+        # hydrodynamic sweep of one step fused with the phase sweep of the next:
+        # the phase body takes u from registers and shares the phi stencil
+        "fused": phase_r + phase_w + hydro_r + hydro_w - 3 * r - 1 * r,
     }
 
 

@@ -321,6 +321,33 @@ def test_fused_steps_match_separate_sweeps(lbm, storage, case, monkeypatch):
         assert max(_maxdiff(o.state(), states["1"])) <= 1e-13
 
 
+def test_step_timed_fused(lbm, monkeypatch):
+    """The timed fused steps return a positive mean kernel time and leave the
+    state lbm_step leaves; 16-bit storage has no fused kernel (LBM_EARG)."""
+    s = SMALL["ragged_walls_bubble"]()
+    phi, u, ps = inputs.build_fields(s)
+    monkeypatch.setenv("LBM_PAIR", "0")
+    st = {}
+    for timed in (False, True):
+        g = lbm.Solver(s.physics(), storage="f32")
+        g.init_fields(phi, u, ps)
+        if timed:
+            ms = g.step_timed_fused(4)
+            assert ms > 0.0
+        else:
+            g.step(4)
+        st[timed] = g.state()
+        del g
+    for a, b in zip(st[False], st[True]):
+        assert np.array_equal(a, b)
+    g = lbm.Solver(s.physics(), storage="f16s")
+    g.init_fields(phi, u, ps)
+    with pytest.raises(lbm.LbmError):
+        g.step_timed_fused(4)
+    with pytest.raises(lbm.LbmError):
+        g.step_timed_fused(1)
+
+
 def test_stream_copy(lbm):
     import torch
     a = torch.randint(0, 2 ** 31, (1 << 20,), dtype=torch.int32, device="cuda")
