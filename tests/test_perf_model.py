@@ -43,3 +43,13 @@ def test_reduced_precision_bytes():
     assert perf.bytes_per_cell("f32")["total"] == 384
     assert perf.bytes_per_cell("f16s")["total"] == 216
     assert perf.bytes_per_cell("bf16s") == perf.bytes_per_cell("f16s")
+
+
+@pytest.mark.parametrize("storage,expect", [("f64", 736), ("f32", 368)])
+def test_fused_kernel_bytes(storage, expect):
+    """The fused kernel (hydrodynamic sweep of one step with the phase sweep
+    of the next) reads u and the phase field once instead of twice: the
+    coupled count less one u read (3 values) and one phi read."""
+    b = perf.bytes_per_cell(storage)
+    r = 8 if storage == "f64" else 4
+    assert b["fused"] == b["total"] - 4 * r == expect
