@@ -8,9 +8,12 @@ at y = 0 and 511) with FP32 PDF storage and FP32 collision arithmetic.
 Inputs are resident in HBM before the timed region starts.
 
 Prints ONE JSON line: coupled MLUPS (fluid cells x steps / s / 1e6), the
-roofline of the dominant kernel (the hydrodynamic sweep) from HIP-event
-timings on the solver stream, and the FP64 CPU oracle timed on the host on a
-bounded sample of the same workload.
+roofline of the dominant kernel (the fused kernel: hydrodynamic sweep of one
+step with the phase-field sweep of the next) from HIP-event timings on the
+solver stream, the same measurements for the other storage formats (FP64,
+the paper's arithmetic, and FP16/BF16 shifted populations) on the same
+workload under "other_storages", and the FP64 CPU oracle timed on the host on
+a bounded sample of the same workload.
 """
 from __future__ import annotations
 
@@ -89,6 +92,70 @@ def load_surrogate_study():
     return d
 
 
+def host_cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def measure_storage(lbm, perf, setup, phi, u, ps, storage, steps, warmup, timed_steps, src_hash):
+    """Throughput of the same workload with another PDF storage format: the
+    coupled steps timed with HIP events on the solver stream, the dominant
+    kernel's mean launch time (the fused kernel where the format has one,
+    else the hydrodynamic sweep) and the relative drift of sum(phi)."""
+    import torch
+    fluid = setup.nx * setup.nz * (setup.ny - 2 if setup.walls_y else setup.ny)
+    solver = lbm.Solver(setup.physics(), storage=storage, device="cuda:0")
+    solver.init_fields(phi, u, ps)
+    stream = torch.cuda.current_stream(torch.device("cuda:0"))
+    m0 = solver.reduce_mass()
+    if warmup > 0:
+        solver.step(warmup)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    solver.step(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    m1 = solver.reduce_mass()
+    bpc = perf.bytes_per_cell(storage)
+    nt = max(2, min(timed_steps, 4096))
+    fused_ms = None
+    if os.environ.get("LBM_FUSE", "1") != "0":
+        try:
+            fused_ms = solver.step_timed_fused(nt)
+        except lbm.LbmError:
+            fused_ms = None
+    if fused_ms is not None:
+        kern, kbpc, kms = "fused_sweep", bpc["fused"], fused_ms
+        step_bpc = bpc["fused"]
+    else:
+        _, hydro_ms = solver.step_timed(nt)
+        kern, kbpc, kms = "hydro_sweep", bpc["hydro"], hydro_ms
+        step_bpc = bpc["total"]
+    solver.close()
+    del solver
+    torch.cuda.empty_cache()
+    kgbs = kbpc * fluid / (kms * 1e-3) / 1e9
+    traffic = load_traffic(kern, setup.name, storage, src_hash)
+    return {
+        "storage": storage, "steps": steps, "warmup": warmup, "ms_per_step": round(ms, 4),
+        "mlups": round(fluid / (ms * 1e-3) / 1e6, 1),
+        "coupled_gbs": round(step_bpc * fluid / (ms * 1e-3) / 1e9, 1), "bytes_per_cell": step_bpc,
+        "roofline": {"bound": "hbm", "kernel": kern, "achieved": round(kgbs, 1), "peak": perf.HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(kgbs / perf.HBM_PEAK_GBS, 4),
+                     "traffic": None if traffic is None else traffic["bytes_per_launch"],
+                     "bytes_per_cell": kbpc, "units_per_launch": fluid, "launch_ms": round(kms, 4)},
+        "mass_drift_rel": (m1 - m0) / m0,
+    }
+
+
 def cpu_baseline(setup, phi, u, ps, target_s: float = 15.0):
     """Time the FP64 oracle on a 128 x ny x 128 slab of the same workload."""
     import numpy as np
@@ -114,6 +181,7 @@ def cpu_baseline(setup, phi, u, ps, target_s: float = 15.0):
     mlups = fluid * steps / (t2 - t0) / 1e6
     o.close()
     return {"value": mlups, "unit": "MLUPS", "cores": orc.num_threads(), "kind": "oracle",
+            "cpu_model": host_cpu_model(),
             "sample": f"{steps} coupled steps of the FP64 oracle on a {nx}x{setup.ny}x{nz} slab of "
                       f"the {setup.name} fields ({fluid} fluid cells), {t2 - t0:.1f} s"}
 
@@ -128,6 +196,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--timed-steps", type=int, default=50,
                     help="steps of the per-kernel event timing (roofline)")
+    ap.add_argument("--other-storages", default="f64,f16s,bf16s",
+                    help="comma-separated storage formats measured after the main one on the same workload "
+                         "(empty: none)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -225,6 +296,18 @@ def main():
     if traffic is not None:
         traffic_val = traffic["bytes_per_launch"]
 
+    solver.close()
+    del solver
+    torch.cuda.empty_cache()
+    others = {}
+    for st in [x for x in args.other_storages.split(",") if x and x != args.storage]:
+        log(f"[bench] storage {st}: warmup {args.warmup}, timed {args.steps} steps")
+        rec = measure_storage(lbm, perf, setup, phi, u, ps, st, args.steps, args.warmup, args.timed_steps,
+                              src_hash)
+        log(f"[bench] storage {st}: {rec['ms_per_step']:.3f} ms/step, {rec['mlups']:.0f} MLUPS, "
+            f"{rec['roofline']['kernel']} {rec['roofline']['achieved']:.0f} GB/s")
+        others[st] = rec
+
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] CPU oracle baseline")
@@ -266,6 +349,7 @@ def main():
         "mass_drift_rel": (mass1 - mass0) / mass0,
         "paper_context": {"mlups": 550, "hardware": "Tesla P100", "precision": "f64",
                           "roofline_frac_of_stream": 0.78},
+        "other_storages": others,
         "cpu_baseline": cpu,
         "surrogate": load_surrogate_study(),
         "kernel_source_hash": src_hash,

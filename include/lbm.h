@@ -78,7 +78,12 @@ typedef enum { LBM_DTYPE_F64 = 0, LBM_DTYPE_F32 = 1 } lbm_dtype;
  *                  in tall domains
  *   normal_eps     interface normal n = grad phi / (|grad phi| + normal_eps)
  *   storage        an lbm_storage value
- *   reserved0      must be 0 */
+ *   density_literal  0: phi is clamped to [min(phi_L, phi_H), max(phi_L, phi_H)]
+ *                  before the density and tau interpolations (the default;
+ *                  the conservative phase field over- and undershoots the
+ *                  interval by ~1e-3, which at rho_H/rho_L = 1000 would give
+ *                  a near-zero density in small bubble cores); 1: eq. density
+ *                  and the tau interpolation as printed, for every phi */
 typedef struct {
     int32_t nx, ny, nz;
     int32_t walls_y;
@@ -88,7 +93,7 @@ typedef struct {
     double buoyancy_rho_ref;
     double normal_eps;
     int32_t storage;
-    int32_t reserved0;
+    int32_t density_literal;
 } lbm_params;
 
 /* FP64 diagnostics over fluid cells (one deterministic two-pass reduction).
@@ -155,9 +160,13 @@ lbm_status lbm_init_fields(lbm_ctx *ctx, const double *phi, const double *u, con
 
 /* Enqueues n >= 1 coupled time steps: per step the phase-field sweep
  * (pull-stream h, phi = sum h, gradient and normal of the previous phi,
- * forcing, collision) then the hydrodynamic sweep (moments, forces from the
- * new phi, velocity update, moment-space collision, push-stream g), then a
- * buffer swap.  Asynchronous. */
+ * forcing, collision) then the hydrodynamic sweep (pull-stream g, moments,
+ * forces from the new phi, velocity update, moment-space collision), then a
+ * buffer swap.  Both sweeps store post-collision populations at their own
+ * cell and pull from the neighbours in the next sweep, which streams the
+ * same values the paper's push of g does (Sec. 4.2).  With n >= 2 the
+ * hydrodynamic sweep of each step and the phase-field sweep of the next run
+ * as one kernel (same numbers).  Asynchronous. */
 lbm_status lbm_step(lbm_ctx *ctx, int32_t n);
 
 /* Same work as lbm_step(ctx, n), with a HIP event recorded on the context

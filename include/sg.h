@@ -41,6 +41,16 @@ sg_status sg_conv3d_fwd(const void *x, int32_t n, int32_t d, int32_t h, int32_t 
  * sum_t sum_co dy[v - offset(t)][co] wt[t][co][ci]. */
 sg_status sg_weight_mirror(const void *wt, int32_t c_out, int32_t c_in, void *wm, void *hip_stream);
 
+/* Input gradient of sg_conv3d_fwd: dx[v][ci] = sum_t sum_co dy[v - offset(t)][co]
+ * wt[t][co][ci] (BF16 output dx with c_in channels, FP32 accumulation).  It
+ * is the forward convolution of dy with the mirrored, transposed weights,
+ * which are written to `workspace` first (27 c_in c_out BF16 values,
+ * 16-byte aligned, as sg_weight_mirror writes them).  c_out % 16 == 0,
+ * c_in % 32 == 0; SG_ESIZE if workspace_bytes is too small. */
+sg_status sg_conv3d_bwd_data(const void *dy, int32_t n, int32_t d, int32_t h, int32_t w, int32_t c_out,
+                             const void *wt, int32_t c_in, void *dx, void *workspace, size_t workspace_bytes,
+                             void *hip_stream);
+
 /* Bytes of FP32 scratch sg_conv3d_bwd_weight needs for this shape. */
 size_t sg_bwd_weight_workspace(int32_t n, int32_t d, int32_t h, int32_t w, int32_t c_in, int32_t c_out);
 
@@ -189,12 +199,19 @@ sg_status sg_pair_to_input(const float *state, const float *state_prev, int64_t 
 sg_status sg_channel_moments(const float *a, int64_t rows, int32_t c, double *out, double *scratch,
                              void *hip_stream);
 
-/* Mass projection of a phase field over ncells cells: phi += c * 4 phi' (1 - phi')
- * with phi' = (phi - phi_min)/(phi_max - phi_min), c chosen (FP64, fixed-order
- * reduction through `scratch`, 2048 doubles) so that sum(phi) equals
- * target_mass; the correction stays in the interface. */
-sg_status sg_mass_project(float *phi, int64_t ncells, double target_mass, float phi_min, float phi_max,
-                          double *scratch, void *hip_stream);
+/* Mass projection of a phase field after a jump (the fast-forward's
+ * substitute for the exact conservation of sum(phi) by the scheme, Section
+ * 3.1): phi is an FP32 field of an nx * ny * nz grid (x fastest); with
+ * walls_y the rows y = 0 and ny-1 are solid and take no part.  Over the
+ * fluid cells, with q = clamp((phi - phi_min)/(phi_max - phi_min), 0, 1):
+ *   phi += c 4 q (1 - q),  c = (target_mass - sum phi) / sum 4 q (1 - q)
+ * (c = 0 if no cell lies inside the interface), so the correction stays in
+ * the interface and the fluid sum equals target_mass up to the FP32
+ * rounding of the stored cells.  Sums are FP64 with a fixed-order reduction
+ * through `scratch` (device, 2048 doubles, overwritten).  SG_EARG for
+ * phi_max <= phi_min, an empty grid or walls_y with ny < 3. */
+sg_status sg_mass_project(float *phi, int32_t nx, int32_t ny, int32_t nz, int32_t walls_y, double target_mass,
+                          float phi_min, float phi_max, double *scratch, void *hip_stream);
 
 const char *sg_last_error(void);
 

@@ -35,6 +35,7 @@ def _lib():
         L.orc_box_moments.argtypes = [_D, i, i, i, i, C.c_double, C.c_double, _D]
         i64 = C.c_int64
         L.orc_projective_step.argtypes = [_D, _D, i64, i64, i64, C.c_double, C.c_double, C.c_double, i, i, _D]
+        L.orc_mass_project.argtypes = [_D, i, i, i, i, C.c_double, C.c_double, C.c_double, _D]
         _ready = True
     return L
 
@@ -174,4 +175,15 @@ def projective_step(s, s_prev, ratio, phi_lo, phi_hi, u_by_phase=True, p_step=Fa
     out = np.zeros_like(a)
     _lib().orc_projective_step(a, b, n, cs, vs, float(ratio), float(phi_lo), float(phi_hi), int(u_by_phase),
                                int(p_step), out)
+    return out
+
+
+def mass_project(phi, walls_y, target, phi_min, phi_max):
+    """Mass projection of a phase field shaped (nz, ny, nx): phi + c 4q(1-q),
+    q = clamp((phi - phi_min)/(phi_max - phi_min), 0, 1), c such that the sum
+    over the fluid cells equals target; wall rows (walls_y) untouched."""
+    a = _f(phi)
+    nz, ny, nx = a.shape
+    out = np.zeros_like(a)
+    _lib().orc_mass_project(a, nx, ny, nz, int(bool(walls_y)), float(target), float(phi_min), float(phi_max), out)
     return out

@@ -310,3 +310,40 @@ void orc_projective_step(const double *s, const double *s_prev, int64_t n, int64
         out[4 * cs + i * vs] = p_step ? p + ratio * (p - s_prev[4 * cs + i * vs]) : p;
     }
 }
+
+/* Mass projection of a phase field after a jump (part of the learned
+ * fast-forward, not of the paper's method).  The jump may change sum(phi),
+ * which the scheme itself conserves exactly (Section 3.1); the projection
+ * restores it by moving phi only inside the interface:
+ *   q   = clamp((phi - phi_min) / (phi_max - phi_min), 0, 1),
+ *   w   = 4 q (1 - q)               (0 in both bulk phases, 1 at q = 1/2),
+ *   c   = (target - sum phi) / sum w  (0 if sum w = 0),
+ *   phi' = phi + c w,
+ * with both sums over the fluid cells of an nx*ny*nz grid (x fastest);
+ * with walls_y the rows y = 0 and ny-1 are solid: they take no part in the
+ * sums and are left unchanged.  Plain FP64, serial in storage order.    */
+void orc_mass_project(const double *phi, int nx, int ny, int nz, int walls_y, double target, double phi_min,
+                      double phi_max, double *out)
+{
+    const int64_t n = (int64_t)nx * ny * nz;
+    double sum_phi = 0.0, sum_w = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        const int y = (int)((i / nx) % ny);
+        if (walls_y && (y == 0 || y == ny - 1)) continue;
+        double q = (phi[i] - phi_min) / (phi_max - phi_min);
+        q = q < 0.0 ? 0.0 : (q > 1.0 ? 1.0 : q);
+        sum_phi += phi[i];
+        sum_w += 4.0 * q * (1.0 - q);
+    }
+    const double c = sum_w > 0.0 ? (target - sum_phi) / sum_w : 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        const int y = (int)((i / nx) % ny);
+        if (walls_y && (y == 0 || y == ny - 1)) {
+            out[i] = phi[i];
+            continue;
+        }
+        double q = (phi[i] - phi_min) / (phi_max - phi_min);
+        q = q < 0.0 ? 0.0 : (q > 1.0 ? 1.0 : q);
+        out[i] = phi[i] + c * 4.0 * q * (1.0 - q);
+    }
+}

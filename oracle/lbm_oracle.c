@@ -67,6 +67,7 @@ typedef struct {
     double accel[3];
     double rho_ref;      /* buoyancy reference density: F_b = (rho - rho_ref) a */
     double normal_eps;
+    int32_t density_literal; /* 1: eq. density for every phi (no clamp) */
 } orc_params;
 
 typedef struct {
@@ -419,9 +420,11 @@ static void iso_gradient(const orc_params *p, const double *phi, int q, int x, i
  * Allen-Cahn model overshoots that interval by ~1e-3 (most in the cores of
  * small bubbles, where |grad phi| ~ 0), and at rho_H/rho_L = 1000 an
  * undershoot of 1e-3 would put rho near zero.  phi is therefore clamped to
- * the interval before interpolating, which keeps rho in [rho_L, rho_H].   */
+ * the interval before interpolating, which keeps rho in [rho_L, rho_H],
+ * unless density_literal asks for the formula as printed.                 */
 static double phase_clamp(const orc_params *p, double phi)
 {
+    if (p->density_literal) return phi;
     const double lo = p->phi_L < p->phi_H ? p->phi_L : p->phi_H;
     const double hi = p->phi_L < p->phi_H ? p->phi_H : p->phi_L;
     return phi < lo ? lo : (phi > hi ? hi : phi);
@@ -701,6 +704,25 @@ void orc_shift_equilibrium(orc_state *s, const double *phi, const double *u, con
                 s->phiA[c] = phi1;
                 for (int a = 0; a < 3; ++a) s->u[a * n + c] = u1[a];
             }
+}
+
+/* Equilibrium state of given macroscopic fields with the pressure p
+ * instead of p*: the initial-state rule of orc_init with
+ * p* = p / (rho(phi) cs^2) (Section 3.2), rho from eq. density as in the
+ * step.  Wall cells hold zeros.                                          */
+void orc_init_pressure(orc_state *s, const double *phi, const double *u, const double *pres)
+{
+    const orc_params *p = &s->p;
+    const int64_t n = s->n;
+    double *ps = (double *)calloc((size_t)n, sizeof(double));
+    if (!ps) return;
+    for (int64_t c = 0; c < n; ++c) {
+        int y = (int)((c / p->nx) % p->ny);
+        if (is_wall_row(p, y)) continue;
+        ps[c] = pres[c] / (density_of(p, phi[c]) * CS2);
+    }
+    orc_init(s, phi, u, ps);
+    free(ps);
 }
 
 /* Pressure p = p* rho cs^2 with p* = sum_i g_i (Section 3.2). */

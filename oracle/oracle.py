@@ -31,6 +31,7 @@ class OrcParams(C.Structure):
         ("rho_L", C.c_double), ("rho_H", C.c_double),
         ("tau_L", C.c_double), ("tau_H", C.c_double),
         ("accel", C.c_double * 3), ("rho_ref", C.c_double), ("normal_eps", C.c_double),
+        ("density_literal", C.c_int32),
     ]
 
 
@@ -77,6 +78,7 @@ def lib():
     L.orc_get_state.argtypes = [C.c_void_p] + [C.c_void_p] * 4
     L.orc_set_state.argtypes = [C.c_void_p] + [C.c_void_p] * 4
     L.orc_pressure.argtypes = [C.c_void_p, _D]
+    L.orc_init_pressure.argtypes = [C.c_void_p, _D, _D, _D]
     L.orc_shift_equilibrium.argtypes = [C.c_void_p, _D, _D, _D]
     L.orc_stats_compute.argtypes = [C.c_void_p, C.POINTER(OrcStats)]
     L.orc_num_threads.argtypes = []
@@ -106,6 +108,7 @@ class Params:
     accel: tuple = (0.0, 0.0, 0.0)
     buoyancy_rho_ref: float = 0.0
     normal_eps: float = 1e-12
+    density_literal: bool = False
 
     def to_c(self) -> OrcParams:
         p = OrcParams()
@@ -117,6 +120,7 @@ class Params:
             p.accel[a] = self.accel[a]
         p.rho_ref = self.buoyancy_rho_ref
         p.normal_eps = self.normal_eps
+        p.density_literal = int(bool(self.density_literal))
         return p
 
 
@@ -215,6 +219,13 @@ class Oracle:
         u = np.ascontiguousarray(u, dtype=np.float64).reshape((3,) + self.shape)
         pstar = np.ascontiguousarray(pstar, dtype=np.float64).reshape(self.shape)
         lib().orc_init(self._h, phi, u, pstar)
+
+    def init_pressure(self, phi, u, p):
+        """Equilibrium state of (phi, u) and the pressure p, p* = p/(rho cs^2)."""
+        phi = np.ascontiguousarray(phi, dtype=np.float64).reshape(self.shape)
+        u = np.ascontiguousarray(u, dtype=np.float64).reshape((3,) + self.shape)
+        p = np.ascontiguousarray(p, dtype=np.float64).reshape(self.shape)
+        lib().orc_init_pressure(self._h, phi, u, p)
 
     def step(self, n: int = 1):
         lib().orc_step(self._h, int(n))

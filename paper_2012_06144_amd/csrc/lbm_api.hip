@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <limits>
 #include <new>
 
 #include "lbm.h"
@@ -85,7 +86,7 @@ lbm_status validate(const lbm_params *p)
     if (!(p->rho_L > 0) || !(p->rho_H > 0)) return fail(LBM_EARG, "densities must be > 0");
     if (!(p->sigma >= 0)) return fail(LBM_EARG, "sigma must be >= 0");
     if (!(p->normal_eps >= 0)) return fail(LBM_EARG, "normal_eps must be >= 0");
-    if (p->reserved0 != 0) return fail(LBM_EARG, "reserved0 must be 0");
+    if (p->density_literal != 0 && p->density_literal != 1) return fail(LBM_EARG, "density_literal must be 0 or 1");
     return LBM_OK;
 }
 
@@ -135,8 +136,14 @@ Phys<R> make_phys(const lbm_params *p)
     ph.phi_H = (R)p->phi_H;
     ph.phi_0 = (R)(0.5 * (p->phi_L + p->phi_H));
     ph.inv_dphi = (R)(1.0 / (p->phi_H - p->phi_L));
-    ph.phi_lo = (R)(p->phi_L < p->phi_H ? p->phi_L : p->phi_H);
-    ph.phi_hi = (R)(p->phi_L < p->phi_H ? p->phi_H : p->phi_L);
+    if (p->density_literal) {
+        // no clamp: the interpolations of eq. density for every phi
+        ph.phi_lo = -std::numeric_limits<R>::max();
+        ph.phi_hi = std::numeric_limits<R>::max();
+    } else {
+        ph.phi_lo = (R)(p->phi_L < p->phi_H ? p->phi_L : p->phi_H);
+        ph.phi_hi = (R)(p->phi_L < p->phi_H ? p->phi_H : p->phi_L);
+    }
     ph.xi = (R)p->xi;
     ph.inv_xi = (R)(1.0 / p->xi);
     const double tau_phi = p->mobility / CS2;  // eq. mobility with dt = 1

@@ -60,10 +60,11 @@ struct Phys {
 };
 
 // Density and relaxation time of a cell (eq. density, tau interpolation of
-// Sec. 3.2), linear in phi between the bulk phases.  phi is clamped to
-// [phi_L, phi_H] first: the phase field overshoots that interval by ~1e-3
-// in the cores of small bubbles, and at rho_H/rho_L = 1000 an undershoot
-// of 1e-3 would put rho near zero.
+// Sec. 3.2), linear in phi between the bulk phases.  By default phi is
+// clamped to [phi_L, phi_H] first: the phase field overshoots that interval
+// by ~1e-3 in the cores of small bubbles, and at rho_H/rho_L = 1000 an
+// undershoot of 1e-3 would put rho near zero.  With the literal
+// interpolation the clamp bounds are +-max and the clamp does nothing.
 template <class R>
 __host__ __device__ inline R phase_clamp(const Phys<R> &ph, R phi)
 {

@@ -2,14 +2,13 @@
 //
 // The 3x3x3 convolution is an implicit GEMM: rows are output voxels, columns
 // output channels, the reduction runs over the 27 taps times the input
-// channels.  Each wavefront owns 32 consecutive voxels and NT x 32 output
-// channels and issues v_mfma_f32_32x32x16_bf16: lane l supplies 8 BF16
-// values of row l % 32 (the voxel, shifted by the tap) at channels
-// 8 * (l / 32) .. +7 of a 16-channel slice, and 8 BF16 weights of column
-// l % 32 at the same channels.  Channels-last activations and weights stored
-// as [tap][c_out][c_in] make both operands single 16-byte loads; zero
-// padding is a predicated load.  Accumulation is FP32; the epilogue adds the
-// bias, applies the activation and rounds to BF16 (or stores FP32).
+// channels.  The matrix cores take 32 x 32 x 16 BF16 products
+// (v_mfma_f32_32x32x16_bf16): lane l supplies 8 BF16 values of row l % 32
+// at channels 8 (l / 32) .. +7 of a 16-channel slice, and 8 BF16 weights of
+// column l % 32 at the same channels.  Channels-last activations and
+// weights stored as [tap][c_out][c_in] make both operands single 16-byte
+// reads.  Accumulation is FP32; the epilogue adds the bias, applies the
+// activation and rounds to BF16 (or stores FP32).
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -42,73 +41,139 @@ sg_status fail(sg_status s, const char *fmt, ...)
     } while (0)
 
 constexpr int kThreads = 256;
-constexpr int kRowsPerBlock = 128;  // 4 waves x 32 voxels
 
 __device__ inline float leaky(float v, float slope) { return v > 0.f ? v : slope * v; }
 
-// ---- convolution forward -------------------------------------------------------
-template <int NT>
-__global__ __launch_bounds__(kThreads) void k_conv3d(const bf16 *__restrict__ x, const bf16 *__restrict__ wt,
-                                                     const float *__restrict__ bias, void *__restrict__ y,
-                                                     int N, int D, int H, int W, int Ci, int Co, int n_store,
-                                                     int act, float slope, int y_f32)
-{
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int64_t V = (int64_t)N * D * H * W;
-    const int64_t m0 = (int64_t)blockIdx.x * kRowsPerBlock + wave * 32;
-    const int col0 = blockIdx.y * NT * 32;  // first output channel of this block
-    const int64_t mv = m0 + (lane & 31);
-    const bool valid = mv < V;
-    int w = 0, h = 0, d = 0, n = 0;
-    if (valid) {
-        int64_t t = mv;
-        w = (int)(t % W);
-        t /= W;
-        h = (int)(t % H);
-        t /= H;
-        d = (int)(t % D);
-        n = (int)(t / D);
-    }
-    const int kh = (lane >> 5) * 8;
-    f32x16 acc[NT];
-#pragma unroll
-    for (int j = 0; j < NT; ++j)
-        for (int r = 0; r < 16; ++r) acc[j][r] = 0.f;
-    const bf16x8 zero = {};
+// ---- convolution forward, input staged in LDS ---------------------------------
+// The same implicit GEMM with the input tile kept in LDS for all 27 taps.  A
+// block owns a box of BD = 4 planes x BH = 4 TH rows x TW columns of one
+// sample: 16 M-tiles of 32 voxels, each a TH x TW patch of a plane
+// (TW = 32, 16 or 8 by the width, TH = 32 / TW).  Wave w computes the four
+// tiles of plane w and NT x 32 output channels.  Per slice of 16 input
+// channels the block stages the box with a one-voxel halo,
+// (BD + 2)(BH + 2)(TW + 2) voxels of 16 channels at a 48-byte pitch (eight
+// consecutive voxels then cover all LDS banks, so the 16-byte operand reads
+// are conflict-free), then runs 27 taps x 4 tiles x NT MFMAs from it; the
+// B operand of a tap (weights, the same for every block, so L2 hits) is
+// loaded once per tap and shared by the four tiles.  Halo cells outside the
+// volume hold zeros (the padding).
+constexpr int kHaloPitch = 24;  // bf16 per staged voxel: 16 channels + 8 padding (48 B)
 
-    for (int t = 0; t < 27; ++t) {
-        const int a = t / 9 - 1, b = (t / 3) % 3 - 1, c = t % 3 - 1;
-        const int dd = d + a, hh = h + b, ww = w + c;
-        const bool in = valid && dd >= 0 && dd < D && hh >= 0 && hh < H && ww >= 0 && ww < W;
-        const int64_t src = in ? ((((int64_t)n * D + dd) * H + hh) * W + ww) : 0;
-        const bf16 *xp = x + src * Ci + kh;
-        const bf16 *wp = wt + ((int64_t)t * Co + col0 + (lane & 31)) * Ci + kh;
-        for (int c0 = 0; c0 < Ci; c0 += 16) {
-            const bf16x8 av = in ? *reinterpret_cast<const bf16x8 *>(xp + c0) : zero;
+template <int TW>
+struct HaloBox {
+    static constexpr int TH = 32 / TW;
+    static constexpr int BD = 4, BH = 4 * TH;
+    static constexpr int HD = BD + 2, HH = BH + 2, HW = TW + 2;
+    static constexpr int NV = HD * HH * HW;          // staged voxels
+    static constexpr int ITEMS = (2 * NV + kThreads - 1) / kThreads;  // 16-byte loads per thread
+};
+
+template <int NT, int TW>
+__global__ __launch_bounds__(kThreads, 2) void k_conv3d_lds(const bf16 *__restrict__ x,
+                                                            const bf16 *__restrict__ wt,
+                                                            const float *__restrict__ bias,
+                                                            void *__restrict__ y, int N, int D, int H, int W,
+                                                            int Ci, int Co, int n_store, int act, float slope,
+                                                            int y_f32, int nbd, int nbh, int nbw)
+{
+    using B = HaloBox<TW>;
+    __shared__ __attribute__((aligned(16))) bf16 hs[B::NV * kHaloPitch];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    // boxes in storage order; consecutive boxes on one XCD (block i runs on XCD i mod 8)
+    const int64_t nbox = (int64_t)N * nbd * nbh * nbw;
+    int64_t bl = blockIdx.x;
+    {
+        const int64_t per = (nbox + 7) / 8;
+        const int64_t rem = nbox % 8 == 0 ? 8 : nbox % 8;
+        const int64_t xcd = bl % 8, k = bl / 8;
+        // XCDs below rem hold `per` boxes, the others per - 1
+        bl = xcd < rem ? xcd * per + k : rem * per + (xcd - rem) * (per - 1) + k;
+    }
+    int64_t t = bl;
+    const int bw = (int)(t % nbw);
+    t /= nbw;
+    const int bh = (int)(t % nbh);
+    t /= nbh;
+    const int bd = (int)(t % nbd);
+    const int n = (int)(t / nbd);
+    const int d0 = bd * B::BD, h0 = bh * B::BH, w0 = bw * TW;
+    const int col0 = blockIdx.y * NT * 32;
+    const int lr = lane & 31, kh = (lane >> 5) * 8;
+    const int th = lr / TW, tw = lr % TW;
+
+    f32x16 acc[4][NT];
 #pragma unroll
-            for (int j = 0; j < NT; ++j) {
-                const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(wp + (int64_t)j * 32 * Ci + c0);
-                acc[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc[j], 0, 0, 0);
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int j = 0; j < NT; ++j)
+            for (int r = 0; r < 16; ++r) acc[m][j][r] = 0.f;
+
+    for (int c0 = 0; c0 < Ci; c0 += 16) {
+        // stage the box and its halo: all loads first, then all LDS stores
+        bf16x8 tmp[B::ITEMS];
+#pragma unroll
+        for (int i = 0; i < B::ITEMS; ++i) {
+            const int item = threadIdx.x + i * kThreads;
+            bf16x8 v = {};
+            if (item < 2 * B::NV) {
+                const int half = item & 1, hv = item >> 1;
+                const int hw = hv % B::HW, hh = (hv / B::HW) % B::HH, hd = hv / (B::HW * B::HH);
+                const int dd = d0 - 1 + hd, yy = h0 - 1 + hh, xx = w0 - 1 + hw;
+                if (dd >= 0 && dd < D && yy >= 0 && yy < H && xx >= 0 && xx < W)
+                    v = *reinterpret_cast<const bf16x8 *>(
+                        x + ((((int64_t)n * D + dd) * H + yy) * W + xx) * Ci + c0 + half * 8);
+            }
+            tmp[i] = v;
+        }
+        __syncthreads();  // the previous slice's operand reads are done
+#pragma unroll
+        for (int i = 0; i < B::ITEMS; ++i) {
+            const int item = threadIdx.x + i * kThreads;
+            if (item < 2 * B::NV)
+                *reinterpret_cast<bf16x8 *>(hs + (item >> 1) * kHaloPitch + (item & 1) * 8) = tmp[i];
+        }
+        __syncthreads();
+        const bf16 *wp = wt + ((int64_t)col0 + lr) * Ci + c0 + kh;
+#pragma unroll 3
+        for (int tap = 0; tap < 27; ++tap) {
+            const int a = tap / 9, b = (tap / 3) % 3, c = tap % 3;  // offsets + 1
+            bf16x8 bv[NT];
+#pragma unroll
+            for (int j = 0; j < NT; ++j)
+                bv[j] = *reinterpret_cast<const bf16x8 *>(wp + ((int64_t)tap * Co + j * 32) * Ci);
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                const int hv = ((wave + a) * B::HH + m * B::TH + th + b) * B::HW + tw + c;
+                const bf16x8 av = *reinterpret_cast<const bf16x8 *>(hs + hv * kHaloPitch + kh);
+#pragma unroll
+                for (int j = 0; j < NT; ++j)
+                    acc[m][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv[j], acc[m][j], 0, 0, 0);
             }
         }
     }
     // D layout of the 32x32 tile: column l % 32, row 8 (r/4) + 4 (l/32) + r % 4
+    const int dv = d0 + wave;
+    if (dv >= D) return;
 #pragma unroll
     for (int j = 0; j < NT; ++j) {
-        const int col = col0 + j * 32 + (lane & 31);
+        const int col = col0 + j * 32 + lr;
         if (col >= n_store) continue;
         const float bc = bias ? bias[col] : 0.f;
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            const int row = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-            const int64_t m = m0 + row;
-            if (m >= V) continue;
-            float v = acc[j][r] + bc;
-            if (act) v = leaky(v, slope);
-            if (y_f32)
-                reinterpret_cast<float *>(y)[m * n_store + col] = v;
-            else
-                reinterpret_cast<bf16 *>(y)[m * n_store + col] = (bf16)v;
+        for (int m = 0; m < 4; ++m) {
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int row = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                const int hv = h0 + m * B::TH + row / TW, wv = w0 + row % TW;
+                if (hv >= H || wv >= W) continue;
+                const int64_t mv = (((int64_t)n * D + dv) * H + hv) * W + wv;
+                float v = acc[m][j][r] + bc;
+                if (act) v = leaky(v, slope);
+                if (y_f32)
+                    reinterpret_cast<float *>(y)[mv * n_store + col] = v;
+                else
+                    reinterpret_cast<bf16 *>(y)[mv * n_store + col] = (bf16)v;
+            }
         }
     }
 }
@@ -151,7 +216,9 @@ struct BwPlan {
     int64_t per;     // row tiles per chunk
 };
 
-BwPlan bw_plan(int n, int d, int h, int w, int ci, int co)
+// max_chunks bounds the number of per-chunk partial sums (the scratch they
+// take); <= 0 leaves it unbounded.
+BwPlan bw_plan(int n, int d, int h, int w, int ci, int co, int64_t max_chunks = 0)
 {
     BwPlan p;
     p.ntw = (w + kBwTile - 1) / kBwTile;
@@ -159,6 +226,7 @@ BwPlan bw_plan(int n, int d, int h, int w, int ci, int co)
     const int64_t mn = (int64_t)(co / 32) * ((ci + 31) / 32);
     int64_t ch = (kBwTargetBlocks + mn - 1) / mn;
     if (ch > p.tiles) ch = p.tiles;
+    if (max_chunks > 0 && ch > max_chunks) ch = max_chunks;
     if (ch < 1) ch = 1;
     p.per = (p.tiles + ch - 1) / ch;
     p.chunks = (int)((p.tiles + p.per - 1) / p.per);
@@ -744,17 +812,34 @@ __global__ void k_moments2(const double *__restrict__ part, double *__restrict__
 }
 
 constexpr int kProjBlocks = 1024;
-__global__ __launch_bounds__(kThreads) void k_mass_sums(const float *__restrict__ phi, int64_t n, float pmin,
-                                                        float pmax, double *__restrict__ part)
+// Weight of a cell in the mass projection: 4 q (1 - q) with q the phase
+// fraction clamped to [0, 1]; zero in both bulk phases and in wall rows.
+__device__ inline double proj_weight(double f, double pmin, double inv)
+{
+    double q = (f - pmin) * inv;
+    q = q < 0.0 ? 0.0 : (q > 1.0 ? 1.0 : q);
+    return 4.0 * q * (1.0 - q);
+}
+
+__device__ inline bool proj_wall(int64_t i, int nx, int ny, int walls_y)
+{
+    if (!walls_y) return false;
+    const int y = (int)((i / nx) % ny);
+    return y == 0 || y == ny - 1;
+}
+
+__global__ __launch_bounds__(kThreads) void k_mass_sums(const float *__restrict__ phi, int nx, int ny, int64_t n,
+                                                        int walls_y, float pmin, float pmax,
+                                                        double *__restrict__ part)
 {
     __shared__ double s0[kThreads], s1[kThreads];
     double a = 0.0, w = 0.0;
     const double inv = 1.0 / ((double)pmax - (double)pmin);
     for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)kProjBlocks * kThreads) {
+        if (proj_wall(i, nx, ny, walls_y)) continue;
         const double f = phi[i];
-        const double q = (f - pmin) * inv;
         a += f;
-        w += 4.0 * q * (1.0 - q);
+        w += proj_weight(f, pmin, inv);
     }
     s0[threadIdx.x] = a;
     s1[threadIdx.x] = w;
@@ -773,8 +858,8 @@ __global__ __launch_bounds__(kThreads) void k_mass_sums(const float *__restrict_
 }
 
 // sums the block partials in a fixed order (one thread), then corrects phi
-__global__ void k_mass_correct(float *__restrict__ phi, int64_t n, const double *__restrict__ part,
-                               double target, float pmin, float pmax)
+__global__ void k_mass_correct(float *__restrict__ phi, int nx, int ny, int64_t n, int walls_y,
+                               const double *__restrict__ part, double target, float pmin, float pmax)
 {
     __shared__ double coef;
     if (threadIdx.x == 0) {
@@ -788,9 +873,9 @@ __global__ void k_mass_correct(float *__restrict__ phi, int64_t n, const double 
     __syncthreads();
     const double inv = 1.0 / ((double)pmax - (double)pmin);
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        if (proj_wall(i, nx, ny, walls_y)) continue;
         const double f = phi[i];
-        const double q = (f - pmin) * inv;
-        phi[i] = (float)(f + coef * 4.0 * q * (1.0 - q));
+        phi[i] = (float)(f + coef * proj_weight(f, pmin, inv));
     }
 }
 
@@ -798,71 +883,26 @@ unsigned blocks_for(int64_t n) { return (unsigned)((n + kThreads - 1) / kThreads
 
 bool aligned16(const void *p) { return ((uintptr_t)p & 15) == 0; }
 
-}  // namespace
-
-extern "C" {
-
-sg_status sg_conv3d_fwd(const void *x, int32_t n, int32_t d, int32_t h, int32_t w, int32_t c_in,
-                        const void *wt, const float *bias, int32_t c_out, int32_t n_store, int32_t act,
-                        float slope, void *y, int32_t y_f32, void *stream)
+sg_status check_bwd_weight_args(const void *x, const void *dy, int n, int d, int h, int w, int c_in, int c_out,
+                                const float *dw)
 {
-    if (!x || !wt || !y) return fail(SG_EARG, "NULL tensor");
-    if (n < 1 || d < 1 || h < 1 || w < 1) return fail(SG_EARG, "bad shape");
-    if (c_in < 16 || c_in % 16) return fail(SG_EARG, "c_in must be a positive multiple of 16 (got %d)", c_in);
-    if (c_out < 32 || c_out % 32) return fail(SG_EARG, "c_out must be a positive multiple of 32 (got %d)", c_out);
-    if (n_store < 1 || n_store > c_out) return fail(SG_EARG, "n_store must be in [1, c_out]");
-    if (!aligned16(x) || !aligned16(wt)) return fail(SG_EARG, "x and wt must be 16-byte aligned");
-    const int64_t V = (int64_t)n * d * h * w;
-    const int tiles = c_out / 32;
-    const int nt = tiles % 4 == 0 ? 4 : tiles % 3 == 0 ? 3 : tiles % 2 == 0 ? 2 : 1;
-    const dim3 grid((unsigned)((V + kRowsPerBlock - 1) / kRowsPerBlock), (unsigned)(tiles / nt));
-    hipStream_t s = (hipStream_t)stream;
-    const bf16 *X = (const bf16 *)x, *Wt = (const bf16 *)wt;
-    switch (nt) {
-    case 4: hipLaunchKernelGGL(k_conv3d<4>, grid, dim3(kThreads), 0, s, X, Wt, bias, y, n, d, h, w, c_in, c_out, n_store, act, slope, y_f32); break;
-    case 3: hipLaunchKernelGGL(k_conv3d<3>, grid, dim3(kThreads), 0, s, X, Wt, bias, y, n, d, h, w, c_in, c_out, n_store, act, slope, y_f32); break;
-    case 2: hipLaunchKernelGGL(k_conv3d<2>, grid, dim3(kThreads), 0, s, X, Wt, bias, y, n, d, h, w, c_in, c_out, n_store, act, slope, y_f32); break;
-    default: hipLaunchKernelGGL(k_conv3d<1>, grid, dim3(kThreads), 0, s, X, Wt, bias, y, n, d, h, w, c_in, c_out, n_store, act, slope, y_f32); break;
-    }
-    SG_LAUNCH_CHECK();
-    return SG_OK;
-}
-
-sg_status sg_weight_mirror(const void *wt, int32_t c_out, int32_t c_in, void *wm, void *stream)
-{
-    if (!wt || !wm || c_out < 1 || c_in < 1) return fail(SG_EARG, "bad arguments");
-    const int64_t total = (int64_t)27 * c_out * c_in;
-    hipLaunchKernelGGL(k_weight_mirror, dim3(blocks_for(total)), dim3(kThreads), 0, (hipStream_t)stream,
-                       (const bf16 *)wt, c_out, c_in, (bf16 *)wm);
-    SG_LAUNCH_CHECK();
-    return SG_OK;
-}
-
-size_t sg_bwd_weight_workspace(int32_t n, int32_t d, int32_t h, int32_t w, int32_t c_in, int32_t c_out)
-{
-    if (n < 1 || d < 1 || h < 1 || w < 1 || c_in < 1 || c_out < 32) return 0;
-    const BwPlan p = bw_plan(n, d, h, w, c_in, c_out);
-    const int64_t V = (int64_t)n * d * h * w;
-    const int64_t nb = (V + kBiasChunk - 1) / kBiasChunk;
-    return ((size_t)p.chunks * 27 * (size_t)c_in * c_out + (size_t)nb * c_out) * sizeof(float);
-}
-
-sg_status sg_conv3d_bwd_weight(const void *x, const void *dy, int32_t n, int32_t d, int32_t h, int32_t w,
-                               int32_t c_in, int32_t c_out, float *dw, float *db, void *ws, size_t ws_bytes,
-                               void *stream)
-{
-    if (!x || !dy || !dw || !ws) return fail(SG_EARG, "NULL tensor");
+    if (!x || !dy || !dw) return fail(SG_EARG, "NULL tensor");
     if (n < 1 || d < 1 || h < 1 || w < 1) return fail(SG_EARG, "bad shape");
     if (c_in < 16 || c_in % 16) return fail(SG_EARG, "c_in must be a positive multiple of 16 (got %d)", c_in);
     if (c_out < 32 || c_out % 32) return fail(SG_EARG, "c_out must be a multiple of 32 (got %d)", c_out);
     if (!aligned16(x) || !aligned16(dy)) return fail(SG_EARG, "x and dy must be 16-byte aligned");
-    const size_t need = sg_bwd_weight_workspace(n, d, h, w, c_in, c_out);
-    if (ws_bytes < need) return fail(SG_ESIZE, "workspace has %zu bytes, needs %zu", ws_bytes, need);
-    const BwPlan p = bw_plan(n, d, h, w, c_in, c_out);
+    return SG_OK;
+}
+
+// Weight and bias gradient through the scratch `ws`: per-chunk partial sums
+// part[chunk][t][co][ci] (every entry written before it is read), then a
+// fixed-order sum over chunks; bias partials behind them.
+sg_status launch_bwd_weight(const void *x, const void *dy, int n, int d, int h, int w, int c_in, int c_out,
+                            float *dw, float *db, const BwPlan &p, float *ws, hipStream_t s)
+{
     const int64_t V = (int64_t)n * d * h * w;
-    float *part = (float *)ws;
+    float *part = ws;
     float *bpart = part + (int64_t)p.chunks * 27 * c_in * c_out;
-    hipStream_t s = (hipStream_t)stream;
     const dim3 grid((unsigned)p.chunks, (unsigned)(c_out / 32), (unsigned)((c_in + 31) / 32));
     hipLaunchKernelGGL(k_conv3d_bwd_weight, grid, dim3(kThreads), 0, s, (const bf16 *)x, (const bf16 *)dy, n, d,
                        h, w, c_in, c_out, p.ntw, p.tiles, p.per, part);
@@ -880,6 +920,93 @@ sg_status sg_conv3d_bwd_weight(const void *x, const void *dy, int32_t n, int32_t
         SG_LAUNCH_CHECK();
     }
     return SG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+sg_status sg_conv3d_fwd(const void *x, int32_t n, int32_t d, int32_t h, int32_t w, int32_t c_in,
+                        const void *wt, const float *bias, int32_t c_out, int32_t n_store, int32_t act,
+                        float slope, void *y, int32_t y_f32, void *stream)
+{
+    if (!x || !wt || !y) return fail(SG_EARG, "NULL tensor");
+    if (n < 1 || d < 1 || h < 1 || w < 1) return fail(SG_EARG, "bad shape");
+    if (c_in < 16 || c_in % 16) return fail(SG_EARG, "c_in must be a positive multiple of 16 (got %d)", c_in);
+    if (c_out < 32 || c_out % 32) return fail(SG_EARG, "c_out must be a positive multiple of 32 (got %d)", c_out);
+    if (n_store < 1 || n_store > c_out) return fail(SG_EARG, "n_store must be in [1, c_out]");
+    if (!aligned16(x) || !aligned16(wt)) return fail(SG_EARG, "x and wt must be 16-byte aligned");
+    const int tiles = c_out / 32;
+    const int nt = tiles % 2 == 0 ? 2 : 1;
+    const int tw = w > 16 ? 32 : w > 8 ? 16 : 8;
+    const int th = 32 / tw;
+    const int nbd = (d + 3) / 4, nbh = (h + 4 * th - 1) / (4 * th), nbw = (w + tw - 1) / tw;
+    const int64_t nbox = (int64_t)n * nbd * nbh * nbw;
+    if (nbox > 0x7fffffff) return fail(SG_ESIZE, "too many voxels");
+    const dim3 grid((unsigned)nbox, (unsigned)(tiles / nt));
+    hipStream_t s = (hipStream_t)stream;
+    const bf16 *X = (const bf16 *)x, *Wt = (const bf16 *)wt;
+#define SG_CONV_LAUNCH(NT_, TW_)                                                                              \
+    hipLaunchKernelGGL((k_conv3d_lds<NT_, TW_>), grid, dim3(kThreads), 0, s, X, Wt, bias, y, n, d, h, w, c_in, \
+                       c_out, n_store, act, slope, y_f32, nbd, nbh, nbw)
+    if (nt == 2) {
+        if (tw == 32) SG_CONV_LAUNCH(2, 32);
+        else if (tw == 16) SG_CONV_LAUNCH(2, 16);
+        else SG_CONV_LAUNCH(2, 8);
+    } else {
+        if (tw == 32) SG_CONV_LAUNCH(1, 32);
+        else if (tw == 16) SG_CONV_LAUNCH(1, 16);
+        else SG_CONV_LAUNCH(1, 8);
+    }
+#undef SG_CONV_LAUNCH
+    SG_LAUNCH_CHECK();
+    return SG_OK;
+}
+
+sg_status sg_weight_mirror(const void *wt, int32_t c_out, int32_t c_in, void *wm, void *stream)
+{
+    if (!wt || !wm || c_out < 1 || c_in < 1) return fail(SG_EARG, "bad arguments");
+    const int64_t total = (int64_t)27 * c_out * c_in;
+    hipLaunchKernelGGL(k_weight_mirror, dim3(blocks_for(total)), dim3(kThreads), 0, (hipStream_t)stream,
+                       (const bf16 *)wt, c_out, c_in, (bf16 *)wm);
+    SG_LAUNCH_CHECK();
+    return SG_OK;
+}
+
+sg_status sg_conv3d_bwd_data(const void *dy, int32_t n, int32_t d, int32_t h, int32_t w, int32_t c_out,
+                             const void *wt, int32_t c_in, void *dx, void *ws, size_t ws_bytes, void *stream)
+{
+    if (!dy || !wt || !dx || !ws) return fail(SG_EARG, "NULL tensor");
+    if (c_in < 32 || c_in % 32) return fail(SG_EARG, "c_in must be a positive multiple of 32 (got %d)", c_in);
+    if (c_out < 16 || c_out % 16) return fail(SG_EARG, "c_out must be a positive multiple of 16 (got %d)", c_out);
+    const size_t need = (size_t)27 * c_in * c_out * sizeof(bf16);
+    if (ws_bytes < need) return fail(SG_ESIZE, "workspace has %zu bytes, needs %zu", ws_bytes, need);
+    if (!aligned16(ws)) return fail(SG_EARG, "workspace must be 16-byte aligned");
+    sg_status st = sg_weight_mirror(wt, c_out, c_in, ws, stream);
+    if (st != SG_OK) return st;
+    return sg_conv3d_fwd(dy, n, d, h, w, c_out, ws, nullptr, c_in, c_in, 0, 0.f, dx, 0, stream);
+}
+
+size_t sg_bwd_weight_workspace(int32_t n, int32_t d, int32_t h, int32_t w, int32_t c_in, int32_t c_out)
+{
+    if (n < 1 || d < 1 || h < 1 || w < 1 || c_in < 1 || c_out < 32) return 0;
+    const BwPlan p = bw_plan(n, d, h, w, c_in, c_out);
+    const int64_t V = (int64_t)n * d * h * w;
+    const int64_t nb = (V + kBiasChunk - 1) / kBiasChunk;
+    return ((size_t)p.chunks * 27 * (size_t)c_in * c_out + (size_t)nb * c_out) * sizeof(float);
+}
+
+sg_status sg_conv3d_bwd_weight(const void *x, const void *dy, int32_t n, int32_t d, int32_t h, int32_t w,
+                               int32_t c_in, int32_t c_out, float *dw, float *db, void *ws, size_t ws_bytes,
+                               void *stream)
+{
+    sg_status st = check_bwd_weight_args(x, dy, n, d, h, w, c_in, c_out, dw);
+    if (st != SG_OK) return st;
+    if (!ws) return fail(SG_EARG, "NULL workspace");
+    const size_t need = sg_bwd_weight_workspace(n, d, h, w, c_in, c_out);
+    if (ws_bytes < need) return fail(SG_ESIZE, "workspace has %zu bytes, needs %zu", ws_bytes, need);
+    const BwPlan p = bw_plan(n, d, h, w, c_in, c_out);
+    return launch_bwd_weight(x, dy, n, d, h, w, c_in, c_out, dw, db, p, (float *)ws, (hipStream_t)stream);
 }
 
 sg_status sg_leaky_bwd(const void *y, const void *dy, void *dp, size_t count, float slope, void *stream)
@@ -1124,14 +1251,18 @@ sg_status sg_channel_moments(const float *a, int64_t rows, int32_t c, double *ou
     return SG_OK;
 }
 
-sg_status sg_mass_project(float *phi, int64_t n, double target, float pmin, float pmax, double *scratch,
-                          void *stream)
+sg_status sg_mass_project(float *phi, int32_t nx, int32_t ny, int32_t nz, int32_t walls_y, double target,
+                          float pmin, float pmax, double *scratch, void *stream)
 {
-    if (!phi || !scratch || n < 1 || !(pmax > pmin)) return fail(SG_EARG, "bad arguments");
+    if (!phi || !scratch || nx < 1 || ny < 1 || nz < 1 || !(pmax > pmin)) return fail(SG_EARG, "bad arguments");
+    if (walls_y && ny < 3) return fail(SG_EARG, "walls_y needs ny >= 3");
+    const int64_t n = (int64_t)nx * ny * nz;
     hipStream_t s = (hipStream_t)stream;
-    hipLaunchKernelGGL(k_mass_sums, dim3(kProjBlocks), dim3(kThreads), 0, s, phi, n, pmin, pmax, scratch);
+    hipLaunchKernelGGL(k_mass_sums, dim3(kProjBlocks), dim3(kThreads), 0, s, phi, nx, ny, n, walls_y, pmin, pmax,
+                       scratch);
     SG_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_mass_correct, dim3(4096), dim3(kThreads), 0, s, phi, n, scratch, target, pmin, pmax);
+    hipLaunchKernelGGL(k_mass_correct, dim3(4096), dim3(kThreads), 0, s, phi, nx, ny, n, walls_y, scratch, target,
+                       pmin, pmax);
     SG_LAUNCH_CHECK();
     return SG_OK;
 }

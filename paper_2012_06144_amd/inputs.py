@@ -41,6 +41,7 @@ class Setup:
     accel: tuple = (0.0, 0.0, 0.0)
     buoyancy_rho_ref: float = 0.0
     normal_eps: float = 1e-12
+    density_literal: bool = False
     steps: int = 1000
     # field recipe
     kind: str = "bubble"          # "bubble" (light inside), "droplet" (heavy inside), "swarm", "uniform"
@@ -66,7 +67,8 @@ class Setup:
                     phi_L=self.phi_L, phi_H=self.phi_H, xi=self.xi, mobility=self.mobility,
                     sigma=self.sigma, rho_L=self.rho_L, rho_H=self.rho_H,
                     tau_L=self.tau_L, tau_H=self.tau_H, accel=tuple(self.accel),
-                    buoyancy_rho_ref=self.buoyancy_rho_ref, normal_eps=self.normal_eps)
+                    buoyancy_rho_ref=self.buoyancy_rho_ref, normal_eps=self.normal_eps,
+                    density_literal=bool(self.density_literal))
 
     def with_grid(self, nx, ny, nz, **kw):
         d = asdict(self)

@@ -38,7 +38,7 @@ class LbmParams(C.Structure):
         ("mobility", C.c_double), ("sigma", C.c_double),
         ("rho_L", C.c_double), ("rho_H", C.c_double), ("tau_L", C.c_double), ("tau_H", C.c_double),
         ("body_accel", C.c_double * 3), ("buoyancy_rho_ref", C.c_double), ("normal_eps", C.c_double),
-        ("storage", C.c_int32), ("reserved0", C.c_int32),
+        ("storage", C.c_int32), ("density_literal", C.c_int32),
     ]
 
 
@@ -228,7 +228,7 @@ def lbm_last_error() -> str:
 
 def make_params(nx, ny, nz, walls_y=False, phi_L=0.0, phi_H=1.0, xi=4.0, mobility=0.02,
                 sigma=1e-3, rho_L=1.0, rho_H=10.0, tau_L=1.0, tau_H=1.0, accel=(0.0, 0.0, 0.0),
-                buoyancy_rho_ref=0.0, normal_eps=1e-12, storage="f64") -> LbmParams:
+                buoyancy_rho_ref=0.0, normal_eps=1e-12, density_literal=False, storage="f64") -> LbmParams:
     p = LbmParams()
     p.nx, p.ny, p.nz, p.walls_y = int(nx), int(ny), int(nz), int(bool(walls_y))
     p.phi_L, p.phi_H, p.xi, p.mobility, p.sigma = phi_L, phi_H, xi, mobility, sigma
@@ -237,6 +237,7 @@ def make_params(nx, ny, nz, walls_y=False, phi_L=0.0, phi_H=1.0, xi=4.0, mobilit
         p.body_accel[a] = float(accel[a])
     p.buoyancy_rho_ref = float(buoyancy_rho_ref)
     p.normal_eps = normal_eps
+    p.density_literal = int(bool(density_literal))
     p.storage = STORAGE[storage] if isinstance(storage, str) else int(storage)
     return p
 

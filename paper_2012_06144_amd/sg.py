@@ -12,7 +12,7 @@ import ctypes as C
 from .lbm import LIB_PATH, LbmError, _lib as _L  # noqa: F401  (loads the library)
 
 EXPORTS = [
-    "sg_conv3d_fwd", "sg_weight_mirror", "sg_bwd_weight_workspace", "sg_conv3d_bwd_weight",
+    "sg_conv3d_fwd", "sg_weight_mirror", "sg_conv3d_bwd_data", "sg_bwd_weight_workspace", "sg_conv3d_bwd_weight",
     "sg_leaky_bwd", "sg_pool2_fwd", "sg_pool2_bwd", "sg_up2_fwd", "sg_up2_bwd", "sg_concat",
     "sg_split", "sg_mse", "sg_adam", "sg_to_bf16", "sg_to_f32", "sg_add", "sg_fields_to_input",
     "sg_state_to_input", "sg_make_target", "sg_apply_prediction", "sg_advect_phase", "sg_projective_step",
@@ -24,6 +24,7 @@ _vp, _i, _i64, _f, _sz = C.c_void_p, C.c_int32, C.c_int64, C.c_float, C.c_size_t
 _SIG = {
     "sg_conv3d_fwd": [_vp, _i, _i, _i, _i, _i, _vp, _vp, _i, _i, _i, _f, _vp, _i, _vp],
     "sg_weight_mirror": [_vp, _i, _i, _vp, _vp],
+    "sg_conv3d_bwd_data": [_vp, _i, _i, _i, _i, _i, _vp, _i, _vp, _vp, _sz, _vp],
     "sg_bwd_weight_workspace": [_i, _i, _i, _i, _i, _i],
     "sg_conv3d_bwd_weight": [_vp, _vp, _i, _i, _i, _i, _i, _i, _vp, _vp, _vp, _sz, _vp],
     "sg_leaky_bwd": [_vp, _vp, _vp, _sz, _f, _vp],
@@ -48,7 +49,7 @@ _SIG = {
     "sg_channel_moments": [_vp, _i64, _i, _vp, _vp, _vp],
     "sg_shift_boxes": [_vp, _i64, _i, _i, _i, _vp, _vp, _vp],
     "sg_box_moments": [_vp, _i64, _i, _i, _i, _f, _f, _vp, _vp],
-    "sg_mass_project": [_vp, _i64, C.c_double, _f, _f, _vp, _vp],
+    "sg_mass_project": [_vp, _i, _i, _i, _i, C.c_double, _f, _f, _vp, _vp],
     "sg_last_error": [],
 }
 for _name, _args in _SIG.items():
@@ -88,6 +89,15 @@ def sg_conv3d_fwd(x, wt, bias, c_out, n_store, act, slope, y, y_f32, stream=None
 def sg_weight_mirror(wt, wm, stream=None):
     _, c_out, c_in = wt.shape
     _check(_L.sg_weight_mirror(_p(wt), c_out, c_in, _p(wm), _stream(stream)), "sg_weight_mirror")
+
+
+def sg_conv3d_bwd_data(dy, wt, dx, wm, stream=None):
+    """dx (N, D, H, W, c_in) from dy (N, D, H, W, c_out) and wt (27, c_out, c_in);
+    wm is a BF16 workspace of 27 c_in c_out elements."""
+    n, d, h, w, c_out = dy.shape
+    c_in = wt.shape[2]
+    _check(_L.sg_conv3d_bwd_data(_p(dy), n, d, h, w, c_out, _p(wt), c_in, _p(dx), _p(wm),
+                                 wm.numel() * wm.element_size(), _stream(stream)), "sg_conv3d_bwd_data")
 
 
 def sg_bwd_weight_workspace(n, d, h, w, c_in, c_out) -> int:
@@ -231,9 +241,11 @@ def sg_box_moments(state, count, bx, by, bz, phi_heavy, phi_light, out, stream=N
                              _stream(stream)), "sg_box_moments")
 
 
-def sg_mass_project(phi, target_mass, phi_min, phi_max, scratch, stream=None):
-    _check(_L.sg_mass_project(_p(phi), phi.numel(), float(target_mass), float(phi_min), float(phi_max),
-                              _p(scratch), _stream(stream)), "sg_mass_project")
+def sg_mass_project(phi, walls_y, target_mass, phi_min, phi_max, scratch, stream=None):
+    """phi: FP32 field shaped (nz, ny, nx)."""
+    nz, ny, nx = phi.shape
+    _check(_L.sg_mass_project(_p(phi), nx, ny, nz, int(bool(walls_y)), float(target_mass), float(phi_min),
+                              float(phi_max), _p(scratch), _stream(stream)), "sg_mass_project")
 
 
 def sg_last_error() -> str:

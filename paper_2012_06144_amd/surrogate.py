@@ -167,9 +167,8 @@ class Net:
         sg.sg_conv3d_bwd_weight(x, dp, d["gw"], d["gb"], self._ws_for(x, co))
         if not need_dx:
             return None
-        sg.sg_weight_mirror(d["wt"], d["wm"])
         dx = self._empty(x.shape)
-        sg.sg_conv3d_fwd(dp, d["wm"], None, ci, ci, 0, 0.0, dx, 0)
+        sg.sg_conv3d_bwd_data(dp, d["wt"], dx, d["wm"])
         return dx
 
     def _split(self, g, ca, cb):
@@ -730,7 +729,8 @@ def run_with_jumps(net, solver, setup, total_steps, jc: JumpConfig, log=print, m
         if across:
             F_keep.copy_(F_now)
         inc = _jump(net, mode, F_now, F_prev, setup, box, jc, diagnostics=len(traj) <= 4, memory=memory)
-        sg.sg_mass_project(F_now[0], m0, setup.phi_L, setup.phi_H, scratch)
+        sg.sg_mass_project(F_now[0], setup.walls_y, m0, min(setup.phi_L, setup.phi_H), max(setup.phi_L, setup.phi_H),
+                           scratch)
         solver.set_macroscopic(F_now[0], F_now[1:4], F_now[4], keep_neq=jc.keep_neq)
         torch.cuda.synchronize()
         t_jump += time.perf_counter() - tp
@@ -948,6 +948,75 @@ def _cmd_jump(a):
     return out
 
 
+def _cmd_convbench(a):
+    """Times the network's convolutions on one batch of the training crop
+    shape with HIP events on the current stream: each layer's forward
+    convolution, input gradient and weight gradient alone (mean of a.reps
+    launches after one warm-up), then the whole forward pass and the whole
+    forward + backward pass.  FLOP counts are the algorithmic 2 x 27 x
+    c_in x c_out per output voxel."""
+    import torch
+    n, dd, hh, ww = (int(v) for v in a.shape.split("x"))
+    net = Net(seed=0)
+    dev = net.device
+    g = torch.Generator(device="cpu").manual_seed(1)
+    x = (torch.randn((n, dd, hh, ww, 16), generator=g) * 0.5).to(dev, torch.bfloat16)
+    stream = torch.cuda.current_stream(dev)
+    levels = {"enc0": 1, "enc1": 2, "enc2": 4, "bot_": 8, "dec2": 4, "dec1": 2, "dec0": 1, "out": 1}
+
+    def timed(fn, reps):
+        fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    layers = []
+    for name, ci, co, act in LAYERS:
+        f = levels[name[:4] if name != "out" else "out"]
+        shp = (n, dd // f, hh // f, ww // f)
+        V = shp[0] * shp[1] * shp[2] * shp[3]
+        xi = (torch.randn(shp + (ci,), generator=g) * 0.5).to(dev, torch.bfloat16)
+        dy = (torch.randn(shp + (co,), generator=g) * 0.5).to(dev, torch.bfloat16)
+        d = net.p[name]
+        y = torch.empty(shp + (co,), device=dev, dtype=torch.bfloat16)
+        dx = torch.empty(shp + (ci,), device=dev, dtype=torch.bfloat16)
+        ws = net._ws_for(xi, co)
+        flop = 2.0 * 27 * ci * co * V
+        t_f = timed(lambda: sg.sg_conv3d_fwd(xi, d["wt"], d["b"], co, co, act, SLOPE, y, 0), a.reps)
+        t_d = (timed(lambda: sg.sg_conv3d_bwd_data(dy, d["wt"], dx, d["wm"]), a.reps)
+               if ci % 32 == 0 else None)
+        t_w = timed(lambda: sg.sg_conv3d_bwd_weight(xi, dy, d["gw"], d["gb"], ws), a.reps)
+        rec = {"layer": name, "shape": list(shp), "c_in": ci, "c_out": co, "gflop": flop / 1e9,
+               "fwd_ms": t_f, "fwd_tflops": flop / (t_f * 1e-3) / 1e12,
+               "bwd_data_ms": t_d, "bwd_data_tflops": None if t_d is None else flop / (t_d * 1e-3) / 1e12,
+               "bwd_weight_ms": t_w, "bwd_weight_tflops": flop / (t_w * 1e-3) / 1e12}
+        layers.append(rec)
+        bd = "-" if t_d is None else f"{t_d:.3f} ms {rec['bwd_data_tflops']:.0f} TF/s"
+        _log(f"[convbench] {name:6s} {ci:3d}->{co:3d} {shp}: fwd {t_f:.3f} ms {rec['fwd_tflops']:.0f} TF/s, "
+             f"bwd-data {bd}, bwd-weight {t_w:.3f} ms {rec['bwd_weight_tflops']:.0f} TF/s")
+        del xi, dy, y, dx
+    V0 = n * dd * hh * ww
+    flop_fwd = flops_per_voxel() * V0
+    t_net = timed(lambda: net.forward(x, keep=False), a.reps)
+
+    def fwd_bwd():
+        out = net.forward(x, keep=True)
+        net.backward(torch.zeros(out.shape, device=dev, dtype=torch.bfloat16))
+
+    t_fb = timed(fwd_bwd, max(1, a.reps // 2))
+    res = {"shape": [n, dd, hh, ww], "layers": layers, "forward_ms": t_net,
+           "forward_tflops": flop_fwd / (t_net * 1e-3) / 1e12, "forward_backward_ms": t_fb,
+           "forward_backward_tflops": 3 * flop_fwd / (t_fb * 1e-3) / 1e12,
+           "peak_tflops_bf16_dense": 2500.0}
+    _log(f"[convbench] network forward {t_net:.2f} ms ({res['forward_tflops']:.0f} TF/s), forward+backward "
+         f"{t_fb:.2f} ms ({res['forward_backward_tflops']:.0f} TF/s, counting 3x the forward FLOP)")
+    return res
+
+
 def _log(msg):
     import sys
     print(msg, file=sys.stderr, flush=True)
@@ -995,8 +1064,12 @@ def main():
     j.add_argument("--keep-neq", action="store_true",
                    help="keep the populations' non-equilibrium parts after a jump (default: rebuild at equilibrium)")
     j.add_argument("--out", default=None)
+    c = sub.add_parser("convbench")
+    c.add_argument("--shape", default="8x64x96x64", help="batch x D x H x W of the network input")
+    c.add_argument("--reps", type=int, default=10)
+    c.add_argument("--out", default=None)
     a = ap.parse_args()
-    res = _cmd_train(a) if a.cmd == "train" else _cmd_jump(a)
+    res = {"train": _cmd_train, "jump": _cmd_jump, "convbench": _cmd_convbench}[a.cmd](a)
     if a.out:
         with open(a.out, "w") as f:
             json.dump(res, f, indent=1)

@@ -64,7 +64,7 @@ def test_struct_layout_matches_header(tmp_path):
 #include "lbm.h"
 int main(void) {
   printf("%zu %zu %zu %zu %zu\\n", sizeof(lbm_params), offsetof(lbm_params, body_accel),
-         offsetof(lbm_params, storage), offsetof(lbm_params, reserved0), sizeof(lbm_stats));
+         offsetof(lbm_params, storage), offsetof(lbm_params, density_literal), sizeof(lbm_stats));
   printf("%zu %zu\\n", offsetof(lbm_stats, centroid), offsetof(lbm_stats, max_speed));
   return 0;
 }
@@ -74,7 +74,7 @@ int main(void) {
     vals = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True,
                                            check=True).stdout.split()]
     P, S = lbm.LbmParams, lbm.LbmStats
-    assert vals[:5] == [C.sizeof(P), P.body_accel.offset, P.storage.offset, P.reserved0.offset,
+    assert vals[:5] == [C.sizeof(P), P.body_accel.offset, P.storage.offset, P.density_literal.offset,
                         C.sizeof(S)]
     assert vals[5:] == [S.centroid.offset, S.max_speed.offset]
 

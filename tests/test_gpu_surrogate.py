@@ -41,6 +41,11 @@ CONV_CASES = [
     (1, 4, 4, 4, 48, 96, 96, 0, 0),       # three column tiles
     (1, 2, 4, 8, 64, 256, 256, 1, 0),     # two column groups of four tiles
     (1, 4, 4, 8, 32, 32, 5, 0, 1),        # FP32 output, first 5 channels kept
+    # boxes of 32-wide rows (W > 16): partial in every direction, two boxes along W
+    (1, 5, 7, 20, 32, 64, 64, 1, 0),
+    (1, 3, 3, 40, 32, 32, 32, 1, 0),
+    # boxes of 16-wide row pairs (8 < W <= 16), two samples
+    (2, 6, 9, 13, 16, 64, 64, 0, 0),
 ]
 
 
@@ -66,7 +71,8 @@ def test_conv3d_fwd(env, case):
     assert np.all(np.abs(got - ref) <= bound), np.max(np.abs(got - ref) / bound)
 
 
-@pytest.mark.parametrize("case", [(1, 4, 6, 8, 32, 64), (2, 3, 5, 7, 64, 32), (1, 2, 4, 8, 96, 192)])
+@pytest.mark.parametrize("case", [(1, 4, 6, 8, 32, 64), (2, 3, 5, 7, 64, 32), (1, 2, 4, 8, 96, 192),
+                                  (1, 3, 5, 24, 32, 64)])
 def test_conv3d_input_gradient(env, case):
     torch, sg = env
     n, d, h, w, ci, co = case
@@ -74,10 +80,11 @@ def test_conv3d_input_gradient(env, case):
     dyt, dy = _bf16(torch, rng.standard_normal((n, d, h, w, co)))
     wt, wv = _bf16(torch, rng.standard_normal((27, co, ci)) / np.sqrt(27 * co))
     wm = torch.empty((27, ci, co), device="cuda", dtype=torch.bfloat16)
-    sg.sg_weight_mirror(wt, wm)
     dx = torch.empty((n, d, h, w, ci), device="cuda", dtype=torch.bfloat16)
-    sg.sg_conv3d_fwd(dyt, wm, None, ci, ci, 0, 0.0, dx, 0)
+    sg.sg_conv3d_bwd_data(dyt, wt, dx, wm)
     torch.cuda.synchronize()
+    # the workspace holds the mirrored weights wm[26 - t][ci][co] = wt[t][co][ci]
+    assert torch.equal(wm, wt.flip(0).transpose(1, 2).contiguous())
     ref = oc.conv3d_bwd_data(dy, wv)
     mag = oc.conv3d_bwd_data(np.abs(dy), np.abs(wv))
     bound = 27 * co * EPS32 * mag + 0.5 * _ulp_bf16(ref) + 1e-30
@@ -85,7 +92,13 @@ def test_conv3d_input_gradient(env, case):
     assert np.all(np.abs(got - ref) <= bound), np.max(np.abs(got - ref) / bound)
 
 
-@pytest.mark.parametrize("case", [(1, 4, 6, 8, 16, 32), (2, 5, 6, 7, 32, 64), (1, 4, 4, 4, 96, 32)])
+@pytest.mark.parametrize("case", [
+    (1, 4, 6, 8, 16, 32), (2, 5, 6, 7, 32, 64), (1, 4, 4, 4, 96, 32),
+    # the launch plans of full-size layers: several 16-voxel row tiles per W
+    # row (W > 16, ragged last tile) and several row tiles per block, here 2
+    # per block with 3 tiles per row, and 3 per block with a ragged last chunk
+    (1, 4, 8, 40, 128, 256), (1, 5, 13, 21, 128, 256),
+])
 def test_conv3d_weight_gradient(env, case):
     torch, sg = env
     n, d, h, w, ci, co = case
@@ -205,12 +218,49 @@ def test_field_packing_and_mass_projection(env):
     o = out.cpu().numpy().reshape(4, 6, 8, 32)
     expect = np.clip(ref[..., 0] + o[..., 0] * 0.5, 0, 1)
     assert np.allclose(phi2[zi][:, yi][:, :, xi], expect, atol=1e-6)
-    # mass projection to a target sum
+
+
+def _ulp32(v):
+    e = np.floor(np.log2(np.maximum(np.abs(v), 2.0 ** -126)))
+    return 2.0 ** (e - 23)
+
+
+@pytest.mark.parametrize("walls,lo,hi", [(True, 0.0, 1.0), (True, 0.2, 1.4), (False, -1.0, 1.0)])
+def test_mass_projection_matches_oracle(env, walls, lo, hi):
+    """sg_mass_project against the FP64 oracle (orc_mass_project) per cell, on
+    a grid with walls holding values no fluid cell has: each stored cell
+    within one FP32 ulp of the oracle's value of the same FP32 input (the GPU
+    rounds once; its FP64 sums differ by order only); wall rows and bulk
+    cells bit-identical; the fluid sum at the target to the FP32 rounding of
+    the stored cells."""
+    torch, sg = env
+    rng = np.random.default_rng(17)
+    nz, ny, nx = 10, 13, 24
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    r = np.sqrt((x - 11.3) ** 2 + (y - 6.2) ** 2 + (z - 4.9) ** 2)
+    phi = lo + (hi - lo) * (0.5 + 0.5 * np.tanh(2 * (r - 3.5) / 3.0))
+    phi += 1e-3 * rng.standard_normal(phi.shape) * (np.abs(r - 3.5) < 4)
+    phi[:, :, 0] = lo                                  # exact bulk values
+    phi[:, :, 1] = hi
+    if walls:
+        phi[:, 0, :] = 5.0
+        phi[:, -1, :] = -5.0
+    phi = phi.astype(np.float32).astype(np.float64)
+    fluid = np.ones(phi.shape, dtype=bool)
+    if walls:
+        fluid[:, 0, :] = fluid[:, -1, :] = False
+    target = float(phi[fluid].sum()) + 1.75
+    pmin, pmax = min(lo, hi), max(lo, hi)
+    ref = oc.mass_project(phi, walls, target, pmin, pmax)
+    tphi = torch.from_numpy(phi.astype(np.float32)).cuda()
     scratch = torch.zeros(2048, device="cuda", dtype=torch.float64)
-    target = float(phi2.sum()) + 3.0
-    sg.sg_mass_project(tphi, target, 0.0, 1.0, scratch)
+    sg.sg_mass_project(tphi, walls, target, pmin, pmax, scratch)
     torch.cuda.synchronize()
-    assert abs(tphi.double().sum().item() - target) < 1e-3
+    got = tphi.cpu().numpy().astype(np.float64)
+    assert np.all(np.abs(got - ref) <= _ulp32(ref)), np.max(np.abs(got - ref) / _ulp32(ref))
+    assert np.array_equal(got[~fluid], phi[~fluid])
+    assert np.array_equal(got[:, 1:-1, :2], phi[:, 1:-1, :2])
+    assert abs(got[fluid].sum() - target) <= 0.5 * _ulp32(got[fluid]).sum()
 
 
 def test_network_gradient_against_oracle(env):

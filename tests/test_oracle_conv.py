@@ -316,3 +316,53 @@ def test_projective_step_layouts_agree():
     last = conv.projective_step(s, sp, 8.0, 0.0, 1.0)
     planar = conv.projective_step(np.moveaxis(s, -1, 0), np.moveaxis(sp, -1, 0), 8.0, 0.0, 1.0, layout="planar")
     assert np.array_equal(np.moveaxis(planar, 0, -1), last)
+
+
+def _tanh_field(nz, ny, nx, lo, hi, R=4.0, xi=3.0):
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    r = np.sqrt((x - nx / 2 + 0.3) ** 2 + (y - ny / 2 - 0.2) ** 2 + (z - nz / 2 + 0.1) ** 2)
+    return lo + (hi - lo) * (0.5 + 0.5 * np.tanh(2 * (r - R) / xi))
+
+
+@pytest.mark.parametrize("lo,hi", [(0.0, 1.0), (0.2, 1.4), (1.0, -1.0)])
+def test_mass_projection_hits_the_target_inside_the_interface(lo, hi):
+    """Mass projection of the jump: the fluid-cell sum of the result equals the
+    target to FP64 rounding; cells in either bulk phase (phi = phi_min or
+    phi_max exactly), over- and undershooting cells, and wall rows are left
+    unchanged; the correction is largest at the mid value and symmetric in q
+    and 1 - q (a multiple of 4 q (1 - q)).  The third case has phi_H < phi_L."""
+    nz, ny, nx = 9, 14, 11
+    phi = _tanh_field(nz, ny, nx, lo, hi)
+    pmin, pmax = min(lo, hi), max(lo, hi)
+    phi[2, 5, 3], phi[2, 5, 4] = pmin, pmax                 # exact bulk values
+    phi[3, 6, 2], phi[3, 6, 3] = pmin - 1e-3, pmax + 1e-3   # outside the interval
+    phi[4, 7, 5], phi[4, 7, 6] = 0.5 * (lo + hi), lo + 0.25 * (hi - lo)
+    phi[4, 7, 7] = lo + 0.75 * (hi - lo)
+    phi[:, 0, :] = 7.0                                      # wall rows (a value no fluid cell has)
+    phi[:, -1, :] = -7.0
+    fluid = np.ones(phi.shape, dtype=bool)
+    fluid[:, 0, :] = fluid[:, -1, :] = False
+    target = phi[fluid].sum() + 2.5
+    out = conv.mass_project(phi, True, target, pmin, pmax)
+    assert abs(out[fluid].sum() - target) <= 64 * np.finfo(float).eps * np.abs(phi[fluid]).sum()
+    for idx in ((2, 5, 3), (2, 5, 4), (3, 6, 2), (3, 6, 3)):
+        assert out[idx] == phi[idx]
+    assert np.array_equal(out[~fluid], phi[~fluid])
+    d = out - phi
+    mid, quarter, three = d[4, 7, 5], d[4, 7, 6], d[4, 7, 7]
+    assert mid > 0 and abs(d[fluid]).max() <= mid * (1 + 1e-12)
+    assert abs(quarter - three) <= 1e-12 * mid                 # q = 1/4 and 3/4 move alike
+    assert abs(quarter / mid - 0.75) <= 1e-12                  # 4 q (1 - q) = 3/4 at q = 1/4
+    # without walls every row takes part
+    phi2 = _tanh_field(nz, ny, nx, lo, hi)
+    out2 = conv.mass_project(phi2, False, phi2.sum() - 1.0, pmin, pmax)
+    assert abs(out2.sum() - (phi2.sum() - 1.0)) <= 64 * np.finfo(float).eps * np.abs(phi2).sum()
+
+
+def test_mass_projection_of_a_bulk_field_changes_nothing():
+    """With no interface cell there is nothing to move: the field is returned
+    unchanged whatever the target."""
+    phi = np.ones((4, 5, 6))
+    phi[:, :, :3] = 0.0
+    out = conv.mass_project(phi, False, phi.sum() + 1.0, 0.0, 1.0)
+    assert np.array_equal(out, phi)

@@ -403,3 +403,136 @@ def test_shift_equilibrium_moments_and_identity():
     assert np.abs(H1.sum(0) - H0.sum(0) - (phi1 - phi0))[fl].max() <= 1e-15
     assert np.array_equal(phi_a[fl], phi1[fl]) and np.array_equal(u_a[:, fl], u1[:, fl])
     assert np.array_equal(H1[:, ~fl], H0[:, ~fl]) and np.array_equal(G1[:, ~fl], G0[:, ~fl])
+
+
+def _uniform_stream_bubble(U, rho_L, rho_H, ny=48, center=(11.3, 14.6, 12.2)):
+    s = inputs.Setup(name="stream", nx=24, ny=ny, nz=24, walls_y=False, xi=4.0, mobility=0.02,
+                     sigma=1e-4, rho_L=rho_L, rho_H=rho_H, tau_L=0.3, tau_H=0.3, kind="bubble",
+                     radius=5.0, center=center)
+    phi, u, ps = inputs.build_fields(s)
+    for a in range(3):
+        u[a][:] = U[a]
+    return s, phi, u, ps
+
+
+def test_stats_of_a_uniform_stream():
+    """Diagnostics on a state whose answers are fixed without the oracle: a
+    light bubble (rho ratio 100) in a uniform stream u = (U_x, U_y, U_z) with
+    three different components.  The chi-weighted rise velocity is U_y
+    (a weighted mean of a constant); the momentum is U times the total mass of
+    fluid, and since rho is linear in phi on [phi_L, phi_H] that total is
+    rho_L N + (rho_H - rho_L)/(phi_H - phi_L) (sum phi - phi_L N), with sum phi
+    the mass statistic; the largest speed is |U|; the gas volume is
+    sum (phi_H - phi)/(phi_H - phi_L) = N - sum phi here."""
+    U = (3e-3, -7e-3, 5e-3)
+    s, phi, u, ps = _uniform_stream_bubble(U, 0.01, 1.0)
+    o = orc.Oracle(_params(s))
+    o.init(phi, u, ps)
+    st = o.stats()
+    N = s.cells
+    assert abs(st["mass"] - phi.sum()) <= 1e-12 * phi.sum()
+    assert abs(st["gas_volume"] - (N - phi.sum())) <= 1e-12 * N
+    assert abs(st["rise_velocity"] - U[1]) <= 16 * EPS64 * abs(U[1])
+    mass_of_fluid = s.rho_L * N + (s.rho_H - s.rho_L) * st["mass"]
+    for a in range(3):
+        assert abs(st["momentum"][a] - U[a] * mass_of_fluid) <= 1e-12 * abs(U[a]) * mass_of_fluid, a
+    assert abs(st["max_speed"] - np.sqrt(sum(c * c for c in U))) <= 4 * EPS64
+
+
+def test_rise_velocity_is_the_gas_weighted_mean():
+    """A velocity field linear across the bubble, u_y = U + A (x - x_0): its
+    chi-weighted mean is U + A (x_c - x_0) with x_c the chi-weighted centroid
+    (both statistics); its plain mean over the box differs (the bubble sits
+    off the box centre), so a wrong weighting or a wrong component fails."""
+    U, A, x0 = 2e-3, 1e-4, 7.0
+    s, phi, u, ps = _uniform_stream_bubble((0.0, U, 0.0), 1.0, 1.0, center=(8.3, 14.6, 12.2))
+    xs = np.arange(s.nx, dtype=float)
+    u[1] = U + A * (xs[None, None, :] - x0)
+    o = orc.Oracle(_params(s))
+    o.init(phi, u, ps)
+    st = o.stats()
+    expect = U + A * (st["centroid"][0] - x0)
+    assert abs(st["rise_velocity"] - expect) <= 1e-13 * abs(expect)
+    assert abs(u[1].mean() - expect) > 5e-2 * abs(expect)
+    # the bubble's centre along y by symmetry of the tanh profile
+    assert abs(st["centroid"][1] - 14.6) < 2e-3
+
+
+def test_bubble_carried_along_y():
+    """The y-twin of the Galilean advection pin: a density-matched bubble in
+    the uniform stream u = (0, U, 0), periodic in y, moves by U t along y
+    within 1 %; its rise velocity stays U within 1 %, and the momentum stays
+    U times the fluid mass (rho = 1 everywhere) up to the small net capillary
+    force of the discrete interface (1e-4 relative; measured 2e-6)."""
+    U, steps = 0.02, 300
+    s, phi, u, ps = _uniform_stream_bubble((0.0, U, 0.0), 1.0, 1.0)
+    o = orc.Oracle(_params(s))
+    o.init(phi, u, ps)
+    st0 = o.stats()
+    o.step(steps)
+    st1 = o.stats()
+    c0, c1 = np.array(st0["centroid"]), np.array(st1["centroid"])
+    assert abs((c1[1] - c0[1]) / (U * steps) - 1.0) < 1e-2
+    assert abs(c1[0] - c0[0]) < 1e-2 and abs(c1[2] - c0[2]) < 1e-2
+    assert abs(st1["rise_velocity"] / U - 1.0) < 1e-2
+    assert abs(st1["momentum"][1] / (U * s.cells) - 1.0) < 1e-4
+
+
+def test_init_from_pressure():
+    """Equilibrium state of (phi, u, p) (the rebuild after a jump): in the
+    heavy bulk the normalised pressure sum_i G_i is p/(rho_H cs^2) = 3 p/rho_H,
+    in the light bulk 3 p/rho_L; the pressure read back from the state is p
+    everywhere (p = p* rho cs^2, Section 3.2); the velocity moment is u; wall
+    rows hold zeros."""
+    s = inputs.rising_bubble(10, 14, 9, D=6.0, center=(4.6, 6.3, 4.1), g=1e-5).with_grid(10, 14, 9, noise=1e-4)
+    phi, u, _ = inputs.build_fields(s)
+    rng = np.random.default_rng(8)
+    p = 1e-4 * rng.standard_normal(phi.shape)
+    phi[:, 12, :] = s.phi_H                  # a row of each bulk phase
+    phi[:, 6, 4] = s.phi_L
+    fluid = np.ones(phi.shape, dtype=bool)
+    fluid[:, 0, :] = fluid[:, -1, :] = False
+    p[~fluid] = 0.0
+    o = orc.Oracle(_params(s))
+    o.init_pressure(phi, u, p)
+    H, G, ph, uu = o.state()
+    ps = G.sum(0)
+    heavy = fluid & (phi == s.phi_H)
+    light = fluid & (phi == s.phi_L)
+    assert heavy.any() and light.any()
+    # each population is formed as p* w_i + Gamma_i(u) - w_i (the initial-state
+    # rule), whose O(w_i) cancellation leaves a rounding of order eps per
+    # population: 27 eps bounds the sum
+    tol = 27 * EPS64
+    assert np.abs(ps[heavy] - 3 * p[heavy] / s.rho_H).max() <= tol
+    assert np.abs(ps[light] - 3 * p[light] / s.rho_L).max() <= tol + 4 * EPS64 * np.abs(3 * p / s.rho_L).max()
+    assert np.abs(o.pressure() - p)[fluid].max() <= s.rho_H / 3 * tol + 8 * EPS64 * np.abs(p).max()
+    e27, _ = orc.velocity_set(27)
+    j = np.tensordot(e27.T.astype(float), G, axes=1)
+    assert np.abs(j - u)[:, fluid].max() <= tol
+    assert np.all(G[:, ~fluid] == 0) and np.all(H[:, ~fluid] == 0)
+
+
+@pytest.mark.parametrize("literal", [False, True])
+def test_density_of_an_overshooting_phase_field(literal):
+    """eq. density outside [phi_L, phi_H], read through the equilibrium state of
+    a pressure field (p* = p/(rho cs^2)): by default phi is clamped first, so
+    phi = 1.5 has rho_H and phi = -0.2 has rho_L; with density_literal the
+    printed interpolation rho_L + (phi - phi_L)(rho_H - rho_L)/(phi_H - phi_L)
+    holds for every phi (here 1.5 rho_H - 0.5 rho_L and 1.2 rho_L - 0.2 rho_H)."""
+    s = inputs.Setup(name="lit", nx=4, ny=3, nz=2, walls_y=False, kind="uniform", rho_L=0.5, rho_H=2.0,
+                     tau_L=0.3, tau_H=0.3, xi=4.0, density_literal=literal)
+    phi = np.full(s.shape, 0.5)
+    phi[0, 0, 0], phi[0, 0, 1] = 1.5, -0.2
+    p = np.full(s.shape, 3e-4)
+    o = orc.Oracle(_params(s))
+    o.init_pressure(phi, np.zeros((3,) + s.shape), p)
+    ps = o.state()[1].sum(0)
+    rho_over, rho_under = 3e-4 / (ps[0, 0, 0] / 3.0), 3e-4 / (ps[0, 0, 1] / 3.0)
+    if literal:
+        exp_over, exp_under = 1.5 * s.rho_H - 0.5 * s.rho_L, 1.2 * s.rho_L - 0.2 * s.rho_H
+    else:
+        exp_over, exp_under = s.rho_H, s.rho_L
+    assert abs(rho_over / exp_over - 1.0) < 1e-13
+    assert abs(rho_under / exp_under - 1.0) < 1e-13
+    assert abs(3e-4 / (ps[0, 1, 0] / 3.0) / (0.5 * (s.rho_L + s.rho_H)) - 1.0) < 1e-13

@@ -1,6 +1,6 @@
 """Host-side model of the paired 16-bit PDF layout and of the paired sweeps'
-pull (pidx / pull_idx for paired storage and k_phase_pair / k_hydro_pair in
-lbm_kernels.hpp): cell c and cell c + half (half = ceil(N/2)) share one
+pull (pidx / pull_idx for paired storage and k_sweep_pair, phase-field and
+hydrodynamic, in lbm_kernels.hpp): cell c and cell c + half (half = ceil(N/2)) share one
 32-bit word, the lower cell in the low 16 bits.  The mapping is a bijection
 into the buffer; for even nz the two cells of a pair are (x, y, z) and
 (x, y, z + nz/2), and a thread that pulls the pair's 32-bit word from the
