@@ -51,6 +51,19 @@ sg_status sg_conv3d_bwd_data(const void *dy, int32_t n, int32_t d, int32_t h, in
                              const void *wt, int32_t c_in, void *dx, void *workspace, size_t workspace_bytes,
                              void *hip_stream);
 
+/* sg_conv3d_bwd_data without a workspace, for callers that cannot allocate
+ * device memory (code under HIP graph capture, serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, kernels and results as
+ * sg_conv3d_bwd_data; the mirrored weights go to a fixed 4 MiB device array
+ * that the library holds on each GPU it runs on until the process ends, so
+ * 27 * c_in * c_out * 2 bytes must not exceed 4 MiB (SG_ESIZE otherwise).
+ * Nothing is allocated.  hip_stream must belong to the current device.  Every
+ * call on one GPU shares that GPU's array: calls that overlap on one GPU (on
+ * different streams or from different threads) race and must be serialised
+ * by the caller. */
+sg_status sg_conv3d_bwd_data_noalloc(const void *dy, int32_t n, int32_t d, int32_t h, int32_t w, int32_t c_out,
+                                     const void *wt, int32_t c_in, void *dx, void *hip_stream);
+
 /* Bytes of FP32 scratch sg_conv3d_bwd_weight needs for this shape. */
 size_t sg_bwd_weight_workspace(int32_t n, int32_t d, int32_t h, int32_t w, int32_t c_in, int32_t c_out);
 

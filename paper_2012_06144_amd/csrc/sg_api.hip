@@ -14,6 +14,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <mutex>
 
 #include "sg.h"
 
@@ -922,6 +923,37 @@ sg_status launch_bwd_weight(const void *x, const void *dy, int n, int d, int h, 
     return SG_OK;
 }
 
+// ---- input gradient without allocation --------------------------------------------
+// The mirrored weights of the input gradient go to a fixed device array
+// instead of a caller workspace.  The array's name is a host-side stand-in in
+// host code, so its device address is looked up once per device (with that
+// device current) and only that address is passed to kernels.
+constexpr size_t kNoAllocScratchBytes = size_t(4) << 20;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) unsigned char noalloc_scratch[kNoAllocScratchBytes];
+
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+sg_status noalloc_scratch_ptr(void **out)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(SG_EHIP, "hipGetDevice: %s", hipGetErrorString(e));
+    if (dev < 0 || dev >= kMaxDevices) return fail(SG_EARG, "device %d beyond the %d supported", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(noalloc_scratch));
+        if (e != hipSuccess || !p)
+            return fail(SG_EHIP, "hipGetSymbolAddress(noalloc_scratch) on device %d: %s", dev,
+                        hipGetErrorString(e));
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return SG_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1265,6 +1297,24 @@ sg_status sg_mass_project(float *phi, int32_t nx, int32_t ny, int32_t nz, int32_
                        pmin, pmax);
     SG_LAUNCH_CHECK();
     return SG_OK;
+}
+
+sg_status sg_conv3d_bwd_data_noalloc(const void *dy, int32_t n, int32_t d, int32_t h, int32_t w, int32_t c_out,
+                                     const void *wt, int32_t c_in, void *dx, void *stream)
+{
+    if (!dy || !wt || !dx) return fail(SG_EARG, "NULL tensor");
+    if (c_in < 32 || c_in % 32) return fail(SG_EARG, "c_in must be a positive multiple of 32 (got %d)", c_in);
+    if (c_out < 16 || c_out % 16) return fail(SG_EARG, "c_out must be a positive multiple of 16 (got %d)", c_out);
+    const size_t need = (size_t)27 * c_in * c_out * sizeof(bf16);
+    if (need > kNoAllocScratchBytes)
+        return fail(SG_ESIZE, "27 * c_in * c_out BF16 weights take %zu bytes, above the %zu-byte fixed scratch",
+                    need, kNoAllocScratchBytes);
+    void *wm = nullptr;
+    sg_status st = noalloc_scratch_ptr(&wm);
+    if (st != SG_OK) return st;
+    st = sg_weight_mirror(wt, c_out, c_in, wm, stream);
+    if (st != SG_OK) return st;
+    return sg_conv3d_fwd(dy, n, d, h, w, c_out, wm, nullptr, c_in, c_in, 0, 0.f, dx, 0, stream);
 }
 
 const char *sg_last_error(void) { return g_err; }

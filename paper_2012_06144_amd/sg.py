@@ -12,7 +12,7 @@ import ctypes as C
 from .lbm import LIB_PATH, LbmError, _lib as _L  # noqa: F401  (loads the library)
 
 EXPORTS = [
-    "sg_conv3d_fwd", "sg_weight_mirror", "sg_conv3d_bwd_data", "sg_bwd_weight_workspace", "sg_conv3d_bwd_weight",
+    "sg_conv3d_fwd", "sg_weight_mirror", "sg_conv3d_bwd_data", "sg_conv3d_bwd_data_noalloc", "sg_bwd_weight_workspace", "sg_conv3d_bwd_weight",
     "sg_leaky_bwd", "sg_pool2_fwd", "sg_pool2_bwd", "sg_up2_fwd", "sg_up2_bwd", "sg_concat",
     "sg_split", "sg_mse", "sg_adam", "sg_to_bf16", "sg_to_f32", "sg_add", "sg_fields_to_input",
     "sg_state_to_input", "sg_make_target", "sg_apply_prediction", "sg_advect_phase", "sg_projective_step",
@@ -25,6 +25,7 @@ _SIG = {
     "sg_conv3d_fwd": [_vp, _i, _i, _i, _i, _i, _vp, _vp, _i, _i, _i, _f, _vp, _i, _vp],
     "sg_weight_mirror": [_vp, _i, _i, _vp, _vp],
     "sg_conv3d_bwd_data": [_vp, _i, _i, _i, _i, _i, _vp, _i, _vp, _vp, _sz, _vp],
+    "sg_conv3d_bwd_data_noalloc": [_vp, _i, _i, _i, _i, _i, _vp, _i, _vp, _vp],
     "sg_bwd_weight_workspace": [_i, _i, _i, _i, _i, _i],
     "sg_conv3d_bwd_weight": [_vp, _vp, _i, _i, _i, _i, _i, _i, _vp, _vp, _vp, _sz, _vp],
     "sg_leaky_bwd": [_vp, _vp, _vp, _sz, _f, _vp],
@@ -98,6 +99,15 @@ def sg_conv3d_bwd_data(dy, wt, dx, wm, stream=None):
     c_in = wt.shape[2]
     _check(_L.sg_conv3d_bwd_data(_p(dy), n, d, h, w, c_out, _p(wt), c_in, _p(dx), _p(wm),
                                  wm.numel() * wm.element_size(), _stream(stream)), "sg_conv3d_bwd_data")
+
+
+def sg_conv3d_bwd_data_noalloc(dy, wt, dx, stream=None):
+    """sg_conv3d_bwd_data with the library's fixed device array in place of
+    the workspace (27 c_in c_out BF16 weights, at most 4 MiB)."""
+    n, d, h, w, c_out = dy.shape
+    c_in = wt.shape[2]
+    _check(_L.sg_conv3d_bwd_data_noalloc(_p(dy), n, d, h, w, c_out, _p(wt), c_in, _p(dx), _stream(stream)),
+           "sg_conv3d_bwd_data_noalloc")
 
 
 def sg_bwd_weight_workspace(n, d, h, w, c_in, c_out) -> int:
