@@ -650,6 +650,176 @@ void orc_step(orc_state *s, int32_t nsteps)
     }
 }
 
+/* ---- straightforward algorithm (Alg. naiveAlgorithm, Sec. 4.2) ---------
+ * The six steps of the straightforward algorithm, each a pass of its own
+ * over all fluid cells: collide h, collide g, stream h, update phi, stream
+ * g, update u.  Read as a time-consistent scheme: every collision of step t
+ * takes phi, grad(phi), theta and u of time t, and the velocity update
+ * takes the streamed g and the new phi, with the stored velocity (of the
+ * previous time) inside the viscous force, as in the fused step.  The
+ * collision of g recomputes the force from the state it collides (its
+ * moments, phi and the updated u).
+ *
+ * The loop is cut where the canonical state of the fused step sits (h
+ * post-collision at the cell, g pre-collision and already streamed), so one
+ * call runs: stream h, update phi, update u, collide h, collide g and
+ * stream g (push).  The initial state is the same as the fused step's.    */
+
+/* Force of eq. forceHydro at cell c from the pre-collision g there, the
+ * phase field `phi` (stencil) and the velocity `uv` inside the viscous
+ * force; also returns rho, s_nu and the moments p* and j.                 */
+static void naive_force(const orc_state *s, const double *phi, int x, int y, int z, const double g[Q27],
+                        const double uv[3], double F[3], double *rho_out, double *s_nu_out,
+                        double *pstar_out, double j[3])
+{
+    const orc_params *p = &s->p;
+    const int64_t c = cidx(p, x, y, z);
+    const double dphi = p->phi_H - p->phi_L;
+    double ph = phi[c];
+    double rho = density_of(p, ph);
+    double tau = p->tau_L + (phase_clamp(p, ph) - p->phi_L) * (p->tau_H - p->tau_L) / dphi;
+    double s_nu = 1.0 / (tau + 0.5);
+    double nu = tau * CS2;
+
+    double grad[3];
+    iso_gradient(p, phi, Q27, x, y, z, grad);
+    double lap = iso_laplacian(p, phi, Q27, x, y, z);
+    double grad_rho[3];
+    for (int a = 0; a < 3; ++a) grad_rho[a] = (p->rho_H - p->rho_L) / dphi * grad[a];
+    double beta = 12.0 * p->sigma / p->xi;
+    double kappa = 1.5 * p->sigma * p->xi;
+    double phi0 = 0.5 * (p->phi_L + p->phi_H);
+    double mu_phi = 4.0 * beta * (ph - p->phi_L) * (ph - p->phi_H) * (ph - phi0) - kappa * lap;
+
+    double pstar = 0.0;
+    for (int a = 0; a < 3; ++a) j[a] = 0.0;
+    for (int i = 0; i < Q27; ++i) {
+        pstar += g[i];
+        for (int a = 0; a < 3; ++a) j[a] += g[i] * E27[i][a];
+    }
+    double V[3][3];
+    viscous_bracket(g, s_nu, uv, V);
+    for (int a = 0; a < 3; ++a) {
+        double Fp = -pstar * CS2 * grad_rho[a];
+        double Fs = mu_phi * grad[a];
+        double Fmu = 0.0;
+        for (int b = 0; b < 3; ++b) Fmu += V[a][b] * grad_rho[b];
+        Fmu *= -nu / CS2;
+        double Fb = (rho - p->rho_ref) * p->accel[a];
+        F[a] = Fp + Fs + Fmu + Fb;
+    }
+    *rho_out = rho;
+    *s_nu_out = s_nu;
+    *pstar_out = pstar;
+}
+
+/* Stream h: the pre-collision population of direction i at x is the
+ * post-collision one of x - e_i (halfway bounce-back at a wall).         */
+static void naive_stream_h(orc_state *s, int x, int y, int z)
+{
+    const orc_params *p = &s->p;
+    const int64_t n = s->n, c = cidx(p, x, y, z);
+    for (int i = 0; i < Q15; ++i) {
+        int sy = ny_nb(p, y, -E15[i][1]);
+        if (is_wall_row(p, sy))
+            s->Hn[i * n + c] = s->H[opposite(i) * n + c];
+        else
+            s->Hn[i * n + c] = s->H[i * n + cidx(p, wrap(x - E15[i][0], p->nx), sy, wrap(z - E15[i][2], p->nz))];
+    }
+}
+
+/* Update phi = sum of the streamed populations (eq. updatePhaseField). */
+static void naive_update_phi(orc_state *s, int x, int y, int z)
+{
+    const int64_t n = s->n, c = cidx(&s->p, x, y, z);
+    double phi = 0.0;
+    for (int i = 0; i < Q15; ++i) phi += s->Hn[i * n + c];
+    s->phiB[c] = phi;
+}
+
+/* Update u = j + F/(2 rho) (eq. updateVelocityField) from the streamed g
+ * and the new phi; the stored velocity enters the viscous force.         */
+static void naive_update_u(orc_state *s, int x, int y, int z)
+{
+    const int64_t n = s->n, c = cidx(&s->p, x, y, z);
+    double g[Q27];
+    for (int i = 0; i < Q27; ++i) g[i] = s->G[i * n + c];
+    double u_old[3] = {s->u[c], s->u[n + c], s->u[2 * n + c]};
+    double F[3], rho, s_nu, pstar, j[3];
+    naive_force(s, s->phiB, x, y, z, g, u_old, F, &rho, &s_nu, &pstar, j);
+    for (int a = 0; a < 3; ++a) s->u[a * n + c] = j[a] + F[a] / (2.0 * rho);
+}
+
+/* Collide h (eq. lb_interface with F^phi of eq. interfaceTracking): phi,
+ * grad(phi), theta and u all of the new time.                            */
+static void naive_collide_h(orc_state *s, int x, int y, int z)
+{
+    const orc_params *p = &s->p;
+    const int64_t n = s->n, c = cidx(p, x, y, z);
+    double phi = s->phiB[c];
+    double grad[3];
+    iso_gradient(p, s->phiB, Q15, x, y, z, grad);
+    double gnorm = sqrt(grad[0] * grad[0] + grad[1] * grad[1] + grad[2] * grad[2]);
+    double nrm[3];
+    for (int a = 0; a < 3; ++a) nrm[a] = grad[a] / (gnorm + p->normal_eps);
+    double phi0 = 0.5 * (p->phi_L + p->phi_H);
+    double theta = (1.0 - 4.0 * (phi - phi0) * (phi - phi0)) / p->xi;
+    double uc[3] = {s->u[c], s->u[n + c], s->u[2 * n + c]};
+    double omega = 1.0 / (p->mobility / CS2 + 0.5);
+    double Fphi[Q15];
+    phase_forcing(theta, nrm, Fphi);
+    for (int i = 0; i < Q15; ++i) {
+        double h = s->Hn[i * n + c];
+        double heq = phi * gamma_i(E15[i], W15[i], uc);
+        s->H[i * n + c] = h + omega * (heq - h - 0.5 * Fphi[i]) + Fphi[i];
+    }
+}
+
+/* Collide g (eq. improved_collision) with the force recomputed from the
+ * state it collides, then push it to x + e_i (bounce-back at a wall).     */
+static void naive_collide_g(orc_state *s, int x, int y, int z)
+{
+    const orc_params *p = &s->p;
+    const int64_t n = s->n, c = cidx(p, x, y, z);
+    double g[Q27];
+    for (int i = 0; i < Q27; ++i) g[i] = s->G[i * n + c];
+    double uc[3] = {s->u[c], s->u[n + c], s->u[2 * n + c]};
+    double F[3], rho, s_nu, pstar, j[3];
+    naive_force(s, s->phiB, x, y, z, g, uc, F, &rho, &s_nu, &pstar, j);
+    double gs[Q27];
+    mrt_collide(g, pstar, uc, F, rho, s_nu, gs);
+    for (int i = 0; i < Q27; ++i) {
+        int dy = ny_nb(p, y, E27[i][1]);
+        if (is_wall_row(p, dy))
+            s->Gn[opposite(i) * n + c] = gs[i];
+        else
+            s->Gn[i * n + cidx(p, wrap(x + E27[i][0], p->nx), dy, wrap(z + E27[i][2], p->nz))] = gs[i];
+    }
+}
+
+#define ORC_FLUID_PASS(fn)                                                   \
+    _Pragma("omp parallel for schedule(static)")                             \
+    for (int yz = 0; yz < p->ny * p->nz; ++yz) {                             \
+        int y = yz % p->ny, z = yz / p->ny;                                  \
+        if (is_wall_row(p, y)) continue;                                     \
+        for (int x = 0; x < p->nx; ++x) fn(s, x, y, z);                      \
+    }
+
+void orc_step_naive(orc_state *s, int32_t nsteps)
+{
+    const orc_params *p = &s->p;
+    for (int t = 0; t < nsteps; ++t) {
+        ORC_FLUID_PASS(naive_stream_h)
+        ORC_FLUID_PASS(naive_update_phi)
+        ORC_FLUID_PASS(naive_update_u)
+        ORC_FLUID_PASS(naive_collide_h)
+        ORC_FLUID_PASS(naive_collide_g)
+        swap_ptr(&s->G, &s->Gn);
+        swap_ptr(&s->phiA, &s->phiB);
+    }
+}
+#undef ORC_FLUID_PASS
+
 /* Canonical state: H (post-collision phase PDFs), G (pre-collision hydro
  * PDFs), phi_A (latest phase field), u (latest velocity). Any pointer may
  * be NULL.                                                             */

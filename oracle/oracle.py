@@ -75,6 +75,7 @@ def lib():
     L.orc_destroy.argtypes = [C.c_void_p]
     L.orc_init.argtypes = [C.c_void_p, _D, _D, _D]
     L.orc_step.argtypes = [C.c_void_p, C.c_int32]
+    L.orc_step_naive.argtypes = [C.c_void_p, C.c_int32]
     L.orc_get_state.argtypes = [C.c_void_p] + [C.c_void_p] * 4
     L.orc_set_state.argtypes = [C.c_void_p] + [C.c_void_p] * 4
     L.orc_pressure.argtypes = [C.c_void_p, _D]
@@ -229,6 +230,12 @@ class Oracle:
 
     def step(self, n: int = 1):
         lib().orc_step(self._h, int(n))
+
+    def step_straightforward(self, n: int = 1):
+        """n steps of the straightforward algorithm (Alg. naiveAlgorithm,
+        Sec. 4.2), read as a time-consistent scheme: the collisions take phi,
+        its gradient and u of the new time."""
+        lib().orc_step_naive(self._h, int(n))
 
     def state(self):
         H = np.zeros((15,) + self.shape)
