@@ -156,6 +156,36 @@ def measure_storage(lbm, perf, setup, phi, u, ps, storage, steps, warmup, timed_
     }
 
 
+def measure_straightforward(lbm, perf, setup, phi, u, ps, storage, steps, warmup):
+    """The straightforward algorithm (six kernels per step, Sec. 4.2) on the
+    same workload: coupled steps timed with HIP events on the solver stream,
+    algorithmic bytes of its six passes, and the drift of sum(phi)."""
+    import torch
+    fluid = setup.nx * setup.nz * (setup.ny - 2 if setup.walls_y else setup.ny)
+    solver = lbm.Solver(setup.physics(), storage=storage, device="cuda:0")
+    solver.init_fields(phi, u, ps)
+    stream = torch.cuda.current_stream(torch.device("cuda:0"))
+    m0 = solver.reduce_mass()
+    if warmup > 0:
+        solver.step_straightforward(warmup)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    solver.step_straightforward(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    m1 = solver.reduce_mass()
+    solver.close()
+    del solver
+    torch.cuda.empty_cache()
+    bpc = perf.bytes_per_cell(storage)["straightforward"]
+    return {"storage": storage, "steps": steps, "warmup": warmup, "ms_per_step": round(ms, 4),
+            "mlups": round(fluid / (ms * 1e-3) / 1e6, 1), "bytes_per_cell": bpc,
+            "achieved_gbs": round(bpc * fluid / (ms * 1e-3) / 1e9, 1), "mass_drift_rel": (m1 - m0) / m0}
+
+
 def cpu_baseline(setup, phi, u, ps, target_s: float = 15.0):
     """Time the FP64 oracle on a 128 x ny x 128 slab of the same workload."""
     import numpy as np
@@ -196,6 +226,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--timed-steps", type=int, default=50,
                     help="steps of the per-kernel event timing (roofline)")
+    ap.add_argument("--straightforward", default="f64,f32",
+                    help="comma-separated storage formats (f64, f32) for which the straightforward six-kernel "
+                         "algorithm is measured on the same workload (empty: none)")
     ap.add_argument("--other-storages", default="f64,f16s,bf16s",
                     help="comma-separated storage formats measured after the main one on the same workload "
                          "(empty: none)")
@@ -308,6 +341,17 @@ def main():
             f"{rec['roofline']['kernel']} {rec['roofline']['achieved']:.0f} GB/s")
         others[st] = rec
 
+    naive = {}
+    for st in [x for x in args.straightforward.split(",") if x]:
+        log(f"[bench] straightforward algorithm, storage {st}: warmup {args.warmup}, timed {args.steps} steps")
+        rec = measure_straightforward(lbm, perf, setup, phi, u, ps, st, args.steps, args.warmup)
+        improved = mlups if st == args.storage else others.get(st, {}).get("mlups")
+        rec["improved_mlups"] = None if improved is None else round(improved, 1)
+        rec["improved_over_straightforward"] = None if improved is None else round(improved / rec["mlups"], 3)
+        log(f"[bench] straightforward {st}: {rec['ms_per_step']:.3f} ms/step, {rec['mlups']:.0f} MLUPS, "
+            f"{rec['achieved_gbs']:.0f} GB/s algorithmic")
+        naive[st] = rec
+
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] CPU oracle baseline")
@@ -350,6 +394,8 @@ def main():
         "paper_context": {"mlups": 550, "hardware": "Tesla P100", "precision": "f64",
                           "roofline_frac_of_stream": 0.78},
         "other_storages": others,
+        "straightforward_algorithm": {"records": naive, "paper": {"straightforward_mlups": 211, "improved_mlups": 550,
+                                                                "hardware": "Tesla P100", "precision": "f64"}},
         "cpu_baseline": cpu,
         "surrogate": load_surrogate_study(),
         "kernel_source_hash": src_hash,

@@ -182,6 +182,22 @@ lbm_status lbm_step_timed(lbm_ctx *ctx, int32_t n, double *phase_ms, double *hyd
  * storage and the z-marching sweeps, which have no fused kernel. */
 lbm_status lbm_step_timed_fused(lbm_ctx *ctx, int32_t n, double *fused_ms);
 
+/* Enqueues n >= 1 time steps of the straightforward algorithm (Alg.
+ * naiveAlgorithm, Sec. 4.2) in place of the improved one: per step six
+ * kernels, each a pass over the grid -- stream h, phi = sum h (eq.
+ * updatePhaseField), stream g, velocity update (eq. updateVelocityField),
+ * collision of h, collision of g -- so every population set is read three
+ * times per step.  Time-consistent: both collisions take phi, its gradient
+ * and u of the new time (the improved step takes the phase field's gradient
+ * and u of the previous one in its phase-field collision); the velocity
+ * update keeps the stored velocity inside the viscous force, and the
+ * collision of g recomputes the force with the updated velocity.  Starts
+ * from and leaves the same kind of state as lbm_step (populations
+ * post-collision at their cell), so the getters, reductions and lbm_step
+ * apply unchanged.  FP64 and FP32 storage only (LBM_EARG otherwise).
+ * Asynchronous.  An ablation of the kernel fusion of Sec. 4.2. */
+lbm_status lbm_step_straightforward(lbm_ctx *ctx, int32_t n);
+
 /* sum of phi over fluid cells in FP64 (host output); synchronises. */
 lbm_status lbm_reduce_mass(lbm_ctx *ctx, double *sum_phi);
 

@@ -20,6 +20,8 @@ LBM_FP32_SWEEPS(LBM_EXTERN_SWEEP)
 #undef LBM_EXTERN_SWEEP
 extern template void launch_fused<StoreF32>(const SweepArgs<StoreF32> &, const SweepArgs<StoreF32> &,
                                             const SweepLaunch &, hipStream_t);
+extern template void launch_naive_step<StoreF32>(const SweepArgs<StoreF32> &, const SweepArgs<StoreF32> &, int,
+                                                 hipStream_t);
 }  // namespace lbm
 
 using namespace lbm;
@@ -317,6 +319,26 @@ struct Ops {
         return LBM_OK;
     }
 
+    // n steps of the straightforward algorithm (six passes per step)
+    static lbm_status step_straightforward(lbm_ctx *c, int n)
+    {
+        if constexpr (S::lowp) {
+            return fail(LBM_EARG, "the straightforward algorithm runs with FP64 or FP32 storage");
+        } else {
+            const Phys<R> ph = make_phys<R>(&c->p);
+            for (int t = 0; t < n; ++t) {
+                const int a = c->cur, b = 1 - c->cur;
+                SweepArgs<S> sp{H(c, a), H(c, b), phi(c, b), phi(c, b), u(c), c->g, ph};
+                SweepArgs<S> sg{G(c, a), G(c, b), phi(c, b), nullptr, u(c), c->g, ph};
+                launch_naive_step<S>(sp, sg, blocks(c), c->stream);
+                LAUNCH_CHECK();
+                c->cur = b;
+                ++c->steps;
+            }
+            return LBM_OK;
+        }
+    }
+
     static lbm_status step_timed(lbm_ctx *c, int n, double *phase_ms, double *hydro_ms)
     {
         const Phys<R> ph = make_phys<R>(&c->p);
@@ -471,6 +493,9 @@ lbm_status dispatch(int storage, A &&...args)
 template <class S> struct DoStep {
     static lbm_status run(lbm_ctx *c, int n) { return Ops<S>::step(c, n); }
 };
+template <class S> struct DoStepStraightforward {
+    static lbm_status run(lbm_ctx *c, int n) { return Ops<S>::step_straightforward(c, n); }
+};
 template <class S> struct DoStepTimed {
     static lbm_status run(lbm_ctx *c, int n, double *a, double *b) { return Ops<S>::step_timed(c, n, a, b); }
 };
@@ -620,6 +645,14 @@ lbm_status lbm_step(lbm_ctx *c, int32_t n)
     if (s != LBM_OK) return s;
     if (n < 1) return fail(LBM_EARG, "n must be >= 1 (got %d)", n);
     return dispatch<DoStep>(c->p.storage, c, (int)n);
+}
+
+lbm_status lbm_step_straightforward(lbm_ctx *c, int32_t n)
+{
+    lbm_status s = check_ctx(c, true);
+    if (s != LBM_OK) return s;
+    if (n < 1) return fail(LBM_EARG, "n must be >= 1 (got %d)", n);
+    return dispatch<DoStepStraightforward>(c->p.storage, c, (int)n);
 }
 
 lbm_status lbm_step_timed(lbm_ctx *c, int32_t n, double *phase_ms, double *hydro_ms)

@@ -330,7 +330,9 @@ struct IORegs {
 // normal and theta from the previous phi (eqs. allen_cahn, grad), forcing
 // (eq. interfaceTracking), equilibrium phi Gamma(u), single-rate collision
 // (eq. lb_interface); store post-collision h at the cell ----------------------
-template <class S, class P, class IO, bool U_REG = false>
+// PHI_OUT = false: the collision step of the straightforward algorithm, whose
+// phase field was already written by a pass of its own.
+template <class S, class P, class IO, bool U_REG = false, bool PHI_OUT = true>
 __device__ inline void phase_cell(const SweepArgs<S> &a, int c, const Nbr &n, const P &phiA, const IO &io,
                                   const typename S::real *u_reg = nullptr)
 {
@@ -361,7 +363,7 @@ __device__ inline void phase_cell(const SweepArgs<S> &a, int c, const Nbr &n, co
         }
     }
     const R phi = R(phi_acc);
-    st_field(a.phi_out + c, phi);
+    if constexpr (PHI_OUT) st_field(a.phi_out + c, phi);
 
     // isotropic gradient (eq. grad) from antisymmetric pairs of the half set
     R acc[3] = {R(0), R(0), R(0)};
@@ -455,7 +457,14 @@ __global__ __launch_bounds__(kBlock) void k_phase(const SweepArgs<S> a)
 //   g*_i = g_eq_i(p*, u) + F_i/2 + (1 - s) w_i/(2 cs^4) (e_i e_i - cs^2 I) : A,
 //   A = Pi - p* cs^2 I - u u^T,  F_i = w_i e_i.F/(rho cs^2),
 // and the bracket of the viscous force is s A(u_old).
-template <class S, class P, class IO, bool U_OUT = false>
+//
+// HMODE selects the steps of the body: kHydroFull (velocity update and
+// collision, the fused step), kHydroUpdateU (velocity update only) or
+// kHydroCollide (collision only, with the stored velocity both in the
+// viscous force and in the equilibrium) -- the last two are separate passes
+// of the straightforward algorithm.
+constexpr int kHydroFull = 0, kHydroUpdateU = 1, kHydroCollide = 2;
+template <class S, class P, class IO, bool U_OUT = false, int HMODE = kHydroFull>
 __device__ inline void hydro_cell(const SweepArgs<S> &a, int c, const Nbr &n, const P &phiB, const IO &io,
                                   typename S::real *u_new = nullptr)
 {
@@ -551,20 +560,27 @@ __device__ inline void hydro_cell(const SweepArgs<S> &a, int c, const Nbr &n, co
 
     R ux, uy, uz;
     R inv_rho = R(0);
-    if constexpr (std::is_same<R, float>::value) {
-        inv_rho = R(1) / rho;
-        const R h = R(0.5) * inv_rho;
-        ux = j[0] + F[0] * h;
-        uy = j[1] + F[1] * h;
-        uz = j[2] + F[2] * h;
+    if constexpr (std::is_same<R, float>::value) inv_rho = R(1) / rho;
+    if constexpr (HMODE == kHydroCollide) {
+        ux = uox;
+        uy = uoy;
+        uz = uoz;
     } else {
-        ux = j[0] + F[0] / (R(2) * rho);
-        uy = j[1] + F[1] / (R(2) * rho);
-        uz = j[2] + F[2] / (R(2) * rho);
+        if constexpr (std::is_same<R, float>::value) {
+            const R h = R(0.5) * inv_rho;
+            ux = j[0] + F[0] * h;
+            uy = j[1] + F[1] * h;
+            uz = j[2] + F[2] * h;
+        } else {
+            ux = j[0] + F[0] / (R(2) * rho);
+            uy = j[1] + F[1] / (R(2) * rho);
+            uz = j[2] + F[2] / (R(2) * rho);
+        }
+        st_field(a.u + c, ux);
+        st_field(a.u + a.g.fplane + c, uy);
+        st_field(a.u + 2 * a.g.fplane + c, uz);
     }
-    st_field(a.u + c, ux);
-    st_field(a.u + a.g.fplane + c, uy);
-    st_field(a.u + 2 * a.g.fplane + c, uz);
+    if constexpr (HMODE == kHydroUpdateU) return;
     if constexpr (U_OUT) {
         u_new[0] = ux;
         u_new[1] = uy;
@@ -856,6 +872,118 @@ void launch_sweep(const SweepArgs<S> &a, const SweepLaunch &L, hipStream_t strea
     } else {
         hipLaunchKernelGGL((k_hydro<S>), dim3(L.blocks), dim3(kBlock), 0, stream, a);
     }
+}
+
+// ---- the straightforward algorithm (Alg. naiveAlgorithm, Sec. 4.2) ----------
+// Six passes per step instead of two sweeps: stream h, update phi, stream g,
+// update u, collide h, collide g -- the order of the algorithm's loop, cut
+// where the fused step's state sits (populations post-collision at the
+// cell), so both share the initial state and the getters.  Each population
+// set is read three times per step (stream, update or collide, and the
+// collision of the new time), as the algorithm is written.  Time-consistent
+// reading: the collisions take phi, its gradient, theta and u of the new
+// time; the velocity update keeps the stored velocity inside the viscous
+// force, as the fused step does; the collision of g recomputes the force
+// with the updated velocity.  FP64 and FP32 storage.  The buffers: a = the
+// current populations (post-collision), b = the other copy; after a step the
+// state is in b.
+template <class S, int Q>
+struct IOCell {
+    typename S::pdf_t *__restrict__ buf;  // read and written at the cell (in place)
+    int c;
+    const Grid *g;
+    __device__ typename S::pdf_t load(int i) const { return buf[pdf_index<S, Q>(i, c, *g)]; }
+    __device__ void store(int i, typename S::pdf_t v) const { st_stream(buf + pdf_index<S, Q>(i, c, *g), v); }
+};
+
+// dst(c) = src pulled from c - e_i (bounce-back at a wall), for every direction
+template <class S, int Q>
+__global__ __launch_bounds__(kBlock) void k_naive_stream(const typename S::pdf_t *__restrict__ src,
+                                                         typename S::pdf_t *__restrict__ dst, const Grid g)
+{
+    const int c = xcd_block() * kBlock + threadIdx.x;
+    if (c >= g.ncells) return;
+    int x, y, z;
+    Nbr n;
+    if (!decode(g, c, x, y, z, n)) return;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) st_stream(dst + pdf_index<S, Q>(i, c, g), ld_stream(src + pull_idx<S, Q>(i, c, n, g)));
+}
+
+// phi = sum of the streamed h at the cell (eq. updatePhaseField), summed in
+// FP64 as the phase sweep sums it
+template <class S>
+__global__ __launch_bounds__(kBlock) void k_naive_phi(const typename S::pdf_t *__restrict__ h,
+                                                      typename S::real *__restrict__ phi, const Grid g)
+{
+    const int c = xcd_block() * kBlock + threadIdx.x;
+    if (c >= g.ncells) return;
+    int x, y, z;
+    Nbr n;
+    if (!decode(g, c, x, y, z, n)) return;
+    double acc = 0.0;
+#pragma unroll
+    for (int i = 0; i < 15; ++i) {
+        if constexpr (std::is_same<typename S::real, double>::value) acc += dec_h<S>(h[pdf_index<S, 15>(i, c, g)], 0.0, i);
+        else acc += dec_h64<S>(h[pdf_index<S, 15>(i, c, g)], 0.f, i);
+    }
+    st_field(phi + c, typename S::real(acc));
+}
+
+// velocity update from the streamed g (a.dst) and the new phi (a.phi_in)
+template <class S>
+__global__ __launch_bounds__(kBlock) void k_naive_update_u(const SweepArgs<S> a)
+{
+    using R = typename S::real;
+    const int c = xcd_block() * kBlock + threadIdx.x;
+    if (c >= a.g.ncells) return;
+    int x, y, z;
+    Nbr n;
+    if (!decode(a.g, c, x, y, z, n)) return;
+    hydro_cell<S, PhiG<R>, IOCell<S, 27>, false, kHydroUpdateU>(a, c, n, PhiG<R>{a.phi_in, c, &n},
+                                                                 IOCell<S, 27>{a.dst, c, &a.g});
+}
+
+// collision of the streamed h (a.dst, in place) with the new phi's stencil
+template <class S>
+__global__ __launch_bounds__(kBlock) void k_naive_collide_h(const SweepArgs<S> a)
+{
+    using R = typename S::real;
+    const int c = xcd_block() * kBlock + threadIdx.x;
+    if (c >= a.g.ncells) return;
+    int x, y, z;
+    Nbr n;
+    if (!decode(a.g, c, x, y, z, n)) return;
+    phase_cell<S, PhiG<R>, IOCell<S, 15>, false, false>(a, c, n, PhiG<R>{a.phi_in, c, &n},
+                                                        IOCell<S, 15>{a.dst, c, &a.g});
+}
+
+// collision of the streamed g (a.dst, in place) with the updated u
+template <class S>
+__global__ __launch_bounds__(kBlock) void k_naive_collide_g(const SweepArgs<S> a)
+{
+    using R = typename S::real;
+    const int c = xcd_block() * kBlock + threadIdx.x;
+    if (c >= a.g.ncells) return;
+    int x, y, z;
+    Nbr n;
+    if (!decode(a.g, c, x, y, z, n)) return;
+    hydro_cell<S, PhiG<R>, IOCell<S, 27>, false, kHydroCollide>(a, c, n, PhiG<R>{a.phi_in, c, &n},
+                                                                 IOCell<S, 27>{a.dst, c, &a.g});
+}
+
+// One step of the straightforward algorithm: H[a] -> H[b], G[a] -> G[b],
+// phi[a] -> phi[b].  ph: h (a.src H[a], a.dst H[b]); gh: g (G[a], G[b]);
+// both with phi_in = phi[b] (the new phase field) and phi_out = phi[b].
+template <class S>
+void launch_naive_step(const SweepArgs<S> &ph, const SweepArgs<S> &gh, int blocks, hipStream_t stream)
+{
+    hipLaunchKernelGGL((k_naive_stream<S, 15>), dim3(blocks), dim3(kBlock), 0, stream, ph.src, ph.dst, ph.g);
+    hipLaunchKernelGGL((k_naive_phi<S>), dim3(blocks), dim3(kBlock), 0, stream, ph.dst, ph.phi_out, ph.g);
+    hipLaunchKernelGGL((k_naive_stream<S, 27>), dim3(blocks), dim3(kBlock), 0, stream, gh.src, gh.dst, gh.g);
+    hipLaunchKernelGGL((k_naive_update_u<S>), dim3(blocks), dim3(kBlock), 0, stream, gh);
+    hipLaunchKernelGGL((k_naive_collide_h<S>), dim3(blocks), dim3(kBlock), 0, stream, ph);
+    hipLaunchKernelGGL((k_naive_collide_g<S>), dim3(blocks), dim3(kBlock), 0, stream, gh);
 }
 
 #define LBM_FP32_SWEEPS(X)                                                                          \

@@ -14,4 +14,5 @@ LBM_FP32_SWEEPS(LBM_INSTANTIATE_SWEEP)
 #undef LBM_INSTANTIATE_SWEEP
 template void launch_fused<StoreF32>(const SweepArgs<StoreF32> &, const SweepArgs<StoreF32> &, const SweepLaunch &,
                                      hipStream_t);
+template void launch_naive_step<StoreF32>(const SweepArgs<StoreF32> &, const SweepArgs<StoreF32> &, int, hipStream_t);
 }  // namespace lbm

@@ -25,7 +25,7 @@ DTYPE_F64, DTYPE_F32 = 0, 1
 
 EXPORTS = [
     "lbm_velocity_set", "lbm_workspace_bytes", "lbm_create", "lbm_set_stream", "lbm_init_fields",
-    "lbm_step", "lbm_step_timed", "lbm_step_timed_fused", "lbm_reduce_mass", "lbm_reduce_stats", "lbm_get_macroscopic",
+    "lbm_step", "lbm_step_straightforward", "lbm_step_timed", "lbm_step_timed_fused", "lbm_reduce_mass", "lbm_reduce_stats", "lbm_get_macroscopic",
     "lbm_set_macroscopic", "lbm_shift_equilibrium", "lbm_get_pdfs", "lbm_set_pdfs", "lbm_stream_copy", "lbm_steps_done",
     "lbm_state_bytes", "lbm_save_state", "lbm_restore_state", "lbm_destroy", "lbm_last_error",
 ]
@@ -73,6 +73,7 @@ def _load():
         "lbm_set_stream": ([vp, vp], C.c_int),
         "lbm_init_fields": ([vp, vp, vp, vp], C.c_int),
         "lbm_step": ([vp, C.c_int32], C.c_int),
+        "lbm_step_straightforward": ([vp, C.c_int32], C.c_int),
         "lbm_step_timed": ([vp, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_double)], C.c_int),
         "lbm_step_timed_fused": ([vp, C.c_int32, C.POINTER(C.c_double)], C.c_int),
         "lbm_reduce_mass": ([vp, C.POINTER(C.c_double)], C.c_int),
@@ -144,6 +145,10 @@ def lbm_init_fields(ctx, phi, u, p_star):
 
 def lbm_step(ctx, n: int):
     _check(_lib.lbm_step(ctx, int(n)), "lbm_step")
+
+
+def lbm_step_straightforward(ctx, n: int):
+    _check(_lib.lbm_step_straightforward(ctx, int(n)), "lbm_step_straightforward")
 
 
 def lbm_step_timed_fused(ctx, n: int) -> float:
@@ -286,6 +291,10 @@ class Solver:
 
     def step(self, n: int = 1):
         lbm_step(self.ctx, n)
+
+    def step_straightforward(self, n: int = 1):
+        """n steps of the straightforward six-kernel algorithm (FP64, FP32)."""
+        lbm_step_straightforward(self.ctx, n)
 
     def step_timed(self, n: int):
         return lbm_step_timed(self.ctx, n)

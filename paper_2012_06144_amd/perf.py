@@ -34,6 +34,12 @@ def bytes_per_cell(storage: str) -> dict:
         # hydrodynamic sweep of one step fused with the phase sweep of the next:
         # the phase body takes u from registers and shares the phi stencil
         "fused": phase_r + phase_w + hydro_r + hydro_w - 3 * r - 1 * r,
+        # the straightforward algorithm (six passes, Sec. 4.2): stream h
+        # (15 + 15), phi = sum h (15 + 1), stream g (27 + 27), velocity update
+        # (27 g + phi + 3 u read, 3 u written), collision of h (15 + phi + 3 u
+        # read, 15 written), collision of g (27 + phi + 3 u read, 27 written)
+        "straightforward": (30 * p) + (15 * p + r) + (54 * p) + (27 * p + 4 * r + 3 * r)
+        + (15 * p + 4 * r + 15 * p) + (27 * p + 4 * r + 27 * p),
     }
 
 

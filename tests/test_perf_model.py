@@ -53,3 +53,13 @@ def test_fused_kernel_bytes(storage, expect):
     b = perf.bytes_per_cell(storage)
     r = 8 if storage == "f64" else 4
     assert b["fused"] == b["total"] - 4 * r == expect
+
+
+@pytest.mark.parametrize("storage,expect", [("f64", 1808), ("f32", 904)])
+def test_straightforward_bytes(storage, expect):
+    """The six passes of the straightforward algorithm read every population
+    set three times and write it twice: 3 x 42 + 2 x 42 populations, phi
+    written once and read three times, u read three times and written once."""
+    b = perf.bytes_per_cell(storage)
+    p = 8 if storage == "f64" else 4
+    assert b["straightforward"] == (5 * 42) * p + (1 + 3 + 9 + 3) * p == expect
