@@ -57,7 +57,9 @@
 #include <string.h>
 
 #define Q15 15
+#define Q19 19
 #define Q27 27
+#define QMAX 27
 
 typedef struct {
     int32_t nx, ny, nz;
@@ -68,6 +70,9 @@ typedef struct {
     double rho_ref;      /* buoyancy reference density: F_b = (rho - rho_ref) a */
     double normal_eps;
     int32_t density_literal; /* 1: eq. density for every phi (no clamp) */
+    int32_t lattice_phase;   /* velocity set of the phase-field step: 15 (0 = 15), 19 or 27 */
+    int32_t lattice_hydro;   /* velocity set of the hydrodynamic step: 27 (0 = 27), 19 or 15 */
+    int32_t phase_mrt;       /* 1: raw-moment MRT phase-field collision instead of SRT */
 } orc_params;
 
 typedef struct {
@@ -100,8 +105,23 @@ static const int E27[Q27][3] = {
     {1, 1, 1}, {-1, -1, -1}, {1, 1, -1}, {-1, -1, 1},
     {1, -1, 1}, {-1, 1, -1}, {-1, 1, 1}, {1, -1, -1}};
 
+/* D3Q19: rest, axis pairs and edge pairs (the first 19 vectors of D3Q27). */
+static const int E19[Q19][3] = {
+    {0, 0, 0},
+    {1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0}, {0, 0, 1}, {0, 0, -1},
+    {1, 1, 0}, {-1, -1, 0}, {1, -1, 0}, {-1, 1, 0},
+    {1, 0, 1}, {-1, 0, -1}, {1, 0, -1}, {-1, 0, 1},
+    {0, 1, 1}, {0, -1, -1}, {0, 1, -1}, {0, -1, 1}};
+
 static double W15[Q15];
+static double W19[Q19];
 static double W27[Q27];
+
+typedef struct {
+    int q;
+    const int (*e)[3];
+    const double *w;
+} orc_lat;
 
 static void init_weights(void)
 {
@@ -109,11 +129,25 @@ static void init_weights(void)
         int n = abs(E15[i][0]) + abs(E15[i][1]) + abs(E15[i][2]);
         W15[i] = (n == 0) ? 2.0 / 9.0 : (n == 1) ? 1.0 / 9.0 : 1.0 / 72.0;
     }
+    for (int i = 0; i < Q19; ++i) {
+        int n = abs(E19[i][0]) + abs(E19[i][1]) + abs(E19[i][2]);
+        W19[i] = (n == 0) ? 1.0 / 3.0 : (n == 1) ? 1.0 / 18.0 : 1.0 / 36.0;
+    }
     for (int i = 0; i < Q27; ++i) {
         int n = abs(E27[i][0]) + abs(E27[i][1]) + abs(E27[i][2]);
         W27[i] = (n == 0) ? 8.0 / 27.0 : (n == 1) ? 2.0 / 27.0
                : (n == 2) ? 1.0 / 54.0 : 1.0 / 216.0;
     }
+}
+
+/* Velocity set of q directions (15, 19 or 27; anything else gives D3Q27). */
+static orc_lat lat_of(int q)
+{
+    orc_lat L;
+    L.q = q == Q15 ? Q15 : (q == Q19 ? Q19 : Q27);
+    L.e = q == Q15 ? E15 : (q == Q19 ? E19 : E27);
+    L.w = q == Q15 ? W15 : (q == Q19 ? W19 : W27);
+    return L;
 }
 
 static int opposite(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1); }
@@ -124,21 +158,13 @@ static const double CS2 = 1.0 / 3.0; /* c_s^2 with dx = dt = 1 */
 int orc_velocity_set(int32_t q, int32_t *e, double *w)
 {
     init_weights();
-    if (q == Q15) {
-        for (int i = 0; i < Q15; ++i) {
-            for (int a = 0; a < 3; ++a) e[3 * i + a] = E15[i][a];
-            w[i] = W15[i];
-        }
-        return 0;
+    if (q != Q15 && q != Q19 && q != Q27) return -1;
+    const orc_lat L = lat_of(q);
+    for (int i = 0; i < L.q; ++i) {
+        for (int a = 0; a < 3; ++a) e[3 * i + a] = L.e[i][a];
+        w[i] = L.w[i];
     }
-    if (q == Q27) {
-        for (int i = 0; i < Q27; ++i) {
-            for (int a = 0; a < 3; ++a) e[3 * i + a] = E27[i][a];
-            w[i] = W27[i];
-        }
-        return 0;
-    }
-    return -1;
+    return 0;
 }
 
 /* Gamma_i(u) = w_i [1 + e.u/cs^2 + (e.u)^2/(2 cs^4) - u.u/(2 cs^2)]
@@ -153,42 +179,57 @@ static double gamma_i(const int e[3], double w, const double u[3])
 void orc_gamma(int32_t q, const double *u, double *out)
 {
     init_weights();
-    for (int i = 0; i < q; ++i)
-        out[i] = (q == Q15) ? gamma_i(E15[i], W15[i], u) : gamma_i(E27[i], W27[i], u);
+    const orc_lat L = lat_of(q);
+    for (int i = 0; i < L.q; ++i) out[i] = gamma_i(L.e[i], L.w[i], u);
 }
 
 /* g_eq_i = p* w_i + (Gamma_i - w_i)  (Section 3.2) */
-static void hydro_equilibrium(double pstar, const double u[3], double out[Q27])
+static void hydro_equilibrium(orc_lat L, double pstar, const double u[3], double *out)
 {
-    for (int i = 0; i < Q27; ++i)
-        out[i] = pstar * W27[i] + (gamma_i(E27[i], W27[i], u) - W27[i]);
+    for (int i = 0; i < L.q; ++i)
+        out[i] = pstar * L.w[i] + (gamma_i(L.e[i], L.w[i], u) - L.w[i]);
 }
 
 void orc_hydro_equilibrium(double pstar, const double *u, double *out)
 {
     init_weights();
-    hydro_equilibrium(pstar, u, out);
+    hydro_equilibrium(lat_of(Q27), pstar, u, out);
 }
 
 /* F^phi_i = theta w_i e_i . n  (eq. interfaceTracking, dt = 1) */
-static void phase_forcing(double theta, const double n[3], double out[Q15])
+static void phase_forcing(orc_lat L, double theta, const double n[3], double *out)
 {
-    for (int i = 0; i < Q15; ++i)
-        out[i] = theta * W15[i] * (E15[i][0] * n[0] + E15[i][1] * n[1] + E15[i][2] * n[2]);
+    for (int i = 0; i < L.q; ++i)
+        out[i] = theta * L.w[i] * (L.e[i][0] * n[0] + L.e[i][1] * n[1] + L.e[i][2] * n[2]);
 }
 
 void orc_phase_forcing(double theta, const double *n, double *out)
 {
     init_weights();
-    phase_forcing(theta, n, out);
+    phase_forcing(lat_of(Q15), theta, n, out);
 }
 
-/* ---- D3Q27 weighted-orthogonal moment matrix ---------------------------- */
-static double MM[Q27][Q27];   /* row k: orthogonalised monomial k at e_i */
-static double MINV[Q27][Q27];
-static int DEG[Q27];          /* total degree of the monomial of row k */
-static int EXPO[Q27][3];      /* exponents (a, b, c) of the monomial of row k */
-static int mrt_ready = 0;
+/* ---- weighted-orthogonal moment matrices -------------------------------------
+ * For a velocity set of q directions: the monomials x^a y^b z^c (a, b, c in
+ * {0, 1, 2}) in order of total degree, orthogonalised one after another
+ * (modified Gram-Schmidt under sum_i w_i f_i g_i, no normalisation); a
+ * monomial that is a combination of the earlier ones on this set (its
+ * remainder vanishes) is left out, which leaves exactly q rows.  The raw
+ * moment matrix of the phase-field MRT takes the same monomials without
+ * the orthogonalisation.                                                   */
+typedef struct {
+    int ready;
+    int q;
+    double M[QMAX][QMAX];    /* row k: orthogonalised monomial k at e_i */
+    double Minv[QMAX][QMAX];
+    double R[QMAX][QMAX];    /* row k: the raw monomial k at e_i */
+    double Rinv[QMAX][QMAX];
+    int deg[QMAX];           /* total degree of the monomial of row k */
+    int expo[QMAX][3];       /* exponents (a, b, c) of the monomial of row k */
+} orc_mrt;
+static orc_mrt MRT[3];       /* D3Q15, D3Q19, D3Q27 */
+
+static int mrt_slot(int q) { return q == Q15 ? 0 : (q == Q19 ? 1 : 2); }
 
 static double monomial(const int e[3], int a, int b, int c)
 {
@@ -199,97 +240,128 @@ static double monomial(const int e[3], int a, int b, int c)
     return v;
 }
 
-static double winner(const double *f, const double *g)
+static double winner(orc_lat L, const double *f, const double *g)
 {
     double s = 0.0;
-    for (int i = 0; i < Q27; ++i) s += W27[i] * f[i] * g[i];
+    for (int i = 0; i < L.q; ++i) s += L.w[i] * f[i] * g[i];
     return s;
 }
 
-/* Gauss-Jordan inverse with partial pivoting. */
-static int invert27(double A[Q27][Q27], double R[Q27][Q27])
+/* Gauss-Jordan inverse of an n x n matrix with partial pivoting. */
+static int invert_n(int n, double A[QMAX][QMAX], double R[QMAX][QMAX])
 {
-    double T[Q27][2 * Q27];
-    for (int r = 0; r < Q27; ++r)
-        for (int c = 0; c < 2 * Q27; ++c)
-            T[r][c] = (c < Q27) ? A[r][c] : (c - Q27 == r ? 1.0 : 0.0);
-    for (int col = 0; col < Q27; ++col) {
+    double T[QMAX][2 * QMAX];
+    for (int r = 0; r < n; ++r)
+        for (int c = 0; c < 2 * n; ++c)
+            T[r][c] = (c < n) ? A[r][c] : (c - n == r ? 1.0 : 0.0);
+    for (int col = 0; col < n; ++col) {
         int piv = col;
-        for (int r = col + 1; r < Q27; ++r)
+        for (int r = col + 1; r < n; ++r)
             if (fabs(T[r][col]) > fabs(T[piv][col])) piv = r;
         if (fabs(T[piv][col]) < 1e-14) return -1;
         if (piv != col)
-            for (int c = 0; c < 2 * Q27; ++c) {
+            for (int c = 0; c < 2 * n; ++c) {
                 double t = T[col][c]; T[col][c] = T[piv][c]; T[piv][c] = t;
             }
         double d = T[col][col];
-        for (int c = 0; c < 2 * Q27; ++c) T[col][c] /= d;
-        for (int r = 0; r < Q27; ++r) {
+        for (int c = 0; c < 2 * n; ++c) T[col][c] /= d;
+        for (int r = 0; r < n; ++r) {
             if (r == col) continue;
             double f = T[r][col];
             if (f != 0.0)
-                for (int c = 0; c < 2 * Q27; ++c) T[r][c] -= f * T[col][c];
+                for (int c = 0; c < 2 * n; ++c) T[r][c] -= f * T[col][c];
         }
     }
-    for (int r = 0; r < Q27; ++r)
-        for (int c = 0; c < Q27; ++c) R[r][c] = T[r][Q27 + c];
+    for (int r = 0; r < n; ++r)
+        for (int c = 0; c < n; ++c) R[r][c] = T[r][n + c];
     return 0;
 }
 
-static int build_mrt(void)
+static orc_mrt *build_mrt_q(int q)
 {
-    if (mrt_ready) return 0;
+    orc_mrt *m = &MRT[mrt_slot(q)];
+    if (m->ready) return m;
     init_weights();
-    /* monomials x^a y^b z^c, a,b,c in {0,1,2}, sorted by total degree;
-     * within a degree the order is fixed but irrelevant (equal rates). */
+    const orc_lat L = lat_of(q);
+    m->q = L.q;
     int k = 0;
-    for (int deg = 0; deg <= 6; ++deg)
+    for (int deg = 0; deg <= 6 && k < L.q; ++deg)
         for (int a = 2; a >= 0; --a)
             for (int b = 2; b >= 0; --b)
                 for (int c = 2; c >= 0; --c) {
-                    if (a + b + c != deg) continue;
-                    for (int i = 0; i < Q27; ++i) MM[k][i] = monomial(E27[i], a, b, c);
-                    DEG[k] = deg;
-                    EXPO[k][0] = a;
-                    EXPO[k][1] = b;
-                    EXPO[k][2] = c;
+                    if (a + b + c != deg || k >= L.q) continue;
+                    double row[QMAX], raw[QMAX];
+                    for (int i = 0; i < L.q; ++i) raw[i] = row[i] = monomial(L.e[i], a, b, c);
+                    for (int s2 = 0; s2 < k; ++s2) {
+                        double proj = winner(L, row, m->M[s2]) / winner(L, m->M[s2], m->M[s2]);
+                        for (int i = 0; i < L.q; ++i) row[i] -= proj * m->M[s2][i];
+                    }
+                    if (winner(L, row, row) < 1e-12) continue;  /* dependent on this set */
+                    for (int i = 0; i < L.q; ++i) {
+                        m->M[k][i] = row[i];
+                        m->R[k][i] = raw[i];
+                    }
+                    m->deg[k] = deg;
+                    m->expo[k][0] = a;
+                    m->expo[k][1] = b;
+                    m->expo[k][2] = c;
                     ++k;
                 }
-    /* modified Gram-Schmidt, weighted inner product, no normalisation */
-    for (int r = 0; r < Q27; ++r)
-        for (int s = 0; s < r; ++s) {
-            double proj = winner(MM[r], MM[s]) / winner(MM[s], MM[s]);
-            for (int i = 0; i < Q27; ++i) MM[r][i] -= proj * MM[s][i];
-        }
-    if (invert27(MM, MINV) != 0) return -1;
-    mrt_ready = 1;
-    return 0;
+    if (k != L.q) return NULL;
+    if (invert_n(L.q, m->M, m->Minv) != 0) return NULL;
+    if (invert_n(L.q, m->R, m->Rinv) != 0) return NULL;
+    m->ready = 1;
+    return m;
 }
 
-/* Export M, M^-1 and the degree of each row for the pins. */
+static int build_mrt(void) { return build_mrt_q(Q27) ? 0 : -1; }
+
+/* Export M, M^-1 and the degree of each row for the pins (D3Q27). */
 int orc_moment_matrix(double *M, double *Minv, int32_t *deg)
 {
-    if (build_mrt() != 0) return -1;
+    const orc_mrt *m = build_mrt_q(Q27);
+    if (!m) return -1;
     for (int r = 0; r < Q27; ++r) {
-        deg[r] = DEG[r];
+        deg[r] = m->deg[r];
         for (int c = 0; c < Q27; ++c) {
-            M[r * Q27 + c] = MM[r][c];
-            Minv[r * Q27 + c] = MINV[r][c];
+            M[r * Q27 + c] = m->M[r][c];
+            Minv[r * Q27 + c] = m->Minv[r][c];
         }
     }
     return 0;
 }
 
-static void relaxation_rates(double s_nu, double S[Q27])
+/* The same for a velocity set of q directions, with the raw monomial
+ * matrix and its inverse and the exponents of each row.                  */
+int orc_moment_matrix_q(int32_t q, double *M, double *Minv, double *R, double *Rinv, int32_t *deg,
+                        int32_t *expo)
 {
-    for (int k = 0; k < Q27; ++k) S[k] = (DEG[k] == 2) ? s_nu : 1.0;
+    if (q != Q15 && q != Q19 && q != Q27) return -1;
+    const orc_mrt *m = build_mrt_q(q);
+    if (!m) return -1;
+    for (int r = 0; r < q; ++r) {
+        deg[r] = m->deg[r];
+        for (int a = 0; a < 3; ++a) expo[3 * r + a] = m->expo[r][a];
+        for (int c = 0; c < q; ++c) {
+            M[r * q + c] = m->M[r][c];
+            Minv[r * q + c] = m->Minv[r][c];
+            R[r * q + c] = m->R[r][c];
+            Rinv[r * q + c] = m->Rinv[r][c];
+        }
+    }
+    return 0;
 }
 
-static void matvec(double A[Q27][Q27], const double *x, double *y)
+static void relaxation_rates(const orc_mrt *m, double s_nu, double *S)
 {
-    for (int r = 0; r < Q27; ++r) {
+    for (int k = 0; k < m->q; ++k) S[k] = (m->deg[k] == 2) ? s_nu : 1.0;
+}
+
+static void matvec(const orc_mrt *m, const double A[QMAX][QMAX], const double *x, double *y)
+{
+    for (int r = 0; r < m->q; ++r) {
         double s = 0.0;
-        for (int c = 0; c < Q27; ++c) s += A[r][c] * x[c];
+        for (int c = 0; c < m->q; ++c) s += A[r][c] * x[c];
         y[r] = s;
     }
 }
@@ -297,22 +369,22 @@ static void matvec(double A[Q27][Q27], const double *x, double *y)
 /* Sum_k e_k e_k^T (Omega (g - g_eq(p*, u)))_k with Omega = M^-1 S M:
  * the bracket of eq. viscousForce, before the factor -nu/cs^2 and the
  * contraction with grad(rho).                                          */
-static void viscous_bracket(const double g[Q27], double s_nu, const double u[3],
-                            double V[3][3])
+static void viscous_bracket(orc_lat L, const double *g, double s_nu, const double u[3], double V[3][3])
 {
+    const orc_mrt *m = build_mrt_q(L.q);
     double pstar = 0.0;
-    for (int i = 0; i < Q27; ++i) pstar += g[i];
-    double geq[Q27], d[Q27], m[Q27], Sd[Q27], om[Q27], S[Q27];
-    hydro_equilibrium(pstar, u, geq);
-    for (int i = 0; i < Q27; ++i) d[i] = g[i] - geq[i];
-    relaxation_rates(s_nu, S);
-    matvec(MM, d, m);
-    for (int k = 0; k < Q27; ++k) Sd[k] = S[k] * m[k];
-    matvec(MINV, Sd, om);
+    for (int i = 0; i < L.q; ++i) pstar += g[i];
+    double geq[QMAX], d[QMAX], mm[QMAX], Sd[QMAX], om[QMAX], S[QMAX];
+    hydro_equilibrium(L, pstar, u, geq);
+    for (int i = 0; i < L.q; ++i) d[i] = g[i] - geq[i];
+    relaxation_rates(m, s_nu, S);
+    matvec(m, m->M, d, mm);
+    for (int k = 0; k < L.q; ++k) Sd[k] = S[k] * mm[k];
+    matvec(m, m->Minv, Sd, om);
     for (int a = 0; a < 3; ++a)
         for (int b = 0; b < 3; ++b) {
             double s = 0.0;
-            for (int i = 0; i < Q27; ++i) s += E27[i][a] * E27[i][b] * om[i];
+            for (int i = 0; i < L.q; ++i) s += L.e[i][a] * L.e[i][b] * om[i];
             V[a][b] = s;
         }
 }
@@ -321,7 +393,7 @@ int orc_viscous_bracket(const double *g, double s_nu, const double *u, double *V
 {
     if (build_mrt() != 0) return -1;
     double v[3][3];
-    viscous_bracket(g, s_nu, u, v);
+    viscous_bracket(lat_of(Q27), g, s_nu, u, v);
     for (int a = 0; a < 3; ++a)
         for (int b = 0; b < 3; ++b) V[3 * a + b] = v[a][b];
     return 0;
@@ -330,31 +402,84 @@ int orc_viscous_bracket(const double *g, double s_nu, const double *u, double *V
 /* Moment-space collision (eq. improved_collision, with the "m -" of the
  * listing): m = M g, m_eq = M g_eq(p*, u), F_m = (0, F/rho, 0, ...),
  * m* = m - S (m - m_eq + F_m/2) + F_m, g* = M^-1 m*.                  */
-static void mrt_collide(const double g[Q27], double pstar, const double u[3],
-                        const double F[3], double rho, double s_nu, double out[Q27])
+static void mrt_collide(orc_lat L, const double *g, double pstar, const double u[3],
+                        const double F[3], double rho, double s_nu, double *out)
 {
-    double geq[Q27], m[Q27], meq[Q27], Fm[Q27], ms[Q27], S[Q27];
-    hydro_equilibrium(pstar, u, geq);
-    matvec(MM, g, m);
-    matvec(MM, geq, meq);
-    relaxation_rates(s_nu, S);
+    const orc_mrt *m = build_mrt_q(L.q);
+    double geq[QMAX], mm[QMAX], meq[QMAX], Fm[QMAX], ms[QMAX], S[QMAX];
+    hydro_equilibrium(L, pstar, u, geq);
+    matvec(m, m->M, g, mm);
+    matvec(m, m->M, geq, meq);
+    relaxation_rates(m, s_nu, S);
     /* F_m is F/rho on the three first-order rows (the monomials x, y, z,
      * already orthogonal to row 0) and zero on every other row.        */
-    for (int k = 0; k < Q27; ++k) {
+    for (int k = 0; k < L.q; ++k) {
         Fm[k] = 0.0;
-        if (DEG[k] == 1)
+        if (m->deg[k] == 1)
             for (int a = 0; a < 3; ++a)
-                if (EXPO[k][a] == 1) Fm[k] = F[a] / rho;
+                if (m->expo[k][a] == 1) Fm[k] = F[a] / rho;
     }
-    for (int k = 0; k < Q27; ++k) ms[k] = m[k] - S[k] * (m[k] - meq[k] + 0.5 * Fm[k]) + Fm[k];
-    matvec(MINV, ms, out);
+    for (int k = 0; k < L.q; ++k) ms[k] = mm[k] - S[k] * (mm[k] - meq[k] + 0.5 * Fm[k]) + Fm[k];
+    matvec(m, m->Minv, ms, out);
 }
 
 int orc_mrt_collide(const double *g, double pstar, const double *u, const double *F,
                     double rho, double s_nu, double *out)
 {
     if (build_mrt() != 0) return -1;
-    mrt_collide(g, pstar, u, F, rho, s_nu, out);
+    mrt_collide(lat_of(Q27), g, pstar, u, F, rho, s_nu, out);
+    return 0;
+}
+
+/* Hydrodynamic equilibrium, collision and viscous bracket on a velocity set
+ * of q directions (pins of the other lattices).                            */
+int orc_hydro_equilibrium_q(int32_t q, double pstar, const double *u, double *out)
+{
+    if (q != Q15 && q != Q19 && q != Q27) return -1;
+    init_weights();
+    hydro_equilibrium(lat_of(q), pstar, u, out);
+    return 0;
+}
+
+int orc_mrt_collide_q(int32_t q, const double *g, double pstar, const double *u, const double *F, double rho,
+                      double s_nu, double *out)
+{
+    if ((q != Q15 && q != Q19 && q != Q27) || !build_mrt_q(q)) return -1;
+    mrt_collide(lat_of(q), g, pstar, u, F, rho, s_nu, out);
+    return 0;
+}
+
+int orc_viscous_bracket_q(int32_t q, const double *g, double s_nu, const double *u, double *V)
+{
+    if ((q != Q15 && q != Q19 && q != Q27) || !build_mrt_q(q)) return -1;
+    double v[3][3];
+    viscous_bracket(lat_of(q), g, s_nu, u, v);
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) V[3 * a + b] = v[a][b];
+    return 0;
+}
+
+/* Phase-field collision (eq. lb_interface), h* = h + Omega (h_eq - h - F/2)
+ * + F with Omega = R^-1 S R in raw moments: the first-order moments relax
+ * with omega, every other moment with one (Sec. 3.1).  The collision of
+ * the fused and straightforward steps with phase_mrt = 1.                  */
+static void phase_mrt_collide(orc_lat L, const double *h, const double *heq, const double *F, double omega,
+                              double *out)
+{
+    const orc_mrt *m = build_mrt_q(L.q);
+    double d[QMAX], md[QMAX];
+    for (int i = 0; i < L.q; ++i) d[i] = heq[i] - h[i] - 0.5 * F[i];
+    matvec(m, m->R, d, md);
+    for (int k = 0; k < L.q; ++k) md[k] *= (m->deg[k] == 1) ? omega : 1.0;
+    matvec(m, m->Rinv, md, out);
+    for (int i = 0; i < L.q; ++i) out[i] += h[i] + F[i];
+}
+
+int orc_phase_mrt_collide_q(int32_t q, const double *h, const double *heq, const double *F, double omega,
+                            double *out)
+{
+    if ((q != Q15 && q != Q19 && q != Q27) || !build_mrt_q(q)) return -1;
+    phase_mrt_collide(lat_of(q), h, heq, F, omega, out);
     return 0;
 }
 
@@ -366,6 +491,7 @@ typedef struct {
     double *G, *Gn;      /* 27 planes: pre-collision hydro PDFs at x */
     double *phiA, *phiB; /* phase field, previous / new               */
     double *u;           /* 3 planes                                   */
+    int qp, qh;          /* velocity sets of the two steps              */
 } orc_state;
 
 static inline int64_t cidx(const orc_params *p, int x, int y, int z)
@@ -402,8 +528,9 @@ static inline double phi_at(const orc_params *p, const double *phi, int x, int y
 static void iso_gradient(const orc_params *p, const double *phi, int q, int x, int y, int z,
                          double grad[3])
 {
-    const int (*E)[3] = (q == Q15) ? E15 : E27;
-    const double *W = (q == Q15) ? W15 : W27;
+    const orc_lat L = lat_of(q);
+    const int (*E)[3] = L.e;
+    const double *W = L.w;
     double acc[3] = {0.0, 0.0, 0.0};
     for (int i = 1; i < q; i += 2) {
         double d = phi_at(p, phi, x, y, z, E[i][0], E[i][1], E[i][2]) -
@@ -437,8 +564,9 @@ static double density_of(const orc_params *p, double phi)
 
 static double iso_laplacian(const orc_params *p, const double *phi, int q, int x, int y, int z)
 {
-    const int (*E)[3] = (q == Q15) ? E15 : E27;
-    const double *W = (q == Q15) ? W15 : W27;
+    const orc_lat L = lat_of(q);
+    const int (*E)[3] = L.e;
+    const double *W = L.w;
     double c = phi[cidx(p, x, y, z)];
     double acc = 0.0;
     for (int i = 0; i < q; ++i)
@@ -460,16 +588,21 @@ orc_state *orc_create(const orc_params *p)
 {
     if (!p || p->nx <= 0 || p->ny <= 0 || p->nz <= 0) return NULL;
     if (p->walls_y && p->ny < 3) return NULL;
-    if (build_mrt() != 0) return NULL;
+    const int qp = p->lattice_phase == 0 ? Q15 : p->lattice_phase;
+    const int qh = p->lattice_hydro == 0 ? Q27 : p->lattice_hydro;
+    if ((qp != Q15 && qp != Q19 && qp != Q27) || (qh != Q15 && qh != Q19 && qh != Q27)) return NULL;
+    if (build_mrt() != 0 || !build_mrt_q(qp) || !build_mrt_q(qh)) return NULL;
     orc_state *s = (orc_state *)calloc(1, sizeof(orc_state));
     if (!s) return NULL;
     s->p = *p;
+    s->qp = qp;
+    s->qh = qh;
     s->n = (int64_t)p->nx * p->ny * p->nz;
     size_t n = (size_t)s->n;
-    s->H = calloc(Q15 * n, sizeof(double));
-    s->Hn = calloc(Q15 * n, sizeof(double));
-    s->G = calloc(Q27 * n, sizeof(double));
-    s->Gn = calloc(Q27 * n, sizeof(double));
+    s->H = calloc((size_t)qp * n, sizeof(double));
+    s->Hn = calloc((size_t)qp * n, sizeof(double));
+    s->G = calloc((size_t)qh * n, sizeof(double));
+    s->Gn = calloc((size_t)qh * n, sizeof(double));
     s->phiA = calloc(n, sizeof(double));
     s->phiB = calloc(n, sizeof(double));
     s->u = calloc(3 * n, sizeof(double));
@@ -494,10 +627,11 @@ void orc_init(orc_state *s, const double *phi, const double *u, const double *ps
 {
     const orc_params *p = &s->p;
     int64_t n = s->n;
-    memset(s->H, 0, sizeof(double) * Q15 * n);
-    memset(s->G, 0, sizeof(double) * Q27 * n);
-    memset(s->Hn, 0, sizeof(double) * Q15 * n);
-    memset(s->Gn, 0, sizeof(double) * Q27 * n);
+    const orc_lat LP = lat_of(s->qp), LH = lat_of(s->qh);
+    memset(s->H, 0, sizeof(double) * LP.q * n);
+    memset(s->G, 0, sizeof(double) * LH.q * n);
+    memset(s->Hn, 0, sizeof(double) * LP.q * n);
+    memset(s->Gn, 0, sizeof(double) * LH.q * n);
     memset(s->phiA, 0, sizeof(double) * n);
     memset(s->phiB, 0, sizeof(double) * n);
     memset(s->u, 0, sizeof(double) * 3 * n);
@@ -507,10 +641,10 @@ void orc_init(orc_state *s, const double *phi, const double *u, const double *ps
                 if (is_wall_row(p, y)) continue;
                 int64_t c = cidx(p, x, y, z);
                 double uc[3] = {u[c], u[n + c], u[2 * n + c]};
-                double geq[Q27];
-                for (int i = 0; i < Q15; ++i) s->H[i * n + c] = phi[c] * gamma_i(E15[i], W15[i], uc);
-                hydro_equilibrium(pstar[c], uc, geq);
-                for (int i = 0; i < Q27; ++i) s->G[i * n + c] = geq[i];
+                double geq[QMAX];
+                for (int i = 0; i < LP.q; ++i) s->H[i * n + c] = phi[c] * gamma_i(LP.e[i], LP.w[i], uc);
+                hydro_equilibrium(LH, pstar[c], uc, geq);
+                for (int i = 0; i < LH.q; ++i) s->G[i * n + c] = geq[i];
                 s->phiA[c] = phi[c];
                 for (int a = 0; a < 3; ++a) s->u[a * n + c] = uc[a];
             }
@@ -522,22 +656,23 @@ static void phase_cell(orc_state *s, int x, int y, int z)
     const orc_params *p = &s->p;
     const int64_t n = s->n;
     const int64_t c = cidx(p, x, y, z);
-    double P[Q15];
-    for (int i = 0; i < Q15; ++i) {
-        int sy = ny_nb(p, y, -E15[i][1]);
+    const orc_lat L = lat_of(s->qp);
+    double P[QMAX];
+    for (int i = 0; i < L.q; ++i) {
+        int sy = ny_nb(p, y, -L.e[i][1]);
         if (is_wall_row(p, sy)) {
             P[i] = s->H[opposite(i) * n + c]; /* halfway bounce-back */
         } else {
-            int64_t src = cidx(p, wrap(x - E15[i][0], p->nx), sy, wrap(z - E15[i][2], p->nz));
+            int64_t src = cidx(p, wrap(x - L.e[i][0], p->nx), sy, wrap(z - L.e[i][2], p->nz));
             P[i] = s->H[i * n + src];
         }
     }
     double phi = 0.0;
-    for (int i = 0; i < Q15; ++i) phi += P[i];
+    for (int i = 0; i < L.q; ++i) phi += P[i];
     s->phiB[c] = phi;
 
     double grad[3];
-    iso_gradient(p, s->phiA, Q15, x, y, z, grad);
+    iso_gradient(p, s->phiA, L.q, x, y, z, grad);
     double gnorm = sqrt(grad[0] * grad[0] + grad[1] * grad[1] + grad[2] * grad[2]);
     double nrm[3];
     for (int a = 0; a < 3; ++a) nrm[a] = grad[a] / (gnorm + p->normal_eps);
@@ -548,11 +683,18 @@ static void phase_cell(orc_state *s, int x, int y, int z)
     double uc[3] = {s->u[c], s->u[n + c], s->u[2 * n + c]};
     double tau_phi = p->mobility / CS2;            /* eq. mobility, dt = 1 */
     double omega = 1.0 / (tau_phi + 0.5);
-    double Fphi[Q15];
-    phase_forcing(theta, nrm, Fphi);
-    for (int i = 0; i < Q15; ++i) {
-        double heq = phi * gamma_i(E15[i], W15[i], uc);
-        s->Hn[i * n + c] = P[i] + omega * (heq - P[i] - 0.5 * Fphi[i]) + Fphi[i];
+    double Fphi[QMAX];
+    phase_forcing(L, theta, nrm, Fphi);
+    if (p->phase_mrt) {
+        double heq[QMAX], hs[QMAX];
+        for (int i = 0; i < L.q; ++i) heq[i] = phi * gamma_i(L.e[i], L.w[i], uc);
+        phase_mrt_collide(L, P, heq, Fphi, omega, hs);
+        for (int i = 0; i < L.q; ++i) s->Hn[i * n + c] = hs[i];
+    } else {
+        for (int i = 0; i < L.q; ++i) {
+            double heq = phi * gamma_i(L.e[i], L.w[i], uc);
+            s->Hn[i * n + c] = P[i] + omega * (heq - P[i] - 0.5 * Fphi[i]) + Fphi[i];
+        }
     }
 }
 
@@ -562,8 +704,9 @@ static void hydro_cell(orc_state *s, int x, int y, int z)
     const orc_params *p = &s->p;
     const int64_t n = s->n;
     const int64_t c = cidx(p, x, y, z);
-    double g[Q27];
-    for (int i = 0; i < Q27; ++i) g[i] = s->G[i * n + c];
+    const orc_lat L = lat_of(s->qh);
+    double g[QMAX];
+    for (int i = 0; i < L.q; ++i) g[i] = s->G[i * n + c];
 
     const double dphi = p->phi_H - p->phi_L;
     double phi = s->phiB[c];
@@ -573,8 +716,8 @@ static void hydro_cell(orc_state *s, int x, int y, int z)
     double nu = tau * CS2;
 
     double grad[3];
-    iso_gradient(p, s->phiB, Q27, x, y, z, grad);
-    double lap = iso_laplacian(p, s->phiB, Q27, x, y, z);
+    iso_gradient(p, s->phiB, L.q, x, y, z, grad);
+    double lap = iso_laplacian(p, s->phiB, L.q, x, y, z);
     double grad_rho[3];
     for (int a = 0; a < 3; ++a) grad_rho[a] = (p->rho_H - p->rho_L) / dphi * grad[a];
 
@@ -584,14 +727,14 @@ static void hydro_cell(orc_state *s, int x, int y, int z)
     double mu_phi = 4.0 * beta * (phi - p->phi_L) * (phi - p->phi_H) * (phi - phi0) - kappa * lap;
 
     double pstar = 0.0, j[3] = {0.0, 0.0, 0.0};
-    for (int i = 0; i < Q27; ++i) {
+    for (int i = 0; i < L.q; ++i) {
         pstar += g[i];
-        for (int a = 0; a < 3; ++a) j[a] += g[i] * E27[i][a];
+        for (int a = 0; a < 3; ++a) j[a] += g[i] * L.e[i][a];
     }
 
     double u_old[3] = {s->u[c], s->u[n + c], s->u[2 * n + c]};
     double V[3][3];
-    viscous_bracket(g, s_nu, u_old, V);
+    viscous_bracket(L, g, s_nu, u_old, V);
 
     double F[3];
     for (int a = 0; a < 3; ++a) {
@@ -608,15 +751,15 @@ static void hydro_cell(orc_state *s, int x, int y, int z)
     for (int a = 0; a < 3; ++a) u_new[a] = j[a] + F[a] / (2.0 * rho);
     for (int a = 0; a < 3; ++a) s->u[a * n + c] = u_new[a];
 
-    double gs[Q27];
-    mrt_collide(g, pstar, u_new, F, rho, s_nu, gs);
+    double gs[QMAX];
+    mrt_collide(L, g, pstar, u_new, F, rho, s_nu, gs);
 
-    for (int i = 0; i < Q27; ++i) {
-        int dy = ny_nb(p, y, E27[i][1]);
+    for (int i = 0; i < L.q; ++i) {
+        int dy = ny_nb(p, y, L.e[i][1]);
         if (is_wall_row(p, dy)) {
             s->Gn[opposite(i) * n + c] = gs[i]; /* halfway bounce-back */
         } else {
-            int64_t dst = cidx(p, wrap(x + E27[i][0], p->nx), dy, wrap(z + E27[i][2], p->nz));
+            int64_t dst = cidx(p, wrap(x + L.e[i][0], p->nx), dy, wrap(z + L.e[i][2], p->nz));
             s->Gn[i * n + dst] = gs[i];
         }
     }
@@ -668,7 +811,7 @@ void orc_step(orc_state *s, int32_t nsteps)
 /* Force of eq. forceHydro at cell c from the pre-collision g there, the
  * phase field `phi` (stencil) and the velocity `uv` inside the viscous
  * force; also returns rho, s_nu and the moments p* and j.                 */
-static void naive_force(const orc_state *s, const double *phi, int x, int y, int z, const double g[Q27],
+static void naive_force(const orc_state *s, const double *phi, int x, int y, int z, const double *g,
                         const double uv[3], double F[3], double *rho_out, double *s_nu_out,
                         double *pstar_out, double j[3])
 {
@@ -682,8 +825,9 @@ static void naive_force(const orc_state *s, const double *phi, int x, int y, int
     double nu = tau * CS2;
 
     double grad[3];
-    iso_gradient(p, phi, Q27, x, y, z, grad);
-    double lap = iso_laplacian(p, phi, Q27, x, y, z);
+    const orc_lat L = lat_of(s->qh);
+    iso_gradient(p, phi, L.q, x, y, z, grad);
+    double lap = iso_laplacian(p, phi, L.q, x, y, z);
     double grad_rho[3];
     for (int a = 0; a < 3; ++a) grad_rho[a] = (p->rho_H - p->rho_L) / dphi * grad[a];
     double beta = 12.0 * p->sigma / p->xi;
@@ -693,12 +837,12 @@ static void naive_force(const orc_state *s, const double *phi, int x, int y, int
 
     double pstar = 0.0;
     for (int a = 0; a < 3; ++a) j[a] = 0.0;
-    for (int i = 0; i < Q27; ++i) {
+    for (int i = 0; i < L.q; ++i) {
         pstar += g[i];
-        for (int a = 0; a < 3; ++a) j[a] += g[i] * E27[i][a];
+        for (int a = 0; a < 3; ++a) j[a] += g[i] * L.e[i][a];
     }
     double V[3][3];
-    viscous_bracket(g, s_nu, uv, V);
+    viscous_bracket(L, g, s_nu, uv, V);
     for (int a = 0; a < 3; ++a) {
         double Fp = -pstar * CS2 * grad_rho[a];
         double Fs = mu_phi * grad[a];
@@ -719,12 +863,13 @@ static void naive_stream_h(orc_state *s, int x, int y, int z)
 {
     const orc_params *p = &s->p;
     const int64_t n = s->n, c = cidx(p, x, y, z);
-    for (int i = 0; i < Q15; ++i) {
-        int sy = ny_nb(p, y, -E15[i][1]);
+    const orc_lat L = lat_of(s->qp);
+    for (int i = 0; i < L.q; ++i) {
+        int sy = ny_nb(p, y, -L.e[i][1]);
         if (is_wall_row(p, sy))
             s->Hn[i * n + c] = s->H[opposite(i) * n + c];
         else
-            s->Hn[i * n + c] = s->H[i * n + cidx(p, wrap(x - E15[i][0], p->nx), sy, wrap(z - E15[i][2], p->nz))];
+            s->Hn[i * n + c] = s->H[i * n + cidx(p, wrap(x - L.e[i][0], p->nx), sy, wrap(z - L.e[i][2], p->nz))];
     }
 }
 
@@ -733,7 +878,7 @@ static void naive_update_phi(orc_state *s, int x, int y, int z)
 {
     const int64_t n = s->n, c = cidx(&s->p, x, y, z);
     double phi = 0.0;
-    for (int i = 0; i < Q15; ++i) phi += s->Hn[i * n + c];
+    for (int i = 0; i < s->qp; ++i) phi += s->Hn[i * n + c];
     s->phiB[c] = phi;
 }
 
@@ -742,8 +887,8 @@ static void naive_update_phi(orc_state *s, int x, int y, int z)
 static void naive_update_u(orc_state *s, int x, int y, int z)
 {
     const int64_t n = s->n, c = cidx(&s->p, x, y, z);
-    double g[Q27];
-    for (int i = 0; i < Q27; ++i) g[i] = s->G[i * n + c];
+    double g[QMAX];
+    for (int i = 0; i < s->qh; ++i) g[i] = s->G[i * n + c];
     double u_old[3] = {s->u[c], s->u[n + c], s->u[2 * n + c]};
     double F[3], rho, s_nu, pstar, j[3];
     naive_force(s, s->phiB, x, y, z, g, u_old, F, &rho, &s_nu, &pstar, j);
@@ -758,7 +903,8 @@ static void naive_collide_h(orc_state *s, int x, int y, int z)
     const int64_t n = s->n, c = cidx(p, x, y, z);
     double phi = s->phiB[c];
     double grad[3];
-    iso_gradient(p, s->phiB, Q15, x, y, z, grad);
+    const orc_lat L = lat_of(s->qp);
+    iso_gradient(p, s->phiB, L.q, x, y, z, grad);
     double gnorm = sqrt(grad[0] * grad[0] + grad[1] * grad[1] + grad[2] * grad[2]);
     double nrm[3];
     for (int a = 0; a < 3; ++a) nrm[a] = grad[a] / (gnorm + p->normal_eps);
@@ -766,12 +912,22 @@ static void naive_collide_h(orc_state *s, int x, int y, int z)
     double theta = (1.0 - 4.0 * (phi - phi0) * (phi - phi0)) / p->xi;
     double uc[3] = {s->u[c], s->u[n + c], s->u[2 * n + c]};
     double omega = 1.0 / (p->mobility / CS2 + 0.5);
-    double Fphi[Q15];
-    phase_forcing(theta, nrm, Fphi);
-    for (int i = 0; i < Q15; ++i) {
-        double h = s->Hn[i * n + c];
-        double heq = phi * gamma_i(E15[i], W15[i], uc);
-        s->H[i * n + c] = h + omega * (heq - h - 0.5 * Fphi[i]) + Fphi[i];
+    double Fphi[QMAX];
+    phase_forcing(L, theta, nrm, Fphi);
+    if (p->phase_mrt) {
+        double hh[QMAX], heq[QMAX], hs[QMAX];
+        for (int i = 0; i < L.q; ++i) {
+            hh[i] = s->Hn[i * n + c];
+            heq[i] = phi * gamma_i(L.e[i], L.w[i], uc);
+        }
+        phase_mrt_collide(L, hh, heq, Fphi, omega, hs);
+        for (int i = 0; i < L.q; ++i) s->H[i * n + c] = hs[i];
+    } else {
+        for (int i = 0; i < L.q; ++i) {
+            double h = s->Hn[i * n + c];
+            double heq = phi * gamma_i(L.e[i], L.w[i], uc);
+            s->H[i * n + c] = h + omega * (heq - h - 0.5 * Fphi[i]) + Fphi[i];
+        }
     }
 }
 
@@ -781,19 +937,20 @@ static void naive_collide_g(orc_state *s, int x, int y, int z)
 {
     const orc_params *p = &s->p;
     const int64_t n = s->n, c = cidx(p, x, y, z);
-    double g[Q27];
-    for (int i = 0; i < Q27; ++i) g[i] = s->G[i * n + c];
+    double g[QMAX];
+    for (int i = 0; i < s->qh; ++i) g[i] = s->G[i * n + c];
     double uc[3] = {s->u[c], s->u[n + c], s->u[2 * n + c]};
     double F[3], rho, s_nu, pstar, j[3];
     naive_force(s, s->phiB, x, y, z, g, uc, F, &rho, &s_nu, &pstar, j);
-    double gs[Q27];
-    mrt_collide(g, pstar, uc, F, rho, s_nu, gs);
-    for (int i = 0; i < Q27; ++i) {
-        int dy = ny_nb(p, y, E27[i][1]);
+    const orc_lat L = lat_of(s->qh);
+    double gs[QMAX];
+    mrt_collide(L, g, pstar, uc, F, rho, s_nu, gs);
+    for (int i = 0; i < L.q; ++i) {
+        int dy = ny_nb(p, y, L.e[i][1]);
         if (is_wall_row(p, dy))
             s->Gn[opposite(i) * n + c] = gs[i];
         else
-            s->Gn[i * n + cidx(p, wrap(x + E27[i][0], p->nx), dy, wrap(z + E27[i][2], p->nz))] = gs[i];
+            s->Gn[i * n + cidx(p, wrap(x + L.e[i][0], p->nx), dy, wrap(z + L.e[i][2], p->nz))] = gs[i];
     }
 }
 
@@ -826,8 +983,8 @@ void orc_step_naive(orc_state *s, int32_t nsteps)
 void orc_get_state(const orc_state *s, double *H, double *G, double *phi, double *u)
 {
     size_t n = (size_t)s->n;
-    if (H) memcpy(H, s->H, sizeof(double) * Q15 * n);
-    if (G) memcpy(G, s->G, sizeof(double) * Q27 * n);
+    if (H) memcpy(H, s->H, sizeof(double) * s->qp * n);
+    if (G) memcpy(G, s->G, sizeof(double) * s->qh * n);
     if (phi) memcpy(phi, s->phiA, sizeof(double) * n);
     if (u) memcpy(u, s->u, sizeof(double) * 3 * n);
 }
@@ -836,8 +993,8 @@ void orc_set_state(orc_state *s, const double *H, const double *G, const double 
                    const double *u)
 {
     size_t n = (size_t)s->n;
-    if (H) memcpy(s->H, H, sizeof(double) * Q15 * n);
-    if (G) memcpy(s->G, G, sizeof(double) * Q27 * n);
+    if (H) memcpy(s->H, H, sizeof(double) * s->qp * n);
+    if (G) memcpy(s->G, G, sizeof(double) * s->qh * n);
     if (phi) memcpy(s->phiA, phi, sizeof(double) * n);
     if (u) memcpy(s->u, u, sizeof(double) * 3 * n);
 }
@@ -854,6 +1011,7 @@ void orc_shift_equilibrium(orc_state *s, const double *phi, const double *u, con
 {
     const orc_params *p = &s->p;
     const int64_t n = s->n;
+    const orc_lat LP = lat_of(s->qp), LH = lat_of(s->qh);
     for (int z = 0; z < p->nz; ++z)
         for (int y = 0; y < p->ny; ++y)
             for (int x = 0; x < p->nx; ++x) {
@@ -862,15 +1020,15 @@ void orc_shift_equilibrium(orc_state *s, const double *phi, const double *u, con
                 const double u0[3] = {s->u[c], s->u[n + c], s->u[2 * n + c]};
                 const double u1[3] = {u[c], u[n + c], u[2 * n + c]};
                 const double phi0 = s->phiA[c], phi1 = phi[c];
-                for (int i = 0; i < Q15; ++i)
-                    s->H[i * n + c] += phi1 * gamma_i(E15[i], W15[i], u1) - phi0 * gamma_i(E15[i], W15[i], u0);
+                for (int i = 0; i < LP.q; ++i)
+                    s->H[i * n + c] += phi1 * gamma_i(LP.e[i], LP.w[i], u1) - phi0 * gamma_i(LP.e[i], LP.w[i], u0);
                 double ps0 = 0.0;
-                for (int i = 0; i < Q27; ++i) ps0 += s->G[i * n + c];
+                for (int i = 0; i < LH.q; ++i) ps0 += s->G[i * n + c];
                 const double ps1 = pres[c] / (density_of(p, phi1) * CS2);
-                double e0[Q27], e1[Q27];
-                hydro_equilibrium(ps0, u0, e0);
-                hydro_equilibrium(ps1, u1, e1);
-                for (int i = 0; i < Q27; ++i) s->G[i * n + c] += e1[i] - e0[i];
+                double e0[QMAX], e1[QMAX];
+                hydro_equilibrium(LH, ps0, u0, e0);
+                hydro_equilibrium(LH, ps1, u1, e1);
+                for (int i = 0; i < LH.q; ++i) s->G[i * n + c] += e1[i] - e0[i];
                 s->phiA[c] = phi1;
                 for (int a = 0; a < 3; ++a) s->u[a * n + c] = u1[a];
             }
@@ -904,7 +1062,7 @@ void orc_pressure(const orc_state *s, double *pout)
         int y = (int)((c / p->nx) % p->ny);
         if (is_wall_row(p, y)) { pout[c] = 0.0; continue; }
         double ps = 0.0;
-        for (int i = 0; i < Q27; ++i) ps += s->G[i * n + c];
+        for (int i = 0; i < s->qh; ++i) ps += s->G[i * n + c];
         double rho = density_of(p, s->phiA[c]);
         pout[c] = ps * rho * CS2;
     }

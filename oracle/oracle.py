@@ -32,6 +32,7 @@ class OrcParams(C.Structure):
         ("tau_L", C.c_double), ("tau_H", C.c_double),
         ("accel", C.c_double * 3), ("rho_ref", C.c_double), ("normal_eps", C.c_double),
         ("density_literal", C.c_int32),
+        ("lattice_phase", C.c_int32), ("lattice_hydro", C.c_int32), ("phase_mrt", C.c_int32),
     ]
 
 
@@ -68,6 +69,16 @@ def lib():
     L.orc_viscous_bracket.restype = C.c_int
     L.orc_mrt_collide.argtypes = [_D, C.c_double, _D, _D, C.c_double, C.c_double, _D]
     L.orc_mrt_collide.restype = C.c_int
+    L.orc_moment_matrix_q.argtypes = [C.c_int32, _D, _D, _D, _D, _I, _I]
+    L.orc_moment_matrix_q.restype = C.c_int
+    L.orc_hydro_equilibrium_q.argtypes = [C.c_int32, C.c_double, _D, _D]
+    L.orc_hydro_equilibrium_q.restype = C.c_int
+    L.orc_mrt_collide_q.argtypes = [C.c_int32, _D, C.c_double, _D, _D, C.c_double, C.c_double, _D]
+    L.orc_mrt_collide_q.restype = C.c_int
+    L.orc_viscous_bracket_q.argtypes = [C.c_int32, _D, C.c_double, _D, _D]
+    L.orc_viscous_bracket_q.restype = C.c_int
+    L.orc_phase_mrt_collide_q.argtypes = [C.c_int32, _D, _D, _D, C.c_double, _D]
+    L.orc_phase_mrt_collide_q.restype = C.c_int
     L.orc_stencil.argtypes = [C.POINTER(OrcParams), _D, C.c_int32, C.c_int32, C.c_int32,
                               C.c_int32, _D, C.POINTER(C.c_double)]
     L.orc_create.argtypes = [C.POINTER(OrcParams)]
@@ -110,6 +121,9 @@ class Params:
     buoyancy_rho_ref: float = 0.0
     normal_eps: float = 1e-12
     density_literal: bool = False
+    lattice_phase: int = 15      # velocity set of the phase-field step (15, 19, 27)
+    lattice_hydro: int = 27      # velocity set of the hydrodynamic step (27, 19, 15)
+    phase_mrt: bool = False      # raw-moment MRT phase-field collision instead of SRT
 
     def to_c(self) -> OrcParams:
         p = OrcParams()
@@ -122,6 +136,8 @@ class Params:
         p.rho_ref = self.buoyancy_rho_ref
         p.normal_eps = self.normal_eps
         p.density_literal = int(bool(self.density_literal))
+        p.lattice_phase, p.lattice_hydro = int(self.lattice_phase), int(self.lattice_hydro)
+        p.phase_mrt = int(bool(self.phase_mrt))
         return p
 
 
@@ -180,6 +196,52 @@ def mrt_collide(g, pstar: float, u, F, rho: float, s_nu: float) -> np.ndarray:
     return out
 
 
+def moment_matrix_q(q: int):
+    """Weighted-orthogonal moment matrix M of the q-velocity set, its inverse,
+    the raw monomial matrix R and its inverse, the degree and the exponents
+    (a, b, c) of the monomial of each row."""
+    M, Mi, R, Ri = (np.zeros(q * q) for _ in range(4))
+    deg = np.zeros(q, dtype=np.int32)
+    expo = np.zeros(3 * q, dtype=np.int32)
+    if lib().orc_moment_matrix_q(q, M, Mi, R, Ri, deg, expo) != 0:
+        raise RuntimeError(f"moment matrices of D3Q{q} failed")
+    return M.reshape(q, q), Mi.reshape(q, q), R.reshape(q, q), Ri.reshape(q, q), deg, expo.reshape(q, 3)
+
+
+def hydro_equilibrium_q(q: int, pstar: float, u) -> np.ndarray:
+    out = np.zeros(q)
+    if lib().orc_hydro_equilibrium_q(q, pstar, np.ascontiguousarray(u, dtype=np.float64), out) != 0:
+        raise ValueError(q)
+    return out
+
+
+def mrt_collide_q(q: int, g, pstar: float, u, F, rho: float, s_nu: float) -> np.ndarray:
+    out = np.zeros(q)
+    if lib().orc_mrt_collide_q(q, np.ascontiguousarray(g, dtype=np.float64), pstar,
+                               np.ascontiguousarray(u, dtype=np.float64),
+                               np.ascontiguousarray(F, dtype=np.float64), rho, s_nu, out) != 0:
+        raise ValueError(q)
+    return out
+
+
+def viscous_bracket_q(q: int, g, s_nu: float, u) -> np.ndarray:
+    V = np.zeros(9)
+    if lib().orc_viscous_bracket_q(q, np.ascontiguousarray(g, dtype=np.float64), s_nu,
+                                   np.ascontiguousarray(u, dtype=np.float64), V) != 0:
+        raise ValueError(q)
+    return V.reshape(3, 3)
+
+
+def phase_mrt_collide_q(q: int, h, heq, F, omega: float) -> np.ndarray:
+    """Raw-moment MRT collision of the phase field (Sec. 3.1):
+    h + R^-1 S R (heq - h - F/2) + F, first-order moments relaxed with omega."""
+    out = np.zeros(q)
+    args = [np.ascontiguousarray(a, dtype=np.float64) for a in (h, heq, F)]
+    if lib().orc_phase_mrt_collide_q(q, *args, omega, out) != 0:
+        raise ValueError(q)
+    return out
+
+
 def stencil(params: Params, phi: np.ndarray, q: int, x: int, y: int, z: int):
     """Isotropic gradient and Laplacian of ``phi`` at (x, y, z) with the
     weights of the q-velocity set (and the wall mirror if walls_y)."""
@@ -206,6 +268,7 @@ class Oracle:
             raise ValueError("oracle rejected the parameters")
         self.shape = (params.nz, params.ny, params.nx)
         self.n = params.nx * params.ny * params.nz
+        self.qp, self.qh = int(params.lattice_phase), int(params.lattice_hydro)
 
     def close(self):
         if self._h:
@@ -238,8 +301,8 @@ class Oracle:
         lib().orc_step_naive(self._h, int(n))
 
     def state(self):
-        H = np.zeros((15,) + self.shape)
-        G = np.zeros((27,) + self.shape)
+        H = np.zeros((self.qp,) + self.shape)
+        G = np.zeros((self.qh,) + self.shape)
         phi = np.zeros(self.shape)
         u = np.zeros((3,) + self.shape)
         lib().orc_get_state(self._h, _ptr(H), _ptr(G), _ptr(phi), _ptr(u))

@@ -32,10 +32,11 @@ def _delta4():
             + np.einsum("ad,bc->abcd", d, d))
 
 
-@pytest.mark.parametrize("q", [15, 27])
+@pytest.mark.parametrize("q", [15, 19, 27])
 def test_velocity_set_structure(q):
-    """D3Q15 = rest + 6 axes + 8 corners; D3Q27 = all of {-1,0,1}^3; each
-    odd index has its opposite at the next index (used by bounce-back)."""
+    """D3Q15 = rest + 6 axes + 8 corners; D3Q19 = rest + 6 axes + 12 edges;
+    D3Q27 = all of {-1,0,1}^3; each odd index has its opposite at the next
+    index (used by bounce-back)."""
     e, w = orc.velocity_set(q)
     vecs = {tuple(v) for v in e}
     assert len(vecs) == q
@@ -43,13 +44,13 @@ def test_velocity_set_structure(q):
         assert vecs == set(itertools.product((-1, 0, 1), repeat=3))
     else:
         norms = sorted(int(np.abs(v).sum()) for v in e)
-        assert norms == [0] + [1] * 6 + [3] * 8
+        assert norms == [0] + [1] * 6 + ([3] * 8 if q == 15 else [2] * 12)
     assert tuple(e[0]) == (0, 0, 0)
     for i in range(1, q, 2):
         assert np.array_equal(e[i + 1], -e[i])
 
 
-@pytest.mark.parametrize("q", [15, 27])
+@pytest.mark.parametrize("q", [15, 19, 27])
 def test_weights_isotropy(q):
     """P1: sum w = 1, sum w e = 0, sum w e e = cs^2 I, sum w e e e = 0,
     sum w e e e e = cs^4 (dd + dd + dd)."""
@@ -62,7 +63,7 @@ def test_weights_isotropy(q):
     assert np.abs(m4 - CS2 * CS2 * _delta4()).max() < 1e-15
 
 
-@pytest.mark.parametrize("q", [15, 27])
+@pytest.mark.parametrize("q", [15, 19, 27])
 def test_weights_are_the_unique_isotropic_solution(q):
     """The class weights solve the isotropy conditions (plus sixth-order
     isotropy for D3Q27, which has one more class) -- solved here with a
