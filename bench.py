@@ -186,6 +186,51 @@ def measure_straightforward(lbm, perf, setup, phi, u, ps, storage, steps, warmup
             "achieved_gbs": round(bpc * fluid / (ms * 1e-3) / 1e9, 1), "mass_drift_rel": (m1 - m0) / m0}
 
 
+LATTICE_VARIANTS = {
+    "d3q15_d3q27": dict(lattice_phase=15, lattice_hydro=27, phase_mrt=False),
+    "d3q15_d3q27_mrt": dict(lattice_phase=15, lattice_hydro=27, phase_mrt=True),
+    "d3q19_d3q19": dict(lattice_phase=19, lattice_hydro=19, phase_mrt=False),
+    "d3q19_d3q19_mrt": dict(lattice_phase=19, lattice_hydro=19, phase_mrt=True),
+    "d3q27_d3q27": dict(lattice_phase=27, lattice_hydro=27, phase_mrt=False),
+    "d3q15_d3q15": dict(lattice_phase=15, lattice_hydro=15, phase_mrt=False),
+}
+
+
+def measure_lattice(lbm, perf, setup, phi, u, ps, name, storage, steps, warmup, timed_steps):
+    """One velocity-set variant (the stencil study of Sec. 5.1) on the same
+    workload: coupled steps timed with HIP events on the solver stream and
+    the fused kernel's mean launch time, against its algorithmic bytes."""
+    import torch
+    lat = LATTICE_VARIANTS[name]
+    fluid = setup.nx * setup.nz * (setup.ny - 2 if setup.walls_y else setup.ny)
+    solver = lbm.Solver(dict(setup.physics(), **lat), storage=storage, device="cuda:0")
+    solver.init_fields(phi, u, ps)
+    stream = torch.cuda.current_stream(torch.device("cuda:0"))
+    m0 = solver.reduce_mass()
+    if warmup > 0:
+        solver.step(warmup)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    solver.step(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    m1 = solver.reduce_mass()
+    fused_ms = solver.step_timed_fused(max(2, min(timed_steps, 4096)))
+    solver.close()
+    del solver
+    torch.cuda.empty_cache()
+    bpc = perf.bytes_per_cell(storage, lat["lattice_phase"], lat["lattice_hydro"])
+    return {"storage": storage, "phase_set": lat["lattice_phase"], "hydro_set": lat["lattice_hydro"],
+            "phase_mrt": lat["phase_mrt"], "ms_per_step": round(ms, 4),
+            "mlups": round(fluid / (ms * 1e-3) / 1e6, 1), "fused_bytes_per_cell": bpc["fused"],
+            "fused_ms": round(fused_ms, 4),
+            "fused_gbs": round(bpc["fused"] * fluid / (fused_ms * 1e-3) / 1e9, 1),
+            "mass_drift_rel": (m1 - m0) / m0}
+
+
 def cpu_baseline(setup, phi, u, ps, target_s: float = 15.0):
     """Time the FP64 oracle on a 128 x ny x 128 slab of the same workload."""
     import numpy as np
@@ -226,6 +271,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--timed-steps", type=int, default=50,
                     help="steps of the per-kernel event timing (roofline)")
+    ap.add_argument("--lattices", default="f64,f32",
+                    help="comma-separated storage formats (f64, f32) for which every built velocity-set variant "
+                         "is measured on the same workload (empty: none)")
     ap.add_argument("--straightforward", default="f64,f32",
                     help="comma-separated storage formats (f64, f32) for which the straightforward six-kernel "
                          "algorithm is measured on the same workload (empty: none)")
@@ -352,6 +400,16 @@ def main():
             f"{rec['achieved_gbs']:.0f} GB/s algorithmic")
         naive[st] = rec
 
+    lattices = {}
+    for st in [x for x in args.lattices.split(",") if x]:
+        for name in LATTICE_VARIANTS:
+            log(f"[bench] lattice {name}, storage {st}: warmup {args.warmup}, timed {args.steps} steps")
+            rec = measure_lattice(lbm, perf, setup, phi, u, ps, name, st, args.steps, args.warmup,
+                                  args.timed_steps)
+            log(f"[bench] lattice {name} {st}: {rec['ms_per_step']:.3f} ms/step, {rec['mlups']:.0f} MLUPS, "
+                f"fused {rec['fused_gbs']:.0f} GB/s algorithmic")
+            lattices[f"{name}_{st}"] = rec
+
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] CPU oracle baseline")
@@ -394,6 +452,7 @@ def main():
         "paper_context": {"mlups": 550, "hardware": "Tesla P100", "precision": "f64",
                           "roofline_frac_of_stream": 0.78},
         "other_storages": others,
+        "lattice_variants": lattices,
         "straightforward_algorithm": {"records": naive, "paper": {"straightforward_mlups": 211, "improved_mlups": 550,
                                                                 "hardware": "Tesla P100", "precision": "f64"}},
         "cpu_baseline": cpu,

@@ -83,7 +83,20 @@ typedef enum { LBM_DTYPE_F64 = 0, LBM_DTYPE_F32 = 1 } lbm_dtype;
  *                  the conservative phase field over- and undershoots the
  *                  interval by ~1e-3, which at rho_H/rho_L = 1000 would give
  *                  a near-zero density in small bubble cores); 1: eq. density
- *                  and the tau interpolation as printed, for every phi */
+ *                  and the tau interpolation as printed, for every phi
+ *   lattice_phase  velocity set of the phase-field step: 15 (0 = the default
+ *                  D3Q15), 19 or 27
+ *   lattice_hydro  velocity set of the hydrodynamic step: 27 (0 = the default
+ *                  D3Q27), 19 or 15; its moment set is the weighted-orthogonal
+ *                  Gram-Schmidt of the monomials independent on the set
+ *   phase_mrt      0: single-rate phase-field collision (the benchmarks of
+ *                  Sec. 5); 1: raw-moment MRT, first-order moments relaxed
+ *                  with the phase-field rate, all others with one (Sec. 3.1)
+ *                  Built combinations (phase, hydro, MRT): (15, 27, 0) for every
+ *                  storage; with FP64 and FP32 storage also (15, 27, 1),
+ *                  (19, 19, 0), (19, 19, 1), (27, 27, 0) and (15, 15, 0), the
+ *                  stencil study of Sec. 5.1 and the D3Q19 lattice of Sec. 6.1;
+ *                  others give LBM_EARG */
 typedef struct {
     int32_t nx, ny, nz;
     int32_t walls_y;
@@ -94,6 +107,9 @@ typedef struct {
     double normal_eps;
     int32_t storage;
     int32_t density_literal;
+    int32_t lattice_phase;
+    int32_t lattice_hydro;
+    int32_t phase_mrt;
 } lbm_params;
 
 /* FP64 diagnostics over fluid cells (one deterministic two-pass reduction).

@@ -22,6 +22,11 @@ extern template void launch_fused<StoreF32>(const SweepArgs<StoreF32> &, const S
                                             const SweepLaunch &, hipStream_t);
 extern template void launch_naive_step<StoreF32>(const SweepArgs<StoreF32> &, const SweepArgs<StoreF32> &, int,
                                                  hipStream_t);
+#define LBM_EXTERN_LATTICE(S)                                                                                  \
+    extern template void launch_fused<S>(const SweepArgs<S> &, const SweepArgs<S> &, const SweepLaunch &, hipStream_t); \
+    extern template void launch_naive_step<S>(const SweepArgs<S> &, const SweepArgs<S> &, int, hipStream_t);
+LBM_FP32_LATTICES(LBM_EXTERN_LATTICE)
+#undef LBM_EXTERN_LATTICE
 }  // namespace lbm
 
 using namespace lbm;
@@ -66,6 +71,25 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 size_t pdf_bytes(int storage) { return storage == LBM_F64 ? 8 : storage == LBM_F32 ? 4 : 2; }
 size_t real_bytes(int storage) { return storage == LBM_F64 ? 8 : 4; }
 
+// Velocity sets and phase-field collision of a parameter set (0 = default).
+int q_phase(const lbm_params *p) { return p->lattice_phase == 0 ? 15 : p->lattice_phase; }
+int q_hydro(const lbm_params *p) { return p->lattice_hydro == 0 ? 27 : p->lattice_hydro; }
+
+// The built lattice variants: 0 is (D3Q15, D3Q27, SRT), every storage; the
+// others FP64 and FP32 only.  -1: not built.
+int lattice_variant(const lbm_params *p)
+{
+    const int qp = q_phase(p), qh = q_hydro(p), mrt = p->phase_mrt;
+    if (qp == 15 && qh == 27 && mrt == 0) return 0;
+    if (p->storage != LBM_F64 && p->storage != LBM_F32) return -1;
+    if (qp == 15 && qh == 27 && mrt == 1) return 1;
+    if (qp == 19 && qh == 19 && mrt == 0) return 2;
+    if (qp == 19 && qh == 19 && mrt == 1) return 3;
+    if (qp == 27 && qh == 27 && mrt == 0) return 4;
+    if (qp == 15 && qh == 15 && mrt == 0) return 5;
+    return -1;
+}
+
 struct Layout {
     int64_t ncells, nblk, fplane;
     int64_t pdf_elems;  // elements per direction of a PDF buffer
@@ -89,6 +113,10 @@ lbm_status validate(const lbm_params *p)
     if (!(p->sigma >= 0)) return fail(LBM_EARG, "sigma must be >= 0");
     if (!(p->normal_eps >= 0)) return fail(LBM_EARG, "normal_eps must be >= 0");
     if (p->density_literal != 0 && p->density_literal != 1) return fail(LBM_EARG, "density_literal must be 0 or 1");
+    if (p->phase_mrt != 0 && p->phase_mrt != 1) return fail(LBM_EARG, "phase_mrt must be 0 or 1");
+    if (lattice_variant(p) < 0)
+        return fail(LBM_EARG, "lattice pair (D3Q%d, D3Q%d, %s) with storage %d is not built", q_phase(p), q_hydro(p),
+                    p->phase_mrt ? "MRT" : "SRT", p->storage);
     return LBM_OK;
 }
 
@@ -109,11 +137,11 @@ Layout layout(const lbm_params *p)
     size_t off = 0;
     for (int k = 0; k < 2; ++k) {
         L.off_H[k] = off;
-        off = align_up(off + 15 * (size_t)L.pdf_elems * pb, kAlign);
+        off = align_up(off + (size_t)q_phase(p) * (size_t)L.pdf_elems * pb, kAlign);
     }
     for (int k = 0; k < 2; ++k) {
         L.off_G[k] = off;
-        off = align_up(off + 27 * (size_t)L.pdf_elems * pb, kAlign);
+        off = align_up(off + (size_t)q_hydro(p) * (size_t)L.pdf_elems * pb, kAlign);
     }
     for (int k = 0; k < 2; ++k) {
         L.off_phi[k] = off;
@@ -216,7 +244,7 @@ struct Ops {
         if (paired(c)) {
             L.mode = 2;
             L.blocks = (c->g.half + kBlock - 1) / kBlock;
-        } else if (c->zmarch) {
+        } else if (is_default_lattice<S>() && c->zmarch) {
             L.mode = 1;
             L.zt = ztiles(c);
             L.blocks = L.zt.tx * L.zt.ty * L.zt.tz;
@@ -254,7 +282,7 @@ struct Ops {
         hipLaunchKernelGGL((k_equilibrium<S, In>), dim3(blocks(c)), dim3(kBlock), 0, c->stream, H(c, 0),
                            G(c, 1), phi(c, 0), u(c), phi_in, u_in, p_in, is_p, c->g, make_phys<R>(&c->p));
         LAUNCH_CHECK();
-        hipLaunchKernelGGL((k_unpull27<S>), dim3(blocks(c)), dim3(kBlock), 0, c->stream, G(c, 1), G(c, 0), c->g);
+        hipLaunchKernelGGL((k_unpull<S>), dim3(blocks(c)), dim3(kBlock), 0, c->stream, G(c, 1), G(c, 0), c->g);
         LAUNCH_CHECK();
         c->initialized = true;
         c->steps = 0;
@@ -269,7 +297,7 @@ struct Ops {
         hipLaunchKernelGGL((k_shift_eq_g<S, In>), dim3(blocks(c)), dim3(kBlock), 0, c->stream, G(c, a), G(c, b),
                            u(c), phi_in, u_in, p_in, c->g, ph);
         LAUNCH_CHECK();
-        hipLaunchKernelGGL((k_unpull27<S>), dim3(blocks(c)), dim3(kBlock), 0, c->stream, G(c, b), G(c, a), c->g);
+        hipLaunchKernelGGL((k_unpull<S>), dim3(blocks(c)), dim3(kBlock), 0, c->stream, G(c, b), G(c, a), c->g);
         LAUNCH_CHECK();
         hipLaunchKernelGGL((k_shift_eq_h<S, In>), dim3(blocks(c)), dim3(kBlock), 0, c->stream, H(c, a), phi(c, a),
                            u(c), phi_in, u_in, c->g);
@@ -461,7 +489,7 @@ struct Ops {
         hipLaunchKernelGGL((k_set_pdfs<S>), dim3(blocks(c)), dim3(kBlock), 0, c->stream, H(c, 0), G(c, 1),
                            phi(c, 0), u(c), Hi, Gi, phi_i, u_i, c->g, make_phys<R>(&c->p));
         LAUNCH_CHECK();
-        hipLaunchKernelGGL((k_unpull27<S>), dim3(blocks(c)), dim3(kBlock), 0, c->stream, G(c, 1), G(c, 0), c->g);
+        hipLaunchKernelGGL((k_unpull<S>), dim3(blocks(c)), dim3(kBlock), 0, c->stream, G(c, 1), G(c, 0), c->g);
         LAUNCH_CHECK();
         c->initialized = true;
         c->steps = 0;
@@ -478,16 +506,31 @@ struct Ops {
     }
 };
 
-template <template <class> class F, class... A>
-lbm_status dispatch(int storage, A &&...args)
+template <template <class> class F, class B, class... A>
+lbm_status dispatch_lattice(int variant, A &&...args)
 {
-    switch (storage) {
-    case LBM_F64: return F<StoreF64>::run(args...);
-    case LBM_F32: return F<StoreF32>::run(args...);
+    switch (variant) {
+    case 0: return F<B>::run(args...);
+    case 1: return F<Lattice<B, 15, 27, true>>::run(args...);
+    case 2: return F<Lattice<B, 19, 19, false>>::run(args...);
+    case 3: return F<Lattice<B, 19, 19, true>>::run(args...);
+    case 4: return F<Lattice<B, 27, 27, false>>::run(args...);
+    case 5: return F<Lattice<B, 15, 15, false>>::run(args...);
+    }
+    return fail(LBM_EARG, "lattice variant %d is not built", variant);
+}
+
+template <template <class> class F, class... A>
+lbm_status dispatch(const lbm_params &p, A &&...args)
+{
+    const int variant = lattice_variant(&p);
+    switch (p.storage) {
+    case LBM_F64: return dispatch_lattice<F, StoreF64>(variant, args...);
+    case LBM_F32: return dispatch_lattice<F, StoreF32>(variant, args...);
     case LBM_F16S: return F<StoreF16S>::run(args...);
     case LBM_BF16S: return F<StoreBF16S>::run(args...);
     }
-    return fail(LBM_EARG, "unknown storage %d", storage);
+    return fail(LBM_EARG, "unknown storage %d", p.storage);
 }
 
 template <class S> struct DoStep {
@@ -560,21 +603,12 @@ extern "C" {
 lbm_status lbm_velocity_set(int32_t q, int32_t *e, double *w)
 {
     if (!e || !w) return fail(LBM_EARG, "NULL output");
-    if (q == 15) {
-        for (int i = 0; i < 15; ++i) {
-            for (int a = 0; a < 3; ++a) e[3 * i + a] = e15(i, a);
-            w[i] = wgt<15, double>(i);
-        }
-        return LBM_OK;
+    if (q != 15 && q != 19 && q != 27) return fail(LBM_EARG, "q must be 15, 19 or 27 (got %d)", q);
+    for (int i = 0; i < q; ++i) {
+        for (int a = 0; a < 3; ++a) e[3 * i + a] = q == 15 ? ev<15>(i, a) : ev<27>(i, a);
+        w[i] = q == 15 ? wgt<15, double>(i) : q == 19 ? wgt<19, double>(i) : wgt<27, double>(i);
     }
-    if (q == 27) {
-        for (int i = 0; i < 27; ++i) {
-            for (int a = 0; a < 3; ++a) e[3 * i + a] = e27(i, a);
-            w[i] = wgt<27, double>(i);
-        }
-        return LBM_OK;
-    }
-    return fail(LBM_EARG, "no velocity set with q = %d", q);
+    return LBM_OK;
 }
 
 size_t lbm_workspace_bytes(const lbm_params *p)
@@ -636,7 +670,7 @@ lbm_status lbm_init_fields(lbm_ctx *c, const double *phi, const double *u, const
     lbm_status s = check_ctx(c, false);
     if (s != LBM_OK) return s;
     if (!phi || !u || !ps) return fail(LBM_EARG, "NULL field pointer");
-    return dispatch<DoInit>(c->p.storage, c, phi, u, ps);
+    return dispatch<DoInit>(c->p, c, phi, u, ps);
 }
 
 lbm_status lbm_step(lbm_ctx *c, int32_t n)
@@ -644,7 +678,7 @@ lbm_status lbm_step(lbm_ctx *c, int32_t n)
     lbm_status s = check_ctx(c, true);
     if (s != LBM_OK) return s;
     if (n < 1) return fail(LBM_EARG, "n must be >= 1 (got %d)", n);
-    return dispatch<DoStep>(c->p.storage, c, (int)n);
+    return dispatch<DoStep>(c->p, c, (int)n);
 }
 
 lbm_status lbm_step_straightforward(lbm_ctx *c, int32_t n)
@@ -652,7 +686,7 @@ lbm_status lbm_step_straightforward(lbm_ctx *c, int32_t n)
     lbm_status s = check_ctx(c, true);
     if (s != LBM_OK) return s;
     if (n < 1) return fail(LBM_EARG, "n must be >= 1 (got %d)", n);
-    return dispatch<DoStepStraightforward>(c->p.storage, c, (int)n);
+    return dispatch<DoStepStraightforward>(c->p, c, (int)n);
 }
 
 lbm_status lbm_step_timed(lbm_ctx *c, int32_t n, double *phase_ms, double *hydro_ms)
@@ -661,7 +695,7 @@ lbm_status lbm_step_timed(lbm_ctx *c, int32_t n, double *phase_ms, double *hydro
     if (s != LBM_OK) return s;
     if (n < 1 || n > 4096) return fail(LBM_EARG, "n must be in [1, 4096] (got %d)", n);
     if (!phase_ms || !hydro_ms) return fail(LBM_EARG, "NULL output");
-    return dispatch<DoStepTimed>(c->p.storage, c, (int)n, phase_ms, hydro_ms);
+    return dispatch<DoStepTimed>(c->p, c, (int)n, phase_ms, hydro_ms);
 }
 
 lbm_status lbm_step_timed_fused(lbm_ctx *c, int32_t n, double *fused_ms)
@@ -670,7 +704,7 @@ lbm_status lbm_step_timed_fused(lbm_ctx *c, int32_t n, double *fused_ms)
     if (s != LBM_OK) return s;
     if (n < 2 || n > 4096) return fail(LBM_EARG, "n must be in [2, 4096] (got %d)", n);
     if (!fused_ms) return fail(LBM_EARG, "NULL output");
-    return dispatch<DoStepTimedFused>(c->p.storage, c, (int)n, fused_ms);
+    return dispatch<DoStepTimedFused>(c->p, c, (int)n, fused_ms);
 }
 
 lbm_status lbm_reduce_mass(lbm_ctx *c, double *sum_phi)
@@ -679,7 +713,7 @@ lbm_status lbm_reduce_mass(lbm_ctx *c, double *sum_phi)
     if (s != LBM_OK) return s;
     if (!sum_phi) return fail(LBM_EARG, "NULL output");
     double v[kRedVals];
-    s = dispatch<DoReduce>(c->p.storage, c, 1, v);
+    s = dispatch<DoReduce>(c->p, c, 1, v);
     if (s != LBM_OK) return s;
     *sum_phi = v[0];
     if (!std::isfinite(v[0])) return fail(LBM_ENONFINITE, "sum of phi is not finite");
@@ -692,7 +726,7 @@ lbm_status lbm_reduce_stats(lbm_ctx *c, lbm_stats *o)
     if (s != LBM_OK) return s;
     if (!o) return fail(LBM_EARG, "NULL output");
     double v[kRedVals];
-    s = dispatch<DoReduce>(c->p.storage, c, 0, v);
+    s = dispatch<DoReduce>(c->p, c, 0, v);
     if (s != LBM_OK) return s;
     std::memset(o, 0, sizeof(*o));
     o->mass = v[0];
@@ -720,7 +754,7 @@ lbm_status lbm_get_macroscopic(lbm_ctx *c, int32_t dtype, void *phi, void *u, vo
     lbm_status s = check_ctx(c, true);
     if (s != LBM_OK) return s;
     if (dtype != LBM_DTYPE_F64 && dtype != LBM_DTYPE_F32) return fail(LBM_EARG, "unknown dtype %d", dtype);
-    return dispatch<DoGetMacro>(c->p.storage, c, (int)dtype, phi, u, p);
+    return dispatch<DoGetMacro>(c->p, c, (int)dtype, phi, u, p);
 }
 
 lbm_status lbm_set_macroscopic(lbm_ctx *c, int32_t dtype, const void *phi, const void *u, const void *p)
@@ -729,7 +763,7 @@ lbm_status lbm_set_macroscopic(lbm_ctx *c, int32_t dtype, const void *phi, const
     if (s != LBM_OK) return s;
     if (dtype != LBM_DTYPE_F64 && dtype != LBM_DTYPE_F32) return fail(LBM_EARG, "unknown dtype %d", dtype);
     if (!phi || !u || !p) return fail(LBM_EARG, "NULL field pointer");
-    return dispatch<DoSetMacro>(c->p.storage, c, (int)dtype, phi, u, p);
+    return dispatch<DoSetMacro>(c->p, c, (int)dtype, phi, u, p);
 }
 
 lbm_status lbm_shift_equilibrium(lbm_ctx *c, int32_t dtype, const void *phi, const void *u, const void *p)
@@ -738,14 +772,14 @@ lbm_status lbm_shift_equilibrium(lbm_ctx *c, int32_t dtype, const void *phi, con
     if (s != LBM_OK) return s;
     if (dtype != LBM_DTYPE_F64 && dtype != LBM_DTYPE_F32) return fail(LBM_EARG, "unknown dtype %d", dtype);
     if (!phi || !u || !p) return fail(LBM_EARG, "NULL field pointer");
-    return dispatch<DoShiftEq>(c->p.storage, c, (int)dtype, phi, u, p);
+    return dispatch<DoShiftEq>(c->p, c, (int)dtype, phi, u, p);
 }
 
 lbm_status lbm_get_pdfs(lbm_ctx *c, double *H, double *G)
 {
     lbm_status s = check_ctx(c, true);
     if (s != LBM_OK) return s;
-    return dispatch<DoGetPdfs>(c->p.storage, c, H, G);
+    return dispatch<DoGetPdfs>(c->p, c, H, G);
 }
 
 lbm_status lbm_set_pdfs(lbm_ctx *c, const double *H, const double *G, const double *phi, const double *u)
@@ -753,7 +787,7 @@ lbm_status lbm_set_pdfs(lbm_ctx *c, const double *H, const double *G, const doub
     lbm_status s = check_ctx(c, false);
     if (s != LBM_OK) return s;
     if (!H || !G || !phi || !u) return fail(LBM_EARG, "NULL field pointer");
-    return dispatch<DoSetPdfs>(c->p.storage, c, H, G, phi, u);
+    return dispatch<DoSetPdfs>(c->p, c, H, G, phi, u);
 }
 
 lbm_status lbm_stream_copy(const void *src, void *dst, size_t bytes, void *stream)
@@ -774,8 +808,8 @@ lbm_status lbm_stream_copy(const void *src, void *dst, size_t bytes, void *strea
 static void state_parts(const lbm_ctx *c, size_t sz[4], size_t off_dst[5])
 {
     const size_t pb = pdf_bytes(c->p.storage), rb = real_bytes(c->p.storage);
-    sz[0] = 15 * (size_t)c->L.pdf_elems * pb;
-    sz[1] = 27 * (size_t)c->L.pdf_elems * pb;
+    sz[0] = (size_t)q_phase(&c->p) * (size_t)c->L.pdf_elems * pb;
+    sz[1] = (size_t)q_hydro(&c->p) * (size_t)c->L.pdf_elems * pb;
     sz[2] = (size_t)c->L.fplane * rb;
     sz[3] = 3 * (size_t)c->L.fplane * rb;
     off_dst[0] = 0;

@@ -194,15 +194,15 @@ __device__ inline R gamma_i(int i, R ux, R uy, R uz, R uu)
 // Hydrodynamic equilibrium g_eq_i = p* w_i + (Gamma_i - w_i) (Sec. 3.2), with
 // the w_i of Gamma cancelled algebraically so small g are not formed as a
 // difference of O(w) numbers.
-template <class R>
+template <int Q, class R>
 __device__ inline R geq_i(int i, R ps, R ux, R uy, R uz, R uu)
 {
-    const R eu = R(e27(i, 0)) * ux + R(e27(i, 1)) * uy + R(e27(i, 2)) * uz;
+    const R eu = R(ev<Q>(i, 0)) * ux + R(ev<Q>(i, 1)) * uy + R(ev<Q>(i, 2)) * uz;
     if constexpr (std::is_same<R, float>::value) {
-        return wgt<27, R>(i) * (ps + by_cs2(eu) + (eu * eu) * R(4.5) - uu * R(1.5));
+        return wgt<Q, R>(i) * (ps + by_cs2(eu) + (eu * eu) * R(4.5) - uu * R(1.5));
     } else {
         const R c2 = cs2<R>();
-        return wgt<27, R>(i) * (ps + by_cs2(eu) + (eu * eu) / (R(2) * c2 * c2) - uu / (R(2) * c2));
+        return wgt<Q, R>(i) * (ps + by_cs2(eu) + (eu * eu) / (R(2) * c2 * c2) - uu / (R(2) * c2));
     }
 }
 
@@ -337,20 +337,21 @@ __device__ inline void phase_cell(const SweepArgs<S> &a, int c, const Nbr &n, co
                                   const typename S::real *u_reg = nullptr)
 {
     using R = typename S::real;
-    // previous phase field at x + e_i (D3Q15 stencil points; wall rows mirrored)
-    R phs[15];
+    constexpr int QP = S::QP;
+    // previous phase field at x + e_i (stencil points of the phase-field set; wall rows mirrored)
+    R phs[QP];
 #pragma unroll
-    for (int i = 0; i < 15; ++i) phs[i] = phiA.at(e15(i, 0), e15(i, 1), e15(i, 2));
+    for (int i = 0; i < QP; ++i) phs[i] = phiA.at(ev<QP>(i, 0), ev<QP>(i, 1), ev<QP>(i, 2));
 
     // The population arrives from x - e_i (phs[opp(i)]) or bounces back at x.
     // The FP32 and 16-bit paths keep the phi budget of the cell in FP64: the
     // decoded populations are summed exactly, so sum(phi) moves only by the
     // single rounding of the rest population below.
-    R Pi[15];
+    R Pi[QP];
     double phi_acc = 0.0;
 #pragma unroll
-    for (int i = 0; i < 15; ++i) {
-        const bool bb = (e15(i, 1) > 0 && n.wm) || (e15(i, 1) < 0 && n.wp);
+    for (int i = 0; i < QP; ++i) {
+        const bool bb = (ev<QP>(i, 1) > 0 && n.wm) || (ev<QP>(i, 1) < 0 && n.wp);
         const typename S::pdf_t v = io.load(i);
         const R up = bb ? phs[0] : phs[opp(i)];
         if constexpr (std::is_same<R, double>::value) {
@@ -368,12 +369,12 @@ __device__ inline void phase_cell(const SweepArgs<S> &a, int c, const Nbr &n, co
     // isotropic gradient (eq. grad) from antisymmetric pairs of the half set
     R acc[3] = {R(0), R(0), R(0)};
 #pragma unroll
-    for (int i = 1; i < 15; i += 2) {
+    for (int i = 1; i < QP; i += 2) {
         const R d = phs[i] - phs[i + 1];
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            if (e15(i, k) > 0) acc[k] += wgt<15, R>(i) * d;
-            if (e15(i, k) < 0) acc[k] -= wgt<15, R>(i) * d;
+            if (ev<QP>(i, k) > 0) acc[k] += wgt<QP, R>(i) * d;
+            if (ev<QP>(i, k) < 0) acc[k] -= wgt<QP, R>(i) * d;
         }
     }
     R grad[3];
@@ -407,17 +408,46 @@ __device__ inline void phase_cell(const SweepArgs<S> &a, int c, const Nbr &n, co
     }
     const R uu = ux * ux + uy * uy + uz * uz;
     const R om = a.ph.omega_phi;
-    R hs[15];
+    R hs[QP];
+    if constexpr (!S::phase_mrt) {
 #pragma unroll
-    for (int i = 0; i < 15; ++i) {
-        const R en = R(e15(i, 0)) * nrm[0] + R(e15(i, 1)) * nrm[1] + R(e15(i, 2)) * nrm[2];
-        const R F = theta * wgt<15, R>(i) * en;
-        const R heq = phi * gamma_i<15, R>(i, ux, uy, uz, uu);
-        hs[i] = Pi[i] + om * (heq - Pi[i] - R(0.5) * F) + F;
+        for (int i = 0; i < QP; ++i) {
+            const R en = R(ev<QP>(i, 0)) * nrm[0] + R(ev<QP>(i, 1)) * nrm[1] + R(ev<QP>(i, 2)) * nrm[2];
+            const R F = theta * wgt<QP, R>(i) * en;
+            const R heq = phi * gamma_i<QP, R>(i, ux, uy, uz, uu);
+            hs[i] = Pi[i] + om * (heq - Pi[i] - R(0.5) * F) + F;
+        }
+    } else {
+        // Raw-moment MRT (Sec. 3.1): the first-order moments relax with
+        // omega, every other moment with one.  With the monomial moment set
+        // the first-order columns of the inverse moment matrix are
+        // (delta_{+k} - delta_{-k})/2 on the axis pair of direction k, so
+        // h* = h_eq + F/2 + (omega - 1)/2 (+-) j_k(h_eq - h - F/2) on the
+        // six axis populations and h_eq + F/2 on all others.
+        R d[3] = {R(0), R(0), R(0)};
+#pragma unroll
+        for (int i = 0; i < QP; ++i) {
+            const R en = R(ev<QP>(i, 0)) * nrm[0] + R(ev<QP>(i, 1)) * nrm[1] + R(ev<QP>(i, 2)) * nrm[2];
+            const R F = theta * wgt<QP, R>(i) * en;
+            const R heq = phi * gamma_i<QP, R>(i, ux, uy, uz, uu);
+            const R di = heq - Pi[i] - R(0.5) * F;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                if (ev<QP>(i, k) > 0) d[k] += di;
+                if (ev<QP>(i, k) < 0) d[k] -= di;
+            }
+            hs[i] = heq + R(0.5) * F;
+        }
+        const R hw = R(0.5) * (om - R(1));
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            hs[1 + 2 * k] += hw * d[k];
+            hs[2 + 2 * k] -= hw * d[k];
+        }
     }
     if constexpr (std::is_same<R, double>::value) {
 #pragma unroll
-        for (int i = 0; i < 15; ++i) io.store(i, enc_h<S>(hs[i], phi, i));
+        for (int i = 0; i < QP; ++i) io.store(i, enc_h<S>(hs[i], phi, i));
     } else {
         // The collision conserves phi exactly; in FP32 the rounded weights do
         // not sum to one and 16-bit storage rounds every population, which
@@ -425,7 +455,7 @@ __device__ inline void phase_cell(const SweepArgs<S> &a, int c, const Nbr &n, co
         // population, using the values the next sweep will decode.
         double rest = phi_acc;
 #pragma unroll
-        for (int i = 1; i < 15; ++i) {
+        for (int i = 1; i < QP; ++i) {
             const typename S::pdf_t v = enc_h<S>(hs[i], phi, i);
             rest -= dec_h64<S>(v, phi, i);
             io.store(i, v);
@@ -442,7 +472,7 @@ __global__ __launch_bounds__(kBlock) void k_phase(const SweepArgs<S> a)
     int x, y, z;
     Nbr n;
     if (!decode(a.g, c, x, y, z, n)) return;
-    phase_cell<S>(a, c, n, PhiG<typename S::real>{a.phi_in, c, &n}, IOGlobal<S, 15>{a.src, a.dst, c, &n, &a.g});
+    phase_cell<S>(a, c, n, PhiG<typename S::real>{a.phi_in, c, &n}, IOGlobal<S, S::QP>{a.src, a.dst, c, &n, &a.g});
 }
 
 // ---- hydrodynamic sweep: pull-stream g, moments, forces from the new phi
@@ -469,6 +499,8 @@ __device__ inline void hydro_cell(const SweepArgs<S> &a, int c, const Nbr &n, co
                                   typename S::real *u_new = nullptr)
 {
     using R = typename S::real;
+    constexpr int QH = S::QH;
+    static_assert(!S::lowp || QH == 27, "16-bit storage keeps the D3Q27 hydrodynamic set");
     R ps = R(0), j[3] = {R(0), R(0), R(0)};
     R Pxx = R(0), Pyy = R(0), Pzz = R(0), Pxy = R(0), Pxz = R(0), Pyz = R(0);
     if constexpr (S::lowp) {
@@ -480,9 +512,9 @@ __device__ inline void hydro_cell(const SweepArgs<S> &a, int c, const Nbr &n, co
 #pragma unroll
             for (int q = 0; q < 10; ++q) m[k][q] = R(0);
 #pragma unroll
-        for (int i = 0; i < 27; ++i) {
+        for (int i = 0; i < QH; ++i) {
             const R v = S::raw_ld(io.load(i));
-            const int ex = e27(i, 0), ey = e27(i, 1), ez = e27(i, 2), k = l1<27>(i);
+            const int ex = ev<QH>(i, 0), ey = ev<QH>(i, 1), ez = ev<QH>(i, 2), k = l1<QH>(i);
             m[k][0] += v;
             if (ex) m[k][1] += ex > 0 ? v : -v;
             if (ey) m[k][2] += ey > 0 ? v : -v;
@@ -513,9 +545,9 @@ __device__ inline void hydro_cell(const SweepArgs<S> &a, int c, const Nbr &n, co
         Pyz = mom[9];
     } else {
 #pragma unroll
-        for (int i = 0; i < 27; ++i) {
+        for (int i = 0; i < QH; ++i) {
             const R gi = dec_g<S>(io.load(i), i);
-            const int ex = e27(i, 0), ey = e27(i, 1), ez = e27(i, 2);
+            const int ex = ev<QH>(i, 0), ey = ev<QH>(i, 1), ez = ev<QH>(i, 2);
             ps += gi;
             if (ex) j[0] += ex > 0 ? gi : -gi;
             if (ey) j[1] += ey > 0 ? gi : -gi;
@@ -531,7 +563,7 @@ __device__ inline void hydro_cell(const SweepArgs<S> &a, int c, const Nbr &n, co
 
     const R phi = phiB.at(0, 0, 0);
     R grad[3], lap;
-    stencil<27, R, true>(phiB, grad, lap);
+    stencil<QH, R, true>(phiB, grad, lap);
 
     const Phys<R> &ph = a.ph;
     const R rho = density_of(ph, phi);
@@ -602,22 +634,22 @@ __device__ inline void hydro_cell(const SweepArgs<S> &a, int c, const Nbr &n, co
         const R ct = trB * (R(1) / R(3));
         const R Bxy2 = R(2) * Bxy, Bxz2 = R(2) * Bxz, Byz2 = R(2) * Byz;
 #pragma unroll
-        for (int i = 0; i < 27; ++i) {
-            const int ex = e27(i, 0), ey = e27(i, 1), ez = e27(i, 2);
+        for (int i = 0; i < QH; ++i) {
+            const int ex = ev<QH>(i, 0), ey = ev<QH>(i, 1), ez = ev<QH>(i, 2);
             const R eu = R(ex) * ux + R(ey) * uy + R(ez) * uz;
             const R eF = R(ex) * F[0] + R(ey) * F[1] + R(ez) * F[2];
             const R eBe = R(ex * ex) * Bxx + R(ey * ey) * Byy + R(ez * ez) * Bzz + R(ex * ey) * Bxy2 +
                           R(ex * ez) * Bxz2 + R(ey * ez) * Byz2 - ct;
             const R sv = P0 + eu * (c3 + c45 * eu) + eF * A + eBe * Nq;
             if constexpr (S::lowp) io.store(i, S::raw_st(sv));
-            else io.store(i, S::st(sv * wgt<27, R>(i)));
+            else io.store(i, S::st(sv * wgt<QH, R>(i)));
         }
     } else {
 #pragma unroll
-        for (int i = 0; i < 27; ++i) {
-            const int ex = e27(i, 0), ey = e27(i, 1), ez = e27(i, 2);
-            const R w = wgt<27, R>(i);
-            const R geq = geq_i<R>(i, ps, ux, uy, uz, uu);
+        for (int i = 0; i < QH; ++i) {
+            const int ex = ev<QH>(i, 0), ey = ev<QH>(i, 1), ez = ev<QH>(i, 2);
+            const R w = wgt<QH, R>(i);
+            const R geq = geq_i<S::QH, R>(i, ps, ux, uy, uz, uu);
             const R eF = R(ex) * F[0] + R(ey) * F[1] + R(ez) * F[2];
             // (e e - cs^2 I) : B
             const R eBe = R(ex * ex) * Bxx + R(ey * ey) * Byy + R(ez * ez) * Bzz +
@@ -636,7 +668,7 @@ __global__ __launch_bounds__(kBlock) void k_hydro(const SweepArgs<S> a)
     int x, y, z;
     Nbr n;
     if (!decode(a.g, c, x, y, z, n)) return;
-    hydro_cell<S>(a, c, n, PhiG<typename S::real>{a.phi_in, c, &n}, IOGlobal<S, 27>{a.src, a.dst, c, &n, &a.g});
+    hydro_cell<S>(a, c, n, PhiG<typename S::real>{a.phi_in, c, &n}, IOGlobal<S, S::QH>{a.src, a.dst, c, &n, &a.g});
 }
 
 // ---- z-marching sweeps with the phase field staged in LDS ----------------------
@@ -728,8 +760,8 @@ __global__ __launch_bounds__(kBlock) void k_sweep_zm(const SweepArgs<S> a, const
             const int c = x + a.g.nx * (y + a.g.ny * z);
             const Nbr n = zm_nbr(a.g, x, y, z);
             const PhiL<R> pl{{buf[sm], buf[sc], buf[sp]}, o};
-            if constexpr (PHASE) phase_cell<S>(a, c, n, pl, IOGlobal<S, 15>{a.src, a.dst, c, &n, &a.g});
-            else hydro_cell<S>(a, c, n, pl, IOGlobal<S, 27>{a.src, a.dst, c, &n, &a.g});
+            if constexpr (PHASE) phase_cell<S>(a, c, n, pl, IOGlobal<S, S::QP>{a.src, a.dst, c, &n, &a.g});
+            else hydro_cell<S>(a, c, n, pl, IOGlobal<S, S::QH>{a.src, a.dst, c, &n, &a.g});
         }
         __syncthreads();
         const int t = sm;
@@ -751,7 +783,7 @@ template <class S, bool PHASE>
 __global__ __launch_bounds__(kBlock) void k_sweep_pair(const SweepArgs<S> a)
 {
     static_assert(S::paired, "paired sweeps need 16-bit storage");
-    constexpr int Q = PHASE ? 15 : 27;
+    constexpr int Q = PHASE ? S::QP : S::QH;
     using pdf_t = typename S::pdf_t;
     using R = typename S::real;
     const Grid &g = a.g;
@@ -816,6 +848,14 @@ __global__ __launch_bounds__(kBlock) void k_sweep_pair(const SweepArgs<S> a)
 }
 
 // ---- launch of one sweep ------------------------------------------------------
+// The default pair (D3Q15 SRT phase field, D3Q27 hydrodynamics) has every
+// sweep variant; the other velocity sets run the one-cell-per-thread sweeps.
+template <class S>
+constexpr bool is_default_lattice()
+{
+    return S::QP == 15 && S::QH == 27 && !S::phase_mrt;
+}
+
 // The sweeps for FP32 arithmetic (FP32 and 16-bit storage) are instantiated in
 // their own translation unit, compiled with contraction of a*b+c into fused
 // multiply-adds; the FP64 sweeps are instantiated with the rest of the
@@ -844,10 +884,10 @@ __global__ __launch_bounds__(kBlock) void k_fused(const SweepArgs<S> ah, const S
     Nbr n;
     if (!decode(ah.g, c, x, y, z, n)) return;
     R un[3];
-    hydro_cell<S, PhiG<R>, IOGlobal<S, 27>, true>(ah, c, n, PhiG<R>{ah.phi_in, c, &n},
-                                                  IOGlobal<S, 27>{ah.src, ah.dst, c, &n, &ah.g}, un);
-    phase_cell<S, PhiG<R>, IOGlobal<S, 15>, true>(ap, c, n, PhiG<R>{ap.phi_in, c, &n},
-                                                  IOGlobal<S, 15>{ap.src, ap.dst, c, &n, &ap.g}, un);
+    hydro_cell<S, PhiG<R>, IOGlobal<S, S::QH>, true>(ah, c, n, PhiG<R>{ah.phi_in, c, &n},
+                                                     IOGlobal<S, S::QH>{ah.src, ah.dst, c, &n, &ah.g}, un);
+    phase_cell<S, PhiG<R>, IOGlobal<S, S::QP>, true>(ap, c, n, PhiG<R>{ap.phi_in, c, &n},
+                                                     IOGlobal<S, S::QP>{ap.src, ap.dst, c, &n, &ap.g}, un);
 }
 
 template <class S>
@@ -865,9 +905,13 @@ void launch_sweep(const SweepArgs<S> &a, const SweepLaunch &L, hipStream_t strea
             return;
         }
     }
-    if (L.mode == 1) {
-        hipLaunchKernelGGL((k_sweep_zm<S, PHASE>), dim3(L.blocks), dim3(kBlock), 0, stream, a, L.zt);
-    } else if constexpr (PHASE) {
+    if constexpr (is_default_lattice<S>()) {
+        if (L.mode == 1) {
+            hipLaunchKernelGGL((k_sweep_zm<S, PHASE>), dim3(L.blocks), dim3(kBlock), 0, stream, a, L.zt);
+            return;
+        }
+    }
+    if constexpr (PHASE) {
         hipLaunchKernelGGL((k_phase<S>), dim3(L.blocks), dim3(kBlock), 0, stream, a);
     } else {
         hipLaunchKernelGGL((k_hydro<S>), dim3(L.blocks), dim3(kBlock), 0, stream, a);
@@ -923,9 +967,9 @@ __global__ __launch_bounds__(kBlock) void k_naive_phi(const typename S::pdf_t *_
     if (!decode(g, c, x, y, z, n)) return;
     double acc = 0.0;
 #pragma unroll
-    for (int i = 0; i < 15; ++i) {
-        if constexpr (std::is_same<typename S::real, double>::value) acc += dec_h<S>(h[pdf_index<S, 15>(i, c, g)], 0.0, i);
-        else acc += dec_h64<S>(h[pdf_index<S, 15>(i, c, g)], 0.f, i);
+    for (int i = 0; i < S::QP; ++i) {
+        if constexpr (std::is_same<typename S::real, double>::value) acc += dec_h<S>(h[pdf_index<S, S::QP>(i, c, g)], 0.0, i);
+        else acc += dec_h64<S>(h[pdf_index<S, S::QP>(i, c, g)], 0.f, i);
     }
     st_field(phi + c, typename S::real(acc));
 }
@@ -940,8 +984,8 @@ __global__ __launch_bounds__(kBlock) void k_naive_update_u(const SweepArgs<S> a)
     int x, y, z;
     Nbr n;
     if (!decode(a.g, c, x, y, z, n)) return;
-    hydro_cell<S, PhiG<R>, IOCell<S, 27>, false, kHydroUpdateU>(a, c, n, PhiG<R>{a.phi_in, c, &n},
-                                                                 IOCell<S, 27>{a.dst, c, &a.g});
+    hydro_cell<S, PhiG<R>, IOCell<S, S::QH>, false, kHydroUpdateU>(a, c, n, PhiG<R>{a.phi_in, c, &n},
+                                                                    IOCell<S, S::QH>{a.dst, c, &a.g});
 }
 
 // collision of the streamed h (a.dst, in place) with the new phi's stencil
@@ -954,8 +998,8 @@ __global__ __launch_bounds__(kBlock) void k_naive_collide_h(const SweepArgs<S> a
     int x, y, z;
     Nbr n;
     if (!decode(a.g, c, x, y, z, n)) return;
-    phase_cell<S, PhiG<R>, IOCell<S, 15>, false, false>(a, c, n, PhiG<R>{a.phi_in, c, &n},
-                                                        IOCell<S, 15>{a.dst, c, &a.g});
+    phase_cell<S, PhiG<R>, IOCell<S, S::QP>, false, false>(a, c, n, PhiG<R>{a.phi_in, c, &n},
+                                                           IOCell<S, S::QP>{a.dst, c, &a.g});
 }
 
 // collision of the streamed g (a.dst, in place) with the updated u
@@ -968,8 +1012,8 @@ __global__ __launch_bounds__(kBlock) void k_naive_collide_g(const SweepArgs<S> a
     int x, y, z;
     Nbr n;
     if (!decode(a.g, c, x, y, z, n)) return;
-    hydro_cell<S, PhiG<R>, IOCell<S, 27>, false, kHydroCollide>(a, c, n, PhiG<R>{a.phi_in, c, &n},
-                                                                 IOCell<S, 27>{a.dst, c, &a.g});
+    hydro_cell<S, PhiG<R>, IOCell<S, S::QH>, false, kHydroCollide>(a, c, n, PhiG<R>{a.phi_in, c, &n},
+                                                                    IOCell<S, S::QH>{a.dst, c, &a.g});
 }
 
 // One step of the straightforward algorithm: H[a] -> H[b], G[a] -> G[b],
@@ -978,22 +1022,32 @@ __global__ __launch_bounds__(kBlock) void k_naive_collide_g(const SweepArgs<S> a
 template <class S>
 void launch_naive_step(const SweepArgs<S> &ph, const SweepArgs<S> &gh, int blocks, hipStream_t stream)
 {
-    hipLaunchKernelGGL((k_naive_stream<S, 15>), dim3(blocks), dim3(kBlock), 0, stream, ph.src, ph.dst, ph.g);
+    hipLaunchKernelGGL((k_naive_stream<S, S::QP>), dim3(blocks), dim3(kBlock), 0, stream, ph.src, ph.dst, ph.g);
     hipLaunchKernelGGL((k_naive_phi<S>), dim3(blocks), dim3(kBlock), 0, stream, ph.dst, ph.phi_out, ph.g);
-    hipLaunchKernelGGL((k_naive_stream<S, 27>), dim3(blocks), dim3(kBlock), 0, stream, gh.src, gh.dst, gh.g);
+    hipLaunchKernelGGL((k_naive_stream<S, S::QH>), dim3(blocks), dim3(kBlock), 0, stream, gh.src, gh.dst, gh.g);
     hipLaunchKernelGGL((k_naive_update_u<S>), dim3(blocks), dim3(kBlock), 0, stream, gh);
     hipLaunchKernelGGL((k_naive_collide_h<S>), dim3(blocks), dim3(kBlock), 0, stream, ph);
     hipLaunchKernelGGL((k_naive_collide_g<S>), dim3(blocks), dim3(kBlock), 0, stream, gh);
 }
 
+// The FP32 storage types with other velocity sets (see Lattice).
+using StoreF32_15_27_mrt = Lattice<StoreF32, 15, 27, true>;
+using StoreF32_19_19 = Lattice<StoreF32, 19, 19, false>;
+using StoreF32_19_19_mrt = Lattice<StoreF32, 19, 19, true>;
+using StoreF32_27_27 = Lattice<StoreF32, 27, 27, false>;
+using StoreF32_15_15 = Lattice<StoreF32, 15, 15, false>;
+#define LBM_FP32_LATTICES(X) X(StoreF32_15_27_mrt) X(StoreF32_19_19) X(StoreF32_19_19_mrt) X(StoreF32_27_27) X(StoreF32_15_15)
+
 #define LBM_FP32_SWEEPS(X)                                                                          \
     X(StoreF32, true) X(StoreF32, false) X(StoreF16S, true) X(StoreF16S, false) X(StoreBF16S, true) \
-    X(StoreBF16S, false)
+    X(StoreBF16S, false) X(StoreF32_15_27_mrt, true) X(StoreF32_15_27_mrt, false) X(StoreF32_19_19, true)    \
+    X(StoreF32_19_19, false) X(StoreF32_19_19_mrt, true) X(StoreF32_19_19_mrt, false) X(StoreF32_27_27, true) \
+    X(StoreF32_27_27, false) X(StoreF32_15_15, true) X(StoreF32_15_15, false)
 
 // ---- initial / equilibrium state from (phi, u, p*) ---------------------------
 // Writes the phase-field PDFs (post-collision, stored as is), the canonical
 // pre-collision hydrodynamic PDFs into Gc (blocked layout; turned into the
-// stored post-collision form by k_unpull27), phi and u.
+// stored post-collision form by k_unpull), phi and u.
 template <class S, class In>
 __global__ __launch_bounds__(kBlock) void k_equilibrium(typename S::pdf_t *__restrict__ H,
                                                         typename S::pdf_t *__restrict__ Gc,
@@ -1019,14 +1073,14 @@ __global__ __launch_bounds__(kBlock) void k_equilibrium(typename S::pdf_t *__res
     }
     const R uu = ux * ux + uy * uy + uz * uz;
 #pragma unroll
-    for (int i = 0; i < 15; ++i) {
-        const R h = wall ? R(0) : phi * gamma_i<15, R>(i, ux, uy, uz, uu);
-        H[pdf_index<S, 15>(i, c, g)] = enc_h<S>(h, phi, i);
+    for (int i = 0; i < S::QP; ++i) {
+        const R h = wall ? R(0) : phi * gamma_i<S::QP, R>(i, ux, uy, uz, uu);
+        H[pdf_index<S, S::QP>(i, c, g)] = enc_h<S>(h, phi, i);
     }
 #pragma unroll
-    for (int i = 0; i < 27; ++i) {
-        const R ge = wall ? R(0) : geq_i<R>(i, ps, ux, uy, uz, uu);
-        Gc[pdf_index<S, 27>(i, c, g)] = enc_g<S>(ge, i);
+    for (int i = 0; i < S::QH; ++i) {
+        const R ge = wall ? R(0) : geq_i<S::QH, R>(i, ps, ux, uy, uz, uu);
+        Gc[pdf_index<S, S::QH>(i, c, g)] = enc_g<S>(ge, i);
     }
     phiA[c] = phi;
     u[c] = ux;
@@ -1039,7 +1093,7 @@ __global__ __launch_bounds__(kBlock) void k_equilibrium(typename S::pdf_t *__res
 // y + e_j is a wall, the reversed one arriving back at y).  Exact inverse of
 // the pull of the sweeps.  Wall cells are left untouched.
 template <class S>
-__global__ __launch_bounds__(kBlock) void k_unpull27(const typename S::pdf_t *__restrict__ Gc,
+__global__ __launch_bounds__(kBlock) void k_unpull(const typename S::pdf_t *__restrict__ Gc,
                                                      typename S::pdf_t *__restrict__ G, Grid g)
 {
     const int c = blockIdx.x * kBlock + threadIdx.x;
@@ -1048,11 +1102,11 @@ __global__ __launch_bounds__(kBlock) void k_unpull27(const typename S::pdf_t *__
     Nbr n;
     if (!decode(g, c, x, y, z, n)) return;
 #pragma unroll
-    for (int j = 0; j < 27; ++j) {
-        const int dx = e27(j, 0), dy = e27(j, 1), dz = e27(j, 2);
+    for (int j = 0; j < S::QH; ++j) {
+        const int dx = ev<S::QH>(j, 0), dy = ev<S::QH>(j, 1), dz = ev<S::QH>(j, 2);
         const bool bb = (dy > 0 && n.wp) || (dy < 0 && n.wm);  // y + e_j is a wall row
-        const int64_t from = bb ? pdf_index<S, 27>(opp(j), c, g) : pdf_index<S, 27>(j, c + n.off(dx, dy, dz), g);
-        G[pdf_index<S, 27>(j, c, g)] = Gc[from];
+        const int64_t from = bb ? pdf_index<S, S::QH>(opp(j), c, g) : pdf_index<S, S::QH>(j, c + n.off(dx, dy, dz), g);
+        G[pdf_index<S, S::QH>(j, c, g)] = Gc[from];
     }
 }
 
@@ -1072,17 +1126,17 @@ __global__ __launch_bounds__(kBlock) void k_get_pdfs(const typename S::pdf_t *__
     const bool fluid = decode(g, c, x, y, z, n);
     if (Ho)
 #pragma unroll
-        for (int i = 0; i < 15; ++i)
-            Ho[i * N + c] = fluid ? (double)dec_h<S>(H[pdf_index<S, 15>(i, c, g)], phiA[c], i) : 0.0;
+        for (int i = 0; i < S::QP; ++i)
+            Ho[i * N + c] = fluid ? (double)dec_h<S>(H[pdf_index<S, S::QP>(i, c, g)], phiA[c], i) : 0.0;
     if (Go)
 #pragma unroll
-        for (int i = 0; i < 27; ++i)
-            Go[i * N + c] = fluid ? (double)dec_g<S>(G[pull_idx<S, 27>(i, c, n, g)], i) : 0.0;
+        for (int i = 0; i < S::QH; ++i)
+            Go[i * N + c] = fluid ? (double)dec_g<S>(G[pull_idx<S, S::QH>(i, c, n, g)], i) : 0.0;
 }
 
 // Storage from canonical FP64 planes: H stored directly, G (pre-collision)
 // written to Gc in storage format, to be turned into the stored form by
-// k_unpull27.
+// k_unpull.
 template <class S>
 __global__ __launch_bounds__(kBlock) void k_set_pdfs(typename S::pdf_t *__restrict__ H,
                                                      typename S::pdf_t *__restrict__ Gc,
@@ -1100,11 +1154,11 @@ __global__ __launch_bounds__(kBlock) void k_set_pdfs(typename S::pdf_t *__restri
     const bool wall = g.walls && (y == 0 || y == g.ny - 1);
     const int64_t N = g.ncells;
 #pragma unroll
-    for (int i = 0; i < 15; ++i) {
-        H[pdf_index<S, 15>(i, c, g)] = enc_h<S>(wall ? R(0) : R(Hi[i * N + c]), wall ? R(0) : R(phi_i[c]), i);
+    for (int i = 0; i < S::QP; ++i) {
+        H[pdf_index<S, S::QP>(i, c, g)] = enc_h<S>(wall ? R(0) : R(Hi[i * N + c]), wall ? R(0) : R(phi_i[c]), i);
     }
 #pragma unroll
-    for (int i = 0; i < 27; ++i) Gc[pdf_index<S, 27>(i, c, g)] = enc_g<S>(wall ? R(0) : R(Gi[i * N + c]), i);
+    for (int i = 0; i < S::QH; ++i) Gc[pdf_index<S, S::QH>(i, c, g)] = enc_g<S>(wall ? R(0) : R(Gi[i * N + c]), i);
     phiA[c] = wall ? R(0) : R(phi_i[c]);
     for (int k = 0; k < 3; ++k) u[k * g.fplane + c] = wall ? R(0) : R(u_i[k * N + c]);
 }
@@ -1114,7 +1168,7 @@ __global__ __launch_bounds__(kBlock) void k_set_pdfs(typename S::pdf_t *__restri
 // of their equilibria, h_i += phi' Gamma_i(u') - phi Gamma_i(u) and
 // g_i += g^eq_i(p*', u') - g^eq_i(p*, u), with phi, u the stored fields and
 // p* = sum_i g_i.  First the canonical pre-collision G (pulled, as in the
-// hydrodynamic sweep) with its increment into Gc, which k_unpull27 turns
+// hydrodynamic sweep) with its increment into Gc, which k_unpull turns
 // back into the stored form; it reads the old u, so it runs before
 // k_shift_eq_h.  Wall cells are left as they are.
 template <class S, class In>
@@ -1132,10 +1186,10 @@ __global__ __launch_bounds__(kBlock) void k_shift_eq_g(const typename S::pdf_t *
     Nbr n;
     if (!decode(g, c, x, y, z, n)) return;
     const int64_t N = g.ncells;
-    R gc[27], ps = R(0);
+    R gc[S::QH], ps = R(0);
 #pragma unroll
-    for (int i = 0; i < 27; ++i) {
-        gc[i] = dec_g<S>(G[pull_idx<S, 27>(i, c, n, g)], i);
+    for (int i = 0; i < S::QH; ++i) {
+        gc[i] = dec_g<S>(G[pull_idx<S, S::QH>(i, c, n, g)], i);
         ps += gc[i];
     }
     const R ux = u[c], uy = u[g.fplane + c], uz = u[2 * g.fplane + c];
@@ -1144,9 +1198,9 @@ __global__ __launch_bounds__(kBlock) void k_shift_eq_g(const typename S::pdf_t *
     const R vv = vx * vx + vy * vy + vz * vz;
     const R qs = R(p_in[c]) / (density_of(ph, R(phi_in[c])) * cs2<R>());
 #pragma unroll
-    for (int i = 0; i < 27; ++i) {
-        const R gn = gc[i] + (geq_i<R>(i, qs, vx, vy, vz, vv) - geq_i<R>(i, ps, ux, uy, uz, uu));
-        Gc[pdf_index<S, 27>(i, c, g)] = enc_g<S>(gn, i);
+    for (int i = 0; i < S::QH; ++i) {
+        const R gn = gc[i] + (geq_i<S::QH, R>(i, qs, vx, vy, vz, vv) - geq_i<S::QH, R>(i, ps, ux, uy, uz, uu));
+        Gc[pdf_index<S, S::QH>(i, c, g)] = enc_g<S>(gn, i);
     }
 }
 
@@ -1172,10 +1226,10 @@ __global__ __launch_bounds__(kBlock) void k_shift_eq_h(typename S::pdf_t *__rest
     const R vx = R(u_in[c]), vy = R(u_in[N + c]), vz = R(u_in[2 * N + c]);
     const R vv = vx * vx + vy * vy + vz * vz;
 #pragma unroll
-    for (int i = 0; i < 15; ++i) {
-        const int64_t k = pdf_index<S, 15>(i, c, g);
+    for (int i = 0; i < S::QP; ++i) {
+        const int64_t k = pdf_index<S, S::QP>(i, c, g);
         const R h = dec_h<S>(H[k], phi, i) +
-                    (phn * gamma_i<15, R>(i, vx, vy, vz, vv) - phi * gamma_i<15, R>(i, ux, uy, uz, uu));
+                    (phn * gamma_i<S::QP, R>(i, vx, vy, vz, vv) - phi * gamma_i<S::QP, R>(i, ux, uy, uz, uu));
         H[k] = enc_h<S>(h, phn, i);
     }
     phiA[c] = phn;
@@ -1206,7 +1260,7 @@ __global__ __launch_bounds__(kBlock) void k_get_macro(const typename S::pdf_t *_
         R ps = R(0);
         if (fluid)
 #pragma unroll
-            for (int i = 0; i < 27; ++i) ps += dec_g<S>(G[pull_idx<S, 27>(i, c, n, g)], i);
+            for (int i = 0; i < S::QH; ++i) ps += dec_g<S>(G[pull_idx<S, S::QH>(i, c, n, g)], i);
         const R rho = density_of(ph, phiA[c]);
         p_o[c] = fluid ? Out(ps * rho * cs2<R>()) : Out(0);
     }

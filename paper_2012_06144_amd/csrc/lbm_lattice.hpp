@@ -39,6 +39,8 @@ __host__ __device__ constexpr int e27(int i, int a)
     return T[i][a];
 }
 
+// D3Q19 is the rest, axis and edge part of D3Q27: its directions are the
+// first 19 of the D3Q27 order.
 template <int Q>
 __host__ __device__ constexpr int ev(int i, int a)
 {
@@ -57,11 +59,12 @@ __host__ __device__ constexpr int l1(int i)
 template <int Q, class R>
 __host__ __device__ constexpr R wgt(int i)
 {
-    return Q == 15 ? (l1<15>(i) == 0 ? R(2) / R(9) : l1<15>(i) == 1 ? R(1) / R(9) : R(1) / R(72))
-                   : (l1<27>(i) == 0 ? R(8) / R(27)
-                      : l1<27>(i) == 1 ? R(2) / R(27)
-                      : l1<27>(i) == 2 ? R(1) / R(54)
-                                       : R(1) / R(216));
+    return Q == 15   ? (l1<15>(i) == 0 ? R(2) / R(9) : l1<15>(i) == 1 ? R(1) / R(9) : R(1) / R(72))
+           : Q == 19 ? (l1<19>(i) == 0 ? R(1) / R(3) : l1<19>(i) == 1 ? R(1) / R(18) : R(1) / R(36))
+                     : (l1<27>(i) == 0 ? R(8) / R(27)
+                        : l1<27>(i) == 1 ? R(2) / R(27)
+                        : l1<27>(i) == 2 ? R(1) / R(54)
+                                         : R(1) / R(216));
 }
 
 // ---- storage codecs ---------------------------------------------------------
@@ -77,6 +80,8 @@ __host__ __device__ constexpr R wgt(int i)
 // with a bias.  BF16 has the exponent range of FP32 and needs no scaling.
 // Rounding is to nearest even.
 struct StoreF64 {
+    static constexpr int QP = 15, QH = 27;  // velocity sets of the phase-field and hydrodynamic steps
+    static constexpr bool phase_mrt = false;  // raw-moment MRT phase-field collision
     using pdf_t = double;
     using real = double;
     static constexpr bool lowp = false;
@@ -87,6 +92,8 @@ struct StoreF64 {
 };
 
 struct StoreF32 {
+    static constexpr int QP = 15, QH = 27;  // velocity sets of the phase-field and hydrodynamic steps
+    static constexpr bool phase_mrt = false;  // raw-moment MRT phase-field collision
     using pdf_t = float;
     using real = float;
     static constexpr bool lowp = false;
@@ -97,6 +104,8 @@ struct StoreF32 {
 };
 
 struct StoreF16S {
+    static constexpr int QP = 15, QH = 27;  // velocity sets of the phase-field and hydrodynamic steps
+    static constexpr bool phase_mrt = false;  // raw-moment MRT phase-field collision
     using pdf_t = __half;
     using real = float;
     static constexpr bool lowp = true;
@@ -109,6 +118,8 @@ struct StoreF16S {
 };
 
 struct StoreBF16S {
+    static constexpr int QP = 15, QH = 27;  // velocity sets of the phase-field and hydrodynamic steps
+    static constexpr bool phase_mrt = false;  // raw-moment MRT phase-field collision
     using pdf_t = __hip_bfloat16;
     using real = float;
     static constexpr bool lowp = true;
@@ -118,6 +129,17 @@ struct StoreBF16S {
     __device__ static pdf_t raw_st(real v) { return __float2bfloat16(v); }
     __device__ static real ld(pdf_t v) { return raw_ld(v); }
     __device__ static pdf_t st(real v) { return raw_st(v); }
+};
+
+// A storage type with other velocity sets (the stencil study of Sec. 5.1 and
+// the D3Q19 lattice of Sec. 6.1) and optionally the raw-moment MRT of the
+// phase field (Sec. 3.1).  FP64 and FP32 storage only.
+template <class B, int QP_, int QH_, bool MRT_>
+struct Lattice : B {
+    static_assert(!B::lowp, "16-bit storage keeps D3Q15 / D3Q27");
+    static_assert((QP_ == 15 || QP_ == 19 || QP_ == 27) && (QH_ == 15 || QH_ == 19 || QH_ == 27), "velocity set");
+    static constexpr int QP = QP_, QH = QH_;
+    static constexpr bool phase_mrt = MRT_;
 };
 
 // 1/w_i of D3Q27 (all exact in binary): 27/8, 27/2, 54, 216.
@@ -139,14 +161,14 @@ template <class S>
 __device__ inline typename S::pdf_t enc_h(typename S::real h, typename S::real phi_cell, int i)
 {
     using R = typename S::real;
-    if constexpr (S::lowp) return S::st(h - phi_cell * wgt<15, R>(i));
+    if constexpr (S::lowp) return S::st(h - phi_cell * wgt<S::QP, R>(i));
     else return S::st(h);
 }
 template <class S>
 __device__ inline typename S::real dec_h(typename S::pdf_t v, typename S::real phi_cell, int i)
 {
     using R = typename S::real;
-    if constexpr (S::lowp) return S::ld(v) + phi_cell * wgt<15, R>(i);
+    if constexpr (S::lowp) return S::ld(v) + phi_cell * wgt<S::QP, R>(i);
     else return S::ld(v);
 }
 // Mass-budget forms of the phase-field codec for the FP32 and 16-bit paths:
@@ -156,14 +178,14 @@ __device__ inline typename S::real dec_h(typename S::pdf_t v, typename S::real p
 template <class S>
 __device__ inline double dec_h64(typename S::pdf_t v, typename S::real phi_cell, int i)
 {
-    if constexpr (S::lowp) return double(S::ld(v)) + double(phi_cell) * wgt<15, double>(i);
+    if constexpr (S::lowp) return double(S::ld(v)) + double(phi_cell) * wgt<S::QP, double>(i);
     else return double(S::ld(v));
 }
 template <class S>
 __device__ inline typename S::pdf_t enc_h64(double h, typename S::real phi_cell, int i)
 {
     using R = typename S::real;
-    if constexpr (S::lowp) return S::st(R(h - double(phi_cell) * wgt<15, double>(i)));
+    if constexpr (S::lowp) return S::st(R(h - double(phi_cell) * wgt<S::QP, double>(i)));
     else return S::st(R(h));
 }
 template <class S>

@@ -15,4 +15,9 @@ LBM_FP32_SWEEPS(LBM_INSTANTIATE_SWEEP)
 template void launch_fused<StoreF32>(const SweepArgs<StoreF32> &, const SweepArgs<StoreF32> &, const SweepLaunch &,
                                      hipStream_t);
 template void launch_naive_step<StoreF32>(const SweepArgs<StoreF32> &, const SweepArgs<StoreF32> &, int, hipStream_t);
+#define LBM_INSTANTIATE_LATTICE(S)                                                                            \
+    template void launch_fused<S>(const SweepArgs<S> &, const SweepArgs<S> &, const SweepLaunch &, hipStream_t); \
+    template void launch_naive_step<S>(const SweepArgs<S> &, const SweepArgs<S> &, int, hipStream_t);
+LBM_FP32_LATTICES(LBM_INSTANTIATE_LATTICE)
+#undef LBM_INSTANTIATE_LATTICE
 }  // namespace lbm

@@ -39,6 +39,7 @@ class LbmParams(C.Structure):
         ("rho_L", C.c_double), ("rho_H", C.c_double), ("tau_L", C.c_double), ("tau_H", C.c_double),
         ("body_accel", C.c_double * 3), ("buoyancy_rho_ref", C.c_double), ("normal_eps", C.c_double),
         ("storage", C.c_int32), ("density_literal", C.c_int32),
+        ("lattice_phase", C.c_int32), ("lattice_hydro", C.c_int32), ("phase_mrt", C.c_int32),
     ]
 
 
@@ -233,7 +234,8 @@ def lbm_last_error() -> str:
 
 def make_params(nx, ny, nz, walls_y=False, phi_L=0.0, phi_H=1.0, xi=4.0, mobility=0.02,
                 sigma=1e-3, rho_L=1.0, rho_H=10.0, tau_L=1.0, tau_H=1.0, accel=(0.0, 0.0, 0.0),
-                buoyancy_rho_ref=0.0, normal_eps=1e-12, density_literal=False, storage="f64") -> LbmParams:
+                buoyancy_rho_ref=0.0, normal_eps=1e-12, density_literal=False, storage="f64",
+                lattice_phase=15, lattice_hydro=27, phase_mrt=False) -> LbmParams:
     p = LbmParams()
     p.nx, p.ny, p.nz, p.walls_y = int(nx), int(ny), int(nz), int(bool(walls_y))
     p.phi_L, p.phi_H, p.xi, p.mobility, p.sigma = phi_L, phi_H, xi, mobility, sigma
@@ -244,6 +246,8 @@ def make_params(nx, ny, nz, walls_y=False, phi_L=0.0, phi_H=1.0, xi=4.0, mobilit
     p.normal_eps = normal_eps
     p.density_literal = int(bool(density_literal))
     p.storage = STORAGE[storage] if isinstance(storage, str) else int(storage)
+    p.lattice_phase, p.lattice_hydro = int(lattice_phase), int(lattice_hydro)
+    p.phase_mrt = int(bool(phase_mrt))
     return p
 
 
@@ -257,6 +261,7 @@ class Solver:
         self.physics = dict(physics)
         self.storage = storage
         self.params = make_params(storage=storage, **physics)
+        self.qp, self.qh = self.params.lattice_phase, self.params.lattice_hydro
         self.shape = (self.params.nz, self.params.ny, self.params.nx)
         self.n = self.params.nx * self.params.ny * self.params.nz
         self.nbytes = lbm_workspace_bytes(self.params)
@@ -338,8 +343,8 @@ class Solver:
 
     def pdfs(self):
         t = self.torch
-        H = t.empty((15,) + self.shape, dtype=t.float64, device=self.device)
-        G = t.empty((27,) + self.shape, dtype=t.float64, device=self.device)
+        H = t.empty((self.qp,) + self.shape, dtype=t.float64, device=self.device)
+        G = t.empty((self.qh,) + self.shape, dtype=t.float64, device=self.device)
         lbm_get_pdfs(self.ctx, H, G)
         return H, G
 
@@ -351,7 +356,7 @@ class Solver:
         return H.cpu().numpy(), G.cpu().numpy(), phi.cpu().numpy(), u.cpu().numpy()
 
     def set_state(self, H, G, phi, u):
-        lbm_set_pdfs(self.ctx, self._dev64(H, (15,) + self.shape), self._dev64(G, (27,) + self.shape),
+        lbm_set_pdfs(self.ctx, self._dev64(H, (self.qp,) + self.shape), self._dev64(G, (self.qh,) + self.shape),
                      self._dev64(phi, self.shape), self._dev64(u, (3,) + self.shape))
         self.stream.synchronize()
 

@@ -19,14 +19,15 @@ def field_bytes(storage: str) -> int:
     return 8 if storage == "f64" else 4
 
 
-def bytes_per_cell(storage: str) -> dict:
-    """Algorithmic HBM bytes per cell update of each sweep."""
+def bytes_per_cell(storage: str, qp: int = 15, qh: int = 27) -> dict:
+    """Algorithmic HBM bytes per cell update of each sweep, for qp phase-field
+    and qh hydrodynamic populations (D3Q15 and D3Q27 by default)."""
     p = PDF_BYTES[storage]
     r = field_bytes(storage)
-    phase_r = 15 * p + 3 * r + 1 * r      # h, u, phi (previous)
-    phase_w = 15 * p + 1 * r              # h, phi (new)
-    hydro_r = 27 * p + 3 * r + 1 * r      # g, u, phi (new)
-    hydro_w = 27 * p + 3 * r              # g, u
+    phase_r = qp * p + 3 * r + 1 * r      # h, u, phi (previous)
+    phase_w = qp * p + 1 * r              # h, phi (new)
+    hydro_r = qh * p + 3 * r + 1 * r      # g, u, phi (new)
+    hydro_w = qh * p + 3 * r              # g, u
     return {
         "phase_read": phase_r, "phase_write": phase_w, "phase": phase_r + phase_w,
         "hydro_read": hydro_r, "hydro_write": hydro_w, "hydro": hydro_r + hydro_w,
@@ -38,8 +39,8 @@ def bytes_per_cell(storage: str) -> dict:
         # (15 + 15), phi = sum h (15 + 1), stream g (27 + 27), velocity update
         # (27 g + phi + 3 u read, 3 u written), collision of h (15 + phi + 3 u
         # read, 15 written), collision of g (27 + phi + 3 u read, 27 written)
-        "straightforward": (30 * p) + (15 * p + r) + (54 * p) + (27 * p + 4 * r + 3 * r)
-        + (15 * p + 4 * r + 15 * p) + (27 * p + 4 * r + 27 * p),
+        "straightforward": (2 * qp * p) + (qp * p + r) + (2 * qh * p) + (qh * p + 4 * r + 3 * r)
+        + (qp * p + 4 * r + qp * p) + (qh * p + 4 * r + qh * p),
     }
 
 

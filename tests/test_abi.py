@@ -63,8 +63,9 @@ def test_struct_layout_matches_header(tmp_path):
 #include <stddef.h>
 #include "lbm.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu\\n", sizeof(lbm_params), offsetof(lbm_params, body_accel),
-         offsetof(lbm_params, storage), offsetof(lbm_params, density_literal), sizeof(lbm_stats));
+  printf("%zu %zu %zu %zu %zu %zu %zu\\n", sizeof(lbm_params), offsetof(lbm_params, body_accel),
+         offsetof(lbm_params, storage), offsetof(lbm_params, density_literal), sizeof(lbm_stats),
+         offsetof(lbm_params, lattice_phase), offsetof(lbm_params, phase_mrt));
   printf("%zu %zu\\n", offsetof(lbm_stats, centroid), offsetof(lbm_stats, max_speed));
   return 0;
 }
@@ -74,12 +75,12 @@ int main(void) {
     vals = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True,
                                            check=True).stdout.split()]
     P, S = lbm.LbmParams, lbm.LbmStats
-    assert vals[:5] == [C.sizeof(P), P.body_accel.offset, P.storage.offset, P.density_literal.offset,
-                        C.sizeof(S)]
-    assert vals[5:] == [S.centroid.offset, S.max_speed.offset]
+    assert vals[:7] == [C.sizeof(P), P.body_accel.offset, P.storage.offset, P.density_literal.offset,
+                        C.sizeof(S), P.lattice_phase.offset, P.phase_mrt.offset]
+    assert vals[7:] == [S.centroid.offset, S.max_speed.offset]
 
 
-@pytest.mark.parametrize("q", [15, 27])
+@pytest.mark.parametrize("q", [15, 19, 27])
 def test_velocity_set_matches_oracle(q):
     lbm = _lbm()
     e, w = lbm.lbm_velocity_set(q)
@@ -90,13 +91,15 @@ def test_velocity_set_matches_oracle(q):
 
 def test_velocity_set_rejects_other_q():
     lbm = _lbm()
-    with pytest.raises(lbm.LbmError):
-        lbm.lbm_velocity_set(19)
+    for q in (9, 21, 0):
+        with pytest.raises(lbm.LbmError):
+            lbm.lbm_velocity_set(q)
 
 
 @pytest.mark.parametrize("bad", [
     dict(mobility=0.0), dict(tau_L=0.0), dict(tau_H=-1.0), dict(xi=0.0), dict(phi_H=0.0),
-    dict(rho_L=0.0), dict(storage=7),
+    dict(rho_L=0.0), dict(storage=7), dict(lattice_phase=19, lattice_hydro=27),
+    dict(lattice_phase=21), dict(lattice_hydro=21), dict(lattice_phase=19, lattice_hydro=19, storage="f16s"),
 ])
 def test_workspace_bytes_rejects_bad_parameters(bad):
     lbm = _lbm()

@@ -63,3 +63,11 @@ def test_straightforward_bytes(storage, expect):
     b = perf.bytes_per_cell(storage)
     p = 8 if storage == "f64" else 4
     assert b["straightforward"] == (5 * 42) * p + (1 + 3 + 9 + 3) * p == expect
+
+
+@pytest.mark.parametrize("qp,qh,expect", [(19, 19, 8 * (4 * 19 + 8)), (27, 27, 8 * (4 * 27 + 8)),
+                                          (15, 15, 8 * (4 * 15 + 8))])
+def test_fused_bytes_other_lattices(qp, qh, expect):
+    """Every population of both sets read and written once, u and phi read once
+    and written once (FP64)."""
+    assert perf.bytes_per_cell("f64", qp, qh)["fused"] == expect
