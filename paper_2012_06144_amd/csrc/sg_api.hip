@@ -190,132 +190,182 @@ __global__ void k_weight_mirror(const bf16 *__restrict__ wt, int Co, int Ci, bf1
     wm[((int64_t)(26 - t) * Ci + ci) * Co + co] = wt[i];
 }
 
-// ---- convolution weight gradient ------------------------------------------------
-// dw[t][co][ci] = sum_v dy[v][co] x[v + off(t)][ci]: per tap a GEMM with the
-// voxels as the reduction (M = co, N = ci, K = voxels).  The MFMA operands
-// need 8 consecutive voxels of one channel per lane, while activations are
-// stored channels last, so both are transposed through LDS.
-//
-// A block owns one 32 x 32 (co, ci) tile for all 27 taps and walks a chunk
-// of row tiles: 16 consecutive voxels (n, d, h, w0 .. w0+15) of one W row.
-// Per row tile it stages
-//   dys[co][k]        = dy[n][d][h][w0 + k][co0 + co]
-//   xs[s][r][ci][k]   = x[n][d + a][h + b][w0 + k + s - 1][ci0 + ci]
-// (r = 3 (a+1) + (b+1), s = c+1; zero outside the volume), i.e. the nine
-// neighbouring rows in three w-shifts, so every MFMA operand is one aligned
-// 16-byte LDS read.  Wave w accumulates taps w, w+4, ... in registers; the
-// block's sums go to partial[chunk][t][co][ci], which k_reduce_partials
-// adds over chunks in a fixed order.
-constexpr int kBwTile = 16;    // voxels per row tile (one MFMA K step)
-constexpr int kBwPitch = 24;   // LDS row pitch in bf16 (48 B: conflict-free 16-byte reads)
-constexpr int kBwTargetBlocks = 2048;
+// ---- convolution weight gradient, channel-major operands --------------------------
+// dw[t][co][ci] = sum_v dy[v][co] x[v + off(t)][ci] is, per tap, a GEMM whose
+// reduction runs over the voxels.  The matrix-core operands need 8
+// consecutive voxels of one channel per lane, so x and dy are first copied
+// channel-major, one W row after another with the rows padded with zeros to
+// Wp = a multiple of 16 voxels: xt[c][r][w], r = (n D + d) H + h.  Then every
+// operand is one aligned 16-byte load, and the w offsets -1 and +1 of a tap
+// are two such loads joined by byte alignment.  A block of three waves owns a
+// 32 x 32 (co, ci) tile; wave a holds the nine taps of d offset a - 1 in
+// registers and walks a chunk of 16-voxel steps along the rows: per step one
+// dy operand and, per h offset, three x loads (the step and its two
+// neighbours) serve three taps.  Block sums go to partial[chunk][t][co][ci]
+// (every entry written), added over chunks in a fixed order afterwards.
+constexpr int kBwStep = 16;          // voxels per matrix-core K step
+constexpr int kBwThreads = 192;      // three waves, one per d offset
+constexpr int kBw2TargetBlocks = 1024;
 
-struct BwPlan {
-    int64_t tiles;   // row tiles
-    int ntw;         // row tiles per W row
-    int chunks;      // blocks along the voxels
-    int64_t per;     // row tiles per chunk
-};
-
-// max_chunks bounds the number of per-chunk partial sums (the scratch they
-// take); <= 0 leaves it unbounded.
-BwPlan bw_plan(int n, int d, int h, int w, int ci, int co, int64_t max_chunks = 0)
+// xt[c][r][w] = x[r][w][c] for w < W, 0 for W <= w < Wp (one thread per
+// channel, row and group of 8 voxels; consecutive threads take consecutive
+// channels, so the strided 2-byte reads of a warp cover whole lines)
+__global__ void k_to_channel_major(const bf16 *__restrict__ x, int64_t rows, int W, int Wp, int C,
+                                   bf16 *__restrict__ xt)
 {
-    BwPlan p;
-    p.ntw = (w + kBwTile - 1) / kBwTile;
-    p.tiles = (int64_t)n * d * h * p.ntw;
-    const int64_t mn = (int64_t)(co / 32) * ((ci + 31) / 32);
-    int64_t ch = (kBwTargetBlocks + mn - 1) / mn;
-    if (ch > p.tiles) ch = p.tiles;
-    if (max_chunks > 0 && ch > max_chunks) ch = max_chunks;
-    if (ch < 1) ch = 1;
-    p.per = (p.tiles + ch - 1) / ch;
-    p.chunks = (int)((p.tiles + p.per - 1) / p.per);
-    return p;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int ng = Wp / 8;
+    const int64_t total = rows * ng * C;
+    if (i >= total) return;
+    const int c = (int)(i % C);
+    const int64_t t = i / C;
+    const int g = (int)(t % ng);
+    const int64_t r = t / ng;
+    bf16x8 v;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const int w = g * 8 + e;
+        v[e] = w < W ? x[(r * W + w) * C + c] : (bf16)0.f;
+    }
+    *reinterpret_cast<bf16x8 *>(xt + ((int64_t)c * rows + r) * Wp + g * 8) = v;
 }
 
-__global__ __launch_bounds__(kThreads) void k_conv3d_bwd_weight(const bf16 *__restrict__ x,
-                                                                const bf16 *__restrict__ dy, int N, int D,
-                                                                int H, int W, int Ci, int Co, int ntw,
-                                                                int64_t tiles, int64_t per,
-                                                                float *__restrict__ partial)
+typedef __attribute__((ext_vector_type(4))) unsigned u32x4;
+
+// The 8 voxels starting one before (S = -1) or after (S = +1) the aligned
+// group `cur`; nb is the neighbouring dword: the last two voxels of the
+// group before (S = -1) or the first two of the group after (S = +1).
+template <int S>
+__device__ inline bf16x8 shift_group(const bf16x8 &cur, unsigned nb)
 {
-    __shared__ __attribute__((aligned(16))) bf16 xs[3][9][32][kBwPitch];
-    __shared__ __attribute__((aligned(16))) bf16 dys[32][kBwPitch];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const u32x4 c = __builtin_bit_cast(u32x4, cur);
+    u32x4 r;
+    if constexpr (S > 0) {
+        r[0] = __builtin_amdgcn_alignbyte(c[1], c[0], 2);
+        r[1] = __builtin_amdgcn_alignbyte(c[2], c[1], 2);
+        r[2] = __builtin_amdgcn_alignbyte(c[3], c[2], 2);
+        r[3] = __builtin_amdgcn_alignbyte(nb, c[3], 2);
+    } else {
+        r[0] = __builtin_amdgcn_alignbyte(c[0], nb, 2);
+        r[1] = __builtin_amdgcn_alignbyte(c[1], c[0], 2);
+        r[2] = __builtin_amdgcn_alignbyte(c[2], c[1], 2);
+        r[3] = __builtin_amdgcn_alignbyte(c[3], c[2], 2);
+    }
+    return __builtin_bit_cast(bf16x8, r);
+}
+
+// Operands of one K step of a wave: the dy group, and per h offset the x
+// group with the neighbouring dwords for the w offsets -1 and +1.
+struct BwOperands {
+    bf16x8 av;
+    bf16x8 cur[3];
+    unsigned prev[3], next[3];
+};
+
+__global__ __launch_bounds__(kBwThreads) void k_conv3d_bwd_weight_cm(const bf16 *__restrict__ xt,
+                                                                    const bf16 *__restrict__ dyt, int N, int D,
+                                                                    int H, int Wp, int Ci, int Co, int64_t steps,
+                                                                    int64_t per, float *__restrict__ partial)
+{
+    const int lane = threadIdx.x & 63, a = threadIdx.x >> 6;  // wave = d offset + 1
     const int chunk = blockIdx.x;
     const int co0 = blockIdx.y * 32, ci0 = blockIdx.z * 32;
-    const int ntap = wave < 3 ? 7 : 6;  // taps wave, wave + 4, ...
-    f32x16 acc[7];
+    const int64_t R = (int64_t)N * D * H;
+    const int nws = Wp / kBwStep;
+    const int lr = lane & 31, half = lane >> 5;
+    const bool ci_ok = ci0 + lr < Ci;
+    const bf16 *dyc = dyt + (int64_t)(co0 + lr) * R * Wp + 8 * half;
+    const bf16 *xc = xt + (int64_t)(ci_ok ? ci0 + lr : 0) * R * Wp + 8 * half;
+    f32x16 acc[9];
 #pragma unroll
-    for (int j = 0; j < 7; ++j)
-        for (int r = 0; r < 16; ++r) acc[j][r] = 0.f;
-    const int64_t tbeg = (int64_t)chunk * per;
-    const int64_t tend = tbeg + per < tiles ? tbeg + per : tiles;
-    const int kh = (lane >> 5) * 8;
+    for (int k = 0; k < 9; ++k)
+        for (int r = 0; r < 16; ++r) acc[k][r] = 0.f;
+    const int64_t sbeg = (int64_t)chunk * per;
+    const int64_t send = sbeg + per < steps ? sbeg + per : steps;
+    if (sbeg >= send) return;
 
-    for (int64_t rt = tbeg; rt < tend; ++rt) {
-        const int wt = (int)(rt % ntw);
-        int64_t row = rt / ntw;  // (n D + d) H + h
-        const int h = (int)(row % H);
-        row /= H;
-        const int d = (int)(row % D);
-        const int n = (int)(row / D);
-        const int w0 = wt * kBwTile;
-        // x: 9 rows x (kBwTile + 2) voxels x 4 groups of 8 channels
-        for (int item = threadIdx.x; item < 9 * (kBwTile + 2) * 4; item += kThreads) {
-            const int cg = item & 3;
-            const int wv = (item >> 2) % (kBwTile + 2);
-            const int r = (item >> 2) / (kBwTile + 2);
-            const int dd = d + r / 3 - 1, hh = h + r % 3 - 1, ww = w0 - 1 + wv;
-            const int cc = ci0 + cg * 8;
-            bf16x8 v = {};
-            if (dd >= 0 && dd < D && hh >= 0 && hh < H && ww >= 0 && ww < W && cc < Ci)
-                v = *reinterpret_cast<const bf16x8 *>(x + ((((int64_t)n * D + dd) * H + hh) * W + ww) * Ci + cc);
+    // operands of the step at (ws, row = (n D + d) H + h)
+    auto load = [&](int ws, int64_t row, int h, int d, BwOperands &o) {
+        o.av = *reinterpret_cast<const bf16x8 *>(dyc + row * Wp + ws * kBwStep);
+        const int w = ws * kBwStep + 8 * half;  // this lane's first voxel
+        const int dd = d + a - 1;
+        const bool dok = dd >= 0 && dd < D && ci_ok;
 #pragma unroll
-            for (int sft = 0; sft < 3; ++sft) {
-                const int k = wv - sft;  // w = w0 + k + sft - 1
-                if (k >= 0 && k < kBwTile) {
-#pragma unroll
-                    for (int e = 0; e < 8; ++e) xs[sft][r][cg * 8 + e][k] = v[e];
-                }
+        for (int b = 0; b < 3; ++b) {
+            const int hh = h + b - 1;
+            o.cur[b] = bf16x8{};
+            o.prev[b] = 0u;
+            o.next[b] = 0u;
+            if (dok && hh >= 0 && hh < H) {
+                const bf16 *xr = xc + (row + (int64_t)(a - 1) * H + (b - 1)) * Wp + ws * kBwStep;
+                o.cur[b] = *reinterpret_cast<const bf16x8 *>(xr);
+                if (w > 0) o.prev[b] = *reinterpret_cast<const unsigned *>(xr - 2);
+                if (w + 8 < Wp) o.next[b] = *reinterpret_cast<const unsigned *>(xr + 8);
             }
         }
-        // dy: kBwTile voxels x 4 groups of 8 channels
-        if (threadIdx.x < kBwTile * 4) {
-            const int cg = threadIdx.x & 3, k = threadIdx.x >> 2;
-            const int ww = w0 + k;
-            bf16x8 v = {};
-            if (ww < W) v = *reinterpret_cast<const bf16x8 *>(dy + ((((int64_t)n * D + d) * H + h) * W + ww) * Co + co0 + cg * 8);
-#pragma unroll
-            for (int e = 0; e < 8; ++e) dys[cg * 8 + e][k] = v[e];
-        }
-        __syncthreads();
-        const bf16x8 av = *reinterpret_cast<const bf16x8 *>(&dys[lane & 31][kh]);
-#pragma unroll
-        for (int j = 0; j < 7; ++j) {
-            if (j < ntap) {
-                const int t = wave + 4 * j;
-                const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(&xs[t % 3][t / 3][lane & 31][kh]);
-                acc[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc[j], 0, 0, 0);
+    };
+
+    // position of the first step; later ones are advanced incrementally
+    int ws = (int)(sbeg % nws);
+    int64_t row = sbeg / nws;
+    int h = (int)(row % H);
+    int d = (int)((row / H) % D);
+    BwOperands cur, nxt;
+    load(ws, row, h, d, cur);
+    for (int64_t st = sbeg; st < send; ++st) {
+        if (++ws == nws) {
+            ws = 0;
+            ++row;
+            if (++h == H) {
+                h = 0;
+                if (++d == D) d = 0;
             }
         }
-        __syncthreads();
+        // the next step's loads are in flight during this step's products
+        if (st + 1 < send) load(ws, row, h, d, nxt);
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            const bf16x8 bm = shift_group<-1>(cur.cur[b], cur.prev[b]);
+            const bf16x8 bp = shift_group<1>(cur.cur[b], cur.next[b]);
+            acc[3 * b + 0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(cur.av, bm, acc[3 * b + 0], 0, 0, 0);
+            acc[3 * b + 1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(cur.av, cur.cur[b], acc[3 * b + 1], 0, 0, 0);
+            acc[3 * b + 2] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(cur.av, bp, acc[3 * b + 2], 0, 0, 0);
+        }
+        cur = nxt;
     }
     // D layout of the 32x32 tile: column l % 32 (ci), row 8 (r/4) + 4 (l/32) + r % 4 (co)
-    const int col = lane & 31;
-    if (ci0 + col >= Ci) return;
+    if (!ci_ok) return;
 #pragma unroll
-    for (int j = 0; j < 7; ++j) {
-        if (j < ntap) {
-            const int t = wave + 4 * j;
+    for (int k = 0; k < 9; ++k) {
+        const int t = a * 9 + k;
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int rowc = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-                partial[(((int64_t)chunk * 27 + t) * Co + co0 + rowc) * Ci + ci0 + col] = acc[j][r];
-            }
+        for (int r = 0; r < 16; ++r) {
+            const int rowc = 8 * (r >> 2) + 4 * half + (r & 3);
+            partial[(((int64_t)chunk * 27 + t) * Co + co0 + rowc) * Ci + ci0 + lr] = acc[k][r];
         }
     }
+}
+
+// db[co] = sum over rows and w of dyt[co][r][w] (padding zeros add nothing):
+// one block per channel and chunk of the channel's plane, fixed order
+__global__ __launch_bounds__(kThreads) void k_bias_grad_cm(const bf16 *__restrict__ dyt, int64_t plane,
+                                                           int64_t per, float *__restrict__ partial, int nchunk)
+{
+    __shared__ float s[kThreads];
+    const int chunk = blockIdx.x, co = blockIdx.y;
+    const int64_t beg = (int64_t)chunk * per;
+    const int64_t end = beg + per < plane ? beg + per : plane;
+    const bf16 *p = dyt + (int64_t)co * plane;
+    float acc = 0.f;
+    for (int64_t i = beg + threadIdx.x; i < end; i += kThreads) acc += (float)p[i];
+    s[threadIdx.x] = acc;
+    __syncthreads();
+    for (int k = kThreads / 2; k > 0; k >>= 1) {
+        if (threadIdx.x < k) s[threadIdx.x] += s[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[(int64_t)chunk * gridDim.y + co] = s[0];
+    (void)nchunk;
 }
 
 __global__ void k_reduce_partials(const float *__restrict__ partial, int nchunk, int64_t stride,
@@ -326,28 +376,6 @@ __global__ void k_reduce_partials(const float *__restrict__ partial, int nchunk,
     float s = 0.f;
     for (int k = 0; k < nchunk; ++k) s += partial[(int64_t)k * stride + i];
     out[i] = s;
-}
-
-// db[co] = sum_v dy[v][co]: one block per 32 channels x chunk of kBiasChunk
-// voxels, fixed order
-constexpr int kBiasChunk = 16384;
-__global__ __launch_bounds__(kThreads) void k_bias_grad_partial(const bf16 *__restrict__ dy, int64_t V, int Co,
-                                                                float *__restrict__ partial)
-{
-    __shared__ float s[kThreads];
-    const int chunk = blockIdx.x;
-    const int co = blockIdx.y;
-    const int64_t vbeg = (int64_t)chunk * kBiasChunk;
-    const int64_t vend = vbeg + kBiasChunk < V ? vbeg + kBiasChunk : V;
-    float acc = 0.f;
-    for (int64_t v = vbeg + threadIdx.x; v < vend; v += kThreads) acc += (float)dy[v * Co + co];
-    s[threadIdx.x] = acc;
-    __syncthreads();
-    for (int k = kThreads / 2; k > 0; k >>= 1) {
-        if (threadIdx.x < k) s[threadIdx.x] += s[threadIdx.x + k];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) partial[(int64_t)chunk * Co + co] = s[0];
 }
 
 // ---- elementwise and resampling ----------------------------------------------------
@@ -465,6 +493,142 @@ __global__ void k_split(const bf16 *__restrict__ y, int ca, int cb, int64_t V, b
     } else {
         if (b) b[v * cb + (c - ca)] = y[i];
     }
+}
+
+// ---- the same elementwise and resampling kernels on groups of 8 channels ------------
+// One thread per voxel and group of 8 channels (16-byte loads and stores),
+// for channel counts that are multiples of 8 and 16-byte aligned tensors;
+// per element the arithmetic and its order are those of the kernels above.
+struct Vox {
+    int n, d, h, w;
+};
+
+__device__ inline Vox vox_of(int64_t v, int D, int H, int W)
+{
+    Vox r;
+    r.w = (int)(v % W);
+    v /= W;
+    r.h = (int)(v % H);
+    v /= H;
+    r.d = (int)(v % D);
+    r.n = (int)(v / D);
+    return r;
+}
+
+__global__ void k_pool2_fwd8(const bf16x8 *__restrict__ x, int N, int D, int H, int W, int C8, bf16x8 *__restrict__ y)
+{
+    const int D2 = D / 2, H2 = H / 2, W2 = W / 2;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)N * D2 * H2 * W2 * C8) return;
+    const int g = (int)(i % C8);
+    const Vox o = vox_of(i / C8, D2, H2, W2);
+    float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b)
+            for (int e = 0; e < 2; ++e) {
+                const bf16x8 v = x[((((int64_t)o.n * D + 2 * o.d + a) * H + 2 * o.h + b) * W + 2 * o.w + e) * C8 + g];
+#pragma unroll
+                for (int k = 0; k < 8; ++k) s[k] += (float)v[k];
+            }
+    bf16x8 r;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) r[k] = (bf16)(s[k] * 0.125f);
+    y[i] = r;
+}
+
+__global__ void k_pool2_bwd8(const bf16x8 *__restrict__ dy, int N, int D, int H, int W, int C8, bf16x8 *__restrict__ dx)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)N * D * H * W * C8) return;
+    const int g = (int)(i % C8);
+    const Vox o = vox_of(i / C8, D, H, W);
+    const bf16x8 v = dy[((((int64_t)o.n * (D / 2) + o.d / 2) * (H / 2) + o.h / 2) * (W / 2) + o.w / 2) * C8 + g];
+    bf16x8 r;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) r[k] = (bf16)((float)v[k] * 0.125f);
+    dx[i] = r;
+}
+
+__global__ void k_up2_fwd8(const bf16x8 *__restrict__ x, int N, int D, int H, int W, int C8, bf16x8 *__restrict__ y)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)N * 8 * D * H * W * C8) return;
+    const int g = (int)(i % C8);
+    const Vox o = vox_of(i / C8, 2 * D, 2 * H, 2 * W);
+    y[i] = x[((((int64_t)o.n * D + o.d / 2) * H + o.h / 2) * W + o.w / 2) * C8 + g];
+}
+
+__global__ void k_up2_bwd8(const bf16x8 *__restrict__ dy, int N, int D, int H, int W, int C8, bf16x8 *__restrict__ dx)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)N * D * H * W * C8) return;
+    const int g = (int)(i % C8);
+    const Vox o = vox_of(i / C8, D, H, W);
+    const int D2 = 2 * D, H2 = 2 * H, W2 = 2 * W;
+    float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b)
+            for (int e = 0; e < 2; ++e) {
+                const bf16x8 v = dy[((((int64_t)o.n * D2 + 2 * o.d + a) * H2 + 2 * o.h + b) * W2 + 2 * o.w + e) * C8 + g];
+#pragma unroll
+                for (int k = 0; k < 8; ++k) s[k] += (float)v[k];
+            }
+    bf16x8 r;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) r[k] = (bf16)s[k];
+    dx[i] = r;
+}
+
+__global__ void k_concat8(const bf16x8 *__restrict__ a, int ca8, const bf16x8 *__restrict__ b, int cb8, int64_t V,
+                          bf16x8 *__restrict__ y)
+{
+    const int cc = ca8 + cb8;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= V * cc) return;
+    const int64_t v = i / cc;
+    const int c = (int)(i % cc);
+    y[i] = c < ca8 ? a[v * ca8 + c] : b[v * cb8 + (c - ca8)];
+}
+
+__global__ void k_split8(const bf16x8 *__restrict__ y, int ca8, int cb8, int64_t V, bf16x8 *__restrict__ a,
+                         bf16x8 *__restrict__ b)
+{
+    const int cc = ca8 + cb8;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= V * cc) return;
+    const int64_t v = i / cc;
+    const int c = (int)(i % cc);
+    if (c < ca8) {
+        if (a) a[v * ca8 + c] = y[i];
+    } else {
+        if (b) b[v * cb8 + (c - ca8)] = y[i];
+    }
+}
+
+__global__ void k_add8(const bf16x8 *__restrict__ a, const bf16x8 *__restrict__ b, bf16x8 *__restrict__ y, int64_t n8)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n8) return;
+    const bf16x8 x = a[i], z = b[i];
+    bf16x8 r;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) r[k] = (bf16)((float)x[k] + (float)z[k]);
+    y[i] = r;
+}
+
+__global__ void k_leaky_bwd8(const bf16x8 *__restrict__ y, const bf16x8 *__restrict__ dy, bf16x8 *__restrict__ dp,
+                             int64_t n8, float slope)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n8) return;
+    const bf16x8 yv = y[i], g = dy[i];
+    bf16x8 r;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const float gk = (float)g[k];
+        r[k] = (bf16)((float)yv[k] > 0.f ? gk : slope * gk);
+    }
+    dp[i] = r;
 }
 
 // MSE: per-block partial sums (fixed order), second pass sums them
@@ -895,28 +1059,77 @@ sg_status check_bwd_weight_args(const void *x, const void *dy, int n, int d, int
     return SG_OK;
 }
 
-// Weight and bias gradient through the scratch `ws`: per-chunk partial sums
-// part[chunk][t][co][ci] (every entry written before it is read), then a
-// fixed-order sum over chunks; bias partials behind them.
-sg_status launch_bwd_weight(const void *x, const void *dy, int n, int d, int h, int w, int c_in, int c_out,
-                            float *dw, float *db, const BwPlan &p, float *ws, hipStream_t s)
+// Launch plan of the weight gradient: W rows padded to Wp voxels, K steps of
+// kBwStep voxels split into `chunks` consecutive ranges of `per` steps (about
+// kBw2TargetBlocks blocks over the (co, ci) tiles); the bias sums split each
+// channel's plane into nb ranges.  Scratch layout: per-chunk partial sums,
+// bias partials, then the channel-major copies of x and dy.
+struct BwPlan {
+    int Wp;
+    int64_t R;       // rows N D H
+    int64_t steps;   // K steps
+    int chunks;
+    int64_t per;
+    int nb;          // bias ranges per channel
+    int64_t bper;
+    size_t off_bpart, off_xt, off_dyt, bytes;
+};
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+BwPlan bw_plan(int n, int d, int h, int w, int ci, int co)
 {
-    const int64_t V = (int64_t)n * d * h * w;
-    float *part = ws;
-    float *bpart = part + (int64_t)p.chunks * 27 * c_in * c_out;
+    BwPlan p;
+    p.Wp = (w + kBwStep - 1) / kBwStep * kBwStep;
+    p.R = (int64_t)n * d * h;
+    p.steps = p.R * (p.Wp / kBwStep);
+    const int64_t mn = (int64_t)(co / 32) * ((ci + 31) / 32);
+    int64_t ch = (kBw2TargetBlocks + mn - 1) / mn;
+    if (ch > p.steps) ch = p.steps;
+    if (ch < 1) ch = 1;
+    p.per = (p.steps + ch - 1) / ch;
+    p.chunks = (int)((p.steps + p.per - 1) / p.per);
+    const int64_t plane = p.R * p.Wp;
+    int64_t nb = plane / 8192;
+    nb = nb < 1 ? 1 : (nb > 256 ? 256 : nb);
+    p.bper = (plane + nb - 1) / nb;
+    p.nb = (int)((plane + p.bper - 1) / p.bper);
+    p.off_bpart = align_up((size_t)p.chunks * 27 * ci * co * sizeof(float), 256);
+    p.off_xt = p.off_bpart + align_up((size_t)p.nb * co * sizeof(float), 256);
+    p.off_dyt = p.off_xt + align_up((size_t)ci * plane * sizeof(bf16), 256);
+    p.bytes = p.off_dyt + align_up((size_t)co * plane * sizeof(bf16), 256);
+    return p;
+}
+
+// Weight and bias gradient through the scratch `ws` (every entry written
+// before it is read): channel-major copies of x and dy, per-chunk partial
+// sums part[chunk][t][co][ci], then a fixed-order sum over chunks.
+sg_status launch_bwd_weight(const void *x, const void *dy, int n, int d, int h, int w, int c_in, int c_out,
+                            float *dw, float *db, const BwPlan &p, char *ws, hipStream_t s)
+{
+    float *part = (float *)ws;
+    float *bpart = (float *)(ws + p.off_bpart);
+    bf16 *xt = (bf16 *)(ws + p.off_xt);
+    bf16 *dyt = (bf16 *)(ws + p.off_dyt);
+    const int64_t ng = p.R * (p.Wp / 8);
+    hipLaunchKernelGGL(k_to_channel_major, dim3(blocks_for(ng * c_in)), dim3(kThreads), 0, s, (const bf16 *)x,
+                       p.R, w, p.Wp, c_in, xt);
+    SG_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_to_channel_major, dim3(blocks_for(ng * c_out)), dim3(kThreads), 0, s, (const bf16 *)dy,
+                       p.R, w, p.Wp, c_out, dyt);
+    SG_LAUNCH_CHECK();
     const dim3 grid((unsigned)p.chunks, (unsigned)(c_out / 32), (unsigned)((c_in + 31) / 32));
-    hipLaunchKernelGGL(k_conv3d_bwd_weight, grid, dim3(kThreads), 0, s, (const bf16 *)x, (const bf16 *)dy, n, d,
-                       h, w, c_in, c_out, p.ntw, p.tiles, p.per, part);
+    hipLaunchKernelGGL(k_conv3d_bwd_weight_cm, grid, dim3(kBwThreads), 0, s, xt, dyt, n, d, h, p.Wp, c_in, c_out,
+                       p.steps, p.per, part);
     SG_LAUNCH_CHECK();
     const int64_t stride = (int64_t)27 * c_in * c_out;
     hipLaunchKernelGGL(k_reduce_partials, dim3(blocks_for(stride)), dim3(kThreads), 0, s, part, p.chunks, stride, dw);
     SG_LAUNCH_CHECK();
     if (db) {
-        const int nb = (int)((V + kBiasChunk - 1) / kBiasChunk);
-        hipLaunchKernelGGL(k_bias_grad_partial, dim3((unsigned)nb, (unsigned)c_out), dim3(kThreads), 0, s,
-                           (const bf16 *)dy, V, c_out, bpart);
+        hipLaunchKernelGGL(k_bias_grad_cm, dim3((unsigned)p.nb, (unsigned)c_out), dim3(kThreads), 0, s, dyt,
+                           p.R * p.Wp, p.bper, bpart, p.nb);
         SG_LAUNCH_CHECK();
-        hipLaunchKernelGGL(k_reduce_partials, dim3(blocks_for(c_out)), dim3(kThreads), 0, s, bpart, nb,
+        hipLaunchKernelGGL(k_reduce_partials, dim3(blocks_for(c_out)), dim3(kThreads), 0, s, bpart, p.nb,
                            (int64_t)c_out, db);
         SG_LAUNCH_CHECK();
     }
@@ -1022,10 +1235,7 @@ sg_status sg_conv3d_bwd_data(const void *dy, int32_t n, int32_t d, int32_t h, in
 size_t sg_bwd_weight_workspace(int32_t n, int32_t d, int32_t h, int32_t w, int32_t c_in, int32_t c_out)
 {
     if (n < 1 || d < 1 || h < 1 || w < 1 || c_in < 1 || c_out < 32) return 0;
-    const BwPlan p = bw_plan(n, d, h, w, c_in, c_out);
-    const int64_t V = (int64_t)n * d * h * w;
-    const int64_t nb = (V + kBiasChunk - 1) / kBiasChunk;
-    return ((size_t)p.chunks * 27 * (size_t)c_in * c_out + (size_t)nb * c_out) * sizeof(float);
+    return bw_plan(n, d, h, w, c_in, c_out).bytes;
 }
 
 sg_status sg_conv3d_bwd_weight(const void *x, const void *dy, int32_t n, int32_t d, int32_t h, int32_t w,
@@ -1037,15 +1247,20 @@ sg_status sg_conv3d_bwd_weight(const void *x, const void *dy, int32_t n, int32_t
     if (!ws) return fail(SG_EARG, "NULL workspace");
     const size_t need = sg_bwd_weight_workspace(n, d, h, w, c_in, c_out);
     if (ws_bytes < need) return fail(SG_ESIZE, "workspace has %zu bytes, needs %zu", ws_bytes, need);
+    if (!aligned16(ws)) return fail(SG_EARG, "workspace must be 16-byte aligned");
     const BwPlan p = bw_plan(n, d, h, w, c_in, c_out);
-    return launch_bwd_weight(x, dy, n, d, h, w, c_in, c_out, dw, db, p, (float *)ws, (hipStream_t)stream);
+    return launch_bwd_weight(x, dy, n, d, h, w, c_in, c_out, dw, db, p, (char *)ws, (hipStream_t)stream);
 }
 
 sg_status sg_leaky_bwd(const void *y, const void *dy, void *dp, size_t count, float slope, void *stream)
 {
     if (!y || !dy || !dp) return fail(SG_EARG, "NULL tensor");
-    hipLaunchKernelGGL(k_leaky_bwd, dim3(blocks_for((int64_t)count)), dim3(kThreads), 0, (hipStream_t)stream,
-                       (const bf16 *)y, (const bf16 *)dy, (bf16 *)dp, (int64_t)count, slope);
+    if (count % 8 == 0 && aligned16(y) && aligned16(dy) && aligned16(dp))
+        hipLaunchKernelGGL(k_leaky_bwd8, dim3(blocks_for((int64_t)count / 8)), dim3(kThreads), 0, (hipStream_t)stream,
+                           (const bf16x8 *)y, (const bf16x8 *)dy, (bf16x8 *)dp, (int64_t)count / 8, slope);
+    else
+        hipLaunchKernelGGL(k_leaky_bwd, dim3(blocks_for((int64_t)count)), dim3(kThreads), 0, (hipStream_t)stream,
+                           (const bf16 *)y, (const bf16 *)dy, (bf16 *)dp, (int64_t)count, slope);
     SG_LAUNCH_CHECK();
     return SG_OK;
 }
@@ -1054,8 +1269,12 @@ sg_status sg_pool2_fwd(const void *x, int32_t n, int32_t d, int32_t h, int32_t w
 {
     if (!x || !y || d % 2 || h % 2 || w % 2) return fail(SG_EARG, "pool2 needs even d, h, w");
     const int64_t total = (int64_t)n * (d / 2) * (h / 2) * (w / 2) * c;
-    hipLaunchKernelGGL(k_pool2_fwd, dim3(blocks_for(total)), dim3(kThreads), 0, (hipStream_t)stream,
-                       (const bf16 *)x, n, d, h, w, c, (bf16 *)y);
+    if (c % 8 == 0 && aligned16(x) && aligned16(y))
+        hipLaunchKernelGGL(k_pool2_fwd8, dim3(blocks_for(total / 8)), dim3(kThreads), 0, (hipStream_t)stream,
+                           (const bf16x8 *)x, n, d, h, w, c / 8, (bf16x8 *)y);
+    else
+        hipLaunchKernelGGL(k_pool2_fwd, dim3(blocks_for(total)), dim3(kThreads), 0, (hipStream_t)stream,
+                           (const bf16 *)x, n, d, h, w, c, (bf16 *)y);
     SG_LAUNCH_CHECK();
     return SG_OK;
 }
@@ -1064,8 +1283,12 @@ sg_status sg_pool2_bwd(const void *dy, int32_t n, int32_t d, int32_t h, int32_t 
 {
     if (!dy || !dx || d % 2 || h % 2 || w % 2) return fail(SG_EARG, "pool2 needs even d, h, w");
     const int64_t total = (int64_t)n * d * h * w * c;
-    hipLaunchKernelGGL(k_pool2_bwd, dim3(blocks_for(total)), dim3(kThreads), 0, (hipStream_t)stream,
-                       (const bf16 *)dy, n, d, h, w, c, (bf16 *)dx);
+    if (c % 8 == 0 && aligned16(dy) && aligned16(dx))
+        hipLaunchKernelGGL(k_pool2_bwd8, dim3(blocks_for(total / 8)), dim3(kThreads), 0, (hipStream_t)stream,
+                           (const bf16x8 *)dy, n, d, h, w, c / 8, (bf16x8 *)dx);
+    else
+        hipLaunchKernelGGL(k_pool2_bwd, dim3(blocks_for(total)), dim3(kThreads), 0, (hipStream_t)stream,
+                           (const bf16 *)dy, n, d, h, w, c, (bf16 *)dx);
     SG_LAUNCH_CHECK();
     return SG_OK;
 }
@@ -1074,8 +1297,12 @@ sg_status sg_up2_fwd(const void *x, int32_t n, int32_t d, int32_t h, int32_t w, 
 {
     if (!x || !y) return fail(SG_EARG, "NULL tensor");
     const int64_t total = (int64_t)n * 8 * d * h * w * c;
-    hipLaunchKernelGGL(k_up2_fwd, dim3(blocks_for(total)), dim3(kThreads), 0, (hipStream_t)stream,
-                       (const bf16 *)x, n, d, h, w, c, (bf16 *)y);
+    if (c % 8 == 0 && aligned16(x) && aligned16(y))
+        hipLaunchKernelGGL(k_up2_fwd8, dim3(blocks_for(total / 8)), dim3(kThreads), 0, (hipStream_t)stream,
+                           (const bf16x8 *)x, n, d, h, w, c / 8, (bf16x8 *)y);
+    else
+        hipLaunchKernelGGL(k_up2_fwd, dim3(blocks_for(total)), dim3(kThreads), 0, (hipStream_t)stream,
+                           (const bf16 *)x, n, d, h, w, c, (bf16 *)y);
     SG_LAUNCH_CHECK();
     return SG_OK;
 }
@@ -1084,8 +1311,12 @@ sg_status sg_up2_bwd(const void *dy, int32_t n, int32_t d, int32_t h, int32_t w,
 {
     if (!dy || !dx) return fail(SG_EARG, "NULL tensor");
     const int64_t total = (int64_t)n * d * h * w * c;
-    hipLaunchKernelGGL(k_up2_bwd, dim3(blocks_for(total)), dim3(kThreads), 0, (hipStream_t)stream,
-                       (const bf16 *)dy, n, d, h, w, c, (bf16 *)dx);
+    if (c % 8 == 0 && aligned16(dy) && aligned16(dx))
+        hipLaunchKernelGGL(k_up2_bwd8, dim3(blocks_for(total / 8)), dim3(kThreads), 0, (hipStream_t)stream,
+                           (const bf16x8 *)dy, n, d, h, w, c / 8, (bf16x8 *)dx);
+    else
+        hipLaunchKernelGGL(k_up2_bwd, dim3(blocks_for(total)), dim3(kThreads), 0, (hipStream_t)stream,
+                           (const bf16 *)dy, n, d, h, w, c, (bf16 *)dx);
     SG_LAUNCH_CHECK();
     return SG_OK;
 }
@@ -1093,8 +1324,12 @@ sg_status sg_up2_bwd(const void *dy, int32_t n, int32_t d, int32_t h, int32_t w,
 sg_status sg_concat(const void *a, int32_t ca, const void *b, int32_t cb, int64_t V, void *y, void *stream)
 {
     if (!a || !b || !y) return fail(SG_EARG, "NULL tensor");
-    hipLaunchKernelGGL(k_concat, dim3(blocks_for(V * (ca + cb))), dim3(kThreads), 0, (hipStream_t)stream,
-                       (const bf16 *)a, ca, (const bf16 *)b, cb, V, (bf16 *)y);
+    if (ca % 8 == 0 && cb % 8 == 0 && aligned16(a) && aligned16(b) && aligned16(y))
+        hipLaunchKernelGGL(k_concat8, dim3(blocks_for(V * (ca + cb) / 8)), dim3(kThreads), 0, (hipStream_t)stream,
+                           (const bf16x8 *)a, ca / 8, (const bf16x8 *)b, cb / 8, V, (bf16x8 *)y);
+    else
+        hipLaunchKernelGGL(k_concat, dim3(blocks_for(V * (ca + cb))), dim3(kThreads), 0, (hipStream_t)stream,
+                           (const bf16 *)a, ca, (const bf16 *)b, cb, V, (bf16 *)y);
     SG_LAUNCH_CHECK();
     return SG_OK;
 }
@@ -1102,8 +1337,12 @@ sg_status sg_concat(const void *a, int32_t ca, const void *b, int32_t cb, int64_
 sg_status sg_split(const void *y, int32_t ca, int32_t cb, int64_t V, void *a, void *b, void *stream)
 {
     if (!y) return fail(SG_EARG, "NULL tensor");
-    hipLaunchKernelGGL(k_split, dim3(blocks_for(V * (ca + cb))), dim3(kThreads), 0, (hipStream_t)stream,
-                       (const bf16 *)y, ca, cb, V, (bf16 *)a, (bf16 *)b);
+    if (ca % 8 == 0 && cb % 8 == 0 && aligned16(y) && aligned16(a) && aligned16(b))
+        hipLaunchKernelGGL(k_split8, dim3(blocks_for(V * (ca + cb) / 8)), dim3(kThreads), 0, (hipStream_t)stream,
+                           (const bf16x8 *)y, ca / 8, cb / 8, V, (bf16x8 *)a, (bf16x8 *)b);
+    else
+        hipLaunchKernelGGL(k_split, dim3(blocks_for(V * (ca + cb))), dim3(kThreads), 0, (hipStream_t)stream,
+                           (const bf16 *)y, ca, cb, V, (bf16 *)a, (bf16 *)b);
     SG_LAUNCH_CHECK();
     return SG_OK;
 }
@@ -1150,8 +1389,12 @@ sg_status sg_to_f32(const void *x, float *y, int64_t count, void *stream)
 sg_status sg_add(const void *a, const void *b, void *y, int64_t count, void *stream)
 {
     if (!a || !b || !y) return fail(SG_EARG, "NULL tensor");
-    hipLaunchKernelGGL(k_add, dim3(blocks_for(count)), dim3(kThreads), 0, (hipStream_t)stream, (const bf16 *)a,
-                       (const bf16 *)b, (bf16 *)y, count);
+    if (count % 8 == 0 && aligned16(a) && aligned16(b) && aligned16(y))
+        hipLaunchKernelGGL(k_add8, dim3(blocks_for(count / 8)), dim3(kThreads), 0, (hipStream_t)stream,
+                           (const bf16x8 *)a, (const bf16x8 *)b, (bf16x8 *)y, count / 8);
+    else
+        hipLaunchKernelGGL(k_add, dim3(blocks_for(count)), dim3(kThreads), 0, (hipStream_t)stream, (const bf16 *)a,
+                           (const bf16 *)b, (bf16 *)y, count);
     SG_LAUNCH_CHECK();
     return SG_OK;
 }

@@ -94,10 +94,12 @@ def test_conv3d_input_gradient(env, case):
 
 @pytest.mark.parametrize("case", [
     (1, 4, 6, 8, 16, 32), (2, 5, 6, 7, 32, 64), (1, 4, 4, 4, 96, 32),
-    # the launch plans of full-size layers: several 16-voxel row tiles per W
-    # row (W > 16, ragged last tile) and several row tiles per block, here 2
-    # per block with 3 tiles per row, and 3 per block with a ragged last chunk
+    # the launch plans of full-size layers: W rows padded to whole 16-voxel
+    # steps (W = 40 -> 48, W = 21 -> 32), several steps per block (3 and 5
+    # here), several (co, ci) tiles, wall-to-wall zero padding in d and h
     (1, 4, 8, 40, 128, 256), (1, 5, 13, 21, 128, 256),
+    # more K steps (2025) than the plan's blocks: 2 steps per block, a last block with one
+    (3, 15, 15, 40, 32, 32),
 ])
 def test_conv3d_weight_gradient(env, case):
     torch, sg = env
