@@ -138,6 +138,30 @@ def surrogate_jump_bubble(steps: int = 40000) -> Setup:
     return s
 
 
+def drag_bubble(re_gr: float, eo: float = 30.0, D: float = 32.0, t_ref: float = 2000.0,
+                grid=(256, 1024, 256), center=None) -> Setup:
+    """The paper's single rising bubble for the drag coefficient (Sec. 6.1):
+    256 x 1024 x 256 with walls at y = 0 and 1023, D = 32 at (128, 256, 128),
+    density ratio 1000 and viscosity ratio 100, xi = 5, M = 0.04.  The
+    dimensionless groups fix the lattice parameters once the reference time
+    t_ref = sqrt(D/g) (in steps) is chosen: g = D / t_ref^2,
+    Eo = g rho_H D^2 / sigma gives sigma, Re_Gr = rho_H sqrt(g D^3) / mu_H gives
+    mu_H, and mu_L = mu_H / 100, rho_L = rho_H / 1000."""
+    nx, ny, nz = grid
+    rho_H, rho_L = 1.0, 1e-3
+    g = D / (t_ref * t_ref)
+    sigma = g * rho_H * D * D / eo
+    mu_H = rho_H * np.sqrt(g * D ** 3) / re_gr
+    mu_L = mu_H / 100.0
+    c = center if center is not None else (nx / 2.0, ny / 4.0, nz / 2.0)
+    s = Setup(name=f"drag_bubble_{nx}x{ny}x{nz}_Eo{eo:g}_Re{re_gr:g}", nx=nx, ny=ny, nz=nz, walls_y=True,
+              xi=5.0, mobility=0.04, sigma=sigma, rho_L=rho_L, rho_H=rho_H,
+              tau_L=tau_from_dynamic_viscosity(mu_L, rho_L), tau_H=tau_from_dynamic_viscosity(mu_H, rho_H),
+              accel=(0.0, -g, 0.0), buoyancy_rho_ref=rho_H, steps=int(round(10 * t_ref)), kind="bubble",
+              radius=D / 2.0, center=tuple(c))
+    return s
+
+
 def paper_benchmark_bubble(n: int = 260) -> Setup:
     """The paper's single-GPU benchmark: n^3 periodic, gas bubble R = 65 in
     the middle, rho 1 / 0.001, M = 0.02, xi = 5, sigma = 1e-4, tau = 0.03, no

@@ -7,6 +7,12 @@ and on the bubble swarm (phase field after N steps, mass drift).
 
     python -m paper_2012_06144_amd.studies rising --steps 20000 --out rising.json
     python -m paper_2012_06144_amd.studies swarm --steps 2000 --out swarm.json
+
+The drag study (Sec. 6.1): the single rising bubble at Eo = 30 for several
+gravity Reynolds numbers; the terminal velocity gives C_D^LBM, compared with
+the Bhaga-Weber correlation.
+
+    python -m paper_2012_06144_amd.studies drag --re 10,20,30,60 --out drag.json
 """
 from __future__ import annotations
 
@@ -154,9 +160,73 @@ def _first_nonfinite_step(s, phi, u, ps, st, steps, chunk=100):
         torch.cuda.empty_cache()
 
 
+def drag_coefficient_lbm(g: float, rho_H: float, rho_L: float, D: float, u_t: float) -> float:
+    """C_D from the terminal velocity (Sec. 6.1): 4/3 g (rho_H - rho_L) D / (rho_H u_t^2)."""
+    return 4.0 / 3.0 * g * (rho_H - rho_L) * D / (rho_H * u_t * u_t)
+
+
+def drag_coefficient_bhaga_weber(re: float) -> float:
+    """Bhaga and Weber's correlation as printed (eq. analytical_drag_coeff):
+    [2.67^(9/10) + (16/Re)^(9/10)]^(10/9)."""
+    return (2.67 ** 0.9 + (16.0 / re) ** 0.9) ** (10.0 / 9.0)
+
+
+def drag(re_list=(10.0, 20.0, 30.0, 60.0), eo: float = 30.0, t_ref: float = 2000.0, t_end: float = 10.0,
+         every: int = 500, storage: str = "f32", grid=(256, 1024, 256), D: float = 32.0):
+    """Rising bubble at Eo = eo for each gravity Reynolds number: trajectory of
+    the gas-weighted rise velocity and centroid to t* = t_end; the terminal
+    velocity is the mean rise velocity over t* in [0.8 t_end, t_end]."""
+    import torch
+
+    from . import inputs, lbm
+    out = {"eo": eo, "t_ref": t_ref, "t_end": t_end, "storage": storage, "grid": list(grid), "D": D, "runs": {}}
+    for re in re_list:
+        s = inputs.drag_bubble(re, eo=eo, D=D, t_ref=t_ref, grid=grid)
+        phi, u, ps = inputs.build_fields(s)
+        sv = lbm.Solver(s.physics(), storage=storage)
+        sv.init_fields(phi, u, ps)
+        steps = int(round(t_end * t_ref))
+        traj = [dict(step=0, **_pick(sv.stats()))]
+        t0 = time.perf_counter()
+        for k in range(every, steps + 1, every):
+            sv.step(every)
+            traj.append(dict(step=k, **_pick(sv.stats())))
+            if k % (10 * every) == 0:
+                _log(f"[drag] Re_Gr {re:g}: step {k}/{steps} t* {k / t_ref:.2f} U {traj[-1]['rise_velocity']:.4e} "
+                     f"y_c {traj[-1]['centroid_y']:.1f}")
+        torch.cuda.synchronize()
+        g = -s.accel[1]
+        tail = [r for r in traj if r["step"] >= 0.8 * steps]
+        u_t = float(np.mean([r["rise_velocity"] for r in tail]))
+        ys = np.array([r["centroid_y"] for r in tail])
+        ts = np.array([r["step"] for r in tail], dtype=float)
+        u_slope = float(np.polyfit(ts, ys, 1)[0]) if len(ts) > 1 else None
+        mu_H = s.rho_H * s.tau_H / 3.0
+        re_t = s.rho_H * u_t * D / mu_H
+        cd = drag_coefficient_lbm(g, s.rho_H, s.rho_L, D, u_t)
+        rec = {"re_gr": re, "g": g, "sigma": s.sigma, "tau_H": s.tau_H, "tau_L": s.tau_L, "steps": steps,
+               "seconds": time.perf_counter() - t0, "u_t": u_t, "u_t_centroid_slope": u_slope,
+               "re_terminal": re_t, "cd_lbm": cd,
+               "cd_bhaga_weber_at_re_gr": drag_coefficient_bhaga_weber(re),
+               "cd_bhaga_weber_at_re_terminal": drag_coefficient_bhaga_weber(re_t),
+               "mass_drift_rel": (traj[-1]["mass"] - traj[0]["mass"]) / traj[0]["mass"],
+               "final_xi_eff": traj[-1]["xi_eff"], "trajectory": traj}
+        out["runs"][f"{re:g}"] = rec
+        _log(f"[drag] Re_Gr {re:g}: u_t {u_t:.4e} (centroid slope {u_slope:.4e}), Re_t {re_t:.2f}, "
+             f"C_D {cd:.3f}; Bhaga-Weber {rec['cd_bhaga_weber_at_re_gr']:.3f} at Re_Gr, "
+             f"{rec['cd_bhaga_weber_at_re_terminal']:.3f} at Re_t; {rec['seconds']:.0f} s")
+        del sv
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("study", choices=["rising", "swarm"])
+    ap.add_argument("study", choices=["rising", "swarm", "drag"])
+    ap.add_argument("--re", default="10,20,30,60", help="gravity Reynolds numbers of the drag study")
+    ap.add_argument("--eo", type=float, default=30.0)
+    ap.add_argument("--t-ref", type=float, default=2000.0, help="reference time sqrt(D/g) in steps (drag study)")
+    ap.add_argument("--t-end", type=float, default=10.0, help="end of the drag study in units of t_ref")
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--every", type=int, default=500)
     ap.add_argument("--storages", default=",".join(STORAGES))
@@ -165,6 +235,10 @@ def main():
     sts = tuple(a.storages.split(","))
     if a.study == "rising":
         res = rising_bubble(a.steps or 20000, a.every, sts)
+    elif a.study == "drag":
+        res = drag(tuple(float(v) for v in a.re.split(",")), eo=a.eo, t_ref=a.t_ref, t_end=a.t_end,
+                   every=a.every, storage=sts[0] if len(sts) == 1 else "f32")
+        res["summary"] = {k: {kk: v for kk, v in r.items() if kk != "trajectory"} for k, r in res["runs"].items()}
     else:
         res = swarm(a.steps or 2000, sts)
     txt = json.dumps(res, indent=1)
