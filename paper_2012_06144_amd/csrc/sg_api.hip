@@ -190,35 +190,39 @@ __global__ void k_weight_mirror(const bf16 *__restrict__ wt, int Co, int Ci, bf1
     wm[((int64_t)(26 - t) * Ci + ci) * Co + co] = wt[i];
 }
 
-// ---- convolution weight gradient, channel-major operands --------------------------
+// ---- convolution weight gradient, group-major operands ------------------------------
 // dw[t][co][ci] = sum_v dy[v][co] x[v + off(t)][ci] is, per tap, a GEMM whose
 // reduction runs over the voxels.  The matrix-core operands need 8
 // consecutive voxels of one channel per lane, so x and dy are first copied
-// channel-major, one W row after another with the rows padded with zeros to
-// Wp = a multiple of 16 voxels: xt[c][r][w], r = (n D + d) H + h.  Then every
-// operand is one aligned 16-byte load, and the w offsets -1 and +1 of a tap
-// are two such loads joined by byte alignment.  A block of three waves owns a
-// 32 x 32 (co, ci) tile; wave a holds the nine taps of d offset a - 1 in
-// registers and walks a chunk of 16-voxel steps along the rows: per step one
-// dy operand and, per h offset, three x loads (the step and its two
-// neighbours) serve three taps.  Block sums go to partial[chunk][t][co][ci]
-// (every entry written), added over chunks in a fixed order afterwards.
+// "group-major": each W row (rows r = (n D + d) H + h) is cut into groups of
+// 8 voxels, padded with zeros to Wp = a multiple of 16, and a group stores
+// all channels' 8-voxel vectors one after another,
+//   xt[((r ng + g) C + c) 8 + e] = x[r][8 g + e][c],  ng = Wp / 8.
+// Every operand is then one aligned 16-byte load, a wave's 64 loads cover two
+// contiguous 512-byte runs (32 channels of two groups), and the w offsets -1
+// and +1 of a tap are joined from the neighbouring groups by byte alignment.
+// A block of three waves owns a 32 x 32 (co, ci) tile; wave a holds the nine
+// taps of d offset a - 1 in registers and walks a chunk of 16-voxel steps
+// along the rows: per step one dy operand and, per h offset, one x group and
+// the neighbouring dwords serve three taps.  Block sums go to
+// partial[chunk][t][co][ci] (every entry written), added over chunks in a
+// fixed order afterwards.
 constexpr int kBwStep = 16;          // voxels per matrix-core K step
 constexpr int kBwThreads = 192;      // three waves, one per d offset
 constexpr int kBw2TargetBlocks = 1024;
 
-// xt[c][r][w] = x[r][w][c] for w < W, 0 for W <= w < Wp (one thread per
-// channel, row and group of 8 voxels; consecutive threads take consecutive
-// channels, so the strided 2-byte reads of a warp cover whole lines)
-__global__ void k_to_channel_major(const bf16 *__restrict__ x, int64_t rows, int W, int Wp, int C,
-                                   bf16 *__restrict__ xt)
+// xt[((r ng + g) C + c) 8 + e] = x[r][8 g + e][c] for 8 g + e < W, 0 up to the
+// padded row length (one thread per row, group and channel: consecutive
+// threads take consecutive channels, so reads and 16-byte writes are
+// contiguous across a wave)
+__global__ void k_to_group_major(const bf16 *__restrict__ x, int64_t rows, int W, int ng, int C,
+                                 bf16 *__restrict__ xt)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int ng = Wp / 8;
     const int64_t total = rows * ng * C;
     if (i >= total) return;
     const int c = (int)(i % C);
-    const int64_t t = i / C;
+    const int64_t t = i / C;  // r ng + g
     const int g = (int)(t % ng);
     const int64_t r = t / ng;
     bf16x8 v;
@@ -227,7 +231,7 @@ __global__ void k_to_channel_major(const bf16 *__restrict__ x, int64_t rows, int
         const int w = g * 8 + e;
         v[e] = w < W ? x[(r * W + w) * C + c] : (bf16)0.f;
     }
-    *reinterpret_cast<bf16x8 *>(xt + ((int64_t)c * rows + r) * Wp + g * 8) = v;
+    *reinterpret_cast<bf16x8 *>(xt + i * 8) = v;
 }
 
 typedef __attribute__((ext_vector_type(4))) unsigned u32x4;
@@ -254,65 +258,53 @@ __device__ inline bf16x8 shift_group(const bf16x8 &cur, unsigned nb)
     return __builtin_bit_cast(bf16x8, r);
 }
 
-// Operands of one K step of a wave: the dy group, and per h offset the x
-// group with the neighbouring dwords for the w offsets -1 and +1.
-struct BwOperands {
-    bf16x8 av;
-    bf16x8 cur[3];
-    unsigned prev[3], next[3];
-};
-
-__global__ __launch_bounds__(kBwThreads) void k_conv3d_bwd_weight_cm(const bf16 *__restrict__ xt,
+__global__ __launch_bounds__(kBwThreads) void k_conv3d_bwd_weight_gm(const bf16 *__restrict__ xt,
                                                                     const bf16 *__restrict__ dyt, int N, int D,
-                                                                    int H, int Wp, int Ci, int Co, int64_t steps,
+                                                                    int H, int ng, int Ci, int Co, int64_t steps,
                                                                     int64_t per, float *__restrict__ partial)
 {
     const int lane = threadIdx.x & 63, a = threadIdx.x >> 6;  // wave = d offset + 1
     const int chunk = blockIdx.x;
     const int co0 = blockIdx.y * 32, ci0 = blockIdx.z * 32;
-    const int64_t R = (int64_t)N * D * H;
-    const int nws = Wp / kBwStep;
+    const int nws = ng / 2;  // 16-voxel steps per row
     const int lr = lane & 31, half = lane >> 5;
     const bool ci_ok = ci0 + lr < Ci;
-    const bf16 *dyc = dyt + (int64_t)(co0 + lr) * R * Wp + 8 * half;
-    const bf16 *xc = xt + (int64_t)(ci_ok ? ci0 + lr : 0) * R * Wp + 8 * half;
+    // element offsets of this lane's channel; a group of a row is (r ng + g) C channels further
+    const bf16 *dyc = dyt + (int64_t)(co0 + lr) * 8;
+    const bf16 *xc = xt + (int64_t)(ci_ok ? ci0 + lr : 0) * 8;
+    const int64_t xgrp = (int64_t)Ci * 8, dgrp = (int64_t)Co * 8;  // elements per group
     f32x16 acc[9];
 #pragma unroll
     for (int k = 0; k < 9; ++k)
         for (int r = 0; r < 16; ++r) acc[k][r] = 0.f;
     const int64_t sbeg = (int64_t)chunk * per;
     const int64_t send = sbeg + per < steps ? sbeg + per : steps;
-    if (sbeg >= send) return;
-
-    // operands of the step at (ws, row = (n D + d) H + h)
-    auto load = [&](int ws, int64_t row, int h, int d, BwOperands &o) {
-        o.av = *reinterpret_cast<const bf16x8 *>(dyc + row * Wp + ws * kBwStep);
-        const int w = ws * kBwStep + 8 * half;  // this lane's first voxel
+    // position of the first step; then advanced incrementally
+    int ws = (int)(sbeg % nws);
+    int64_t row = sbeg / nws;  // (n D + d) H + h
+    int h = (int)(row % H);
+    int d = (int)((row / H) % D);
+    for (int64_t st = sbeg; st < send; ++st) {
+        const int g = ws * 2 + half;  // this lane's group of 8 voxels
+        const bf16x8 av = *reinterpret_cast<const bf16x8 *>(dyc + (row * ng + g) * dgrp);
         const int dd = d + a - 1;
         const bool dok = dd >= 0 && dd < D && ci_ok;
 #pragma unroll
         for (int b = 0; b < 3; ++b) {
             const int hh = h + b - 1;
-            o.cur[b] = bf16x8{};
-            o.prev[b] = 0u;
-            o.next[b] = 0u;
+            bf16x8 cur = {};
+            unsigned prev = 0u, next = 0u;
             if (dok && hh >= 0 && hh < H) {
-                const bf16 *xr = xc + (row + (int64_t)(a - 1) * H + (b - 1)) * Wp + ws * kBwStep;
-                o.cur[b] = *reinterpret_cast<const bf16x8 *>(xr);
-                if (w > 0) o.prev[b] = *reinterpret_cast<const unsigned *>(xr - 2);
-                if (w + 8 < Wp) o.next[b] = *reinterpret_cast<const unsigned *>(xr + 8);
+                const bf16 *xg = xc + ((row + (int64_t)(a - 1) * H + (b - 1)) * ng + g) * xgrp;
+                cur = *reinterpret_cast<const bf16x8 *>(xg);
+                if (g > 0) prev = *reinterpret_cast<const unsigned *>(xg - xgrp + 6);
+                if (g + 1 < ng) next = *reinterpret_cast<const unsigned *>(xg + xgrp);
             }
+            const bf16x8 bm = shift_group<-1>(cur, prev), bp = shift_group<1>(cur, next);
+            acc[3 * b + 0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bm, acc[3 * b + 0], 0, 0, 0);
+            acc[3 * b + 1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, cur, acc[3 * b + 1], 0, 0, 0);
+            acc[3 * b + 2] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bp, acc[3 * b + 2], 0, 0, 0);
         }
-    };
-
-    // position of the first step; later ones are advanced incrementally
-    int ws = (int)(sbeg % nws);
-    int64_t row = sbeg / nws;
-    int h = (int)(row % H);
-    int d = (int)((row / H) % D);
-    BwOperands cur, nxt;
-    load(ws, row, h, d, cur);
-    for (int64_t st = sbeg; st < send; ++st) {
         if (++ws == nws) {
             ws = 0;
             ++row;
@@ -321,17 +313,6 @@ __global__ __launch_bounds__(kBwThreads) void k_conv3d_bwd_weight_cm(const bf16 
                 if (++d == D) d = 0;
             }
         }
-        // the next step's loads are in flight during this step's products
-        if (st + 1 < send) load(ws, row, h, d, nxt);
-#pragma unroll
-        for (int b = 0; b < 3; ++b) {
-            const bf16x8 bm = shift_group<-1>(cur.cur[b], cur.prev[b]);
-            const bf16x8 bp = shift_group<1>(cur.cur[b], cur.next[b]);
-            acc[3 * b + 0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(cur.av, bm, acc[3 * b + 0], 0, 0, 0);
-            acc[3 * b + 1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(cur.av, cur.cur[b], acc[3 * b + 1], 0, 0, 0);
-            acc[3 * b + 2] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(cur.av, bp, acc[3 * b + 2], 0, 0, 0);
-        }
-        cur = nxt;
     }
     // D layout of the 32x32 tile: column l % 32 (ci), row 8 (r/4) + 4 (l/32) + r % 4 (co)
     if (!ci_ok) return;
@@ -346,26 +327,28 @@ __global__ __launch_bounds__(kBwThreads) void k_conv3d_bwd_weight_cm(const bf16 
     }
 }
 
-// db[co] = sum over rows and w of dyt[co][r][w] (padding zeros add nothing):
-// one block per channel and chunk of the channel's plane, fixed order
-__global__ __launch_bounds__(kThreads) void k_bias_grad_cm(const bf16 *__restrict__ dyt, int64_t plane,
-                                                           int64_t per, float *__restrict__ partial, int nchunk)
+// db[co] = sum of dyt over all groups of channel co (padding zeros add
+// nothing): one block per chunk of groups and channel, fixed order
+__global__ __launch_bounds__(kThreads) void k_bias_grad_gm(const bf16 *__restrict__ dyt, int64_t groups, int Co,
+                                                           int64_t per, float *__restrict__ partial)
 {
     __shared__ float s[kThreads];
     const int chunk = blockIdx.x, co = blockIdx.y;
     const int64_t beg = (int64_t)chunk * per;
-    const int64_t end = beg + per < plane ? beg + per : plane;
-    const bf16 *p = dyt + (int64_t)co * plane;
+    const int64_t end = beg + per < groups ? beg + per : groups;
     float acc = 0.f;
-    for (int64_t i = beg + threadIdx.x; i < end; i += kThreads) acc += (float)p[i];
+    for (int64_t i = beg + threadIdx.x; i < end; i += kThreads) {
+        const bf16x8 v = *reinterpret_cast<const bf16x8 *>(dyt + (i * Co + co) * 8);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) acc += (float)v[e];
+    }
     s[threadIdx.x] = acc;
     __syncthreads();
     for (int k = kThreads / 2; k > 0; k >>= 1) {
         if (threadIdx.x < k) s[threadIdx.x] += s[threadIdx.x + k];
         __syncthreads();
     }
-    if (threadIdx.x == 0) partial[(int64_t)chunk * gridDim.y + co] = s[0];
-    (void)nchunk;
+    if (threadIdx.x == 0) partial[(int64_t)chunk * Co + co] = s[0];
 }
 
 __global__ void k_reduce_partials(const float *__restrict__ partial, int nchunk, int64_t stride,
@@ -1061,9 +1044,9 @@ sg_status check_bwd_weight_args(const void *x, const void *dy, int n, int d, int
 
 // Launch plan of the weight gradient: W rows padded to Wp voxels, K steps of
 // kBwStep voxels split into `chunks` consecutive ranges of `per` steps (about
-// kBw2TargetBlocks blocks over the (co, ci) tiles); the bias sums split each
-// channel's plane into nb ranges.  Scratch layout: per-chunk partial sums,
-// bias partials, then the channel-major copies of x and dy.
+// kBw2TargetBlocks blocks over the (co, ci) tiles); the bias sums split the
+// groups into nb ranges.  Scratch layout: per-chunk partial sums, bias
+// partials, then the group-major copies of x and dy.
 struct BwPlan {
     int Wp;
     int64_t R;       // rows N D H
@@ -1089,21 +1072,21 @@ BwPlan bw_plan(int n, int d, int h, int w, int ci, int co)
     if (ch < 1) ch = 1;
     p.per = (p.steps + ch - 1) / ch;
     p.chunks = (int)((p.steps + p.per - 1) / p.per);
-    const int64_t plane = p.R * p.Wp;
-    int64_t nb = plane / 8192;
+    const int64_t groups = p.R * (p.Wp / 8);
+    int64_t nb = groups / 1024;
     nb = nb < 1 ? 1 : (nb > 256 ? 256 : nb);
-    p.bper = (plane + nb - 1) / nb;
-    p.nb = (int)((plane + p.bper - 1) / p.bper);
+    p.bper = (groups + nb - 1) / nb;
+    p.nb = (int)((groups + p.bper - 1) / p.bper);
     p.off_bpart = align_up((size_t)p.chunks * 27 * ci * co * sizeof(float), 256);
     p.off_xt = p.off_bpart + align_up((size_t)p.nb * co * sizeof(float), 256);
-    p.off_dyt = p.off_xt + align_up((size_t)ci * plane * sizeof(bf16), 256);
-    p.bytes = p.off_dyt + align_up((size_t)co * plane * sizeof(bf16), 256);
+    p.off_dyt = p.off_xt + align_up((size_t)ci * groups * 8 * sizeof(bf16), 256);
+    p.bytes = p.off_dyt + align_up((size_t)co * groups * 8 * sizeof(bf16), 256);
     return p;
 }
 
 // Weight and bias gradient through the scratch `ws` (every entry written
-// before it is read): channel-major copies of x and dy, per-chunk partial
-// sums part[chunk][t][co][ci], then a fixed-order sum over chunks.
+// before it is read): group-major copies of x and dy, per-chunk partial sums
+// part[chunk][t][co][ci], then a fixed-order sum over chunks.
 sg_status launch_bwd_weight(const void *x, const void *dy, int n, int d, int h, int w, int c_in, int c_out,
                             float *dw, float *db, const BwPlan &p, char *ws, hipStream_t s)
 {
@@ -1111,23 +1094,24 @@ sg_status launch_bwd_weight(const void *x, const void *dy, int n, int d, int h, 
     float *bpart = (float *)(ws + p.off_bpart);
     bf16 *xt = (bf16 *)(ws + p.off_xt);
     bf16 *dyt = (bf16 *)(ws + p.off_dyt);
-    const int64_t ng = p.R * (p.Wp / 8);
-    hipLaunchKernelGGL(k_to_channel_major, dim3(blocks_for(ng * c_in)), dim3(kThreads), 0, s, (const bf16 *)x,
-                       p.R, w, p.Wp, c_in, xt);
+    const int ng = p.Wp / 8;
+    const int64_t groups = p.R * ng;
+    hipLaunchKernelGGL(k_to_group_major, dim3(blocks_for(groups * c_in)), dim3(kThreads), 0, s, (const bf16 *)x,
+                       p.R, w, ng, c_in, xt);
     SG_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_to_channel_major, dim3(blocks_for(ng * c_out)), dim3(kThreads), 0, s, (const bf16 *)dy,
-                       p.R, w, p.Wp, c_out, dyt);
+    hipLaunchKernelGGL(k_to_group_major, dim3(blocks_for(groups * c_out)), dim3(kThreads), 0, s, (const bf16 *)dy,
+                       p.R, w, ng, c_out, dyt);
     SG_LAUNCH_CHECK();
     const dim3 grid((unsigned)p.chunks, (unsigned)(c_out / 32), (unsigned)((c_in + 31) / 32));
-    hipLaunchKernelGGL(k_conv3d_bwd_weight_cm, grid, dim3(kBwThreads), 0, s, xt, dyt, n, d, h, p.Wp, c_in, c_out,
+    hipLaunchKernelGGL(k_conv3d_bwd_weight_gm, grid, dim3(kBwThreads), 0, s, xt, dyt, n, d, h, ng, c_in, c_out,
                        p.steps, p.per, part);
     SG_LAUNCH_CHECK();
     const int64_t stride = (int64_t)27 * c_in * c_out;
     hipLaunchKernelGGL(k_reduce_partials, dim3(blocks_for(stride)), dim3(kThreads), 0, s, part, p.chunks, stride, dw);
     SG_LAUNCH_CHECK();
     if (db) {
-        hipLaunchKernelGGL(k_bias_grad_cm, dim3((unsigned)p.nb, (unsigned)c_out), dim3(kThreads), 0, s, dyt,
-                           p.R * p.Wp, p.bper, bpart, p.nb);
+        hipLaunchKernelGGL(k_bias_grad_gm, dim3((unsigned)p.nb, (unsigned)c_out), dim3(kThreads), 0, s, dyt,
+                           groups, c_out, p.bper, bpart);
         SG_LAUNCH_CHECK();
         hipLaunchKernelGGL(k_reduce_partials, dim3(blocks_for(c_out)), dim3(kThreads), 0, s, bpart, p.nb,
                            (int64_t)c_out, db);
