@@ -201,14 +201,15 @@ __global__ void k_weight_mirror(const bf16 *__restrict__ wt, int Co, int Ci, bf1
 // Every operand is then one aligned 16-byte load, a wave's 64 loads cover two
 // contiguous 512-byte runs (32 channels of two groups), and the w offsets -1
 // and +1 of a tap are joined from the neighbouring groups by byte alignment.
-// A block of three waves owns a 32 x 32 (co, ci) tile; wave a holds the nine
-// taps of d offset a - 1 in registers and walks a chunk of 16-voxel steps
-// along the rows: per step one dy operand and, per h offset, one x group and
-// the neighbouring dwords serve three taps.  Block sums go to
+// Three one-wave blocks own a 32 x 32 (co, ci) tile and a chunk of 16-voxel
+// steps; wave a holds the nine taps of d offset a - 1 in registers and walks
+// the chunk: per step one dy operand and, per h offset, one x group with the
+// neighbouring dwords serve three taps; along h the three x rows slide, so a
+// step loads one of them (see the kernel).  Block sums go to
 // partial[chunk][t][co][ci] (every entry written), added over chunks in a
 // fixed order afterwards.
 constexpr int kBwStep = 16;          // voxels per matrix-core K step
-constexpr int kBwThreads = 192;      // three waves, one per d offset
+constexpr int kBwThreads = 64;       // one wave per block: blocks 3c, 3c + 1, 3c + 2 take the d offsets of chunk c
 constexpr int kBw2TargetBlocks = 1024;
 
 // xt[((r ng + g) C + c) 8 + e] = x[r][8 g + e][c] for 8 g + e < W, 0 up to the
@@ -258,18 +259,52 @@ __device__ inline bf16x8 shift_group(const bf16x8 &cur, unsigned nb)
     return __builtin_bit_cast(bf16x8, r);
 }
 
-__global__ __launch_bounds__(kBwThreads) void k_conv3d_bwd_weight_gm(const bf16 *__restrict__ xt,
-                                                                    const bf16 *__restrict__ dyt, int N, int D,
-                                                                    int H, int ng, int Ci, int Co, int64_t steps,
-                                                                    int64_t per, float *__restrict__ partial)
+// One x row of the wave's channel and group: the aligned group and the
+// neighbouring dwords for the w offsets -1 and +1 (zeros outside the volume).
+struct XRow {
+    bf16x8 cur;
+    unsigned prev, next;
+};
+
+__device__ inline XRow load_xrow(const bf16 *xc, int64_t xrow, int g, int ng, int64_t xgrp, bool ok)
 {
-    const int lane = threadIdx.x & 63, a = threadIdx.x >> 6;  // wave = d offset + 1
-    const int chunk = blockIdx.x;
+    XRow r{{}, 0u, 0u};
+    if (ok) {
+        const bf16 *xg = xc + (xrow * ng + g) * xgrp;
+        r.cur = *reinterpret_cast<const bf16x8 *>(xg);
+        if (g > 0) r.prev = *reinterpret_cast<const unsigned *>(xg - xgrp + 6);
+        if (g + 1 < ng) r.next = *reinterpret_cast<const unsigned *>(xg + xgrp);
+    }
+    return r;
+}
+
+__device__ inline void bw_taps(const bf16x8 &av, const XRow &x, f32x16 &am, f32x16 &a0, f32x16 &ap)
+{
+    const bf16x8 bm = shift_group<-1>(x.cur, x.prev), bp = shift_group<1>(x.cur, x.next);
+    am = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bm, am, 0, 0, 0);
+    a0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, x.cur, a0, 0, 0, 0);
+    ap = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bp, ap, 0, 0, 0);
+}
+
+// Steps are ordered by the 16-voxel column ws first, then by row
+// r = (n D + d) H + h, h fastest: s = ws R + r.  Along a run of consecutive h
+// a wave's three x rows (h - 1, h, h + 1 at its d offset) slide by one row
+// per step, so each step loads one new x row and one dy operand, and the
+// next step's loads are issued before this step's products.
+// Two waves per SIMD: the accumulators then live in ordinary VGPRs (about 200, no
+// spills), where the default allocation took 171 VGPRs plus 144 AGPRs and
+// left one wave per SIMD.
+__global__ __launch_bounds__(kBwThreads) __attribute__((amdgpu_waves_per_eu(2))) void k_conv3d_bwd_weight_gm(
+    const bf16 *__restrict__ xt, const bf16 *__restrict__ dyt, int N, int D, int H, int ng, int Ci, int Co,
+    int64_t steps, int64_t per, float *__restrict__ partial)
+{
+    const int lane = threadIdx.x, a = (int)(blockIdx.x % 3);  // a = d offset + 1
+    const int chunk = (int)(blockIdx.x / 3);
     const int co0 = blockIdx.y * 32, ci0 = blockIdx.z * 32;
-    const int nws = ng / 2;  // 16-voxel steps per row
+    const int64_t R = (int64_t)N * D * H;
     const int lr = lane & 31, half = lane >> 5;
     const bool ci_ok = ci0 + lr < Ci;
-    // element offsets of this lane's channel; a group of a row is (r ng + g) C channels further
+    // element offsets of this lane's channel; group g of row r is (r ng + g) C channels further
     const bf16 *dyc = dyt + (int64_t)(co0 + lr) * 8;
     const bf16 *xc = xt + (int64_t)(ci_ok ? ci0 + lr : 0) * 8;
     const int64_t xgrp = (int64_t)Ci * 8, dgrp = (int64_t)Co * 8;  // elements per group
@@ -279,40 +314,34 @@ __global__ __launch_bounds__(kBwThreads) void k_conv3d_bwd_weight_gm(const bf16 
         for (int r = 0; r < 16; ++r) acc[k][r] = 0.f;
     const int64_t sbeg = (int64_t)chunk * per;
     const int64_t send = sbeg + per < steps ? sbeg + per : steps;
-    // position of the first step; then advanced incrementally
-    int ws = (int)(sbeg % nws);
-    int64_t row = sbeg / nws;  // (n D + d) H + h
-    int h = (int)(row % H);
-    int d = (int)((row / H) % D);
-    for (int64_t st = sbeg; st < send; ++st) {
-        const int g = ws * 2 + half;  // this lane's group of 8 voxels
-        const bf16x8 av = *reinterpret_cast<const bf16x8 *>(dyc + (row * ng + g) * dgrp);
-        const int dd = d + a - 1;
-        const bool dok = dd >= 0 && dd < D && ci_ok;
-#pragma unroll
-        for (int b = 0; b < 3; ++b) {
-            const int hh = h + b - 1;
-            bf16x8 cur = {};
-            unsigned prev = 0u, next = 0u;
-            if (dok && hh >= 0 && hh < H) {
-                const bf16 *xg = xc + ((row + (int64_t)(a - 1) * H + (b - 1)) * ng + g) * xgrp;
-                cur = *reinterpret_cast<const bf16x8 *>(xg);
-                if (g > 0) prev = *reinterpret_cast<const unsigned *>(xg - xgrp + 6);
-                if (g + 1 < ng) next = *reinterpret_cast<const unsigned *>(xg + xgrp);
+    for (int64_t s = sbeg; s < send;) {
+        const int g = (int)(s / R) * 2 + half;  // this lane's group of 8 voxels
+        const int64_t row = s % R;
+        const int h = (int)(row % H);
+        const int d = (int)((row / H) % D);
+        const int run = (int)(send - s < (int64_t)(H - h) ? send - s : (int64_t)(H - h));
+        const bool dok = d + a - 1 >= 0 && d + a - 1 < D && ci_ok;
+        const int64_t xr = row + (int64_t)(a - 1) * H;  // x row at (d + a - 1, h)
+        XRow r0 = load_xrow(xc, xr - 1, g, ng, xgrp, dok && h >= 1);
+        XRow r1 = load_xrow(xc, xr, g, ng, xgrp, dok);
+        XRow r2 = load_xrow(xc, xr + 1, g, ng, xgrp, dok && h + 1 < H);
+        bf16x8 av = *reinterpret_cast<const bf16x8 *>(dyc + (row * ng + g) * dgrp);
+        for (int k = 0; k < run; ++k) {
+            XRow r3{{}, 0u, 0u};
+            bf16x8 an = {};
+            if (k + 1 < run) {
+                r3 = load_xrow(xc, xr + k + 2, g, ng, xgrp, dok && h + k + 2 < H);
+                an = *reinterpret_cast<const bf16x8 *>(dyc + ((row + k + 1) * ng + g) * dgrp);
             }
-            const bf16x8 bm = shift_group<-1>(cur, prev), bp = shift_group<1>(cur, next);
-            acc[3 * b + 0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bm, acc[3 * b + 0], 0, 0, 0);
-            acc[3 * b + 1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, cur, acc[3 * b + 1], 0, 0, 0);
-            acc[3 * b + 2] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bp, acc[3 * b + 2], 0, 0, 0);
+            bw_taps(av, r0, acc[0], acc[1], acc[2]);
+            bw_taps(av, r1, acc[3], acc[4], acc[5]);
+            bw_taps(av, r2, acc[6], acc[7], acc[8]);
+            r0 = r1;
+            r1 = r2;
+            r2 = r3;
+            av = an;
         }
-        if (++ws == nws) {
-            ws = 0;
-            ++row;
-            if (++h == H) {
-                h = 0;
-                if (++d == D) d = 0;
-            }
-        }
+        s += run;
     }
     // D layout of the 32x32 tile: column l % 32 (ci), row 8 (r/4) + 4 (l/32) + r % 4 (co)
     if (!ci_ok) return;
@@ -1102,7 +1131,7 @@ sg_status launch_bwd_weight(const void *x, const void *dy, int n, int d, int h, 
     hipLaunchKernelGGL(k_to_group_major, dim3(blocks_for(groups * c_out)), dim3(kThreads), 0, s, (const bf16 *)dy,
                        p.R, w, ng, c_out, dyt);
     SG_LAUNCH_CHECK();
-    const dim3 grid((unsigned)p.chunks, (unsigned)(c_out / 32), (unsigned)((c_in + 31) / 32));
+    const dim3 grid((unsigned)(3 * p.chunks), (unsigned)(c_out / 32), (unsigned)((c_in + 31) / 32));
     hipLaunchKernelGGL(k_conv3d_bwd_weight_gm, grid, dim3(kBwThreads), 0, s, xt, dyt, n, d, h, ng, c_in, c_out,
                        p.steps, p.per, part);
     SG_LAUNCH_CHECK();
