@@ -191,12 +191,15 @@ sg_status sg_box_moments(const float *state, int64_t count, int32_t bx, int32_t 
  * channels (phi, u_x, u_y, u_z, p); element (i, k) at f[k cs + i vs], either
  * planar (cs = n, vs = 1: the solver's FP32 field planes, phi then u then p
  * as one allocation per argument) or channels last (cs = 1, vs = 5: box
- * states).  phi is clipped to [phi_lo, phi_hi]; with u_by_phase the velocity
- * increment is weighted by the heavy-phase fraction of the current phi;
- * with p_step == 0 the pressure is carried over.  out may alias s. */
+ * states).  phi is clipped to [phi_lo, phi_hi]; with u_by_phase == 1 the
+ * velocity increment is weighted by the heavy-phase fraction q of the
+ * current phi, with u_by_phase == 2 by clamp(10 q - 9, 0, 1) (the bulk of
+ * the heavy phase only);
+ * with phi_step == 0 phi is carried over (and clipped), with p_step == 0
+ * the pressure.  out may alias s. */
 sg_status sg_projective_step(const float *s, const float *s_prev, int64_t n, int64_t cs, int64_t vs, float ratio,
-                             float phi_lo, float phi_hi, int32_t u_by_phase, int32_t p_step, float *out,
-                             void *hip_stream);
+                             float phi_lo, float phi_hi, int32_t u_by_phase, int32_t phi_step, int32_t p_step,
+                             float *out, void *hip_stream);
 
 /* Network input of a box state s and the same box m steps earlier (5 FP32
  * channels per voxel each): channels 0-4 = s / scale_in, 5-9 =

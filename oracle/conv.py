@@ -34,7 +34,7 @@ def _lib():
         L.orc_shift_boxes.argtypes = [_D, i, i, i, i, _D, _D]
         L.orc_box_moments.argtypes = [_D, i, i, i, i, C.c_double, C.c_double, _D]
         i64 = C.c_int64
-        L.orc_projective_step.argtypes = [_D, _D, i64, i64, i64, C.c_double, C.c_double, C.c_double, i, i, _D]
+        L.orc_projective_step.argtypes = [_D, _D, i64, i64, i64, C.c_double, C.c_double, C.c_double, i, i, i, _D]
         L.orc_mass_project.argtypes = [_D, i, i, i, i, C.c_double, C.c_double, C.c_double, _D]
         _ready = True
     return L
@@ -161,9 +161,10 @@ def box_moments(state, phi_heavy, phi_light):
     return out
 
 
-def projective_step(s, s_prev, ratio, phi_lo, phi_hi, u_by_phase=True, p_step=False, layout="last"):
+def projective_step(s, s_prev, ratio, phi_lo, phi_hi, u_by_phase=True, p_step=False, layout="last", phi_step=True):
     """Projective step s + ratio (s - s_prev) of field sets: layout "last"
-    (..., 5) channels last, or "planar" (5, ...) one plane per channel."""
+    (..., 5) channels last, or "planar" (5, ...) one plane per channel;
+    phi_step False carries phi over, p_step False the pressure."""
     a, b = _f(s), _f(s_prev)
     assert a.shape == b.shape
     if layout == "last":
@@ -174,7 +175,7 @@ def projective_step(s, s_prev, ratio, phi_lo, phi_hi, u_by_phase=True, p_step=Fa
         cs, vs = n, 1
     out = np.zeros_like(a)
     _lib().orc_projective_step(a, b, n, cs, vs, float(ratio), float(phi_lo), float(phi_hi), int(u_by_phase),
-                               int(p_step), out)
+                               int(phi_step), int(p_step), out)
     return out
 
 

@@ -289,22 +289,28 @@ void orc_box_moments(const double *state, int count, int bx, int by, int bz, dou
  * channel by channel for n points.  Element (i, k) of a field set sits at
  * f[k * cs + i * vs] (planar: cs = n, vs = 1; channels last: cs = 1,
  * vs = 5); channels are (phi, u_x, u_y, u_z, p).  phi' is clipped to
- * [phi_lo, phi_hi]; with u_by_phase the velocity increment is weighted by
- * the heavy-phase fraction clamp((phi - phi_lo)/(phi_hi - phi_lo), 0, 1) of
- * the current phi; with p_step == 0 the pressure is carried over.        */
+ * [phi_lo, phi_hi]; with u_by_phase == 1 the velocity increment is weighted
+ * by the heavy-phase fraction q = clamp((phi - phi_lo)/(phi_hi - phi_lo),
+ * 0, 1) of the current phi, with u_by_phase == 2 by clamp(10 q - 9, 0, 1)
+ * (the bulk of the heavy phase only, none within the interface); with
+ * phi_step == 0 phi is carried over (then only clipped), with p_step == 0
+ * the pressure.                                                          */
 void orc_projective_step(const double *s, const double *s_prev, int64_t n, int64_t cs, int64_t vs, double ratio,
-                         double phi_lo, double phi_hi, int u_by_phase, int p_step, double *out)
+                         double phi_lo, double phi_hi, int u_by_phase, int phi_step, int p_step, double *out)
 {
     for (int64_t i = 0; i < n; ++i) {
         const double phi = s[i * vs], dphi = phi - s_prev[i * vs];
         double q = (phi - phi_lo) / (phi_hi - phi_lo);
         q = q < 0.0 ? 0.0 : (q > 1.0 ? 1.0 : q);
-        double np = phi + ratio * dphi;
+        double np = phi_step ? phi + ratio * dphi : phi;
         np = np < phi_lo ? phi_lo : (np > phi_hi ? phi_hi : np);
         out[i * vs] = np;
         for (int k = 1; k <= 3; ++k) {
             const double v = s[k * cs + i * vs], dv = v - s_prev[k * cs + i * vs];
-            out[k * cs + i * vs] = v + (u_by_phase ? q : 1.0) * ratio * dv;
+            double wq = 1.0;
+            if (u_by_phase == 1) wq = q;
+            if (u_by_phase == 2) wq = 10.0 * q - 9.0 < 0.0 ? 0.0 : 10.0 * q - 9.0;
+            out[k * cs + i * vs] = v + wq * ratio * dv;
         }
         const double p = s[4 * cs + i * vs];
         out[4 * cs + i * vs] = p_step ? p + ratio * (p - s_prev[4 * cs + i * vs]) : p;

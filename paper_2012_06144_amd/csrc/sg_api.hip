@@ -209,7 +209,7 @@ __global__ void k_weight_mirror(const bf16 *__restrict__ wt, int Co, int Ci, bf1
 // partial[chunk][t][co][ci] (every entry written), added over chunks in a
 // fixed order afterwards.
 constexpr int kBwStep = 16;          // voxels per matrix-core K step
-constexpr int kBwThreads = 64;       // one wave per block: blocks 3c, 3c + 1, 3c + 2 take the d offsets of chunk c
+constexpr int kBwThreads = 64;       // one wave per block (block to chunk, d offset and tile: see the kernel)
 constexpr int kBw2TargetBlocks = 1024;
 
 // xt[((r ng + g) C + c) 8 + e] = x[r][8 g + e][c] for 8 g + e < W, 0 up to the
@@ -296,11 +296,19 @@ __device__ inline void bw_taps(const bf16x8 &av, const XRow &x, f32x16 &am, f32x
 // left one wave per SIMD.
 __global__ __launch_bounds__(kBwThreads) __attribute__((amdgpu_waves_per_eu(2))) void k_conv3d_bwd_weight_gm(
     const bf16 *__restrict__ xt, const bf16 *__restrict__ dyt, int N, int D, int H, int ng, int Ci, int Co,
-    int64_t steps, int64_t per, float *__restrict__ partial)
+    int64_t steps, int64_t per, int nchunks, float *__restrict__ partial)
 {
-    const int lane = threadIdx.x, a = (int)(blockIdx.x % 3);  // a = d offset + 1
-    const int chunk = (int)(blockIdx.x / 3);
-    const int co0 = blockIdx.y * 32, ci0 = blockIdx.z * 32;
+    // Block b runs on XCD b mod 8.  Each XCD takes a contiguous eighth of the
+    // chunks (nchunks is a multiple of 8) and runs, per chunk, the three d
+    // offsets of every (co, ci) tile back to back, so the x and dy rows of a
+    // chunk are read into that XCD's L2 once for all of them.
+    const int tco = Co / 32, tiles = tco * ((Ci + 31) / 32);
+    const int64_t k = blockIdx.x / 8;
+    const int tile = (int)(k % tiles);
+    const int a = (int)((k / tiles) % 3);  // a = d offset + 1
+    const int chunk = (int)(blockIdx.x % 8) * (nchunks / 8) + (int)(k / (3 * tiles));
+    const int co0 = (tile % tco) * 32, ci0 = (tile / tco) * 32;
+    const int lane = threadIdx.x;
     const int64_t R = (int64_t)N * D * H;
     const int lr = lane & 31, half = lane >> 5;
     const bool ci_ok = ci0 + lr < Ci;
@@ -913,13 +921,14 @@ __global__ __launch_bounds__(kBoxThreads) void k_box_moments(const float *__rest
 // velocity increments weighted by the heavy-phase fraction of the current
 // phi if u_by_phase; pressure stepped only if p_step.  out may alias s.
 __global__ void k_projective(const float *__restrict__ s, const float *__restrict__ sp, int64_t n, int64_t cs,
-                             int64_t vs, float ratio, float lo, float hi, int u_by_phase, int p_step, float *out)
+                             int64_t vs, float ratio, float lo, float hi, int u_by_phase, int phi_step, int p_step,
+                             float *out)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const float phi = s[i * vs], dphi = phi - sp[i * vs];
     const float q = fminf(fmaxf((phi - lo) / (hi - lo), 0.f), 1.f);
-    const float wu = u_by_phase ? q : 1.f;
+    const float wu = u_by_phase == 1 ? q : (u_by_phase == 2 ? fmaxf(10.f * q - 9.f, 0.f) : 1.f);
     float v[3], dv[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
@@ -927,7 +936,7 @@ __global__ void k_projective(const float *__restrict__ s, const float *__restric
         dv[k] = v[k] - sp[(k + 1) * cs + i * vs];
     }
     const float p = s[4 * cs + i * vs], dp = p - sp[4 * cs + i * vs];
-    out[i * vs] = fminf(fmaxf(phi + ratio * dphi, lo), hi);
+    out[i * vs] = fminf(fmaxf(phi_step ? phi + ratio * dphi : phi, lo), hi);
 #pragma unroll
     for (int k = 0; k < 3; ++k) out[(k + 1) * cs + i * vs] = v[k] + wu * (ratio * dv[k]);
     out[4 * cs + i * vs] = p_step ? p + ratio * dp : p;
@@ -1100,7 +1109,8 @@ BwPlan bw_plan(int n, int d, int h, int w, int ci, int co)
     if (ch > p.steps) ch = p.steps;
     if (ch < 1) ch = 1;
     p.per = (p.steps + ch - 1) / ch;
-    p.chunks = (int)((p.steps + p.per - 1) / p.per);
+    p.chunks = (int)((p.steps + p.per - 1) / p.per + 7) / 8 * 8;  // a multiple of 8 (see the kernel); extra
+                                                                  // chunks are empty and write zeros
     const int64_t groups = p.R * (p.Wp / 8);
     int64_t nb = groups / 1024;
     nb = nb < 1 ? 1 : (nb > 256 ? 256 : nb);
@@ -1131,9 +1141,10 @@ sg_status launch_bwd_weight(const void *x, const void *dy, int n, int d, int h, 
     hipLaunchKernelGGL(k_to_group_major, dim3(blocks_for(groups * c_out)), dim3(kThreads), 0, s, (const bf16 *)dy,
                        p.R, w, ng, c_out, dyt);
     SG_LAUNCH_CHECK();
-    const dim3 grid((unsigned)(3 * p.chunks), (unsigned)(c_out / 32), (unsigned)((c_in + 31) / 32));
+    const int tiles = (c_out / 32) * ((c_in + 31) / 32);
+    const dim3 grid((unsigned)(3 * p.chunks * tiles));
     hipLaunchKernelGGL(k_conv3d_bwd_weight_gm, grid, dim3(kBwThreads), 0, s, xt, dyt, n, d, h, ng, c_in, c_out,
-                       p.steps, p.per, part);
+                       p.steps, p.per, p.chunks, part);
     SG_LAUNCH_CHECK();
     const int64_t stride = (int64_t)27 * c_in * c_out;
     hipLaunchKernelGGL(k_reduce_partials, dim3(blocks_for(stride)), dim3(kThreads), 0, s, part, p.chunks, stride, dw);
@@ -1507,13 +1518,14 @@ sg_status sg_box_moments(const float *state, int64_t count, int32_t bx, int32_t 
 }
 
 sg_status sg_projective_step(const float *s, const float *s_prev, int64_t n, int64_t cs, int64_t vs, float ratio,
-                             float phi_lo, float phi_hi, int32_t u_by_phase, int32_t p_step, float *out,
-                             void *stream)
+                             float phi_lo, float phi_hi, int32_t u_by_phase, int32_t phi_step, int32_t p_step,
+                             float *out, void *stream)
 {
     if (!s || !s_prev || !out || n < 1 || cs < 1 || vs < 1 || !(phi_hi > phi_lo)) return fail(SG_EARG, "bad arguments");
     if (!((cs == n && vs == 1) || (cs == 1 && vs == 5))) return fail(SG_EARG, "layout must be planar or channels last");
+    if (u_by_phase < 0 || u_by_phase > 2) return fail(SG_EARG, "u_by_phase must be 0, 1 or 2 (got %d)", u_by_phase);
     hipLaunchKernelGGL(k_projective, dim3(blocks_for(n)), dim3(kThreads), 0, (hipStream_t)stream, s, s_prev, n, cs,
-                       vs, ratio, phi_lo, phi_hi, u_by_phase, p_step, out);
+                       vs, ratio, phi_lo, phi_hi, u_by_phase, phi_step, p_step, out);
     SG_LAUNCH_CHECK();
     return SG_OK;
 }

@@ -45,7 +45,7 @@ _SIG = {
     "sg_make_target": [_vp, _vp, _i64, _vp, _i, _vp, _vp],
     "sg_apply_prediction": [_vp, _i, _vp, _vp, _vp, _vp, _vp, _i, _i, _i, _vp, _i, _f, _f, _i, _vp],
     "sg_advect_phase": [_vp, _i64, _i, _i, _i, _f, _vp, _vp],
-    "sg_projective_step": [_vp, _vp, _i64, _i64, _i64, _f, _f, _f, _i, _i, _vp, _vp],
+    "sg_projective_step": [_vp, _vp, _i64, _i64, _i64, _f, _f, _f, _i, _i, _i, _vp, _vp],
     "sg_pair_to_input": [_vp, _vp, _i64, _vp, _vp, _i, _vp, _vp],
     "sg_channel_moments": [_vp, _i64, _i, _vp, _vp, _vp],
     "sg_shift_boxes": [_vp, _i64, _i, _i, _i, _vp, _vp, _vp],
@@ -224,9 +224,10 @@ def sg_advect_phase(state, count, bx, by, bz, K, out, stream=None):
            "sg_advect_phase")
 
 
-def sg_projective_step(s, s_prev, n, cs, vs, ratio, phi_lo, phi_hi, u_by_phase, p_step, out, stream=None):
+def sg_projective_step(s, s_prev, n, cs, vs, ratio, phi_lo, phi_hi, u_by_phase, phi_step, p_step, out, stream=None):
     _check(_L.sg_projective_step(_p(s), _p(s_prev), int(n), int(cs), int(vs), float(ratio), float(phi_lo),
-                                 float(phi_hi), int(u_by_phase), int(p_step), _p(out), _stream(stream)),
+                                 float(phi_hi), int(u_by_phase), int(phi_step), int(p_step), _p(out),
+                                 _stream(stream)),
            "sg_projective_step")
 
 

@@ -385,7 +385,7 @@ def _gas_moments(states, count, box, phi_heavy, phi_light):
 
 
 def comoving_shift(states, count, box, K, prev=None, m=None, phi_heavy=PHI_HEAVY, phi_light=PHI_LIGHT,
-                   max_gain=0.02, velocity="gas", memory=None, smooth=1.0):
+                   max_gain=0.02, velocity="gas", memory=None, smooth=1.0, whole_cells=False):
     """Co-moving jump of each of `count` box states (contiguous, 5 FP32
     channels per voxel) over K steps.  velocity="gas": the bubble's
     gas-weighted velocity U and, given the same boxes `prev` m steps
@@ -396,8 +396,14 @@ def comoving_shift(states, count, box, K, prev=None, m=None, phi_heavy=PHI_HEAVY
     velocity="centroid": U is the displacement of the gas centroid since
     `prev` over m, and f = 1.  With a dict `memory` (kept by the caller
     between calls on the same boxes) the acceleration is smoothed over calls,
-    a <- smooth a + (1 - smooth) a_previous.  Returns a (count, 4) FP32
-    device tensor of rows (dx, dy, dz, f); a box without gas stays put."""
+    a <- smooth a + (1 - smooth) a_previous.  With whole_cells the
+    displacement is rounded to whole cells, so the translation copies values
+    instead of interpolating them (trilinear interpolation at a fractional
+    shift s smooths every field by about s (1 - s) / 2 cell^2 per jump); the
+    rounding remainder is carried in `memory` to the next call, so the
+    displacements add up to the unrounded ones within half a cell.  Returns a
+    (count, 4) FP32 device tensor of rows (dx, dy, dz, f); a box without gas
+    stays put."""
     import torch
     vol, cen, U = _gas_moments(states, count, box, phi_heavy, phi_light)
     a = np.zeros_like(U)
@@ -417,12 +423,67 @@ def comoving_shift(states, count, box, K, prev=None, m=None, phi_heavy=PHI_HEAVY
     nacc = np.linalg.norm(acc, axis=1, keepdims=True)
     acc = np.where(nacc > lim, acc * lim / np.maximum(nacc, 1e-300), acc)
     d = K * U + acc
+    if whole_cells:
+        if memory is not None and "carry" in memory and memory["carry"].shape == d.shape:
+            d = d + memory["carry"]
+        r = np.round(d)
+        if memory is not None:
+            memory["carry"] = d - r
+        d = r
     uu = (U * U).sum(1)
     f = 1.0 + K * np.where(uu > 0, (a * U).sum(1) / np.maximum(uu, 1e-300), 0.0)
     f = np.clip(f, 1.0 - max_gain, 1.0 + max_gain)
     out = np.concatenate([d, f[:, None]], axis=1)
     out[vol <= 0.5] = (0.0, 0.0, 0.0, 1.0)
     return torch.from_numpy(out.astype(np.float32)).to(states.device)
+
+
+def bubble_frame_shifts(s0, sm, box, K, m, phi_heavy=PHI_HEAVY, phi_light=PHI_LIGHT):
+    """Displacements of the co-moving trend jump of one box state s0, given
+    the same box m steps earlier (sm): the bubble's gas-weighted velocities U
+    and U_m give its displacement over the trend window, m (U + U_m) / 2,
+    and over the jump, K U + K^2 a / 2 with a = (U - U_m) / m (the
+    acceleration term at most K |U| / 2).  Returns two (4,) FP32 device
+    tensors (dx, dy, dz, 1) for sg_shift_boxes (velocity factor 1)."""
+    import torch
+    vol, _, U = _gas_moments(s0, 1, box, phi_heavy, phi_light)
+    vol_m, _, Um = _gas_moments(sm, 1, box, phi_heavy, phi_light)
+    if vol[0] <= 0.5 or vol_m[0] <= 0.5:
+        U = Um = np.zeros((1, 3))
+    a = (U[0] - Um[0]) / float(m)
+    acc = 0.5 * K * K * a
+    lim = 0.5 * K * np.linalg.norm(U[0])
+    if np.linalg.norm(acc) > lim:
+        acc = acc * lim / np.linalg.norm(acc)
+    d_m = 0.5 * m * (U[0] + Um[0])
+    d_k = K * U[0] + acc
+    mk = lambda d: torch.tensor([d[0], d[1], d[2], 1.0], dtype=torch.float32).to(s0.device)
+    return mk(d_m), mk(d_k)
+
+
+def comoving_trend_base(s0, sm, box, K, m, phi_lo, phi_hi, u_by_phase, out, phi_heavy=PHI_HEAVY,
+                        phi_light=PHI_LIGHT, gain=1.0):
+    """Co-moving trend jump: the state's development in the bubble's frame is
+    extrapolated (a projective step, Gear and Kevrekidis 2003, taken in the
+    frame that moves with the bubble), then the result is translated with
+    the bubble:
+      s(t + K) = T_dK[ s(t) + (K/m) (s(t) - T_dm[s(t - m)]) ],
+    T_d being the window translation by d (sg_shift_boxes) and dm, dK the
+    displacements of bubble_frame_shifts.  Unlike the plain co-moving jump
+    this follows the growth of the wake, not only the growth of the
+    velocity.  phi is only translated (extrapolating its trend thinned the
+    interface over many cycles) and the pressure is carried over;
+    u_by_phase weights the velocity trend by the heavy-phase fraction (1) or
+    by the bulk of the heavy phase only (2), and `gain` scales K/m
+    (sg_projective_step)."""
+    import torch
+    bx, by, bz = box
+    d_m, d_k = bubble_frame_shifts(s0, sm, box, K, m, phi_heavy, phi_light)
+    moved = torch.empty_like(s0)
+    sg.sg_shift_boxes(sm, 1, bx, by, bz, d_m, moved)
+    ext = torch.empty_like(s0)
+    sg.sg_projective_step(s0, moved, bx * by * bz, 1, 5, gain * K / m, phi_lo, phi_hi, int(u_by_phase), 0, 0, ext)
+    sg.sg_shift_boxes(ext, 1, bx, by, bz, d_k, out)
 
 
 def jump_base(kind, s0, box, K, out, shift=None):
@@ -618,10 +679,18 @@ class JumpConfig:
     clip_phi: bool = True       # clip the jumped phi to [phi_L, phi_H] (removes the phase field's own
                                 # small over- and undershoots, which the mass projection then moves
                                 # into the interface)
+    whole_cells: bool = False   # co-moving displacement rounded to whole cells, remainder carried over
+    trend_gain: float = 1.0     # co-moving trend jump: factor on the extrapolation ratio K/m
+    trend_bulk: bool = False    # co-moving trend jump: velocity trend in the bulk of the heavy phase only
     keep_neq: bool = False      # after a jump keep the populations' non-equilibrium parts
                                 # (lbm_shift_equilibrium) instead of rebuilding them at equilibrium;
                                 # they stay at their cells while the interface moves, which
                                 # destabilised long runs at a density ratio of 1000
+
+
+def across_trend(jc) -> bool:
+    """The trend is taken between consecutive cycle ends (m = K + relax)."""
+    return jc.m == jc.K + jc.relax
 
 
 def _traj_entry(step, st, **kw):
@@ -646,7 +715,7 @@ def _jump(net, mode, F_now, F_prev, setup, box, jc: JumpConfig, diagnostics=Fals
     if mode == "persistence":
         return None
     if mode == "projective":
-        sg.sg_projective_step(F_now, F_prev, N, N, 1, jc.K / jc.m, lo, hi, int(jc.u_by_phase), 0, F_now)
+        sg.sg_projective_step(F_now, F_prev, N, N, 1, jc.K / jc.m, lo, hi, int(jc.u_by_phase), 1, 0, F_now)
         return None
     bx, by, bz = box[3], box[4], box[5]
     V = bx * by * bz
@@ -662,8 +731,14 @@ def _jump(net, mode, F_now, F_prev, setup, box, jc: JumpConfig, diagnostics=Fals
     if kind == "comoving":
         shift = comoving_shift(s0, 1, (bx, by, bz), jc.K, prev=sm if jc.accel else None, m=jc.m,
                                phi_heavy=setup.phi_H, phi_light=setup.phi_L, max_gain=jc.max_gain,
-                               velocity=jc.velocity, memory=memory, smooth=jc.accel_smooth)[0]
-    jump_base(kind, s0, (bx, by, bz), jc.K, base, shift)
+                               velocity=jc.velocity, memory=memory, smooth=jc.accel_smooth,
+                               whole_cells=jc.whole_cells)[0]
+    if kind == "comoving_trend":
+        assert not across_trend(jc), "the co-moving trend jump takes its trend inside the relaxation"
+        comoving_trend_base(s0, sm, (bx, by, bz), jc.K, jc.m, lo, hi, 2 if jc.trend_bulk else int(jc.u_by_phase),
+                            base, phi_heavy=setup.phi_H, phi_light=setup.phi_L, gain=jc.trend_gain)
+    else:
+        jump_base(kind, s0, (bx, by, bz), jc.K, base, shift)
     inc = None
     if mode == "network":
         sg.sg_pair_to_input(s0, sm, net.scale_in, trend_scale(net, jc.K, jc.m), C_IN, x)
@@ -691,7 +766,10 @@ def run_with_jumps(net, solver, setup, total_steps, jc: JumpConfig, log=print, m
     its end.  After each cycle the indicators are checked (finite, mass drift
     over the cycle <= mass_tol, interface width in [xi_lo, xi_hi] xi, max |u|
     <= u_max); if one trips, the state saved before the jump is restored and
-    the cycle's K + relax steps are run with the plain LBM.  The jumped
+    the cycle's K + relax steps are run with the plain LBM.  If the state is
+    still unusable after that (a divergence seeded by the previous, accepted
+    jump), the state saved one cycle earlier is restored and both cycles are
+    run plainly; a run that fails even then raises.  The jumped
     fields enter the solver through lbm_shift_equilibrium (populations keep
     their non-equilibrium parts) or, with jc.keep_neq False, are rebuilt at
     equilibrium."""
@@ -701,6 +779,8 @@ def run_with_jumps(net, solver, setup, total_steps, jc: JumpConfig, log=print, m
     F_now = torch.empty(shape, device=solver.device, dtype=torch.float32)
     F_prev = torch.empty_like(F_now)
     backup = solver.new_state_buffer()
+    older = solver.new_state_buffer()   # the state saved one cycle before `backup`
+    have_older = False
     scratch = torch.zeros(2048, device=solver.device, dtype=torch.float64)
     cyc = jc.K + jc.relax
     accepted = rejected = 0
@@ -720,9 +800,23 @@ def run_with_jumps(net, solver, setup, total_steps, jc: JumpConfig, log=print, m
     done = jc.warmup + jc.m
     solver.macroscopic(out=F_now)
     F_keep = torch.empty_like(F_now) if across else None
+
+    def plain_cycle():
+        # one cycle of plain steps, with the trend fields taken as a jump cycle takes them
+        if across:
+            solver.step(cyc)
+        else:
+            solver.step(cyc - jc.m)
+            solver.macroscopic(out=F_prev)
+            solver.step(jc.m)
+        return solver.stats()
+
     while done + cyc <= total_steps:
         m0 = solver.reduce_mass()
         cent = solver.stats()["centroid"]
+        if done > jc.warmup + jc.m:     # keep the previous cycle's start as the older checkpoint
+            backup, older = older, backup
+            have_older = True
         solver.save_state(backup)
         box = _window(cent, jc.box, (nx, ny, nz))
         tp = time.perf_counter()
@@ -758,13 +852,21 @@ def run_with_jumps(net, solver, setup, total_steps, jc: JumpConfig, log=print, m
         else:
             rejected += 1
             solver.restore_state(backup)
-            if across:
-                solver.step(cyc)
-            else:
-                solver.step(cyc - jc.m)
-                solver.macroscopic(out=F_prev)
-                solver.step(jc.m)
-            st = solver.stats()
+            try:
+                st = plain_cycle()
+            except Exception as e:
+                if not have_older:
+                    raise
+                log(f"[jump] cycle at step {done}: plain rerun failed ({e}); back to step {done - cyc}")
+                solver.restore_state(older)
+                if traj[-1].get("jump"):
+                    accepted -= 1
+                    rejected += 1
+                traj[-1] = _traj_entry(done, plain_cycle(), jump=False, drift=float("nan"))
+                if across:
+                    solver.macroscopic(out=F_prev)
+                st = plain_cycle()
+                drift = float("nan")
         solver.macroscopic(out=F_now)
         done += cyc
         traj.append(_traj_entry(done, st, jump=bool(ok), drift=drift))
@@ -877,8 +979,8 @@ def _cmd_train(a):
     t_data = time.perf_counter() - t0
     net = Net(seed=a.seed)
     net.base = a.base
-    shifts = (comoving_shift(S0, S0.shape[0], cfg.box, cfg.K, prev=Sm, m=cfg.m) if a.base == "comoving"
-              else None)
+    shifts = (comoving_shift(S0, S0.shape[0], cfg.box, cfg.K, prev=Sm, m=cfg.m, whole_cells=a.whole_cells)
+              if a.base == "comoving" else None)
     net.scale_in, net.scale_out, net.scale_trend = channel_scales(Sm, S0, S1, cfg.box, cfg.K, cfg.m,
                                                                   base_kind=a.base, shifts=shifts)
     res = train(net, Sm, S0, S1, cfg.box, cfg.K, cfg.m, run_of=run_of, steps=a.train_steps, batch=a.batch,
@@ -908,7 +1010,9 @@ def _cmd_jump(a):
     jc = JumpConfig(K=a.K, relax=a.relax, m=a.m)
     if a.box:
         jc.box = tuple(int(v) for v in a.box.split("x"))
-    out = {"workload": s.name, "steps": a.steps, "jump": jc.__dict__, "runs": {}}
+    from .perf import surrogate_source_hash
+    out = {"workload": s.name, "steps": a.steps, "jump": jc.__dict__, "source_hash": surrogate_source_hash(),
+           "runs": {}}
     if a.plain_from:
         out["runs"]["plain"] = json.load(open(a.plain_from))["runs"]["plain"]
         _log(f"[plain] reference trajectory from {a.plain_from}")
@@ -920,7 +1024,8 @@ def _cmd_jump(a):
         del sv
         torch.cuda.empty_cache()
     modes = a.modes.split(",")
-    variants = [(mname, None, mname) for mname in ("persistence", "transport", "comoving", "projective")
+    variants = [(mname, None, mname) for mname in ("persistence", "transport", "comoving", "comoving_trend",
+                                                   "projective")
                 if mname in modes]
     if a.weights and "network" in modes:
         net = Net(seed=0)
@@ -933,6 +1038,9 @@ def _cmd_jump(a):
     jc.warmup = a.warmup
     jc.accel = not a.no_accel
     jc.keep_neq = bool(a.keep_neq)
+    jc.whole_cells = bool(a.whole_cells)
+    jc.trend_gain = a.trend_gain
+    jc.trend_bulk = bool(a.trend_bulk)
     jc.clip_phi = not a.no_clip
     jc.phi_at_interface = not a.no_phi_at_interface
     for name, net, mode in variants:
@@ -1037,6 +1145,8 @@ def main():
     t.add_argument("--m", type=int, default=25, help="steps between the trend states (<= 400)")
     t.add_argument("--base", default="comoving", choices=["comoving", "transport"],
                    help="baseline whose residual the network learns")
+    t.add_argument("--whole-cells", action="store_true",
+                   help="co-moving baseline displaced by whole cells (the driver's --whole-cells)")
     t.add_argument("--weights", default=None)
     t.add_argument("--out", default=None)
     j = sub.add_parser("jump")
@@ -1063,6 +1173,11 @@ def main():
     j.add_argument("--no-clip", action="store_true", help="do not clip the jumped phi to [phi_L, phi_H]")
     j.add_argument("--keep-neq", action="store_true",
                    help="keep the populations' non-equilibrium parts after a jump (default: rebuild at equilibrium)")
+    j.add_argument("--trend-gain", type=float, default=1.0, help="co-moving trend jump: factor on K/m")
+    j.add_argument("--trend-bulk", action="store_true",
+                   help="co-moving trend jump: velocity trend in the bulk of the heavy phase only")
+    j.add_argument("--whole-cells", action="store_true",
+                   help="co-moving displacement rounded to whole cells, the remainder carried to the next jump")
     j.add_argument("--out", default=None)
     c = sub.add_parser("convbench")
     c.add_argument("--shape", default="8x64x96x64", help="batch x D x H x W of the network input")

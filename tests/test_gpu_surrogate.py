@@ -426,6 +426,55 @@ def test_shift_boxes_matches_oracle(env):
         sg.sg_shift_boxes(ts, n, bx, by, bz, torch.from_numpy(d).cuda(), ts)
 
 
+def test_comoving_trend_base_matches_oracle(env):
+    """The co-moving trend jump, T_dK[s + (K/m)(s - T_dm[s_m])] with phi
+    carried, against the same three steps in the FP64 oracle (shift_boxes,
+    projective_step with phi_step off, shift_boxes) at the displacements the
+    jump computed.  Bound: each translation adds the shift test's bound for
+    its input; the projective step multiplies the first one's error by K/m
+    and adds 8 eps32 (|s| + (K/m)|s - T s_m|)."""
+    torch, sg = env
+    from paper_2012_06144_amd import surrogate as sgm
+    rng = np.random.default_rng(31)
+    bz, by, bx = 12, 16, 10
+    z, y, x = np.meshgrid(np.arange(bz), np.arange(by), np.arange(bx), indexing="ij")
+    r = np.sqrt((x - 4.6) ** 2 + (y - 7.3) ** 2 + (z - 5.8) ** 2)
+    s0 = np.zeros((bz, by, bx, 5))
+    s0[..., 0] = 0.5 + 0.5 * np.tanh((r - 3.0) / 1.5)            # gas bubble of radius 3
+    s0[..., 2] = 0.01 + 0.002 * np.sin(0.3 * y) + 1e-3 * rng.standard_normal(r.shape)
+    s0[..., 1] = 1e-3 * np.cos(0.4 * x)
+    s0[..., 4] = 1e-4 * r
+    sm = s0.copy()
+    sm[..., 0] = 0.5 + 0.5 * np.tanh((np.sqrt((x - 4.6) ** 2 + (y - 6.1) ** 2 + (z - 5.8) ** 2) - 3.0) / 1.5)
+    sm[..., 1:4] *= 0.97
+    s0, sm = s0.astype(np.float32), sm.astype(np.float32)
+    K, m = 100, 150
+    t0, tm = torch.from_numpy(s0).cuda().view(-1), torch.from_numpy(sm).cuda().view(-1)
+    out = torch.empty_like(t0)
+    sgm.comoving_trend_base(t0, tm, (bx, by, bz), K, m, 0.0, 1.0, True, out)
+    d_m, d_k = sgm.bubble_frame_shifts(t0, tm, (bx, by, bz), K, m)
+    torch.cuda.synchronize()
+    dm, dk = d_m.cpu().numpy().astype(np.float64), d_k.cpu().numpy().astype(np.float64)
+    assert dm[1] > 0.5 and dk[1] > 0.5 and dm[3] == 1.0 and dk[3] == 1.0
+    s64, m64 = s0.astype(np.float64)[None], sm.astype(np.float64)[None]
+    moved = oc.shift_boxes(m64, dm[None])
+    ext = oc.projective_step(s64, moved, K / m, 0.0, 1.0, u_by_phase=True, p_step=False, phi_step=False)
+    ref = oc.shift_boxes(ext, dk[None])[0]
+    got = out.cpu().numpy().astype(np.float64).reshape(ref.shape)
+
+    def shift_bound(a, d):
+        jump = max(np.abs(np.diff(a, axis=k)).max() for k in (1, 2, 3))
+        return 2 * EPS32 * (max(bx, by, bz) + np.abs(d[:3]).max()) * jump + 8 * EPS32 * np.abs(a).max()
+
+    ratio = K / m
+    e1 = shift_bound(m64, dm)
+    e2 = ratio * e1 + 8 * EPS32 * (np.abs(s64).max() + ratio * np.abs(s64 - moved).max())
+    bound = e2 + shift_bound(ext, dk)
+    assert np.abs(got - ref).max() <= bound
+    # phi is only translated: equal to the translated phi of s0
+    assert np.abs(got[..., 0] - oc.shift_boxes(s64, dk[None])[0][..., 0]).max() <= shift_bound(s64, dk)
+
+
 def test_box_moments_matches_oracle(env):
     """FP64 sums of FP32 inputs: |error| <= V eps64 x (sum of |terms|) per
     entry (ordering only); phi spans beyond [0, 1] to exercise the clip."""
@@ -544,14 +593,17 @@ def test_projective_step_matches_oracle(env, layout):
         a, b, cs, vs = s, sp, 1, 5
     ta, tb = torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda()
     out = torch.empty_like(ta)
-    sg.sg_projective_step(ta, tb, n, cs, vs, ratio, 0.0, 1.0, 1, 1, out)
-    torch.cuda.synchronize()
-    ref = oc.projective_step(a.astype(np.float64), b.astype(np.float64), ratio, 0.0, 1.0, u_by_phase=True,
-                             p_step=True, layout=layout)
     bound = 8 * EPS32 * (np.abs(a) + ratio * np.abs(a.astype(np.float64) - b)) + 1e-30
-    assert np.all(np.abs(out.cpu().numpy() - ref) <= bound)
-    # in place
-    sg.sg_projective_step(ta, tb, n, cs, vs, ratio, 0.0, 1.0, 1, 1, ta)
+    for ubp, phi_step in ((2, 1), (0, 0), (1, 0), (1, 1)):
+        sg.sg_projective_step(ta, tb, n, cs, vs, ratio, 0.0, 1.0, ubp, phi_step, 1, out)
+        torch.cuda.synchronize()
+        ref = oc.projective_step(a.astype(np.float64), b.astype(np.float64), ratio, 0.0, 1.0, u_by_phase=ubp,
+                                 p_step=True, layout=layout, phi_step=bool(phi_step))
+        assert np.all(np.abs(out.cpu().numpy() - ref) <= bound), (ubp, phi_step)
+    with pytest.raises(sg.SgError):
+        sg.sg_projective_step(ta, tb, n, cs, vs, ratio, 0.0, 1.0, 3, 1, 1, out)
+    # in place (the arguments of the last call above)
+    sg.sg_projective_step(ta, tb, n, cs, vs, ratio, 0.0, 1.0, 1, 1, 1, ta)
     torch.cuda.synchronize()
     assert torch.equal(ta, out)
 

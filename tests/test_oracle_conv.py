@@ -307,6 +307,19 @@ def test_projective_step_limits():
     out2 = conv.projective_step(s2, sp, 8.0, 0.0, 1.0, u_by_phase=True)
     assert np.array_equal(out2[:25, 1:4], s2[:25, 1:4])
     assert np.allclose(out2[25:, 1:4], s2[25:, 1:4] + 8.0 * (s2[25:, 1:4] - sp[25:, 1:4]), rtol=0, atol=1e-15)
+    # u_by_phase = 2: the bulk of the heavy phase only (weight clamp(10 q - 9, 0, 1))
+    s4 = s2.copy()
+    s4[:, 0] = np.linspace(0.0, 1.0, 50)
+    out4 = conv.projective_step(s4, sp, 8.0, 0.0, 1.0, u_by_phase=2)
+    w = np.clip(10.0 * s4[:, 0] - 9.0, 0.0, 1.0)
+    assert np.allclose(out4[:, 1:4], s4[:, 1:4] + w[:, None] * 8.0 * (s4[:, 1:4] - sp[:, 1:4]), rtol=0, atol=1e-15)
+    assert np.array_equal(out4[s4[:, 0] <= 0.9, 1:4], s4[s4[:, 0] <= 0.9, 1:4])
+    # phi_step off: phi carried over (clipped), the other channels stepped as before
+    s3 = s2.copy()
+    s3[:5, 0] = 1.2
+    out3 = conv.projective_step(s3, sp, 8.0, 0.0, 1.0, u_by_phase=True, phi_step=False)
+    assert np.array_equal(out3[:, 0], np.clip(s3[:, 0], 0.0, 1.0))
+    assert np.array_equal(out3[5:, 1:], conv.projective_step(s3, sp, 8.0, 0.0, 1.0, u_by_phase=True)[5:, 1:])
 
 
 def test_projective_step_layouts_agree():
