@@ -18,7 +18,6 @@ a bounded sample of the same workload.
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import re
@@ -43,12 +42,8 @@ def log(msg):
 
 
 def kernel_source_hash() -> str:
-    h = hashlib.sha256()
-    for f in ("csrc/lbm_kernels.hpp", "csrc/lbm_lattice.hpp", "csrc/lbm_api.hip", "csrc/lbm_sweeps_f32.hip",
-              "build.py"):
-        with open(os.path.join(ROOT, "paper_2012_06144_amd", f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
+    from paper_2012_06144_amd import perf
+    return perf.kernel_source_hash()
 
 
 def load_traffic(kernel: str, workload: str, storage: str, src_hash: str):
@@ -68,12 +63,8 @@ def load_traffic(kernel: str, workload: str, storage: str, src_hash: str):
 
 
 def surrogate_source_hash() -> str:
-    h = hashlib.sha256()
-    for f in ("csrc/sg_api.hip", "surrogate.py", "csrc/lbm_kernels.hpp", "csrc/lbm_lattice.hpp", "csrc/lbm_api.hip",
-              "csrc/lbm_sweeps_f32.hip", "build.py"):
-        with open(os.path.join(ROOT, "paper_2012_06144_amd", f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
+    from paper_2012_06144_amd import perf
+    return perf.surrogate_source_hash()
 
 
 def load_surrogate_study():

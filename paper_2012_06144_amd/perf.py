@@ -55,3 +55,32 @@ def balance(n_b: float, n_f: float, b_s_gbs: float, p_peak_tflops: float) -> dic
     B_c = n_b / n_f
     B_m = b_s_gbs / (p_peak_tflops * 1e3)
     return {"B_c": B_c, "B_m": B_m, "l": min(1.0, B_m / B_c)}
+
+
+_KERNEL_SOURCES = ("csrc/lbm_kernels.hpp", "csrc/lbm_lattice.hpp", "csrc/lbm_api.hip", "csrc/lbm_sweeps_f32.hip",
+                   "build.py")
+_SURROGATE_SOURCES = ("csrc/sg_api.hip", "surrogate.py") + _KERNEL_SOURCES
+
+
+def _hash_files(names) -> str:
+    import hashlib
+    import os
+    root = os.path.dirname(os.path.abspath(__file__))
+    h = hashlib.sha256()
+    for f in names:
+        with open(os.path.join(root, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def kernel_source_hash() -> str:
+    """Digest of the LBM kernel sources and their build script: a recorded
+    measurement belongs to the current kernels only if its hash matches."""
+    return _hash_files(_KERNEL_SOURCES)
+
+
+def surrogate_source_hash() -> str:
+    """Digest of the surrogate and LBM kernel sources, the jump driver and
+    the build script (what a jump-study row depends on)."""
+    return _hash_files(_SURROGATE_SOURCES)
+

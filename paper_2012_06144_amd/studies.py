@@ -172,18 +172,20 @@ def drag_coefficient_bhaga_weber(re: float) -> float:
 
 
 def drag(re_list=(10.0, 20.0, 30.0, 60.0), eo: float = 30.0, t_ref: float = 2000.0, t_end: float = 10.0,
-         every: int = 500, storage: str = "f32", grid=(256, 1024, 256), D: float = 32.0):
+         every: int = 500, storage: str = "f32", grid=(256, 1024, 256), D: float = 32.0, lattice=None):
     """Rising bubble at Eo = eo for each gravity Reynolds number: trajectory of
     the gas-weighted rise velocity and centroid to t* = t_end; the terminal
     velocity is the mean rise velocity over t* in [0.8 t_end, t_end]."""
     import torch
 
     from . import inputs, lbm
-    out = {"eo": eo, "t_ref": t_ref, "t_end": t_end, "storage": storage, "grid": list(grid), "D": D, "runs": {}}
+    lattice = dict(lattice or {})
+    out = {"eo": eo, "t_ref": t_ref, "t_end": t_end, "storage": storage, "grid": list(grid), "D": D,
+           "lattice": lattice, "runs": {}}
     for re in re_list:
         s = inputs.drag_bubble(re, eo=eo, D=D, t_ref=t_ref, grid=grid)
         phi, u, ps = inputs.build_fields(s)
-        sv = lbm.Solver(s.physics(), storage=storage)
+        sv = lbm.Solver(dict(s.physics(), **lattice), storage=storage)
         sv.init_fields(phi, u, ps)
         steps = int(round(t_end * t_ref))
         traj = [dict(step=0, **_pick(sv.stats()))]
@@ -227,6 +229,8 @@ def main():
     ap.add_argument("--eo", type=float, default=30.0)
     ap.add_argument("--t-ref", type=float, default=2000.0, help="reference time sqrt(D/g) in steps (drag study)")
     ap.add_argument("--t-end", type=float, default=10.0, help="end of the drag study in units of t_ref")
+    ap.add_argument("--lattice", default="15,27,0",
+                    help="phase-field set, hydrodynamic set and phase-field MRT (0/1) of the drag study")
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--every", type=int, default=500)
     ap.add_argument("--storages", default=",".join(STORAGES))
@@ -236,8 +240,10 @@ def main():
     if a.study == "rising":
         res = rising_bubble(a.steps or 20000, a.every, sts)
     elif a.study == "drag":
+        qp, qh, mrt = (int(v) for v in a.lattice.split(","))
         res = drag(tuple(float(v) for v in a.re.split(",")), eo=a.eo, t_ref=a.t_ref, t_end=a.t_end,
-                   every=a.every, storage=sts[0] if len(sts) == 1 else "f32")
+                   every=a.every, storage=sts[0] if len(sts) == 1 else "f32",
+                   lattice=dict(lattice_phase=qp, lattice_hydro=qh, phase_mrt=bool(mrt)))
         res["summary"] = {k: {kk: v for kk, v in r.items() if kk != "trajectory"} for k, r in res["runs"].items()}
     else:
         res = swarm(a.steps or 2000, sts)
