@@ -503,7 +503,11 @@ def jump_base(kind, s0, box, K, out, shift=None):
 def _base_crop(S0, i, box, K, out, base, shifts, Sm=None, m=None):
     """Baseline of sample i; the co-moving displacement comes from `shifts`
     (all samples, comoving_shift) or is measured on the sample itself (and
-    its state m steps earlier, Sm[i])."""
+    its state m steps earlier, Sm[i]); the co-moving trend baseline takes
+    Sm[i] as its trend state."""
+    if base == "comoving_trend":
+        comoving_trend_base(S0[i], Sm[i], box, K, m, PHI_LIGHT, PHI_HEAVY, 1, out)
+        return
     if base == "comoving" and shifts is None:
         shift = comoving_shift(S0[i], 1, box, K, prev=None if Sm is None else Sm[i], m=m)[0]
     else:
@@ -972,7 +976,7 @@ def load_weights(net, path):
 
 def _cmd_train(a):
     import torch
-    cfg = DataConfig(n_runs=a.runs, steps=a.lbm_steps, pairs_per_run=a.pairs_per_run, m=a.m)
+    cfg = DataConfig(n_runs=a.runs, steps=a.lbm_steps, pairs_per_run=a.pairs_per_run, m=a.m, K=a.K)
     t0 = time.perf_counter()
     Sm, S0, S1, run_of, meta = generate_snapshots(cfg, log=_log)
     torch.cuda.synchronize()
@@ -1143,7 +1147,8 @@ def main():
     t.add_argument("--lr", type=float, default=2e-4)
     t.add_argument("--seed", type=int, default=0)
     t.add_argument("--m", type=int, default=25, help="steps between the trend states (<= 400)")
-    t.add_argument("--base", default="comoving", choices=["comoving", "transport"],
+    t.add_argument("--K", type=int, default=200, help="steps the network jumps (a multiple of 50)")
+    t.add_argument("--base", default="comoving", choices=["comoving", "comoving_trend", "transport"],
                    help="baseline whose residual the network learns")
     t.add_argument("--whole-cells", action="store_true",
                    help="co-moving baseline displaced by whole cells (the driver's --whole-cells)")
