@@ -147,3 +147,25 @@ def test_whole_cell_shift_carries_the_remainder(monkeypatch):
     assert seen == {1.0, 2.0}
     d = surrogate.comoving_shift(st, 1, (8, 8, 8), 100, whole_cells=False)[0]
     assert math.isclose(float(d[1]), 1.3, rel_tol=1e-6)
+
+
+def test_cycle_hook_sees_each_cycle_start_and_may_advance_and_restore():
+    # the rollout data generation samples K plain steps from each cycle start
+    # inside the hook and restores the saved state: the run must not change
+    seen = []
+
+    def hook(k, box, F_now, F_prev, backup):
+        seen.append((k, sv.t, float(F_now.flatten()[0]), float(F_prev.flatten()[0])))
+        sv.step(10)
+        sv.restore_state(backup)
+
+    sv = FakeSolver()
+    jc = surrogate.JumpConfig(K=10, relax=20, m=5, box=(8, 8, 8))
+    r = surrogate.run_with_jumps(None, sv, Setup(), 5 + 4 * 30, jc, log=lambda *_: None, mode="persistence",
+                                 on_cycle=hook)
+    assert [k for k, *_ in seen] == [0, 1, 2, 3]
+    # solver steps at each cycle start (a jump skips K = 10 of each 30-step cycle), with the trend
+    # fields of that moment: F_now at the cycle start, F_prev m = 5 steps before
+    assert [t for _, t, _, _ in seen] == [5, 25, 45, 65]
+    assert [(a, b) for _, _, a, b in seen] == [(5.0, 0.0), (25.0, 20.0), (45.0, 40.0), (65.0, 60.0)]
+    assert (r["accepted"], r["rejected"]) == (4, 0) and sv.t == 5 + 4 * 20
