@@ -211,6 +211,7 @@ __global__ void k_weight_mirror(const bf16 *__restrict__ wt, int Co, int Ci, bf1
 constexpr int kBwStep = 16;          // voxels per matrix-core K step
 constexpr int kBwThreads = 64;       // one wave per block (block to chunk, d offset and tile: see the kernel)
 constexpr int kBw2TargetBlocks = 1024;
+constexpr int kBwReduceGroup = 32;   // chunks per group of the two-level chunk sum
 
 // xt[((r ng + g) C + c) 8 + e] = x[r][8 g + e][c] for 8 g + e < W, 0 up to the
 // padded row length (one thread per row, group and channel: consecutive
@@ -396,6 +397,21 @@ __global__ void k_reduce_partials(const float *__restrict__ partial, int nchunk,
     float s = 0.f;
     for (int k = 0; k < nchunk; ++k) s += partial[(int64_t)k * stride + i];
     out[i] = s;
+}
+
+// First level of a two-level fixed-order sum over chunks: group blockIdx.y
+// adds chunks [g per, (g + 1) per) into out[g][i] (one thread per entry and
+// group, so long sums are spread over many more threads than entries).
+__global__ void k_reduce_partials_grouped(const float *__restrict__ partial, int nchunk, int per, int64_t stride,
+                                          float *__restrict__ out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= stride) return;
+    const int g = blockIdx.y;
+    const int k1 = (g + 1) * per < nchunk ? (g + 1) * per : nchunk;
+    float s = 0.f;
+    for (int k = g * per; k < k1; ++k) s += partial[(int64_t)k * stride + i];
+    out[(int64_t)g * stride + i] = s;
 }
 
 // ---- elementwise and resampling ----------------------------------------------------
@@ -1093,7 +1109,8 @@ struct BwPlan {
     int64_t per;
     int nb;          // bias ranges per channel
     int64_t bper;
-    size_t off_bpart, off_xt, off_dyt, bytes;
+    int rgroups;     // groups of the two-level chunk sum (1: one level)
+    size_t off_part2, off_bpart, off_xt, off_dyt, bytes;
 };
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
@@ -1116,7 +1133,9 @@ BwPlan bw_plan(int n, int d, int h, int w, int ci, int co)
     nb = nb < 1 ? 1 : (nb > 256 ? 256 : nb);
     p.bper = (groups + nb - 1) / nb;
     p.nb = (int)((groups + p.bper - 1) / p.bper);
-    p.off_bpart = align_up((size_t)p.chunks * 27 * ci * co * sizeof(float), 256);
+    p.rgroups = (p.chunks + kBwReduceGroup - 1) / kBwReduceGroup;
+    p.off_part2 = align_up((size_t)p.chunks * 27 * ci * co * sizeof(float), 256);
+    p.off_bpart = p.off_part2 + (p.rgroups > 1 ? align_up((size_t)p.rgroups * 27 * ci * co * sizeof(float), 256) : 0);
     p.off_xt = p.off_bpart + align_up((size_t)p.nb * co * sizeof(float), 256);
     p.off_dyt = p.off_xt + align_up((size_t)ci * groups * 8 * sizeof(bf16), 256);
     p.bytes = p.off_dyt + align_up((size_t)co * groups * 8 * sizeof(bf16), 256);
@@ -1125,7 +1144,8 @@ BwPlan bw_plan(int n, int d, int h, int w, int ci, int co)
 
 // Weight and bias gradient through the scratch `ws` (every entry written
 // before it is read): group-major copies of x and dy, per-chunk partial sums
-// part[chunk][t][co][ci], then a fixed-order sum over chunks.
+// part[chunk][t][co][ci], then a fixed-order sum over chunks (in groups of
+// kBwReduceGroup chunks, then over the groups).
 sg_status launch_bwd_weight(const void *x, const void *dy, int n, int d, int h, int w, int c_in, int c_out,
                             float *dw, float *db, const BwPlan &p, char *ws, hipStream_t s)
 {
@@ -1147,7 +1167,17 @@ sg_status launch_bwd_weight(const void *x, const void *dy, int n, int d, int h, 
                        p.steps, p.per, p.chunks, part);
     SG_LAUNCH_CHECK();
     const int64_t stride = (int64_t)27 * c_in * c_out;
-    hipLaunchKernelGGL(k_reduce_partials, dim3(blocks_for(stride)), dim3(kThreads), 0, s, part, p.chunks, stride, dw);
+    if (p.rgroups > 1) {
+        float *part2 = (float *)(ws + p.off_part2);
+        hipLaunchKernelGGL(k_reduce_partials_grouped, dim3(blocks_for(stride), (unsigned)p.rgroups), dim3(kThreads), 0,
+                           s, part, p.chunks, kBwReduceGroup, stride, part2);
+        SG_LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_reduce_partials, dim3(blocks_for(stride)), dim3(kThreads), 0, s, part2, p.rgroups, stride,
+                           dw);
+    } else {
+        hipLaunchKernelGGL(k_reduce_partials, dim3(blocks_for(stride)), dim3(kThreads), 0, s, part, p.chunks, stride,
+                           dw);
+    }
     SG_LAUNCH_CHECK();
     if (db) {
         hipLaunchKernelGGL(k_bias_grad_gm, dim3((unsigned)p.nb, (unsigned)c_out), dim3(kThreads), 0, s, dyt,

@@ -358,6 +358,89 @@ def generate_snapshots(cfg: DataConfig, device="cuda:0", log=print):
     return Sm[:slot], S0[:slot], S1[:slot], np.array(run_of), meta
 
 
+@dataclass
+class RolloutConfig:
+    """Training states taken from the jump driver itself: rising-bubble runs
+    (seeded diameter, Eotvos number and centre offset) advanced by the
+    driver with the co-moving trend jump; at every sampled cycle the states
+    m steps before the cycle start and at it (the jump's inputs) are cropped
+    to the driver's window, and the target is the state after K plain LBM
+    steps from the cycle start, after which the driver resumes from its
+    saved state.  The network so learns the residual of the baseline on the
+    states it meets in the driver, which relaxed after earlier jumps."""
+    n_runs: int = 30
+    grid: tuple = (192, 640, 192)
+    d_range: tuple = (32.0, 48.0)
+    eo_range: tuple = (6.0, 14.0)
+    offset: float = 8.0
+    centre_y: float = 160.0
+    warmup: int = 4000
+    K: int = 100
+    relax: int = 250
+    m: int = 200
+    cycles: int = 20
+    first_sample: int = 2          # first sampled cycle (the first ones follow the start-up)
+    box: tuple = (112, 128, 112)
+    seed: int = 11
+    storage: str = "f32"
+
+
+def generate_rollout_snapshots(cfg: RolloutConfig, device="cuda:0", log=print):
+    """Sm, S0, S1 crops (see RolloutConfig) on the device, the run index of
+    every sample and the run parameters."""
+    import torch
+
+    from . import inputs, lbm
+    rng = np.random.default_rng(cfg.seed)
+    nx, ny, nz = cfg.grid
+    bx, by, bz = cfg.box
+    V = bx * by * bz
+    per_run = cfg.cycles - cfg.first_sample
+    total = cfg.n_runs * per_run
+    Sm = torch.empty((total, V * NCH), device=device, dtype=torch.float32)
+    S0, S1 = torch.empty_like(Sm), torch.empty_like(Sm)
+    xb = torch.empty(V * C_IN, device=device, dtype=torch.bfloat16)
+    one = [1.0] * NCH
+    run_of, meta = [], []
+    slot = 0
+    t0 = time.perf_counter()
+    for r in range(cfg.n_runs):
+        D = float(rng.uniform(*cfg.d_range))
+        eo = float(rng.uniform(*cfg.eo_range))
+        off = rng.uniform(-cfg.offset, cfg.offset, 3)
+        g = eo * 1e-4 / (1.0 * D * D)          # Eo = g rho_H D^2 / sigma, sigma = 1e-4, rho_H = 1
+        c = (nx / 2 + off[0], cfg.centre_y + off[1], nz / 2 + off[2])
+        s = inputs.rising_bubble(nx, ny, nz, D=D, center=c, g=g)
+        phi, u, ps = inputs.build_fields(s)
+        sv = lbm.Solver(s.physics(), storage=cfg.storage, device=device)
+        sv.init_fields(phi, u, ps)
+        jc = JumpConfig(K=cfg.K, relax=cfg.relax, m=cfg.m, warmup=cfg.warmup, box=cfg.box)
+        start = slot
+
+        def sample(k, box, F_now, F_prev, backup):
+            nonlocal slot
+            if k < cfg.first_sample or slot - start >= per_run:
+                return
+            sg.sg_fields_to_input(F_prev[0], F_prev[1:4], F_prev[4], nx, ny, nz, box, one, C_IN, xb, Sm[slot])
+            sg.sg_fields_to_input(F_now[0], F_now[1:4], F_now[4], nx, ny, nz, box, one, C_IN, xb, S0[slot])
+            sv.step(cfg.K)
+            f = sv.macroscopic(torch.float32)
+            sg.sg_fields_to_input(*f, nx, ny, nz, box, one, C_IN, xb, S1[slot])
+            del f
+            sv.restore_state(backup)
+            slot += 1
+
+        steps = cfg.warmup + cfg.m + cfg.cycles * (cfg.K + cfg.relax)
+        run_with_jumps(None, sv, s, steps, jc, log=lambda *_: None, mode="comoving_trend", on_cycle=sample)
+        run_of += [r] * (slot - start)
+        meta.append({"D": D, "Eo": eo, "g": g, "centre": [float(v) for v in c]})
+        log(f"[data] rollout run {r}: D={D:.1f} Eo={eo:.1f}: {slot - start} samples ({time.perf_counter() - t0:.0f}s)")
+        del sv
+        torch.cuda.empty_cache()
+    torch.cuda.synchronize()
+    return Sm[:slot], S0[:slot], S1[:slot], np.array(run_of), meta
+
+
 def _moments(a, rows, scratch, out):
     sg.sg_channel_moments(a, rows, NCH, out, scratch)
     m = out.tolist()
@@ -762,7 +845,7 @@ def _jump(net, mode, F_now, F_prev, setup, box, jc: JumpConfig, diagnostics=Fals
     return inc
 
 
-def run_with_jumps(net, solver, setup, total_steps, jc: JumpConfig, log=print, mode="network"):
+def run_with_jumps(net, solver, setup, total_steps, jc: JumpConfig, log=print, mode="network", on_cycle=None):
     """Advances `solver` by total_steps: jc.warmup plain steps (the start-up
     from rest), m plain steps to start the trend,
     then cycles of one jump (K steps, see _jump) plus jc.relax LBM steps,
@@ -776,7 +859,9 @@ def run_with_jumps(net, solver, setup, total_steps, jc: JumpConfig, log=print, m
     run plainly; a run that fails even then raises.  The jumped
     fields enter the solver through lbm_shift_equilibrium (populations keep
     their non-equilibrium parts) or, with jc.keep_neq False, are rebuilt at
-    equilibrium."""
+    equilibrium.  on_cycle(k, box, F_now, F_prev, backup), if given, is
+    called at the start of cycle k once its state is saved to `backup` and
+    before the jump; it may advance the solver if it restores `backup`."""
     import torch
     nx, ny, nz = setup.nx, setup.ny, setup.nz
     shape = (5, nz, ny, nx)
@@ -795,6 +880,7 @@ def run_with_jumps(net, solver, setup, total_steps, jc: JumpConfig, log=print, m
     t_log = t0
     across = jc.m == cyc               # trend between consecutive cycle ends
     memory = {}                         # acceleration estimate carried between cycles
+    cycle = 0
     assert across or 0 < jc.m <= jc.relax
     if jc.warmup:                       # plain steps before the first jump
         solver.step(jc.warmup)
@@ -823,6 +909,9 @@ def run_with_jumps(net, solver, setup, total_steps, jc: JumpConfig, log=print, m
             have_older = True
         solver.save_state(backup)
         box = _window(cent, jc.box, (nx, ny, nz))
+        if on_cycle is not None:
+            on_cycle(cycle, box, F_now, F_prev, backup)
+        cycle += 1
         tp = time.perf_counter()
         if across:
             F_keep.copy_(F_now)
@@ -976,9 +1065,14 @@ def load_weights(net, path):
 
 def _cmd_train(a):
     import torch
-    cfg = DataConfig(n_runs=a.runs, steps=a.lbm_steps, pairs_per_run=a.pairs_per_run, m=a.m, K=a.K)
+    if a.rollout:
+        cfg = RolloutConfig(n_runs=a.runs, K=a.K, m=a.m, relax=a.relax, cycles=a.cycles)
+        if a.box:
+            cfg.box = tuple(int(v) for v in a.box.split("x"))
+    else:
+        cfg = DataConfig(n_runs=a.runs, steps=a.lbm_steps, pairs_per_run=a.pairs_per_run, m=a.m, K=a.K)
     t0 = time.perf_counter()
-    Sm, S0, S1, run_of, meta = generate_snapshots(cfg, log=_log)
+    Sm, S0, S1, run_of, meta = (generate_rollout_snapshots if a.rollout else generate_snapshots)(cfg, log=_log)
     torch.cuda.synchronize()
     t_data = time.perf_counter() - t0
     net = Net(seed=a.seed)
@@ -1152,6 +1246,11 @@ def main():
                    help="baseline whose residual the network learns")
     t.add_argument("--whole-cells", action="store_true",
                    help="co-moving baseline displaced by whole cells (the driver's --whole-cells)")
+    t.add_argument("--rollout", action="store_true",
+                   help="training states from the jump driver (co-moving trend jumps), targets K plain steps on")
+    t.add_argument("--relax", type=int, default=250, help="relaxation steps per cycle of the rollout runs")
+    t.add_argument("--cycles", type=int, default=20, help="jump cycles per rollout run")
+    t.add_argument("--box", default=None, help="window bx x by x bz of the rollout samples")
     t.add_argument("--weights", default=None)
     t.add_argument("--out", default=None)
     j = sub.add_parser("jump")
