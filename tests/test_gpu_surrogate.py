@@ -94,12 +94,16 @@ def test_conv3d_input_gradient(env, case):
 
 @pytest.mark.parametrize("case", [
     (1, 4, 6, 8, 16, 32), (2, 5, 6, 7, 32, 64), (1, 4, 4, 4, 96, 32),
-    # the launch plans of full-size layers: W rows padded to whole 16-voxel
-    # steps (W = 40 -> 48, W = 21 -> 32), several steps per block (3 and 5
-    # here), several (co, ci) tiles, wall-to-wall zero padding in d and h
+    # W rows padded to whole 16-voxel steps (W = 40 -> 48, W = 21 -> 32),
+    # many (co, ci) tiles (8 x 4), wall-to-wall zero padding in d and h
     (1, 4, 8, 40, 128, 256), (1, 5, 13, 21, 128, 256),
-    # more K steps (2025) than the plan's blocks: 2 steps per block, a last block with one
+    # more K steps (2025) than the plan's chunks: 2 steps per chunk, empty
+    # chunks up to a multiple of 8, the two-level chunk sum (32 groups)
     (3, 15, 15, 40, 32, 32),
+    # 5 steps per chunk with H = 4: a chunk's h runs end inside it and restart
+    # on the next (n, d) plane or 16-voxel column, as in the full-size layers
+    # (W = 200 -> 208, 13 columns, 4992 steps in 1000 chunks)
+    (2, 48, 4, 200, 32, 32),
 ])
 def test_conv3d_weight_gradient(env, case):
     torch, sg = env
