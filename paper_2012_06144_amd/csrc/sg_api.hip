@@ -109,9 +109,9 @@ __global__ __launch_bounds__(kThreads, 2) void k_conv3d_lds(const bf16 *__restri
         for (int j = 0; j < NT; ++j)
             for (int r = 0; r < 16; ++r) acc[m][j][r] = 0.f;
 
-    for (int c0 = 0; c0 < Ci; c0 += 16) {
-        // stage the box and its halo: all loads first, then all LDS stores
-        bf16x8 tmp[B::ITEMS];
+    // The box and its halo for the channel slice c0, one 16-byte load per item
+    // (zeros outside the volume), into registers.
+    auto load_slice = [&](int c0, bf16x8 (&tmp)[B::ITEMS]) {
 #pragma unroll
         for (int i = 0; i < B::ITEMS; ++i) {
             const int item = threadIdx.x + i * kThreads;
@@ -126,14 +126,17 @@ __global__ __launch_bounds__(kThreads, 2) void k_conv3d_lds(const bf16 *__restri
             }
             tmp[i] = v;
         }
-        __syncthreads();  // the previous slice's operand reads are done
+    };
+    auto store_slice = [&](const bf16x8 (&tmp)[B::ITEMS]) {
 #pragma unroll
         for (int i = 0; i < B::ITEMS; ++i) {
             const int item = threadIdx.x + i * kThreads;
             if (item < 2 * B::NV)
                 *reinterpret_cast<bf16x8 *>(hs + (item >> 1) * kHaloPitch + (item & 1) * 8) = tmp[i];
         }
-        __syncthreads();
+    };
+    // 27 taps x 4 tiles x NT products of one slice from the staged box
+    auto taps = [&](int c0) {
         const bf16 *wp = wt + ((int64_t)col0 + lr) * Ci + c0 + kh;
 #pragma unroll 3
         for (int tap = 0; tap < 27; ++tap) {
@@ -150,6 +153,30 @@ __global__ __launch_bounds__(kThreads, 2) void k_conv3d_lds(const bf16 *__restri
                 for (int j = 0; j < NT; ++j)
                     acc[m][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv[j], acc[m][j], 0, 0, 0);
             }
+        }
+    };
+
+    if constexpr (NT == 1) {
+        // Registers allow the next slice's loads to be in flight during this
+        // slice's products (the NT = 2 kernel is at 223 VGPRs without them).
+        bf16x8 tmp[B::ITEMS];
+        load_slice(0, tmp);
+        for (int c0 = 0; c0 < Ci; c0 += 16) {
+            __syncthreads();  // the previous slice's operand reads are done
+            store_slice(tmp);
+            __syncthreads();
+            if (c0 + 16 < Ci) load_slice(c0 + 16, tmp);
+            taps(c0);
+        }
+    } else {
+        for (int c0 = 0; c0 < Ci; c0 += 16) {
+            // stage the box and its halo: all loads first, then all LDS stores
+            bf16x8 tmp[B::ITEMS];
+            load_slice(c0, tmp);
+            __syncthreads();  // the previous slice's operand reads are done
+            store_slice(tmp);
+            __syncthreads();
+            taps(c0);
         }
     }
     // D layout of the 32x32 tile: column l % 32, row 8 (r/4) + 4 (l/32) + r % 4
