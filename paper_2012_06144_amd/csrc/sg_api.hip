@@ -1263,11 +1263,13 @@ sg_status sg_conv3d_fwd(const void *x, int32_t n, int32_t d, int32_t h, int32_t 
     if (n_store < 1 || n_store > c_out) return fail(SG_EARG, "n_store must be in [1, c_out]");
     if (!aligned16(x) || !aligned16(wt)) return fail(SG_EARG, "x and wt must be 16-byte aligned");
     const int tiles = c_out / 32;
-    const int nt = tiles % 2 == 0 ? 2 : 1;
     const int tw = w > 16 ? 32 : w > 8 ? 16 : 8;
     const int th = 32 / tw;
     const int nbd = (d + 3) / 4, nbh = (h + 4 * th - 1) / (4 * th), nbw = (w + tw - 1) / tw;
     const int64_t nbox = (int64_t)n * nbd * nbh * nbw;
+    // 64 output channels per block where that still gives two blocks per CU
+    // (256 CUs); below that, 32 per block doubles the blocks of small layers
+    const int nt = tiles % 2 == 0 && nbox * (tiles / 2) >= 512 ? 2 : 1;
     if (nbox > 0x7fffffff) return fail(SG_ESIZE, "too many voxels");
     const dim3 grid((unsigned)nbox, (unsigned)(tiles / nt));
     hipStream_t s = (hipStream_t)stream;
