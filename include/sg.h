@@ -36,6 +36,18 @@ sg_status sg_conv3d_fwd(const void *x, int32_t n, int32_t d, int32_t h, int32_t 
                         const void *wt, const float *bias, int32_t c_out, int32_t n_store, int32_t act,
                         float slope, void *y, int32_t y_f32, void *hip_stream);
 
+/* sg_conv3d_fwd of the channel concatenation [up2(xa), xb] without forming
+ * it (the U-Net decoder's input): xa holds ca channels at half resolution,
+ * (n, d/2, h/2, w/2, ca), and is upsampled by nearest 2x (as sg_up2_fwd);
+ * xb holds cb channels at full resolution, (n, d, h, w, cb); the weights wt
+ * have c_in = ca + cb input channels in that order.  The same staging and
+ * products as sg_conv3d_fwd on the concatenated tensor, so the output is
+ * bit-identical to it.  ca, cb positive multiples of 16; d, h, w even. */
+sg_status sg_conv3d_fwd_up_cat(const void *xa, int32_t ca, const void *xb, int32_t cb, int32_t n, int32_t d,
+                               int32_t h, int32_t w, const void *wt, const float *bias, int32_t c_out,
+                               int32_t n_store, int32_t act, float slope, void *y, int32_t y_f32,
+                               void *hip_stream);
+
 /* Weights of the input gradient: wm[26 - t][ci][co] = wt[t][co][ci] (BF16).
  * sg_conv3d_fwd(dy, wm, bias = NULL) then gives dx[v][ci] =
  * sum_t sum_co dy[v - offset(t)][co] wt[t][co][ci]. */

@@ -69,8 +69,15 @@ struct HaloBox {
     static constexpr int ITEMS = (2 * NV + kThreads - 1) / kThreads;  // 16-byte loads per thread
 };
 
-template <int NT, int TW>
-__global__ __launch_bounds__(kThreads, 2) void k_conv3d_lds(const bf16 *__restrict__ x,
+// The input may come from two tensors: channels [0, ca) from xa, at half
+// resolution (nearest 2x upsampling, up_a != 0) or full, and channels
+// [ca, Ci) from xb at full resolution -- the decoder's concatenation of an
+// upsampled tensor and a skip connection, read without forming it.  A single
+// input is xa with ca = Ci, up_a = 0.  ca is a multiple of 16, so each
+// staged channel slice comes from one tensor.
+template <int NT, int TW, bool CAT>
+__global__ __launch_bounds__(kThreads, 2) void k_conv3d_lds(const bf16 *__restrict__ xa, int ca, int up_a,
+                                                            const bf16 *__restrict__ xb,
                                                             const bf16 *__restrict__ wt,
                                                             const float *__restrict__ bias,
                                                             void *__restrict__ y, int N, int D, int H, int W,
@@ -112,6 +119,13 @@ __global__ __launch_bounds__(kThreads, 2) void k_conv3d_lds(const bf16 *__restri
     // The box and its halo for the channel slice c0, one 16-byte load per item
     // (zeros outside the volume), into registers.
     auto load_slice = [&](int c0, bf16x8 (&tmp)[B::ITEMS]) {
+        // the slice's tensor: its base, channel count and resolution shift
+        // (CAT); a single input is xa with Ci channels at full resolution
+        const bool from_a = !CAT || c0 < ca;
+        const bf16 *base = from_a ? xa + c0 : xb + (c0 - ca);
+        const int64_t cst = CAT ? (from_a ? ca : Ci - ca) : Ci;
+        const int sh = CAT && from_a && up_a ? 1 : 0;
+        const int Ds = D >> sh, Hs = H >> sh, Ws = W >> sh;
 #pragma unroll
         for (int i = 0; i < B::ITEMS; ++i) {
             const int item = threadIdx.x + i * kThreads;
@@ -120,9 +134,10 @@ __global__ __launch_bounds__(kThreads, 2) void k_conv3d_lds(const bf16 *__restri
                 const int half = item & 1, hv = item >> 1;
                 const int hw = hv % B::HW, hh = (hv / B::HW) % B::HH, hd = hv / (B::HW * B::HH);
                 const int dd = d0 - 1 + hd, yy = h0 - 1 + hh, xx = w0 - 1 + hw;
-                if (dd >= 0 && dd < D && yy >= 0 && yy < H && xx >= 0 && xx < W)
-                    v = *reinterpret_cast<const bf16x8 *>(
-                        x + ((((int64_t)n * D + dd) * H + yy) * W + xx) * Ci + c0 + half * 8);
+                if (dd >= 0 && dd < D && yy >= 0 && yy < H && xx >= 0 && xx < W) {
+                    const int64_t vox = (((int64_t)n * Ds + (dd >> sh)) * Hs + (yy >> sh)) * Ws + (xx >> sh);
+                    v = *reinterpret_cast<const bf16x8 *>(base + vox * cst + half * 8);
+                }
             }
             tmp[i] = v;
         }
@@ -1252,16 +1267,19 @@ sg_status noalloc_scratch_ptr(void **out)
 
 extern "C" {
 
-sg_status sg_conv3d_fwd(const void *x, int32_t n, int32_t d, int32_t h, int32_t w, int32_t c_in,
-                        const void *wt, const float *bias, int32_t c_out, int32_t n_store, int32_t act,
-                        float slope, void *y, int32_t y_f32, void *stream)
+// The forward launch for one input (xa, ca = c_in, up_a = 0, xb = NULL) or
+// the upsampled-and-concatenated pair (arguments checked by the callers).
+static sg_status conv3d_fwd_launch(const void *xa, int32_t ca, int32_t up_a, const void *xb, int32_t n,
+                                   int32_t d, int32_t h, int32_t w, int32_t c_in, const void *wt, const float *bias,
+                                   int32_t c_out, int32_t n_store, int32_t act, float slope, void *y, int32_t y_f32,
+                                   void *stream)
 {
-    if (!x || !wt || !y) return fail(SG_EARG, "NULL tensor");
+    if (!wt || !y) return fail(SG_EARG, "NULL tensor");
     if (n < 1 || d < 1 || h < 1 || w < 1) return fail(SG_EARG, "bad shape");
     if (c_in < 16 || c_in % 16) return fail(SG_EARG, "c_in must be a positive multiple of 16 (got %d)", c_in);
     if (c_out < 32 || c_out % 32) return fail(SG_EARG, "c_out must be a positive multiple of 32 (got %d)", c_out);
     if (n_store < 1 || n_store > c_out) return fail(SG_EARG, "n_store must be in [1, c_out]");
-    if (!aligned16(x) || !aligned16(wt)) return fail(SG_EARG, "x and wt must be 16-byte aligned");
+    if (!aligned16(wt)) return fail(SG_EARG, "wt must be 16-byte aligned");
     const int tiles = c_out / 32;
     const int tw = w > 16 ? 32 : w > 8 ? 16 : 8;
     const int th = 32 / tw;
@@ -1273,10 +1291,16 @@ sg_status sg_conv3d_fwd(const void *x, int32_t n, int32_t d, int32_t h, int32_t 
     if (nbox > 0x7fffffff) return fail(SG_ESIZE, "too many voxels");
     const dim3 grid((unsigned)nbox, (unsigned)(tiles / nt));
     hipStream_t s = (hipStream_t)stream;
-    const bf16 *X = (const bf16 *)x, *Wt = (const bf16 *)wt;
+    const bf16 *XA = (const bf16 *)xa, *XB = (const bf16 *)xb, *Wt = (const bf16 *)wt;
 #define SG_CONV_LAUNCH(NT_, TW_)                                                                              \
-    hipLaunchKernelGGL((k_conv3d_lds<NT_, TW_>), grid, dim3(kThreads), 0, s, X, Wt, bias, y, n, d, h, w, c_in, \
-                       c_out, n_store, act, slope, y_f32, nbd, nbh, nbw)
+    do {                                                                                                      \
+        if (XB)                                                                                               \
+            hipLaunchKernelGGL((k_conv3d_lds<NT_, TW_, true>), grid, dim3(kThreads), 0, s, XA, ca, up_a, XB, Wt, \
+                               bias, y, n, d, h, w, c_in, c_out, n_store, act, slope, y_f32, nbd, nbh, nbw);    \
+        else                                                                                                  \
+            hipLaunchKernelGGL((k_conv3d_lds<NT_, TW_, false>), grid, dim3(kThreads), 0, s, XA, ca, up_a, XB,   \
+                               Wt, bias, y, n, d, h, w, c_in, c_out, n_store, act, slope, y_f32, nbd, nbh, nbw); \
+    } while (0)
     if (nt == 2) {
         if (tw == 32) SG_CONV_LAUNCH(2, 32);
         else if (tw == 16) SG_CONV_LAUNCH(2, 16);
@@ -1289,6 +1313,29 @@ sg_status sg_conv3d_fwd(const void *x, int32_t n, int32_t d, int32_t h, int32_t 
 #undef SG_CONV_LAUNCH
     SG_LAUNCH_CHECK();
     return SG_OK;
+}
+
+sg_status sg_conv3d_fwd(const void *x, int32_t n, int32_t d, int32_t h, int32_t w, int32_t c_in,
+                        const void *wt, const float *bias, int32_t c_out, int32_t n_store, int32_t act,
+                        float slope, void *y, int32_t y_f32, void *stream)
+{
+    if (!x) return fail(SG_EARG, "NULL tensor");
+    if (!aligned16(x)) return fail(SG_EARG, "x and wt must be 16-byte aligned");
+    return conv3d_fwd_launch(x, c_in, 0, nullptr, n, d, h, w, c_in, wt, bias, c_out, n_store, act, slope, y, y_f32,
+                             stream);
+}
+
+sg_status sg_conv3d_fwd_up_cat(const void *xa, int32_t ca, const void *xb, int32_t cb, int32_t n, int32_t d,
+                               int32_t h, int32_t w, const void *wt, const float *bias, int32_t c_out,
+                               int32_t n_store, int32_t act, float slope, void *y, int32_t y_f32, void *stream)
+{
+    if (!xa || !xb) return fail(SG_EARG, "NULL tensor");
+    if (!aligned16(xa) || !aligned16(xb)) return fail(SG_EARG, "xa and xb must be 16-byte aligned");
+    if (ca < 16 || ca % 16 || cb < 16 || cb % 16)
+        return fail(SG_EARG, "ca and cb must be positive multiples of 16 (got %d, %d)", ca, cb);
+    if (d % 2 || h % 2 || w % 2) return fail(SG_EARG, "d, h and w must be even (upsampling by 2)");
+    return conv3d_fwd_launch(xa, ca, 1, xb, n, d, h, w, ca + cb, wt, bias, c_out, n_store, act, slope, y, y_f32,
+                             stream);
 }
 
 sg_status sg_weight_mirror(const void *wt, int32_t c_out, int32_t c_in, void *wm, void *stream)

@@ -12,7 +12,7 @@ import ctypes as C
 from .lbm import LIB_PATH, LbmError, _lib as _L  # noqa: F401  (loads the library)
 
 EXPORTS = [
-    "sg_conv3d_fwd", "sg_weight_mirror", "sg_conv3d_bwd_data", "sg_conv3d_bwd_data_noalloc", "sg_bwd_weight_workspace", "sg_conv3d_bwd_weight",
+    "sg_conv3d_fwd", "sg_conv3d_fwd_up_cat", "sg_weight_mirror", "sg_conv3d_bwd_data", "sg_conv3d_bwd_data_noalloc", "sg_bwd_weight_workspace", "sg_conv3d_bwd_weight",
     "sg_leaky_bwd", "sg_pool2_fwd", "sg_pool2_bwd", "sg_up2_fwd", "sg_up2_bwd", "sg_concat",
     "sg_split", "sg_mse", "sg_adam", "sg_to_bf16", "sg_to_f32", "sg_add", "sg_fields_to_input",
     "sg_state_to_input", "sg_make_target", "sg_apply_prediction", "sg_advect_phase", "sg_projective_step",
@@ -23,6 +23,7 @@ EXPORTS = [
 _vp, _i, _i64, _f, _sz = C.c_void_p, C.c_int32, C.c_int64, C.c_float, C.c_size_t
 _SIG = {
     "sg_conv3d_fwd": [_vp, _i, _i, _i, _i, _i, _vp, _vp, _i, _i, _i, _f, _vp, _i, _vp],
+    "sg_conv3d_fwd_up_cat": [_vp, _i, _vp, _i, _i, _i, _i, _i, _vp, _vp, _i, _i, _i, _f, _vp, _i, _vp],
     "sg_weight_mirror": [_vp, _i, _i, _vp, _vp],
     "sg_conv3d_bwd_data": [_vp, _i, _i, _i, _i, _i, _vp, _i, _vp, _vp, _sz, _vp],
     "sg_conv3d_bwd_data_noalloc": [_vp, _i, _i, _i, _i, _i, _vp, _i, _vp, _vp],
@@ -85,6 +86,15 @@ def sg_conv3d_fwd(x, wt, bias, c_out, n_store, act, slope, y, y_f32, stream=None
     n, d, h, w, c_in = x.shape
     _check(_L.sg_conv3d_fwd(_p(x), n, d, h, w, c_in, _p(wt), _p(bias), c_out, n_store, int(act),
                             float(slope), _p(y), int(y_f32), _stream(stream)), "sg_conv3d_fwd")
+
+
+def sg_conv3d_fwd_up_cat(xa, xb, wt, bias, c_out, n_store, act, slope, y, y_f32, stream=None):
+    """sg_conv3d_fwd of [up2(xa), xb] along the channels: xa (N, D/2, H/2, W/2, ca), xb (N, D, H, W, cb)."""
+    n, d, h, w, cb = xb.shape
+    ca = xa.shape[-1]
+    assert tuple(xa.shape[:4]) == (n, d // 2, h // 2, w // 2)
+    _check(_L.sg_conv3d_fwd_up_cat(_p(xa), ca, _p(xb), cb, n, d, h, w, _p(wt), _p(bias), c_out, n_store, int(act),
+                                   float(slope), _p(y), int(y_f32), _stream(stream)), "sg_conv3d_fwd_up_cat")
 
 
 def sg_weight_mirror(wt, wm, stream=None):

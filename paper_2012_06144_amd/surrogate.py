@@ -98,6 +98,15 @@ class Net:
         sg.sg_conv3d_fwd(x, d["wt"], d["b"], co, co, act, SLOPE, y, int(f32_out))
         return y
 
+    def _conv_up_cat(self, name, low, skip):
+        """The layer applied to [up2(low), skip] without forming that tensor."""
+        d = self.p[name]
+        _, ci, co, act = next(l for l in LAYERS if l[0] == name)
+        assert low.shape[-1] + skip.shape[-1] == ci, (name, low.shape, skip.shape, ci)
+        y = self._empty(skip.shape[:-1] + (co,))
+        sg.sg_conv3d_fwd_up_cat(low, skip, d["wt"], d["b"], co, co, act, SLOPE, y, 0)
+        return y
+
     def _pool(self, x):
         n, dd, h, w, c = x.shape
         y = self._empty((n, dd // 2, h // 2, w // 2, c))
@@ -131,14 +140,25 @@ class Net:
         a["p3"] = self._pool(a["s2"])
         a["ba"] = self._conv("bot_a", a["p3"])
         a["bb"] = self._conv("bot_b", a["ba"])
-        a["c2"] = self._cat(self._up(a["bb"]), a["s2"])
-        a["d2a"] = self._conv("dec2a", a["c2"])
+        # the decoder's inputs [up2(coarse), skip] are formed only when the
+        # backward pass needs them; inference reads both parts directly
+        if keep:
+            a["c2"] = self._cat(self._up(a["bb"]), a["s2"])
+            a["d2a"] = self._conv("dec2a", a["c2"])
+        else:
+            a["d2a"] = self._conv_up_cat("dec2a", a["bb"], a["s2"])
         a["t2"] = self._conv("dec2b", a["d2a"])
-        a["c1"] = self._cat(self._up(a["t2"]), a["s1"])
-        a["d1a"] = self._conv("dec1a", a["c1"])
+        if keep:
+            a["c1"] = self._cat(self._up(a["t2"]), a["s1"])
+            a["d1a"] = self._conv("dec1a", a["c1"])
+        else:
+            a["d1a"] = self._conv_up_cat("dec1a", a["t2"], a["s1"])
         a["t1"] = self._conv("dec1b", a["d1a"])
-        a["c0"] = self._cat(self._up(a["t1"]), a["s0"])
-        a["d0a"] = self._conv("dec0a", a["c0"])
+        if keep:
+            a["c0"] = self._cat(self._up(a["t1"]), a["s0"])
+            a["d0a"] = self._conv("dec0a", a["c0"])
+        else:
+            a["d0a"] = self._conv_up_cat("dec0a", a["t1"], a["s0"])
         a["t0"] = self._conv("dec0b", a["d0a"])
         out = self._conv("out", a["t0"], f32_out=True)
         if keep:

@@ -269,6 +269,55 @@ def test_mass_projection_matches_oracle(env, walls, lo, hi):
     assert abs(got[fluid].sum() - target) <= 0.5 * _ulp32(got[fluid]).sum()
 
 
+@pytest.mark.parametrize("case", [
+    # (n, d, h, w, ca, cb, co): the decoder's three levels (64 + 32 -> 32 at W = 64 takes NT = 1, TW = 32;
+    # 128 + 64 -> 64 at W = 32 NT = 2; 128 + 128 -> 128 at W = 16 NT = 1, TW = 16), a small-W case, and
+    # partial boxes in d and h
+    (2, 8, 6, 64, 64, 32, 32), (1, 4, 8, 32, 128, 64, 64), (2, 4, 6, 16, 128, 128, 128), (1, 6, 10, 8, 16, 48, 64),
+])
+def test_conv3d_fwd_up_cat_matches_the_formed_input(env, case):
+    """sg_conv3d_fwd_up_cat(xa, xb) stages the same values as sg_conv3d_fwd
+    on concat(up2(xa), xb) and runs the same products: bit-identical output,
+    and the formed path is itself checked against the oracle (CONV_CASES)."""
+    torch, sg = env
+    n, d, h, w, ca, cb, co = case
+    rng = np.random.default_rng(sum(case))
+    xa, _ = _bf16(torch, rng.standard_normal((n, d // 2, h // 2, w // 2, ca)))
+    xb, _ = _bf16(torch, rng.standard_normal((n, d, h, w, cb)))
+    wt, _ = _bf16(torch, rng.standard_normal((27, co, ca + cb)) / np.sqrt(27 * (ca + cb)))
+    bias = torch.from_numpy(rng.standard_normal(co).astype(np.float32)).cuda()
+    up = torch.empty((n, d, h, w, ca), device="cuda", dtype=torch.bfloat16)
+    sg.sg_up2_fwd(xa, up)
+    cat = torch.empty((n, d, h, w, ca + cb), device="cuda", dtype=torch.bfloat16)
+    sg.sg_concat(up, xb, cat)
+    for act, f32 in ((1, 0), (0, 1)):
+        dt = torch.float32 if f32 else torch.bfloat16
+        y0 = torch.empty((n, d, h, w, co), device="cuda", dtype=dt)
+        y1 = torch.full((n, d, h, w, co), float("nan"), device="cuda", dtype=dt)
+        sg.sg_conv3d_fwd(cat, wt, bias, co, co, act, 0.1, y0, f32)
+        sg.sg_conv3d_fwd_up_cat(xa, xb, wt, bias, co, co, act, 0.1, y1, f32)
+        torch.cuda.synchronize()
+        assert torch.equal(y0, y1), (case, act, f32)
+    # an odd extent cannot be an upsampled one: refused before any launch
+    status = sg._L.sg_conv3d_fwd_up_cat(sg._p(xa), ca, sg._p(xb), cb, n, d - 1, h, w, sg._p(wt), sg._p(bias), co,
+                                        co, 1, 0.1, sg._p(y1), 0, None)
+    assert status == -1 and b"even" in sg._L.sg_last_error()
+
+
+def test_network_inference_forward_matches_training_forward(env):
+    """Net.forward(keep=False) reads the decoder's [up2(coarse), skip] inputs
+    directly; keep=True forms them for the backward pass: same output bits."""
+    torch, sg = env
+    from paper_2012_06144_amd import surrogate as S
+    net = S.Net(seed=9)
+    rng = np.random.default_rng(9)
+    x, _ = _bf16(torch, rng.standard_normal((2, 16, 24, 16, S.C_IN)) * 0.5)
+    a = net.forward(x, keep=True)
+    b = net.forward(x, keep=False)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+
+
 def test_network_gradient_against_oracle(env):
     """The whole encoder-decoder: loss gradient of the GPU network (BF16
     activations, FP32 accumulation) against the same network built from the
