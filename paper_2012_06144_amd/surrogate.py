@@ -17,6 +17,7 @@ scale_out; the input's first 5 channels are state(t) / scale_in.
 """
 from __future__ import annotations
 
+import dataclasses
 import json
 import math
 import time
@@ -775,6 +776,7 @@ class JumpConfig:
     u_max: float = 0.05         # indicator: max |u| after the relaxation (lattice units)
     box: tuple = (112, 128, 112)  # network window around the bubble (bx, by, bz), divisible by 8
     predict_pressure: bool = False  # apply the network's pressure residual (else p follows the baseline)
+    net_phi_only: bool = False  # apply only the network's phase-field residual (u follows the baseline)
     u_by_phase: bool = True     # weight velocity increments by the heavy-phase fraction
     phi_at_interface: bool = True  # weight phi increments by 4 q (1 - q): none in the bulk phases
     accel: bool = True          # co-moving jumps use the state of the trend window (acceleration or
@@ -853,6 +855,8 @@ def _jump(net, mode, F_now, F_prev, setup, box, jc: JumpConfig, diagnostics=Fals
         so = list(net.scale_out)
         if not jc.predict_pressure:
             so[4] = 0.0
+        if jc.net_phi_only:
+            so[1] = so[2] = so[3] = 0.0
     else:
         out = torch.zeros((V, C_OUT), device=F_now.device, dtype=torch.float32)
         so = [0.0] * NCH
@@ -1142,13 +1146,16 @@ def _cmd_jump(a):
         del sv
         torch.cuda.empty_cache()
     modes = a.modes.split(",")
-    variants = [(mname, None, mname) for mname in ("persistence", "transport", "comoving", "comoving_trend",
-                                                   "projective")
+    variants = [(mname, None, mname, {}) for mname in ("persistence", "transport", "comoving", "comoving_trend",
+                                                       "projective")
                 if mname in modes]
-    if a.weights and "network" in modes:
+    if a.weights and ("network" in modes or "network_phi" in modes):
         net = Net(seed=0)
         load_weights(net, a.weights)
-        variants.append(("surrogate", net, "network"))
+        if "network" in modes:
+            variants.append(("surrogate", net, "network", {}))
+        if "network_phi" in modes:         # the network's phase-field residual only
+            variants.append(("surrogate_phi", net, "network", {"net_phi_only": True}))
     jc.predict_pressure = bool(a.predict_pressure)
     jc.velocity = a.velocity
     jc.max_gain = a.max_gain
@@ -1159,12 +1166,13 @@ def _cmd_jump(a):
     jc.whole_cells = bool(a.whole_cells)
     jc.trend_gain = a.trend_gain
     jc.trend_bulk = bool(a.trend_bulk)
+    jc.net_phi_only = bool(a.net_phi_only)
     jc.clip_phi = not a.no_clip
     jc.phi_at_interface = not a.no_phi_at_interface
-    for name, net, mode in variants:
+    for name, net, mode, over in variants:
         sv = lbm.Solver(s.physics(), storage="f32")
         sv.init_fields(phi, u, ps)
-        r = run_with_jumps(net, sv, s, a.steps, jc, log=_log, mode=mode)
+        r = run_with_jumps(net, sv, s, a.steps, dataclasses.replace(jc, **over), log=_log, mode=mode)
         r["errors"] = compare_trajectories(out["runs"]["plain"], r)
         r["speedup"] = out["runs"]["plain"]["seconds"] / r["seconds"]
         out["runs"][name] = r
@@ -1279,7 +1287,9 @@ def main():
     j.add_argument("--K", type=int, default=200)
     j.add_argument("--relax", type=int, default=50)
     j.add_argument("--m", type=int, default=25, help="trend window (<= relax, or K + relax for cycle ends)")
-    j.add_argument("--modes", default="persistence,transport,comoving,network")
+    j.add_argument("--modes", default="persistence,transport,comoving,network",
+                   help="jumps to run after the plain run: persistence, transport, comoving, comoving_trend, "
+                        "projective, network, network_phi (the network's phase-field residual only)")
     j.add_argument("--grid", default=None, help="override the grid, e.g. 128x512x128")
     j.add_argument("--D", type=float, default=None, help="bubble diameter with --grid")
     j.add_argument("--eo", type=float, default=10.0, help="Eotvos number with --grid")
@@ -1298,6 +1308,8 @@ def main():
     j.add_argument("--keep-neq", action="store_true",
                    help="keep the populations' non-equilibrium parts after a jump (default: rebuild at equilibrium)")
     j.add_argument("--trend-gain", type=float, default=1.0, help="co-moving trend jump: factor on K/m")
+    j.add_argument("--net-phi-only", action="store_true",
+                   help="apply only the network's phase-field residual; the velocity follows the baseline")
     j.add_argument("--trend-bulk", action="store_true",
                    help="co-moving trend jump: velocity trend in the bulk of the heavy phase only")
     j.add_argument("--whole-cells", action="store_true",
