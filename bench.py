@@ -12,8 +12,12 @@ roofline of the dominant kernel (the fused kernel: hydrodynamic sweep of one
 step with the phase-field sweep of the next) from HIP-event timings on the
 solver stream, the same measurements for the other storage formats (FP64,
 the paper's arithmetic, and FP16/BF16 shifted populations) on the same
-workload under "other_storages", and the FP64 CPU oracle timed on the host on
-a bounded sample of the same workload.
+workload under "other_storages", the straightforward six-kernel algorithm
+(Alg. naiveAlgorithm, Sec. 4.2) under "straightforward_algorithm" beside the
+paper's 211 vs 550 MLUPS, every built pair of velocity sets (the stencil study
+of Sec. 5.1) under "lattice_variants", the surrogate study's figures from its
+committed summary (marked stale if the sources changed since), and the FP64
+CPU oracle timed on the host on a bounded sample of the same workload.
 """
 from __future__ import annotations
 
