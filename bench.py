@@ -16,8 +16,10 @@ workload under "other_storages", the straightforward six-kernel algorithm
 (Alg. naiveAlgorithm, Sec. 4.2) under "straightforward_algorithm" beside the
 paper's 211 vs 550 MLUPS, every built pair of velocity sets (the stencil study
 of Sec. 5.1) under "lattice_variants", the surrogate study's figures from its
-committed summary (marked stale if the sources changed since), and the FP64
-CPU oracle timed on the host on a bounded sample of the same workload.
+committed summary (marked stale if the sources changed since), the surrogate
+network's convolutions against the BF16 MFMA peak under "surrogate_network",
+and the FP64 CPU oracle timed on the host on a bounded sample of the same
+workload.
 """
 from __future__ import annotations
 
@@ -256,6 +258,49 @@ def cpu_baseline(setup, phi, u, ps, target_s: float = 15.0):
                       f"the {setup.name} fields ({fluid} fluid cells), {t2 - t0:.1f} s"}
 
 
+def measure_network(shape=(8, 64, 96, 64), reps=5):
+    """The surrogate network's MFMA convolutions on one batch of the
+    training crop: the inference forward pass (decoder inputs read without
+    forming them) and a forward + backward pass, timed with HIP events on
+    the current stream, against the 2.5 PFLOP/s BF16 dense peak."""
+    import torch
+
+    from paper_2012_06144_amd import surrogate as S
+    net = S.Net(seed=0)
+    n, d, h, w = shape
+    g = torch.Generator(device="cpu").manual_seed(1)
+    x = (torch.randn((n, d, h, w, S.C_IN), generator=g) * 0.5).to(net.device, torch.bfloat16)
+    stream = torch.cuda.current_stream(net.device)
+
+    def timed(fn, k):
+        fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(k):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / k
+
+    def fwd_bwd():
+        out = net.forward(x, keep=True)
+        net.backward(torch.zeros(out.shape, device=net.device, dtype=torch.bfloat16))
+
+    flop = S.flops_per_voxel() * n * d * h * w
+    t_f = timed(lambda: net.forward(x, keep=False), reps)
+    t_fb = timed(fwd_bwd, max(1, reps // 2))
+    peak = 2500.0
+    rec = {"shape": list(shape), "params": net.n_params(), "forward_ms": round(t_f, 4),
+           "forward_tflops": round(flop / (t_f * 1e-3) / 1e12, 1),
+           "roofline": {"bound": "mfma", "achieved": round(flop / (t_f * 1e-3) / 1e12, 1), "peak": peak,
+                        "unit": "TFLOP/s", "frac": round(flop / (t_f * 1e-3) / 1e12 / peak, 4)},
+           "forward_backward_ms": round(t_fb, 4),
+           "forward_backward_tflops": round(3 * flop / (t_fb * 1e-3) / 1e12, 1)}
+    del net, x
+    torch.cuda.empty_cache()
+    return rec
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -272,6 +317,7 @@ def main():
     ap.add_argument("--straightforward", default="f64,f32",
                     help="comma-separated storage formats (f64, f32) for which the straightforward six-kernel "
                          "algorithm is measured on the same workload (empty: none)")
+    ap.add_argument("--no-network", action="store_true", help="skip the surrogate network's convolution timing")
     ap.add_argument("--other-storages", default="f64,f16s,bf16s",
                     help="comma-separated storage formats measured after the main one on the same workload "
                          "(empty: none)")
@@ -405,6 +451,13 @@ def main():
                 f"fused {rec['fused_gbs']:.0f} GB/s algorithmic")
             lattices[f"{name}_{st}"] = rec
 
+    network = None
+    if not args.no_network:
+        log("[bench] surrogate network convolutions (batch 8 x 64 x 96 x 64)")
+        network = measure_network()
+        log(f"[bench] network forward {network['forward_ms']:.2f} ms ({network['forward_tflops']:.0f} TFLOP/s), "
+            f"forward+backward {network['forward_backward_ms']:.2f} ms")
+
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] CPU oracle baseline")
@@ -452,6 +505,7 @@ def main():
                                                                 "hardware": "Tesla P100", "precision": "f64"}},
         "cpu_baseline": cpu,
         "surrogate": load_surrogate_study(),
+        "surrogate_network": network,
         "kernel_source_hash": src_hash,
     }
     print(json.dumps(line), flush=True)
